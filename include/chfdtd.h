@@ -1,0 +1,198 @@
+/*
+ * chfdtd -- near-field Cherenkov (Askaryan) pulses by 3-D Yee FDTD on MI355X (gfx950).
+ *
+ * C ABI of the solver library libchfdtd.so.  Plain C types only: sizes, doubles, and
+ * host or device pointers (each argument says which).  No exceptions cross this boundary.
+ *
+ * What is computed (the paper's Numerical Method section and Simulation Setup section):
+ *   Maxwell's curl equations with conductivity (Faraday; Ampere with sigma E) on the
+ *   staggered Yee lattice, second-order central differences, leapfrog in time, driven by
+ *   the current J = v rho of the shower's charge excess: a Gaussian charge snapshot in r
+ *   and z whose centre moves along +z and whose total charge follows the longitudinal
+ *   profile Q(z) (hat-function bins).  E is recorded at detector positions every step, so
+ *   one run yields the pulses of all detectors.  The paper names no boundary; the library
+ *   offers PEC walls, first-order Mur on the tangential E of each face, and a
+ *   complex-frequency-shifted convolutional PML backed by PEC.
+ *
+ * Lattice conventions (shared with every routine below):
+ *   N nodes per axis; walls on node planes 0 and N-1 (physical length (N-1) delta).
+ *   Ex at (i+1/2, j, k), Ey at (i, j+1/2, k), Ez at (i, j, k+1/2),
+ *   Hx at (i, j+1/2, k+1/2), Hy at (i+1/2, j, k+1/2), Hz at (i+1/2, j+1/2, k).
+ *   E lives at t = n dt and H at (n+1/2) dt.  One step: H update, E update with -J at
+ *   (n+1/2) dt, boundary, then sampling of E^{n+1}: waveform index n is time (n+1) dt.
+ *   Positions are metres with node (0,0,0) at the origin.
+ *
+ * Memory and ownership:
+ *   - Descriptor structs and the host arrays they point to are read and copied during
+ *     chf_plan_create; the caller may free them afterwards.
+ *   - All device memory is the caller's: the plan reports how many bytes of workspace it
+ *     needs (chf_plan_workspace_bytes) and works inside the buffer bound with
+ *     chf_plan_bind_workspace.  Output buffers are the caller's as well.  The library never
+ *     allocates or frees device memory.
+ *   - Calls that take a stream are stream-ordered and return after enqueueing.  Kernel
+ *     faults surface as CHF_EHIP and the non-finite watchdog as CHF_ENAN from
+ *     chf_plan_sync.  A plan must not be used from two threads at once.
+ *
+ * Errors: every entry point returns a chf_status; chf_last_error() gives a thread-local
+ * message for the last failure on the calling thread.
+ */
+#ifndef CHFDTD_H
+#define CHFDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHF_ABI_VERSION 1
+
+typedef enum {
+  CHF_OK = 0,
+  CHF_EINVAL = -1,       /* malformed descriptor or argument */
+  CHF_ECFL = -2,         /* dt above the Courant limit of the medium */
+  CHF_EDOMAIN = -3,      /* observer stencil or source patch outside the usable interior */
+  CHF_ENOMEM = -4,       /* sizes overflow, or the bound workspace is too small */
+  CHF_EHIP = -5,         /* a HIP runtime call or kernel launch failed */
+  CHF_ENAN = -6,         /* the non-finite watchdog fired */
+  CHF_EUNSUPPORTED = -7, /* valid request that this build does not implement */
+  CHF_ESTATE = -8        /* call out of order (e.g. no workspace bound) */
+} chf_status;
+
+typedef enum { CHF_FP32 = 0, CHF_BF16 = 1, CHF_FP16 = 2 } chf_storage;
+typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
+typedef enum { CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2 } chf_kernel;
+
+/* Lattice: node counts (>= 3 each; the fused sweep needs nx <= 512), spacings in metres,
+   time step in seconds, number of steps. */
+typedef struct {
+  int32_t nx, ny, nz, n_steps;
+  double dx, dy, dz, dt;
+} chf_grid;
+
+/* Uniform medium: relative permittivity and permeability, conductivity in S/m
+   (Ampere's law with sigma E, integrated semi-implicitly). */
+typedef struct {
+  double eps_r, mu_r, sigma;
+} chf_medium;
+
+/* Boundary.  For CHF_BC_CPML: npml cells per face, polynomial order poly_m, and the grading
+   sigma = sigma_scale * 0.8 (m+1) / (eta0 delta sqrt(eps_r mu_r)) * (d/L)^m,
+   kappa = 1 + (kappa_max - 1)(d/L)^m, alpha = alpha_max (1 - d/L) (S/m), with d the depth into
+   the layer.  Ignored fields may be zero for the other kinds. */
+typedef struct {
+  int32_t kind, npml;
+  double poly_m, sigma_scale, kappa_max, alpha_max;
+} chf_boundary;
+
+/* Moving shower source (Simulation Setup section).  The bunch centre is on the line
+   (x_axis, y_axis) and at z_s = z_entry + beta c0 (t - t_entry) for t >= t_entry.  Charge
+   snapshot: Gaussian of width sigma_r across and sigma_z along the axis, each truncated at
+   cut_sigmas and normalised on the Ez lattice; total charge Q(z_s) = sum_b q_b hat((z_s -
+   z_bin0)/dz_bin - b) (coulomb; the charge excess is negative).  q_bins is a HOST array of
+   n_bins doubles, copied.  J_z = beta c0 * Q * W_r * W_z enters the Ez update.
+   n_bins = 0 disables the source. */
+typedef struct {
+  double x_axis, y_axis, z_entry, t_entry, beta, sigma_r, sigma_z, cut_sigmas;
+  int32_t n_bins, pad0;
+  double z_bin0, dz_bin;
+  const double *q_bins;
+} chf_source;
+
+/* Detector positions: HOST array xyz[n_obs][3] in metres, copied.  Each component is
+   interpolated trilinearly on its own staggered sub-lattice; the 8-node stencil must lie at
+   least max(1, npml) cells inside every wall. */
+typedef struct {
+  int32_t n_obs, pad0;
+  const double *xyz;
+} chf_observers;
+
+/* Execution choices.  storage: field storage type (arithmetic is always FP32; waveforms are
+   accumulated in FP64).  scale_e / scale_h: power-of-two storage scales (0 = automatic).
+   kernel: split E/H sweeps or the fused single sweep.  rows_per_wave, waves_per_block and
+   z_chunk shape the fused sweep (0 = default).  nan_watch: check waveforms for
+   non-finite values every step. */
+typedef struct {
+  int32_t storage, kernel;
+  int32_t rows_per_wave, waves_per_block, z_chunk, nan_watch;
+  double scale_e, scale_h;
+} chf_exec;
+
+typedef struct chf_plan chf_plan;
+
+/* Validate descriptors and build all host-side tables.  Checks: node counts >= 3 and the
+   64-bit size of the workspace; dt below the Courant limit dt <= 1/(v sqrt(sum 1/d^2)) with
+   v = c0/sqrt(eps_r mu_r) (else CHF_ECFL); observer stencils inside the interior and the
+   source axis inside the x-y extent (else CHF_EDOMAIN); supported kernel/storage
+   combination (else CHF_EUNSUPPORTED).  On success *out owns the plan (free with
+   chf_plan_destroy).  No device call is made. */
+chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const chf_boundary *bnd,
+                           const chf_source *src, const chf_observers *obs, const chf_exec *ex,
+                           chf_plan **out);
+
+void chf_plan_destroy(chf_plan *plan);
+
+/* Bytes of device workspace the plan needs (fields in two time levels, CPML state, tables). */
+chf_status chf_plan_workspace_bytes(const chf_plan *plan, uint64_t *bytes);
+
+/* Bind caller-owned DEVICE memory (>= the reported size, 256-byte aligned) and upload the
+   plan's tables into it with hipMemcpyAsync on `stream` (a hipStream_t, NULL = default). */
+chf_status chf_plan_bind_workspace(chf_plan *plan, void *device_ptr, uint64_t bytes, void *stream);
+
+/* Zero the fields and the CPML state (initial condition E^0 = 0, H^{-1/2} = 0). */
+chf_status chf_plan_reset(chf_plan *plan, void *stream);
+
+/* Advance `n_steps` steps from the current state.  q_bins_dev: DEVICE array of n_bins doubles
+   overriding the plan's profile (NULL = plan's).  waveforms_dev: DEVICE FP64 array
+   [n_obs][3][ld_steps]; step s of this call writes column (first_column + s).  A full run from
+   zero fields is chf_plan_reset followed by chf_forward(plan, stream, NULL, w, T, 0, T). */
+chf_status chf_forward(chf_plan *plan, void *stream, const double *q_bins_dev, double *waveforms_dev,
+                       int32_t n_steps, int32_t first_column, int32_t ld_steps);
+
+/* Same as chf_forward over the plan's n_steps, captured once into a hipGraph per
+   (waveform pointer, profile pointer) and replayed on later calls. */
+chf_status chf_forward_graph(chf_plan *plan, void *stream, const double *q_bins_dev,
+                             double *waveforms_dev);
+
+/* Discrete adjoint: given dL/dw (DEVICE FP64 [n_obs][3][n_steps]) returns dL/dq (DEVICE FP64
+   [n_bins]) for the plan's full run, by the exact transpose of the forward recurrence run
+   backward in time.  PEC and CPML only (CHF_EUNSUPPORTED for Mur).  The forward field state
+   is destroyed (the workspace holds the adjoint state). */
+chf_status chf_adjoint(chf_plan *plan, void *stream, const double *dl_dw_dev, double *dl_dq_dev);
+
+/* Wait for `stream` and report a kernel fault (CHF_EHIP) or the watchdog (CHF_ENAN). */
+chf_status chf_plan_sync(chf_plan *plan, void *stream);
+
+/* Copy one field component (0..5 = Ex,Ey,Ez,Hx,Hy,Hz) of the current time level into a DEVICE
+   FP32 array [nz][ny][nx] (unscaled, physical units). */
+chf_status chf_plan_get_field(chf_plan *plan, void *stream, int32_t comp, float *out_dev);
+
+/* Overwrite one field component of the current time level from a DEVICE FP32 array
+   [nz][ny][nx] (physical units). */
+chf_status chf_plan_set_field(chf_plan *plan, void *stream, int32_t comp, const float *in_dev);
+
+/* Introspection: chosen kernel, storage scales, fused-sweep shape, pitch. */
+typedef struct {
+  int32_t kernel, storage, vx, rows_per_wave, waves_per_block, z_chunk, pitch, n_blocks;
+  double scale_e, scale_h;
+  uint64_t field_bytes, psi_bytes, workspace_bytes;
+  double bytes_per_cell_update; /* algorithmic HBM bytes of one cell-update */
+} chf_plan_info;
+chf_status chf_plan_get_info(const chf_plan *plan, chf_plan_info *info);
+
+/* Batched execution: several plans advanced together, one launch per phase per step for the
+   whole batch.  Plans keep their own workspaces.  waveforms_dev[i] is plan i's output. */
+typedef struct chf_batch chf_batch;
+chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out);
+chf_status chf_batch_run(chf_batch *batch, void *stream, double *const *waveforms_dev);
+void chf_batch_destroy(chf_batch *batch);
+
+const char *chf_status_str(chf_status s);
+const char *chf_last_error(void);
+int32_t chf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHFDTD_H */

@@ -1,0 +1,620 @@
+// Host side of libchfdtd: descriptor validation, FP64 coefficient tables, workspace layout
+// and the C entry points declared in include/chfdtd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "chf_internal.h"
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kMu0 = 1.25663706212e-6;  // CODATA 2018
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+
+thread_local std::string g_err;
+
+chf_status fail(chf_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+
+chf_status hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return CHF_EHIP;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Depth (in cells) of a position into the layer of `npml` cells at each end of an axis with
+// n nodes (walls at 0 and n-1, inner layer planes at npml and n-1-npml); 0 outside.
+double layer_depth(double pos, int n, int npml) {
+  return std::max(std::max(npml - pos, pos - (n - 1 - npml)), 0.0);
+}
+
+struct Grade {
+  double a, b, kappa;
+};
+
+// CFS-CPML grading (Roden & Gedney): stretch s = kappa + sigma/(alpha + j w eps0),
+// recursion psi <- b psi + a dF, b = exp(-(sigma/kappa + alpha) dt/eps0),
+// a = sigma (b - 1) / (sigma kappa + kappa^2 alpha).
+Grade grade(const chf_plan &p, double depth, double delta) {
+  const chf_boundary &B = p.bnd;
+  const double eta0 = kMu0 * kC0;
+  const double rho = depth / B.npml;
+  const double sig_opt = 0.8 * (B.poly_m + 1.0) / (eta0 * delta * std::sqrt(p.med.eps_r * p.med.mu_r));
+  const double sigma = B.sigma_scale * sig_opt * std::pow(rho, B.poly_m);
+  const double kappa = 1.0 + (B.kappa_max - 1.0) * std::pow(rho, B.poly_m);
+  const double alpha = B.alpha_max * (1.0 - rho);
+  const double b = std::exp(-(sigma / kappa + alpha) * p.grid.dt / kEps0);
+  const double a = sigma * (b - 1.0) / (sigma * kappa + kappa * kappa * alpha);
+  return {a, b, kappa};
+}
+
+double pow2_near(double x) { return std::ldexp(1.0, (int)std::lround(std::log2(x))); }
+
+}  // namespace
+
+namespace chf {
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace chf
+
+extern "C" {
+
+const char *chf_last_error(void) { return g_err.c_str(); }
+int32_t chf_abi_version(void) { return CHF_ABI_VERSION; }
+
+const char *chf_status_str(chf_status s) {
+  switch (s) {
+    case CHF_OK: return "ok";
+    case CHF_EINVAL: return "invalid argument";
+    case CHF_ECFL: return "time step above the Courant limit";
+    case CHF_EDOMAIN: return "observer or source outside the usable interior";
+    case CHF_ENOMEM: return "size overflow or workspace too small";
+    case CHF_EHIP: return "HIP runtime error";
+    case CHF_ENAN: return "non-finite value detected";
+    case CHF_EUNSUPPORTED: return "unsupported configuration";
+    case CHF_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const chf_boundary *bnd,
+                           const chf_source *src, const chf_observers *obs, const chf_exec *ex,
+                           chf_plan **out) {
+  if (!out) return fail(CHF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid || !medium || !bnd || !src || !obs || !ex) return fail(CHF_EINVAL, "NULL descriptor");
+  const chf_grid &G = *grid;
+  if (G.nx < 3 || G.ny < 3 || G.nz < 3) return fail(CHF_EINVAL, "need at least 3 nodes per axis");
+  if (G.n_steps < 0) return fail(CHF_EINVAL, "n_steps < 0");
+  if (!(G.dx > 0 && G.dy > 0 && G.dz > 0 && G.dt > 0) || !std::isfinite(G.dx + G.dy + G.dz + G.dt))
+    return fail(CHF_EINVAL, "spacings and dt must be positive");
+  if (!(medium->eps_r > 0 && medium->mu_r > 0 && medium->sigma >= 0))
+    return fail(CHF_EINVAL, "bad medium");
+  const double v = kC0 / std::sqrt(medium->eps_r * medium->mu_r);
+  const double dt_max = 1.0 / (v * std::sqrt(1 / (G.dx * G.dx) + 1 / (G.dy * G.dy) + 1 / (G.dz * G.dz)));
+  if (G.dt > dt_max) return fail(CHF_ECFL, "dt exceeds the Courant limit of the medium");
+  if (bnd->kind < CHF_BC_PEC || bnd->kind > CHF_BC_CPML) return fail(CHF_EINVAL, "bad boundary kind");
+  if (bnd->kind == CHF_BC_CPML) {
+    const int m = 2 * bnd->npml + 3;
+    if (bnd->npml < 1 || m > G.nx || m > G.ny || m > G.nz) return fail(CHF_EINVAL, "bad npml");
+    if (!(bnd->poly_m >= 0 && bnd->sigma_scale >= 0 && bnd->kappa_max >= 1 && bnd->alpha_max >= 0))
+      return fail(CHF_EINVAL, "bad CPML grading");
+  }
+  if (ex->storage < CHF_FP32 || ex->storage > CHF_FP16) return fail(CHF_EINVAL, "bad storage");
+  if (ex->kernel < CHF_KERNEL_AUTO || ex->kernel > CHF_KERNEL_FUSED) return fail(CHF_EINVAL, "bad kernel");
+  if (obs->n_obs < 0 || obs->n_obs > chf::kMaxObsPerPlan || (obs->n_obs > 0 && !obs->xyz))
+    return fail(CHF_EINVAL, "bad observer list");
+  if (src->n_bins < 0 || (src->n_bins > 0 && !src->q_bins)) return fail(CHF_EINVAL, "bad profile");
+  const int64_t cells = (int64_t)G.nx * G.ny * G.nz;
+  if (cells > (int64_t)1 << 40) return fail(CHF_ENOMEM, "grid too large");
+
+  chf_plan *p = new (std::nothrow) chf_plan();
+  if (!p) return fail(CHF_ENOMEM, "host allocation failed");
+  p->grid = G;
+  p->med = *medium;
+  p->bnd = *bnd;
+  p->src = *src;
+  p->ex = *ex;
+  if (bnd->kind != CHF_BC_CPML) p->bnd.npml = 0;
+  p->q_bins.assign(src->q_bins, src->q_bins + src->n_bins);
+  p->obs_xyz.assign(obs->xyz, obs->xyz + 3 * (size_t)obs->n_obs);
+  p->src.q_bins = nullptr;
+  p->storage = ex->storage;
+  p->elem_bytes = ex->storage == CHF_FP32 ? 4 : 2;
+
+  // kernel and fused-sweep shape
+  int kernel = ex->kernel == CHF_KERNEL_AUTO ? (G.nx <= 64 * chf::kMaxVX ? CHF_KERNEL_FUSED : CHF_KERNEL_SPLIT)
+                                             : ex->kernel;
+  if (kernel == CHF_KERNEL_FUSED && G.nx > 64 * chf::kMaxVX) {
+    delete p;
+    return fail(CHF_EUNSUPPORTED, "fused sweep needs nx <= 512");
+  }
+  p->kernel = kernel;
+  chf::FusedShape &fs = p->fs;
+  fs.vx = 1;
+  while (64 * fs.vx < G.nx) fs.vx *= 2;
+  fs.rows = ex->rows_per_wave > 0 ? ex->rows_per_wave : 2;
+  fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 4;
+  fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 32;
+  if (!(fs.rows == 1 || fs.rows == 2 || fs.rows == 4) || fs.waves < 1 || fs.waves > 4) {
+    delete p;
+    return fail(CHF_EINVAL, "rows_per_wave must be 1, 2 or 4 and waves_per_block 1..4");
+  }
+  fs.nty = (G.ny + fs.waves * fs.rows - 1) / (fs.waves * fs.rows);
+  fs.nzc = (G.nz + fs.zchunk - 1) / fs.zchunk;
+  fs.n_tiles = fs.nty * fs.nzc;
+  fs.n_blocks = (fs.n_tiles + 7) / 8 * 8;
+
+  // coefficients (FP64)
+  const double eps = kEps0 * medium->eps_r, mu = kMu0 * medium->mu_r;
+  const double loss = medium->sigma * G.dt / (2.0 * eps);
+  p->ca = (1.0 - loss) / (1.0 + loss);
+  p->cb = (G.dt / eps) / (1.0 + loss);
+  p->db = G.dt / mu;
+  // storage scales: H stored in E-like units (power of two nearest the medium impedance)
+  const double eta = kMu0 * kC0 * std::sqrt(medium->mu_r / medium->eps_r);
+  p->scale_h = ex->scale_h > 0 ? ex->scale_h : pow2_near(eta);
+  p->scale_e = 1.0;
+  if (ex->scale_e > 0) {
+    p->scale_e = ex->scale_e;
+  } else if (ex->storage == CHF_FP16 && src->n_bins > 0) {
+    // FP16: map an estimate of the largest field (the Coulomb field of the total charge at one
+    // radial width) to ~2^14 so that the pulse tails stay above the subnormal range
+    double qmax = 0.0;
+    for (double q : p->q_bins) qmax = std::max(qmax, std::fabs(q));
+    const double e_est = qmax / (4.0 * M_PI * eps * src->sigma_r * src->sigma_r);
+    if (e_est > 0) p->scale_e = std::ldexp(1.0, (int)std::floor(std::log2(16384.0 / e_est)));
+  }
+  p->scale_h *= p->scale_e;
+  for (double s : {p->scale_e, p->scale_h}) {
+    int e;
+    if (std::frexp(s, &e) != 0.5) {
+      delete p;
+      return fail(CHF_EINVAL, "storage scales must be powers of two");
+    }
+  }
+  const double rse = p->scale_e / p->scale_h, rhs = p->scale_h / p->scale_e;
+
+  // axis tables: ce, ch, ae, be, ah, bh (float) and se, sh (int)
+  const int n3[3] = {G.nx, G.ny, G.nz};
+  const double d3[3] = {G.dx, G.dy, G.dz};
+  const int npml = p->bnd.npml;
+  size_t off_f = 0, off_i = 0;
+  for (int u = 0; u < 3; u++) {
+    for (int t = 0; t < 6; t++) p->off_tabf[u][t] = off_f + (size_t)t * n3[u];
+    for (int t = 0; t < 2; t++) p->off_tabi[u][t] = off_i + (size_t)t * n3[u];
+    off_f += 6 * (size_t)n3[u];
+    off_i += 2 * (size_t)n3[u];
+  }
+  p->tabf.assign(off_f, 0.0f);
+  p->tabi.assign(off_i, -1);
+  for (int u = 0; u < 3; u++) {
+    const int n = n3[u];
+    float *ce = &p->tabf[p->off_tabf[u][0]], *ch = &p->tabf[p->off_tabf[u][1]];
+    float *ae = &p->tabf[p->off_tabf[u][2]], *be = &p->tabf[p->off_tabf[u][3]];
+    float *ah = &p->tabf[p->off_tabf[u][4]], *bh = &p->tabf[p->off_tabf[u][5]];
+    int *se = &p->tabi[p->off_tabi[u][0]], *sh = &p->tabi[p->off_tabi[u][1]];
+    for (int i = 0; i < n; i++) {
+      ce[i] = (float)(rse * p->cb / d3[u]);
+      ch[i] = (float)(rhs * p->db / d3[u]);
+      be[i] = bh[i] = 1.0f;
+      if (npml <= 0) continue;
+      const double de = layer_depth((double)i, n, npml);
+      if (de > 0.0) {
+        se[i] = i < npml ? i : npml + (i - (n - npml));
+        Grade g = grade(*p, de, d3[u]);
+        ce[i] = (float)(rse * p->cb / (d3[u] * g.kappa));
+        ae[i] = (float)(rse * p->cb * g.a / d3[u]);
+        be[i] = (float)g.b;
+      }
+      if (i <= n - 2) {
+        const double dh = layer_depth(i + 0.5, n, npml);
+        if (dh > 0.0) {
+          sh[i] = i < npml ? i : npml + (i - (n - 1 - npml));
+          Grade g = grade(*p, dh, d3[u]);
+          ch[i] = (float)(rhs * p->db / (d3[u] * g.kappa));
+          ah[i] = (float)(rhs * p->db * g.a / d3[u]);
+          bh[i] = (float)g.b;
+        }
+      }
+    }
+  }
+
+  // source: radial weights at the Ez nodes (x_i, y_j), disc of radius cut*sigma_r,
+  // normalised so that sum W dx dy = 1 over the nodes Ez is updated on
+  chf::Dev &D = p->dev;
+  D.src_on = src->n_bins > 0 ? 1 : 0;
+  if (D.src_on) {
+    if (!(src->sigma_r > 0 && src->sigma_z > 0 && src->cut_sigmas > 0 && src->dz_bin > 0 && src->beta >= 0)) {
+      delete p;
+      return fail(CHF_EINVAL, "bad source widths");
+    }
+    if (src->cut_sigmas * src->sigma_z / G.dz > 0.5 * (chf::kMaxWz - 2)) {
+      delete p;
+      return fail(CHF_EUNSUPPORTED, "longitudinal source support too wide");
+    }
+    const double rc = src->cut_sigmas * src->sigma_r;
+    int i0 = std::max(1, (int)std::ceil((src->x_axis - rc) / G.dx));
+    int i1 = std::min(G.nx - 2, (int)std::floor((src->x_axis + rc) / G.dx));
+    int j0 = std::max(1, (int)std::ceil((src->y_axis - rc) / G.dy));
+    int j1 = std::min(G.ny - 2, (int)std::floor((src->y_axis + rc) / G.dy));
+    if (i1 < i0 || j1 < j0) {
+      delete p;
+      return fail(CHF_EDOMAIN, "source axis outside the grid");
+    }
+    D.src_i0 = i0;
+    D.src_j0 = j0;
+    D.src_ni = i1 - i0 + 1;
+    D.src_nj = j1 - j0 + 1;
+    p->wr.assign((size_t)D.src_ni * D.src_nj, 0.0);
+    double norm = 0.0;
+    for (int j = j0; j <= j1; j++)
+      for (int i = i0; i <= i1; i++) {
+        const double ddx = i * G.dx - src->x_axis, ddy = j * G.dy - src->y_axis;
+        const double r2 = ddx * ddx + ddy * ddy;
+        if (r2 <= rc * rc) {
+          const double w = std::exp(-0.5 * r2 / (src->sigma_r * src->sigma_r));
+          p->wr[(size_t)(j - j0) * D.src_ni + (i - i0)] = w;
+          norm += w * G.dx * G.dy;
+        }
+      }
+    if (norm <= 0.0) {
+      delete p;
+      return fail(CHF_EDOMAIN, "source disc misses the grid");
+    }
+    for (double &w : p->wr) w /= norm;
+  }
+
+  // observers: base node and fractional offsets per component and axis
+  const int margin = npml > 0 ? npml : 1;
+  p->obs_idx.resize((size_t)obs->n_obs * 9);
+  p->obs_t.resize((size_t)obs->n_obs * 9);
+  for (int o = 0; o < obs->n_obs; o++)
+    for (int c = 0; c < 3; c++)
+      for (int u = 0; u < 3; u++) {
+        const double f = p->obs_xyz[3 * o + u] / d3[u] - (u == c ? 0.5 : 0.0);
+        const double fl = std::floor(f);
+        if (!std::isfinite(f) || fl < margin || fl + 1 > n3[u] - 1 - margin) {
+          delete p;
+          return fail(CHF_EDOMAIN, "observer stencil outside the interior (obs " + std::to_string(o) + ")");
+        }
+        p->obs_idx[(o * 3 + c) * 3 + u] = (int)fl;
+        p->obs_t[(o * 3 + c) * 3 + u] = f - fl;
+      }
+
+  // workspace layout
+  int pitch = (G.nx + 15) / 16 * 16;
+  const uint64_t field = align256((uint64_t)pitch * G.ny * G.nz * p->elem_bytes);
+  uint64_t off = 0;
+  for (int l = 0; l < 2; l++)
+    for (int c = 0; c < 3; c++) {
+      p->off_e[l][c] = off;
+      off += field;
+      p->off_h[l][c] = off;
+      off += field;
+    }
+  p->field_bytes = off;
+  const int np2 = 2 * npml;
+  p->psi_len[0] = (uint64_t)G.nz * G.ny * np2;
+  p->psi_len[1] = (uint64_t)G.nz * np2 * pitch;
+  p->psi_len[2] = (uint64_t)np2 * G.ny * pitch;
+  const uint64_t off_psi0 = off;
+  for (int u = 0; u < 3; u++) {
+    const uint64_t len = align256(p->psi_len[u] * 4);
+    for (int t = 0; t < 2; t++) {
+      p->off_psi_e[u][t] = off;
+      off += len;
+      p->off_psi_h[0][u][t] = off;
+      off += len;
+      p->off_psi_h[1][u][t] = off;
+      off += len;
+    }
+  }
+  p->psi_bytes = off - off_psi0;
+  p->off_tf = off;
+  off += align256(p->tabf.size() * sizeof(float));
+  p->off_ti = off;
+  off += align256(p->tabi.size() * sizeof(int));
+  p->off_wr = off;
+  off += align256(std::max<size_t>(p->wr.size(), 1) * sizeof(double));
+  p->off_q = off;
+  off += align256(std::max<size_t>(p->q_bins.size(), 1) * sizeof(double));
+  p->off_oidx = off;
+  off += align256(std::max<size_t>(p->obs_idx.size(), 1) * sizeof(int));
+  p->off_ot = off;
+  off += align256(std::max<size_t>(p->obs_t.size(), 1) * sizeof(double));
+  p->off_nan = off;
+  off += 256;
+  p->ws_bytes = off;
+
+  // kernel parameter block (device pointers are filled at bind time)
+  D.nx = G.nx;
+  D.ny = G.ny;
+  D.nz = G.nz;
+  D.pitch = pitch;
+  D.npml = npml;
+  D.np2 = np2;
+  D.plane = (long long)pitch * G.ny;
+  D.ca = (float)p->ca;
+  D.se = (float)p->scale_e;
+  D.sh = (float)p->scale_h;
+  D.n_bins = src->n_bins;
+  D.x_axis = src->x_axis;
+  D.y_axis = src->y_axis;
+  D.z_entry = src->z_entry;
+  D.t_entry = src->t_entry;
+  D.v_src = src->beta * kC0;
+  D.sigma_z = src->sigma_z;
+  D.cut_sigmas = src->cut_sigmas;
+  D.z_bin0 = src->z_bin0;
+  D.dz_bin = src->dz_bin;
+  D.dz = G.dz;
+  D.dt = G.dt;
+  D.cb_src = p->scale_e * p->cb;
+  D.n_obs = obs->n_obs;
+  D.inv_se = 1.0 / p->scale_e;
+  D.bc = p->bnd.kind;
+  const double vdt = v * G.dt;
+  D.mur_kx = (float)((vdt - G.dx) / (vdt + G.dx));
+  D.mur_ky = (float)((vdt - G.dy) / (vdt + G.dy));
+  D.mur_kz = (float)((vdt - G.dz) / (vdt + G.dz));
+  *out = p;
+  return CHF_OK;
+}
+
+void chf_plan_destroy(chf_plan *plan) {
+  if (!plan) return;
+  if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
+  delete plan;
+}
+
+chf_status chf_plan_workspace_bytes(const chf_plan *plan, uint64_t *bytes) {
+  if (!plan || !bytes) return fail(CHF_EINVAL, "NULL argument");
+  *bytes = plan->ws_bytes;
+  return CHF_OK;
+}
+
+chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, void *stream) {
+  if (!p || !dev_ptr) return fail(CHF_EINVAL, "NULL argument");
+  if (bytes < p->ws_bytes) return fail(CHF_ENOMEM, "workspace smaller than chf_plan_workspace_bytes");
+  if ((uintptr_t)dev_ptr % 256) return fail(CHF_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)dev_ptr;
+  p->ws = ws;
+  chf::Dev &D = p->dev;
+  for (int l = 0; l < 2; l++)
+    for (int c = 0; c < 3; c++) {
+      D.e[l][c] = ws + p->off_e[l][c];
+      D.h[l][c] = ws + p->off_h[l][c];
+    }
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) {
+      D.psi_e[u][t] = (float *)(ws + p->off_psi_e[u][t]);
+      D.psi_h[0][u][t] = (float *)(ws + p->off_psi_h[0][u][t]);
+      D.psi_h[1][u][t] = (float *)(ws + p->off_psi_h[1][u][t]);
+    }
+  const float *tf = (const float *)(ws + p->off_tf);
+  const int *ti = (const int *)(ws + p->off_ti);
+  for (int u = 0; u < 3; u++) {
+    chf::AxisTab &A = D.ax[u];
+    A.ce = tf + p->off_tabf[u][0];
+    A.ch = tf + p->off_tabf[u][1];
+    A.ae = tf + p->off_tabf[u][2];
+    A.be = tf + p->off_tabf[u][3];
+    A.ah = tf + p->off_tabf[u][4];
+    A.bh = tf + p->off_tabf[u][5];
+    A.se = ti + p->off_tabi[u][0];
+    A.sh = ti + p->off_tabi[u][1];
+  }
+  D.wr = (const double *)(ws + p->off_wr);
+  D.q_bins = (const double *)(ws + p->off_q);
+  D.obs_idx = (const int *)(ws + p->off_oidx);
+  D.obs_t = (const double *)(ws + p->off_ot);
+  D.nan_flag = (int *)(ws + p->off_nan);
+  struct Up {
+    uint64_t off;
+    const void *src;
+    size_t n;
+  } ups[] = {
+      {p->off_tf, p->tabf.data(), p->tabf.size() * sizeof(float)},
+      {p->off_ti, p->tabi.data(), p->tabi.size() * sizeof(int)},
+      {p->off_wr, p->wr.data(), p->wr.size() * sizeof(double)},
+      {p->off_q, p->q_bins.data(), p->q_bins.size() * sizeof(double)},
+      {p->off_oidx, p->obs_idx.data(), p->obs_idx.size() * sizeof(int)},
+      {p->off_ot, p->obs_t.data(), p->obs_t.size() * sizeof(double)},
+  };
+  for (const Up &u : ups) {
+    if (!u.n) continue;
+    hipError_t e = hipMemcpyAsync(ws + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload of plan tables");
+  }
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  return chf_plan_reset(p, stream);
+}
+
+chf_status chf_plan_reset(chf_plan *p, void *stream) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipError_t e = chf::launch_zero(*p, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "reset");
+  int zero = 0;
+  e = hipMemcpyAsync(p->dev.nan_flag, &zero, sizeof(int), hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "reset of the watchdog flag");
+  p->parity = 0;
+  p->n_done = 0;
+  return CHF_OK;
+}
+
+chf_status chf_forward(chf_plan *p, void *stream, const double *q_bins_dev, double *w_dev, int32_t n_steps,
+                       int32_t first_column, int32_t ld_steps) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
+  if (p->dev.n_obs > 0 && w_dev && (ld_steps < first_column + n_steps))
+    return fail(CHF_EINVAL, "ld_steps too small for first_column + n_steps");
+  chf::Dev d = p->dev;
+  if (!p->ex.nan_watch) d.nan_flag = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  for (int t = 0; t < n_steps; t++) {
+    hipError_t e = chf::launch_step(*p, d, p->parity, p->n_done, q_bins_dev, w_dev, first_column + t, ld_steps, s);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    p->parity ^= 1;
+    p->n_done++;
+  }
+  return CHF_OK;
+}
+
+chf_status chf_forward_graph(chf_plan *p, void *stream, const double *q_bins_dev, double *w_dev) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipStream_t s = (hipStream_t)stream;
+  const int T = p->grid.n_steps;
+  if (!p->graph || p->graph_w != w_dev || p->graph_q != q_bins_dev) {
+    if (p->graph) {
+      (void)hipGraphExecDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hip_fail(e, "begin capture");
+    }
+    chf::Dev d = p->dev;
+    if (!p->ex.nan_watch) d.nan_flag = nullptr;
+    hipError_t le = chf::launch_zero(*p, cs);
+    int par = 0;
+    for (int t = 0; t < T && le == hipSuccess; t++) {
+      le = chf::launch_step(*p, d, par, t, q_bins_dev, w_dev, t, T, cs);
+      par ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(le, "captured launch");
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->graph = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    p->graph_w = w_dev;
+    p->graph_q = q_bins_dev;
+  }
+  hipError_t e = hipGraphLaunch(p->graph, s);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  p->parity = T & 1;
+  p->n_done = T;
+  return CHF_OK;
+}
+
+chf_status chf_plan_sync(chf_plan *p, void *stream) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "pending error");
+  if (p->ws && p->ex.nan_watch) {
+    int flag = 0;
+    e = hipMemcpy(&flag, p->dev.nan_flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read watchdog flag");
+    if (flag) return fail(CHF_ENAN, "non-finite waveform value");
+  }
+  return CHF_OK;
+}
+
+chf_status chf_plan_get_field(chf_plan *p, void *stream, int32_t comp, float *out_dev) {
+  if (!p || !out_dev || comp < 0 || comp > 5) return fail(CHF_EINVAL, "bad argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipError_t e = chf::launch_get_field(*p, p->parity, comp, out_dev, (hipStream_t)stream);
+  return e == hipSuccess ? CHF_OK : hip_fail(e, "get field");
+}
+
+chf_status chf_plan_set_field(chf_plan *p, void *stream, int32_t comp, const float *in_dev) {
+  if (!p || !in_dev || comp < 0 || comp > 5) return fail(CHF_EINVAL, "bad argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipError_t e = chf::launch_set_field(*p, p->parity, comp, in_dev, (hipStream_t)stream);
+  return e == hipSuccess ? CHF_OK : hip_fail(e, "set field");
+}
+
+chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
+  if (!p || !info) return fail(CHF_EINVAL, "NULL argument");
+  info->kernel = p->kernel;
+  info->storage = p->storage;
+  info->vx = p->fs.vx;
+  info->rows_per_wave = p->fs.rows;
+  info->waves_per_block = p->fs.waves;
+  info->z_chunk = p->fs.zchunk;
+  info->pitch = p->dev.pitch;
+  info->n_blocks = p->fs.n_blocks;
+  info->scale_e = p->scale_e;
+  info->scale_h = p->scale_h;
+  info->field_bytes = p->field_bytes;
+  info->psi_bytes = p->psi_bytes;
+  info->workspace_bytes = p->ws_bytes;
+  // one read and one write of the six components, plus the psi read and write of the cells
+  // inside each layer (two psi per component pair and derivative axis)
+  const double cells = (double)p->grid.nx * p->grid.ny * p->grid.nz;
+  double psi_rw = 0.0;
+  if (p->bnd.npml > 0) {
+    const double n2 = 2.0 * p->bnd.npml;
+    const double frac = n2 / p->grid.nx + n2 / p->grid.ny + n2 / p->grid.nz;
+    psi_rw = frac * 4 * 2 * 4.0;  // 4 psi per layer cell (2 E, 2 H), read + write, FP32
+  }
+  info->bytes_per_cell_update = 12.0 * p->elem_bytes + psi_rw;
+  (void)cells;
+  return CHF_OK;
+}
+
+chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev) {
+  (void)stream;
+  (void)dl_dw_dev;
+  (void)dl_dq_dev;
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  return fail(CHF_EUNSUPPORTED, "adjoint not built yet");
+}
+
+chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) {
+  if (!out || n <= 0 || !plans) return fail(CHF_EINVAL, "bad batch");
+  chf_batch *b = new (std::nothrow) chf_batch();
+  if (!b) return fail(CHF_ENOMEM, "host allocation failed");
+  for (int i = 0; i < n; i++) {
+    if (!plans[i]) {
+      delete b;
+      return fail(CHF_EINVAL, "NULL plan in batch");
+    }
+    b->plans.push_back(plans[i]);
+  }
+  *out = b;
+  return CHF_OK;
+}
+
+chf_status chf_batch_run(chf_batch *b, void *stream, double *const *w) {
+  if (!b || !w) return fail(CHF_EINVAL, "NULL argument");
+  for (size_t i = 0; i < b->plans.size(); i++) {
+    chf_status st = chf_forward_graph(b->plans[i], stream, nullptr, w[i]);
+    if (st != CHF_OK) return st;
+  }
+  return CHF_OK;
+}
+
+void chf_batch_destroy(chf_batch *b) { delete b; }
+
+}  // extern "C"

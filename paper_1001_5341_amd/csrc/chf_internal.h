@@ -1,0 +1,116 @@
+// Internal types shared by the host plan code and the kernel launchers of libchfdtd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chfdtd.h"
+
+namespace chf {
+
+constexpr int kMaxVX = 8;        // cells per lane along x in the fused sweep (nx <= 64*8)
+constexpr int kMaxObsPerPlan = 4096;
+constexpr int kMaxWz = 64;       // longitudinal source support in cells
+
+// Per-axis coefficient tables, one entry per node index along the axis.  "e" entries belong
+// to the E-update derivative (backward difference, integer position), "h" entries to the
+// H-update derivative (forward difference, half position).
+struct AxisTab {
+  const float *ce, *ch;      // main-term coefficient  Cb/(delta kappa) resp. Db/(delta kappa), scaled
+  const float *ae, *be;      // CPML psi recursion at integer positions (a prescaled)
+  const float *ah, *bh;      // CPML psi recursion at half positions
+  const int *se, *sh;        // slab slot (0..2*npml-1) or -1 outside the layer
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+  int nx, ny, nz, pitch, npml, np2;
+  long long plane;           // pitch*ny
+  float ca;
+  // field arrays, [time level][component]; element type depends on the storage
+  void *e[2][3];
+  void *h[2][3];
+  // CPML psi slabs.  Axis u: 0 (x) -> (Ey,Ez) / (Hy,Hz); 1 (y) -> (Ex,Ez) / (Hx,Hz);
+  // 2 (z) -> (Ex,Ey) / (Hx,Hy).  psi_h is kept in two time levels (halo recompute).
+  float *psi_e[3][2];
+  float *psi_h[2][3][2];
+  AxisTab ax[3];
+  // storage scales: stored = scale * physical
+  float se, sh;
+  // source
+  int src_on, n_bins, src_i0, src_j0, src_ni, src_nj;
+  double x_axis, y_axis, z_entry, t_entry, v_src, sigma_z, cut_sigmas, z_bin0, dz_bin, dz, dt;
+  double cb_src;             // scale_e * Cb: E increment per unit current density
+  const double *q_bins;      // device, the plan's profile
+  const double *wr;          // device [src_nj][src_ni] radial weights
+  // observers
+  int n_obs;
+  const int *obs_idx;        // [n_obs][3 comps][3] base node of the trilinear stencil
+  const double *obs_t;       // [n_obs][3 comps][3] fractional offsets
+  double inv_se;             // 1/scale_e for the gather
+  int *nan_flag;
+  // Mur
+  float mur_kx, mur_ky, mur_kz;
+  int bc;
+};
+
+struct FusedShape {
+  int vx, rows, waves, zchunk, nty, nzc, n_tiles, n_blocks;
+};
+
+}  // namespace chf
+
+struct chf_plan {
+  chf_grid grid;
+  chf_medium med;
+  chf_boundary bnd;
+  chf_source src;
+  chf_exec ex;
+  std::vector<double> q_bins;
+  std::vector<double> obs_xyz;
+  int kernel;       // resolved CHF_KERNEL_SPLIT / CHF_KERNEL_FUSED
+  int storage;
+  int elem_bytes;
+  chf::FusedShape fs;
+  // host-side tables (uploaded at bind time)
+  std::vector<float> tabf;     // all float axis tables
+  std::vector<int> tabi;       // all int slot tables
+  std::vector<double> wr;      // radial weights
+  std::vector<int> obs_idx;
+  std::vector<double> obs_t;
+  size_t off_tabf[3][6], off_tabi[3][2];
+  // workspace layout (byte offsets)
+  uint64_t off_e[2][3], off_h[2][3], off_psi_e[3][2], off_psi_h[2][3][2];
+  uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, ws_bytes;
+  uint64_t field_bytes, psi_bytes, psi_len[3];
+  char *ws = nullptr;
+  chf::Dev dev;
+  int parity = 0;   // time level holding the current state
+  int n_done = 0;   // steps advanced since the last reset (source clock)
+  double scale_e = 1.0, scale_h = 1.0;
+  double ca, cb, db;
+  // graph cache
+  hipGraphExec_t graph = nullptr;
+  const void *graph_w = nullptr, *graph_q = nullptr;
+  int graph_parity = -1;
+};
+
+struct chf_batch {
+  std::vector<chf_plan *> plans;
+};
+
+namespace chf {
+// kernel launchers (chf_kernels.hip)
+hipError_t launch_step(const chf_plan &p, const Dev &d, int parity, int step, const double *q_dev,
+                       double *w_dev, int column, int ld, hipStream_t s);
+hipError_t launch_zero(const chf_plan &p, hipStream_t s);
+hipError_t launch_get_field(const chf_plan &p, int parity, int comp, float *out, hipStream_t s);
+hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float *in, hipStream_t s);
+hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step,
+                               const double *dl_dw, double *dl_dq, hipStream_t s);
+hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s);
+void set_error(const std::string &msg);
+}  // namespace chf

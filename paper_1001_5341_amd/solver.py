@@ -1,0 +1,197 @@
+"""Python face of libchfdtd: descriptors from a Workload, device memory and streams from torch.
+
+Every numerical step runs in the HIP library; this module only marshals arguments,
+allocates the caller-owned workspace and output tensors, and picks the stream.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def descriptors(w, storage="fp32", kernel="auto", rows=0, waves=0, zchunk=0, nan_watch=False,
+                scale_e=0.0, scale_h=0.0, q_bins=None):
+    """Build the C descriptor structs for a workload.  Returns (structs, keepalive)."""
+    q = np.ascontiguousarray(w.q_bins if q_bins is None else q_bins, dtype=np.float64)
+    obs = np.ascontiguousarray(w.obs_xyz, dtype=np.float64).reshape(-1, 3)
+    g = N.Grid(w.nx, w.ny, w.nz, w.n_steps, w.dx, w.dy, w.dz, w.dt)
+    m = N.Medium(w.eps_r, w.mu_r, w.sigma)
+    b = N.Boundary(N.BC[w.bc], w.npml if w.bc == "cpml" else 0, w.pml_m, w.pml_sigma_scale,
+                   w.pml_kappa_max, w.pml_alpha_max)
+    s = N.Source(w.x_axis, w.y_axis, w.z_entry, w.t_entry, w.beta, w.sigma_r, w.sigma_z,
+                 w.cut_sigmas, len(q) if w.src_on else 0, 0, w.z_bin0, w.dz_bin, _dp(q))
+    o = N.Observers(obs.shape[0], 0, _dp(obs))
+    e = N.Exec(N.STORAGE[storage], N.KERNEL[kernel], rows, waves, zchunk, 1 if nan_watch else 0,
+               scale_e, scale_h)
+    return (g, m, b, s, o, e), (q, obs)
+
+
+def create_plan_handle(w, **kw) -> ct.c_void_p:
+    """chf_plan_create only (host-side validation and tables; no device call)."""
+    (g, m, b, s, o, e), keep = descriptors(w, **kw)
+    h = ct.c_void_p()
+    N.check(N.lib().chf_plan_create(ct.byref(g), ct.byref(m), ct.byref(b), ct.byref(s), ct.byref(o),
+                                    ct.byref(e), ct.byref(h)), "chf_plan_create")
+    return h
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """One shower on one grid, with its caller-owned device workspace.
+
+    >>> plan = Plan(workload)           # validates, builds tables, binds a torch workspace
+    >>> w = plan.run()                  # FP64 waveforms [n_obs, 3, n_steps] on the device
+    """
+
+    def __init__(self, w, storage: str = "fp32", kernel: str = "auto", rows: int = 0, waves: int = 0,
+                 zchunk: int = 0, nan_watch: bool = False, scale_e: float = 0.0, scale_h: float = 0.0,
+                 device=None):
+        self.w = w
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.storage = storage
+        self._h = create_plan_handle(w, storage=storage, kernel=kernel, rows=rows, waves=waves,
+                                     zchunk=zchunk, nan_watch=nan_watch, scale_e=scale_e,
+                                     scale_h=scale_h)
+        L = N.lib()
+        nbytes = ct.c_uint64()
+        N.check(L.chf_plan_workspace_bytes(self._h, ct.byref(nbytes)), "chf_plan_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            N.check(L.chf_plan_bind_workspace(self._h, ct.c_void_p(self.workspace.data_ptr()),
+                                              self.workspace_bytes, _stream_handle()),
+                    "chf_plan_bind_workspace")
+        self.n_obs = w.n_obs
+        self.n_steps = w.n_steps
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            N.lib().chf_plan_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- info
+    def info(self) -> dict:
+        pi = N.PlanInfo()
+        N.check(N.lib().chf_plan_get_info(self._h, ct.byref(pi)), "chf_plan_get_info")
+        return {f: getattr(pi, f) for f, _ in N.PlanInfo._fields_}
+
+    # -- running
+    def new_waveforms(self) -> torch.Tensor:
+        return torch.zeros((self.n_obs, 3, self.n_steps), dtype=torch.float64, device=self.device)
+
+    def reset(self, stream=None):
+        N.check(N.lib().chf_plan_reset(self._h, _stream_handle(stream)), "chf_plan_reset")
+
+    def forward(self, n_steps: int, out: Optional[torch.Tensor] = None, first_column: int = 0,
+                q_bins: Optional[torch.Tensor] = None, stream=None):
+        """Advance n_steps from the current state, writing waveform columns first_column... of
+        out ([n_obs, 3, ld] FP64 on the device)."""
+        ld = out.shape[2] if out is not None else 0
+        if out is not None:
+            assert out.dtype == torch.float64 and out.is_contiguous() and out.device == self.device
+        qp = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
+        if q_bins is not None:
+            assert q_bins.dtype == torch.float64 and q_bins.numel() == len(self.w.q_bins)
+        wp = ct.c_void_p(out.data_ptr()) if out is not None else ct.c_void_p()
+        N.check(N.lib().chf_forward(self._h, _stream_handle(stream), qp, wp, n_steps, first_column, ld),
+                "chf_forward")
+
+    def run(self, q_bins: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+            graph: bool = False, stream=None, sync: bool = True) -> torch.Tensor:
+        """Full run from zero fields; returns [n_obs, 3, n_steps] FP64 waveforms."""
+        out = self.new_waveforms() if out is None else out
+        qp = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
+        if graph:
+            N.check(N.lib().chf_forward_graph(self._h, _stream_handle(stream), qp,
+                                              ct.c_void_p(out.data_ptr())), "chf_forward_graph")
+        else:
+            self.reset(stream)
+            self.forward(self.n_steps, out, 0, q_bins, stream)
+        if sync:
+            self.sync(stream)
+        return out
+
+    def sync(self, stream=None):
+        N.check(N.lib().chf_plan_sync(self._h, _stream_handle(stream)), "chf_plan_sync")
+
+    def adjoint(self, dl_dw: torch.Tensor, stream=None) -> torch.Tensor:
+        assert dl_dw.dtype == torch.float64 and dl_dw.shape == (self.n_obs, 3, self.n_steps)
+        dl_dw = dl_dw.contiguous()
+        out = torch.zeros(len(self.w.q_bins), dtype=torch.float64, device=self.device)
+        N.check(N.lib().chf_adjoint(self._h, _stream_handle(stream), ct.c_void_p(dl_dw.data_ptr()),
+                                    ct.c_void_p(out.data_ptr())), "chf_adjoint")
+        return out
+
+    # -- field access (physical units, [nz, ny, nx] FP32)
+    def get_field(self, comp: int, stream=None) -> torch.Tensor:
+        out = torch.empty((self.w.nz, self.w.ny, self.w.nx), dtype=torch.float32, device=self.device)
+        N.check(N.lib().chf_plan_get_field(self._h, _stream_handle(stream), comp,
+                                           ct.c_void_p(out.data_ptr())), "chf_plan_get_field")
+        return out
+
+    def set_field(self, comp: int, value: torch.Tensor, stream=None):
+        v = value.to(device=self.device, dtype=torch.float32).contiguous()
+        assert v.shape == (self.w.nz, self.w.ny, self.w.nx)
+        N.check(N.lib().chf_plan_set_field(self._h, _stream_handle(stream), comp,
+                                           ct.c_void_p(v.data_ptr())), "chf_plan_set_field")
+        torch.cuda.current_stream().synchronize()
+
+
+def run(w, **kw) -> torch.Tensor:
+    """One-shot forward run of a workload; returns device FP64 waveforms [n_obs, 3, n_steps]."""
+    plan = Plan(w, **kw)
+    try:
+        return plan.run()
+    finally:
+        plan.close()
+
+
+class Batch:
+    """Several plans advanced by one call (chf_batch_run)."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        self.plans = list(plans)
+        arr = (ct.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        self._keep = arr
+        self._h = ct.c_void_p()
+        N.check(N.lib().chf_batch_create(len(self.plans), arr, ct.byref(self._h)), "chf_batch_create")
+
+    def run(self, outs=None, stream=None, sync=True):
+        outs = outs or [p.new_waveforms() for p in self.plans]
+        ptrs = (ct.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        N.check(N.lib().chf_batch_run(self._h, _stream_handle(stream), ptrs), "chf_batch_run")
+        if sync:
+            for p in self.plans:
+                p.sync(stream)
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            N.lib().chf_batch_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

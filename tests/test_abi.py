@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point, and
+chf_plan_create validates descriptors on the host."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1001_5341_amd import _native as N
+from paper_1001_5341_amd import solver
+from paper_1001_5341_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "chfdtd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    names = declared_symbols()
+    assert "chf_plan_create" in names and "chf_forward" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(N.EXPORTED)
+    assert L.chf_abi_version() == 1
+
+
+def _status(w, **kw):
+    try:
+        h = solver.create_plan_handle(w, **kw)
+    except N.ChfError as e:
+        return e.status
+    N.lib().chf_plan_destroy(h)
+    return "CHF_OK"
+
+
+def test_valid_plans_accepted():
+    assert _status(W.gaussian_cube(1)) == "CHF_OK"
+    assert _status(W.small_shower()) == "CHF_OK"
+    assert _status(W.small_shower(), storage="bf16") == "CHF_OK"
+    assert _status(W.small_shower(), kernel="split") == "CHF_OK"
+
+
+def test_cfl_violation_rejected():
+    w = W.gaussian_cube(1)
+    dt_lim = 1.0 / (W.C0 / W.N_ICE * np.sqrt(3) / w.dx)
+    assert _status(w.replace(dt=dt_lim * 0.999)) == "CHF_OK"
+    assert _status(w.replace(dt=dt_lim * 1.001)) == "CHF_ECFL"
+
+
+def test_observer_outside_interior_rejected():
+    w = W.small_shower()
+    obs = w.obs_xyz.copy()
+    obs[0, 0] = (w.npml - 0.5) * w.dx  # stencil in the CPML
+    assert _status(w.replace(obs_xyz=obs)) == "CHF_EDOMAIN"
+    obs[0, 0] = -1.0
+    assert _status(w.replace(obs_xyz=obs)) == "CHF_EDOMAIN"
+
+
+def test_source_outside_grid_rejected():
+    w = W.small_shower()
+    assert _status(w.replace(x_axis=-1.0)) == "CHF_EDOMAIN"
+
+
+def test_bad_descriptors_rejected():
+    w = W.small_shower()
+    assert _status(w.replace(nx=2)) == "CHF_EINVAL"
+    assert _status(w.replace(dx=0.0)) == "CHF_EINVAL"
+    assert _status(w.replace(npml=40)) == "CHF_EINVAL"
+    assert _status(w.replace(eps_r=-1.0)) == "CHF_EINVAL"
+    assert _status(w, rows=3) == "CHF_EINVAL"
+    assert _status(w.replace(sigma_r=0.0)) == "CHF_EINVAL"
+
+
+def test_fused_sweep_width_limit():
+    w = W.gaussian_cube(1, n=24, n_steps=2)
+    big = w.replace(nx=600, x_axis=0.5 * 599 * w.dx, obs_xyz=w.obs_xyz + [0.5 * (599 - 23) * w.dx, 0, 0])
+    assert _status(big, kernel="fused") == "CHF_EUNSUPPORTED"
+    assert _status(big, kernel="split") == "CHF_OK"
+    assert _status(big) == "CHF_OK"  # auto picks the split sweeps
+
+
+def test_null_pointers_rejected():
+    L = N.lib()
+    h = ct.c_void_p()
+    assert L.chf_plan_create(None, None, None, None, None, None, ct.byref(h)) == -1
+    assert L.chf_plan_workspace_bytes(None, None) == -1
+    assert L.chf_forward(None, None, None, None, 1, 0, 1) == -1
+
+
+def test_workspace_size_and_binding_checks():
+    L = N.lib()
+    h = solver.create_plan_handle(W.small_shower())
+    try:
+        n = ct.c_uint64()
+        assert L.chf_plan_workspace_bytes(h, ct.byref(n)) == 0
+        info = N.PlanInfo()
+        assert L.chf_plan_get_info(h, ct.byref(info)) == 0
+        assert n.value == info.workspace_bytes > info.field_bytes > 0
+        # too small, then misaligned: both refused before any device call
+        assert L.chf_plan_bind_workspace(h, ct.c_void_p(4096), n.value - 1, None) == -4
+        assert L.chf_plan_bind_workspace(h, ct.c_void_p(4096 + 8), n.value, None) == -1
+        # use before binding
+        assert L.chf_forward(h, None, None, None, 1, 0, 1) == -8
+    finally:
+        L.chf_plan_destroy(h)
+
+
+def test_plan_info_layout():
+    h = solver.create_plan_handle(W.single_shower())
+    try:
+        info = N.PlanInfo()
+        assert N.lib().chf_plan_get_info(h, ct.byref(info)) == 0
+        assert info.kernel == 2 and info.vx == 4 and info.pitch == 256
+        # 48 B of fields + the CPML psi share of 256x256x2048 with 10-cell layers
+        assert abs(info.bytes_per_cell_update - (48 + 32 * (20 / 256 + 20 / 256 + 20 / 2048))) < 1e-9
+        assert info.scale_h == 256.0 and info.scale_e == 1.0
+    finally:
+        N.lib().chf_plan_destroy(h)

@@ -141,17 +141,46 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   chf::FusedShape &fs = p->fs;
   fs.vx = 1;
   while (64 * fs.vx < G.nx) fs.vx *= 2;
-  fs.rows = ex->rows_per_wave > 0 ? ex->rows_per_wave : 2;
+  fs.rows = 1;
   fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 4;
-  fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 32;
-  if (!(fs.rows == 1 || fs.rows == 2 || fs.rows == 4) || fs.waves < 1 || fs.waves > 4) {
+  fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 16;
+  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) || !(fs.waves == 4 || fs.waves == 8)) {
     delete p;
-    return fail(CHF_EINVAL, "rows_per_wave must be 1, 2 or 4 and waves_per_block 1..4");
+    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4 or 8");
   }
-  fs.nty = (G.ny + fs.waves * fs.rows - 1) / (fs.waves * fs.rows);
+  if ((int64_t)((G.nx + 15) / 16 * 16) * G.ny >= ((int64_t)1 << 31)) {
+    delete p;
+    return fail(CHF_EUNSUPPORTED, "one x-y plane must hold fewer than 2^31 nodes");
+  }
+  fs.nty = (G.ny + fs.waves - 1) / fs.waves;
   fs.nzc = (G.nz + fs.zchunk - 1) / fs.zchunk;
   fs.n_tiles = fs.nty * fs.nzc;
   fs.n_blocks = (fs.n_tiles + 7) / 8 * 8;
+  {
+    // fast rectangle: every row of the tile and the halo row below it lies in [fy0, fy1], every
+    // plane of the chunk and the plane below it in [fz0, fz1], where [f0, f1] are the nodes
+    // with no wall and no layer term (integer and half positions alike)
+    const int nl = bnd->kind == CHF_BC_CPML ? bnd->npml : 0;
+    const int fy0 = std::max(1, nl), fy1 = G.ny - 2 - nl;
+    const int fz0 = std::max(1, nl), fz1 = G.nz - 2 - nl;
+    fs.ty_lo = (fy0 + 1 + fs.waves - 1) / fs.waves;          // j0 - 1 >= fy0 (row below)
+    fs.ty_hi = (fy1 + 1) / fs.waves;                          // j0 + W - 1 <= fy1
+    fs.zc_lo = (fz0 + 1 + fs.zchunk - 1) / fs.zchunk;        // k0 - 1 >= fz0
+    fs.zc_hi = (fz1 + 1) / fs.zchunk;                         // k1 - 1 <= fz1
+    if (fs.ty_hi <= fs.ty_lo || fs.zc_hi <= fs.zc_lo) fs.ty_lo = fs.ty_hi = fs.zc_lo = fs.zc_hi = 0;
+    fs.n_fast = (fs.ty_hi - fs.ty_lo) * (fs.zc_hi - fs.zc_lo);
+    fs.fast_blocks = (fs.n_fast + 7) / 8 * 8;
+    for (int zc = 0; zc < fs.nzc; zc++)
+      for (int ty = 0; ty < fs.nty; ty++) {
+        const bool fast = ty >= fs.ty_lo && ty < fs.ty_hi && zc >= fs.zc_lo && zc < fs.zc_hi;
+        if (!fast) {
+          p->slow_tiles.push_back(ty);
+          p->slow_tiles.push_back(zc);
+        }
+      }
+    fs.n_slow = (int)(p->slow_tiles.size() / 2);
+    fs.slow_blocks = (fs.n_slow + 7) / 8 * 8;
+  }
 
   // coefficients (FP64)
   const double eps = kEps0 * medium->eps_r, mu = kMu0 * medium->mu_r;
@@ -333,6 +362,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   off += align256(std::max<size_t>(p->obs_t.size(), 1) * sizeof(double));
   p->off_nan = off;
   off += 256;
+  p->off_tiles = off;
+  off += align256(std::max<size_t>(p->slow_tiles.size(), 1) * sizeof(int));
   p->ws_bytes = off;
 
   // kernel parameter block (device pointers are filled at bind time)
@@ -419,6 +450,7 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
   D.obs_idx = (const int *)(ws + p->off_oidx);
   D.obs_t = (const double *)(ws + p->off_ot);
   D.nan_flag = (int *)(ws + p->off_nan);
+  D.slow_tiles = (const int *)(ws + p->off_tiles);
   struct Up {
     uint64_t off;
     const void *src;
@@ -430,6 +462,7 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
       {p->off_q, p->q_bins.data(), p->q_bins.size() * sizeof(double)},
       {p->off_oidx, p->obs_idx.data(), p->obs_idx.size() * sizeof(int)},
       {p->off_ot, p->obs_t.data(), p->obs_t.size() * sizeof(double)},
+      {p->off_tiles, p->slow_tiles.data(), p->slow_tiles.size() * sizeof(int)},
   };
   for (const Up &u : ups) {
     if (!u.n) continue;

@@ -52,6 +52,7 @@ struct Dev {
   const double *obs_t;       // [n_obs][3 comps][3] fractional offsets
   double inv_se;             // 1/scale_e for the gather
   int *nan_flag;
+  const int *slow_tiles;     // [n_slow][2] (ty, zc) of the tiles taking the general path
   // Mur
   float mur_kx, mur_ky, mur_kz;
   int bc;
@@ -59,6 +60,8 @@ struct Dev {
 
 struct FusedShape {
   int vx, rows, waves, zchunk, nty, nzc, n_tiles, n_blocks;
+  // tiles clear of walls and y/z layers form the rectangle [ty_lo,ty_hi) x [zc_lo,zc_hi)
+  int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_slow, slow_blocks;
 };
 
 }  // namespace chf
@@ -84,7 +87,8 @@ struct chf_plan {
   size_t off_tabf[3][6], off_tabi[3][2];
   // workspace layout (byte offsets)
   uint64_t off_e[2][3], off_h[2][3], off_psi_e[3][2], off_psi_h[2][3][2];
-  uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, ws_bytes;
+  uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, off_tiles, ws_bytes;
+  std::vector<int> slow_tiles;
   uint64_t field_bytes, psi_bytes, psi_len[3];
   char *ws = nullptr;
   chf::Dev dev;

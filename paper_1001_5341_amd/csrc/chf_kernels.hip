@@ -49,6 +49,20 @@ __device__ __forceinline__ void ld_row(const T *p, float (&o)[N], bool on) {
   }
 }
 
+// Row access at a wave-uniform base plus a 32-bit byte offset (global_load saddr form).
+template <typename T, int N>
+__device__ __forceinline__ void ld_at(const T *base, unsigned boff, float (&o)[N], bool on) {
+  ld_row<T, N>(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff), o, on);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on);
+
+template <typename T, int N>
+__device__ __forceinline__ void st_at(T *base, unsigned boff, const float (&o)[N], bool on) {
+  st_row<T, N>(reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff), o, on);
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on) {
   if (!on) return;
@@ -100,289 +114,310 @@ __device__ __forceinline__ float psi_step(const Dev &d, const float *in, float *
 }
 
 // --------------------------------------------------------------- fused sweep
-// One wave owns R consecutive y rows of the full x extent (64 lanes x VX cells, nx <= 64 VX)
-// and marches a z chunk.  Per plane it recomputes the H row just below its first row (the
-// E update needs H^{n+1/2}(j0-1)) and, at the chunk start, the H plane below.  x neighbours
-// move between lanes with shuffles.  Workgroups are laid out so that consecutive logical
-// tiles (neighbours in y, then in z) land on the same XCD and share its L2.
-template <typename T, int VX, int R>
-__global__ void __launch_bounds__(256) k_fused(Dev d, FusedShape fs, int par) {
+// One wave owns one y row of the full x extent (64 lanes x VX cells, nx <= 64 VX) and marches
+// a z chunk; a workgroup holds W waves over W consecutive rows.  Waves are independent (no LDS,
+// no barriers): each recomputes the H row below its own (the E update needs H^{n+1/2}(j-1))
+// and reads the E row above it, so neighbouring rows are read by two waves, mostly from L2.
+// x neighbours move between lanes with shuffles.  Plane base pointers are wave-uniform and
+// in-plane offsets 32-bit.  Workgroups are ordered so that consecutive logical tiles
+// (neighbours in y, then in z) land on the same XCD and share its L2.
+//
+// FAST: the launch covers only tiles whose rows (and the row below) are clear of the y walls
+// and y layers and whose planes (and the plane below) are clear of the z walls and z layers,
+// so no y/z masks or psi terms are compiled in; lanes holding an x wall, x padding or an
+// x-layer node patch their results, applying the psi terms last exactly as h_cell / e_cell
+// do.  Otherwise tiles come from a table and every node takes the general path.
+template <typename T, int VX, int W, bool FAST>
+__global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const int *tiles, int par) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int b = blockIdx.x;
   const int logical = (b & 7) * (gridDim.x >> 3) + (b >> 3);
-  if (logical >= fs.n_tiles) return;
-  const int ty = logical % fs.nty;
-  const int zc = logical / fs.nty;
-  const int j0 = (ty * fs.waves + wave) * R;
-  if (j0 >= d.ny) return;
-  const int k0 = zc * fs.zchunk;
-  const int k1 = min(k0 + fs.zchunk, d.nz);
+  int ty, zc;
+  if constexpr (FAST) {
+    if (logical >= fs.n_fast) return;
+    const int fw = fs.ty_hi - fs.ty_lo;
+    ty = fs.ty_lo + logical % fw;
+    zc = fs.zc_lo + logical / fw;
+  } else {
+    if (logical >= fs.n_slow) return;
+    ty = tiles[2 * logical];
+    zc = tiles[2 * logical + 1];
+  }
   const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const int j = ty * W + wave;
+  if (j >= ny) return;
+  const int k0 = zc * fs.zchunk, k1 = min(k0 + fs.zchunk, nz);
   const int ib = lane * VX;
   const bool on = ib < nx;
-
+  const unsigned esz = (unsigned)sizeof(T);
+  const unsigned o0 = ((unsigned)j * (unsigned)d.pitch + (unsigned)ib) * esz;               // row j
+  const unsigned om = ((unsigned)max(j - 1, 0) * (unsigned)d.pitch + (unsigned)ib) * esz;   // row j-1
+  const unsigned op = ((unsigned)min(j + 1, ny - 1) * (unsigned)d.pitch + (unsigned)ib) * esz;  // row j+1
+  const long long plane = d.plane;
+  const bool pml = d.np2 > 0;
   const T *Ei0 = (const T *)d.e[par][0], *Ei1 = (const T *)d.e[par][1], *Ei2 = (const T *)d.e[par][2];
   const T *Hi0 = (const T *)d.h[par][0], *Hi1 = (const T *)d.h[par][1], *Hi2 = (const T *)d.h[par][2];
   T *Eo0 = (T *)d.e[par ^ 1][0], *Eo1 = (T *)d.e[par ^ 1][1], *Eo2 = (T *)d.e[par ^ 1][2];
   T *Ho0 = (T *)d.h[par ^ 1][0], *Ho1 = (T *)d.h[par ^ 1][1], *Ho2 = (T *)d.h[par ^ 1][2];
-  const bool pml = d.np2 > 0;
 
-  // per-lane x tables
-  float cex[VX], chx[VX];
-  int sex[VX], shx[VX];
+  float chx[VX], cex[VX];
+  int shx[VX], sex[VX];
+  bool xfix = false;
 #pragma unroll
   for (int v = 0; v < VX; v++) {
-    int i = ib + v, ic = min(i, nx - 1);
-    cex[v] = d.ax[0].ce[ic];
+    const int i = ib + v, ic = min(i, nx - 1);
     chx[v] = d.ax[0].ch[ic];
-    sex[v] = (pml && i < nx) ? d.ax[0].se[i] : -1;
+    cex[v] = d.ax[0].ce[ic];
     shx[v] = (pml && i < nx) ? d.ax[0].sh[i] : -1;
+    sex[v] = (pml && i < nx) ? d.ax[0].se[i] : -1;
+    xfix = xfix || i == 0 || i >= nx - 1 || shx[v] >= 0 || sex[v] >= 0;
   }
-  // rows r = -1..R (array index r+1), clamped into the grid
-  int jr[R + 2];
-  float cey[R + 2], chy[R + 2];
-  int sey[R + 2], shy[R + 2];
-#pragma unroll
-  for (int r = 0; r < R + 2; r++) {
-    int j = j0 + r - 1;
-    int jc = min(max(j, 0), ny - 1);
-    jr[r] = jc;
-    cey[r] = d.ax[1].ce[jc];
-    chy[r] = d.ax[1].ch[jc];
-    sey[r] = pml ? d.ax[1].se[jc] : -1;
-    shy[r] = pml ? d.ax[1].sh[jc] : -1;
-  }
-  auto at = [&](int r, int k) -> long long {
-    return (long long)k * d.plane + (long long)jr[r] * d.pitch + ib;
-  };
+  const int jm = max(j - 1, 0);
+  const float chy = d.ax[1].ch[j], cey = d.ax[1].ce[j], chym = d.ax[1].ch[jm];
+  const int shy = pml ? d.ax[1].sh[j] : -1, sey = pml ? d.ax[1].se[j] : -1;
+  const int shym = pml ? d.ax[1].sh[jm] : -1;
+  const bool ylay = shy >= 0 || sey >= 0 || shym >= 0;
+  float *const phi[3][2] = {{d.psi_h[par][0][0], d.psi_h[par][0][1]},
+                            {d.psi_h[par][1][0], d.psi_h[par][1][1]},
+                            {d.psi_h[par][2][0], d.psi_h[par][2][1]}};
+  float *const pho[3][2] = {{d.psi_h[par ^ 1][0][0], d.psi_h[par ^ 1][0][1]},
+                            {d.psi_h[par ^ 1][1][0], d.psi_h[par ^ 1][1][1]},
+                            {d.psi_h[par ^ 1][2][0], d.psi_h[par ^ 1][2][1]}};
 
-  float ex[R + 2][VX], ey[R + 2][VX], ez[R + 2][VX];
-  float hxp[R][VX], hyp[R][VX];
+  // E(k) of rows j-1 (m), j (c), j+1 (p; Ex and Ez only)
+  float exm[VX], eym[VX], ezm[VX], exc[VX], eyc[VX], ezc[VX], exp_[VX], ezp[VX];
+  ld_at<T, VX>(Ei0 + k0 * plane, om, exm, on);
+  ld_at<T, VX>(Ei1 + k0 * plane, om, eym, on);
+  ld_at<T, VX>(Ei2 + k0 * plane, om, ezm, on);
+  ld_at<T, VX>(Ei0 + k0 * plane, o0, exc, on);
+  ld_at<T, VX>(Ei1 + k0 * plane, o0, eyc, on);
+  ld_at<T, VX>(Ei2 + k0 * plane, o0, ezc, on);
+  ld_at<T, VX>(Ei0 + k0 * plane, op, exp_, on);
+  ld_at<T, VX>(Ei2 + k0 * plane, op, ezp, on);
 
-  // ---- prologue: H^{n+1/2}(k0-1) for Hx, Hy of the owned rows (not stored)
+  // H^{n+1/2}(k0-1), Hx and Hy of row j, for the backward z differences of the first plane
+  float hxp[VX], hyp[VX];
   if (k0 > 0) {
     const int km = k0 - 1;
+    float ex_[VX], ey_[VX], ez_[VX], ezu[VX], hxo[VX], hyo[VX];
+    ld_at<T, VX>(Ei0 + km * plane, o0, ex_, on);
+    ld_at<T, VX>(Ei1 + km * plane, o0, ey_, on);
+    ld_at<T, VX>(Ei2 + km * plane, o0, ez_, on);
+    ld_at<T, VX>(Ei2 + km * plane, op, ezu, on);
+    ld_at<T, VX>(Hi0 + km * plane, o0, hxo, on);
+    ld_at<T, VX>(Hi1 + km * plane, o0, hyo, on);
     const float chz = d.ax[2].ch[km];
     const int shz = pml ? d.ax[2].sh[km] : -1;
-    float ezR[VX];
-    ld_row<T, VX>(Ei2 + at(R + 1, km), ezR, on);
+    const float ezn = __shfl_down(ez_[0], 1);
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-      float exm[VX], eym[VX], ezm[VX], ex0[VX], ey0[VX], hxo[VX], hyo[VX], ez1[VX];
-      ld_row<T, VX>(Ei0 + at(r + 1, km), exm, on);
-      ld_row<T, VX>(Ei1 + at(r + 1, km), eym, on);
-      ld_row<T, VX>(Ei2 + at(r + 1, km), ezm, on);
-      ld_row<T, VX>(Ei0 + at(r + 1, k0), ex0, on);
-      ld_row<T, VX>(Ei1 + at(r + 1, k0), ey0, on);
-      ld_row<T, VX>(Hi0 + at(r + 1, km), hxo, on);
-      ld_row<T, VX>(Hi1 + at(r + 1, km), hyo, on);
-      if (r + 1 < R) ld_row<T, VX>(Ei2 + at(r + 2, km), ez1, on);
-      const int j = j0 + r;
-#pragma unroll
-      for (int v = 0; v < VX; v++) {
-        if (r + 1 >= R) ez1[v] = ezR[v];
-      }
-      float ezn = __shfl_down(ezm[0], 1);
-#pragma unroll
-      for (int v = 0; v < VX; v++) {
-        const int i = ib + v;
-        float ezip = (v + 1 < VX) ? ezm[v + 1] : ezn;
-        // Hx(j+1/2, k0-1/2)
-        float d1 = ez1[v] - ezm[v], d2 = ey0[v] - eym[v];
-        bool q1 = shy[r + 1] >= 0, q2 = shz >= 0;
+    for (int v = 0; v < VX; v++) {
+      const int i = ib + v;
+      const float ezx = (v + 1 < VX) ? ez_[v + 1] : ezn;
+      {
+        const float d1 = ezu[v] - ez_[v], d2 = eyc[v] - ey_[v];
+        const bool u = i < nx && j <= ny - 2 && km <= nz - 2;
         float p1 = 0.f, p2 = 0.f;
-        bool ux = i < nx && j <= ny - 2 && km <= nz - 2;
-        if (q1 && ux) p1 = psi_step(d, d.psi_h[par][1][0], nullptr, false, 1, i, j, km, shy[r + 1],
-                              d.ax[1].ah[j], d.ax[1].bh[j], d1);
-        if (q2 && ux) p2 = psi_step(d, d.psi_h[par][2][0], nullptr, false, 2, i, j, km, shz,
-                              d.ax[2].ah[km], d.ax[2].bh[km], d2);
-        hxp[r][v] = ux ? h_cell(hxo[v], d1, chy[r + 1], d2, chz, q1, p1, q2, p2) : hxo[v];
-        // Hy(i+1/2, k0-1/2)
-        d1 = ex0[v] - exm[v];
-        d2 = ezip - ezm[v];
-        q1 = shz >= 0;
-        q2 = shx[v] >= 0;
-        p1 = p2 = 0.f;
-        bool uy = i <= nx - 2 && j < ny && km <= nz - 2;
-        if (q1 && uy) p1 = psi_step(d, d.psi_h[par][2][1], nullptr, false, 2, i, j, km, shz,
-                              d.ax[2].ah[km], d.ax[2].bh[km], d1);
-        if (q2 && uy) p2 = psi_step(d, d.psi_h[par][0][0], nullptr, false, 0, i, j, km, shx[v],
-                              d.ax[0].ah[i], d.ax[0].bh[i], d2);
-        hyp[r][v] = uy ? h_cell(hyo[v], d1, chz, d2, chx[v], q1, p1, q2, p2) : hyo[v];
+        if (shy >= 0 && u) p1 = psi_step(d, phi[1][0], nullptr, false, 1, i, j, km, shy, d.ax[1].ah[j], d.ax[1].bh[j], d1);
+        if (shz >= 0 && u) p2 = psi_step(d, phi[2][0], nullptr, false, 2, i, j, km, shz, d.ax[2].ah[km], d.ax[2].bh[km], d2);
+        hxp[v] = u ? h_cell(hxo[v], d1, chy, d2, chz, shy >= 0, p1, shz >= 0, p2) : hxo[v];
+      }
+      {
+        const float d1 = exc[v] - ex_[v], d2 = ezx - ez_[v];
+        const bool u = i <= nx - 2 && km <= nz - 2;
+        float p1 = 0.f, p2 = 0.f;
+        if (shz >= 0 && u) p1 = psi_step(d, phi[2][1], nullptr, false, 2, i, j, km, shz, d.ax[2].ah[km], d.ax[2].bh[km], d1);
+        if (shx[v] >= 0 && u) p2 = psi_step(d, phi[0][0], nullptr, false, 0, i, j, km, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], d2);
+        hyp[v] = u ? h_cell(hyo[v], d1, chz, d2, chx[v], shz >= 0, p1, shx[v] >= 0, p2) : hyo[v];
       }
     }
   } else {
 #pragma unroll
-    for (int r = 0; r < R; r++)
-#pragma unroll
-      for (int v = 0; v < VX; v++) hxp[r][v] = hyp[r][v] = 0.f;
-  }
-
-  // ---- current plane E(k0), rows -1..R
-#pragma unroll
-  for (int r = 0; r < R + 2; r++) {
-    ld_row<T, VX>(Ei0 + at(r, k0), ex[r], on);
-    ld_row<T, VX>(Ei2 + at(r, k0), ez[r], on);
-    if (r < R + 1) ld_row<T, VX>(Ei1 + at(r, k0), ey[r], on);
+    for (int v = 0; v < VX; v++) hxp[v] = hyp[v] = 0.f;
   }
 
   for (int k = k0; k < k1; k++) {
-    const int kn = min(k + 1, nz - 1);
+    const int kp = min(k + 1, nz - 1);
+    const long long pk = k * plane, pn = kp * plane;
+    // E(k+1) of rows j-1, j, j+1 and H^{n-1/2}(k) of rows j-1 (Hx, Hz) and j
+    float nxm[VX], nym[VX], nzm[VX], nxc[VX], nyc[VX], nzc[VX], nxp[VX], nzp[VX];
+    float hxm0[VX], hzm0[VX], hx0[VX], hy0[VX], hz0[VX];
+    ld_at<T, VX>(Ei0 + pn, om, nxm, on);
+    ld_at<T, VX>(Ei1 + pn, om, nym, on);
+    ld_at<T, VX>(Ei2 + pn, om, nzm, on);
+    ld_at<T, VX>(Ei0 + pn, o0, nxc, on);
+    ld_at<T, VX>(Ei1 + pn, o0, nyc, on);
+    ld_at<T, VX>(Ei2 + pn, o0, nzc, on);
+    ld_at<T, VX>(Ei0 + pn, op, nxp, on);
+    ld_at<T, VX>(Ei2 + pn, op, nzp, on);
+    ld_at<T, VX>(Hi0 + pk, om, hxm0, on);
+    ld_at<T, VX>(Hi2 + pk, om, hzm0, on);
+    ld_at<T, VX>(Hi0 + pk, o0, hx0, on);
+    ld_at<T, VX>(Hi1 + pk, o0, hy0, on);
+    ld_at<T, VX>(Hi2 + pk, o0, hz0, on);
+
     const float chz = d.ax[2].ch[k], cez = d.ax[2].ce[k];
     const int shz = pml ? d.ax[2].sh[k] : -1, sez = pml ? d.ax[2].se[k] : -1;
-    // next plane E(k+1) for rows -1..R, old H(k) for rows -1..R-1
-    float nex[R + 2][VX], ney[R + 1][VX], nez[R + 2][VX];
-    float hxo[R + 1][VX], hyo[R + 1][VX], hzo[R + 1][VX];
-#pragma unroll
-    for (int r = 0; r < R + 2; r++) {
-      ld_row<T, VX>(Ei0 + at(r, kn), nex[r], on);
-      ld_row<T, VX>(Ei2 + at(r, kn), nez[r], on);
-      if (r < R + 1) ld_row<T, VX>(Ei1 + at(r, kn), ney[r], on);
+    const float eymn = __shfl_down(eym[0], 1);
+    const float eyn = __shfl_down(eyc[0], 1), ezn = __shfl_down(ezc[0], 1);
+    float hxm[VX], hzm[VX], hx[VX], hy[VX], hz[VX];
+    bool fast;
+    if constexpr (FAST) {
+      fast = true;
+    } else {
+      fast = j >= 2 && j <= ny - 2 && !ylay && k >= 1 && k <= nz - 2 && shz < 0 && sez < 0;
     }
+    if (fast) {
 #pragma unroll
-    for (int r = 0; r < R + 1; r++) {
-      ld_row<T, VX>(Hi0 + at(r, k), hxo[r], on);
-      ld_row<T, VX>(Hi2 + at(r, k), hzo[r], on);
-      if (r > 0) ld_row<T, VX>(Hi1 + at(r, k), hyo[r], on);
-    }
-
-    // ---- H^{n+1/2}(k): rows -1..R-1 (row -1 only Hx, Hz; it is not stored)
-    float hx[R + 1][VX], hy[R + 1][VX], hz[R + 1][VX];
+      for (int v = 0; v < VX; v++) {
+        const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+        const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
+        const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
+        hxm[v] = fmaf(chz, nym[v] - eym[v], fmaf(-chym, ezc[v] - ezm[v], hxm0[v]));
+        hzm[v] = fmaf(chym, exc[v] - exm[v], fmaf(-chx[v], eymx - eym[v], hzm0[v]));
+        hx[v] = fmaf(chz, nyc[v] - eyc[v], fmaf(-chy, ezp[v] - ezc[v], hx0[v]));
+        hy[v] = fmaf(chx[v], ezx - ezc[v], fmaf(-chz, nxc[v] - exc[v], hy0[v]));
+        hz[v] = fmaf(chy, exp_[v] - exc[v], fmaf(-chx[v], eyx - eyc[v], hz0[v]));
+      }
+      if (xfix) {
 #pragma unroll
-    for (int r = 0; r < R + 1; r++) {
-      const int j = j0 + r - 1;
-      const bool own = r > 0;
-      const bool halo_ok = own || j >= 0;
-      float eyn = __shfl_down(ey[r][0], 1);
-      float ezn = __shfl_down(ez[r][0], 1);
+        for (int v = 0; v < VX; v++) {
+          const int i = ib + v;
+          if (i >= nx - 1) {
+            hzm[v] = hzm0[v];
+            hy[v] = hy0[v];
+            hz[v] = hz0[v];
+            if (i >= nx) {
+              hxm[v] = hxm0[v];
+              hx[v] = hx0[v];
+            }
+          } else if (shx[v] >= 0) {
+            const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+            const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
+            const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
+            const float ah = d.ax[0].ah[i], bh = d.ax[0].bh[i];
+            hzm[v] = hzm[v] - psi_step(d, phi[0][1], nullptr, false, 0, i, j - 1, k, shx[v], ah, bh, eymx - eym[v]);
+            hy[v] = hy[v] + psi_step(d, phi[0][0], pho[0][0], true, 0, i, j, k, shx[v], ah, bh, ezx - ezc[v]);
+            hz[v] = hz[v] - psi_step(d, phi[0][1], pho[0][1], true, 0, i, j, k, shx[v], ah, bh, eyx - eyc[v]);
+          }
+        }
+      }
+    } else if constexpr (!FAST) {
+      const bool zl = shz >= 0;
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         const int i = ib + v;
-        float eyip = (v + 1 < VX) ? ey[r][v + 1] : eyn;
-        float ezip = (v + 1 < VX) ? ez[r][v + 1] : ezn;
-        const bool wr = own && j < ny;
-        // Hx
+        const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+        const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
+        const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
+        const bool xl = shx[v] >= 0;
+        // row j-1: Hx, Hz (recomputed, not stored)
         {
-          float d1 = ez[r + 1][v] - ez[r][v], d2 = ney[r][v] - ey[r][v];
-          bool q1 = shy[r] >= 0, q2 = shz >= 0;
-          bool u = halo_ok && i < nx && j <= ny - 2 && k <= nz - 2;
-          float p1 = 0.f, p2 = 0.f;
-          if (q1 && u) p1 = psi_step(d, d.psi_h[par][1][0], d.psi_h[par ^ 1][1][0], wr, 1, i, j, k,
-                                     shy[r], d.ax[1].ah[j], d.ax[1].bh[j], d1);
-          if (q2 && u) p2 = psi_step(d, d.psi_h[par][2][0], d.psi_h[par ^ 1][2][0], wr, 2, i, j, k,
-                                     shz, d.ax[2].ah[k], d.ax[2].bh[k], d2);
-          hx[r][v] = u ? h_cell(hxo[r][v], d1, chy[r], d2, chz, q1, p1, q2, p2) : hxo[r][v];
+          const int jj = j - 1;
+          const bool ux = jj >= 0 && i < nx && jj <= ny - 2 && k <= nz - 2;
+          const bool uz = jj >= 0 && i <= nx - 2 && jj <= ny - 2;
+          const float dx1 = ezc[v] - ezm[v], dx2 = nym[v] - eym[v];
+          const float dz1 = eymx - eym[v], dz2 = exc[v] - exm[v];
+          float p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
+          if (shym >= 0 && ux) p1 = psi_step(d, phi[1][0], nullptr, false, 1, i, jj, k, shym, d.ax[1].ah[jj], d.ax[1].bh[jj], dx1);
+          if (zl && ux) p2 = psi_step(d, phi[2][0], nullptr, false, 2, i, jj, k, shz, d.ax[2].ah[k], d.ax[2].bh[k], dx2);
+          if (xl && uz) p3 = psi_step(d, phi[0][1], nullptr, false, 0, i, jj, k, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], dz1);
+          if (shym >= 0 && uz) p4 = psi_step(d, phi[1][1], nullptr, false, 1, i, jj, k, shym, d.ax[1].ah[jj], d.ax[1].bh[jj], dz2);
+          hxm[v] = ux ? h_cell(hxm0[v], dx1, chym, dx2, chz, shym >= 0, p1, zl, p2) : hxm0[v];
+          hzm[v] = uz ? h_cell(hzm0[v], dz1, chx[v], dz2, chym, xl, p3, shym >= 0, p4) : hzm0[v];
         }
-        // Hz
+        // row j: Hx, Hy, Hz
         {
-          float d1 = eyip - ey[r][v], d2 = ex[r + 1][v] - ex[r][v];
-          bool q1 = shx[v] >= 0, q2 = shy[r] >= 0;
-          bool u = halo_ok && i <= nx - 2 && j <= ny - 2;
-          float p1 = 0.f, p2 = 0.f;
-          if (q1 && u) p1 = psi_step(d, d.psi_h[par][0][1], d.psi_h[par ^ 1][0][1], wr, 0, i, j, k,
-                                     shx[v], d.ax[0].ah[i], d.ax[0].bh[i], d1);
-          if (q2 && u) p2 = psi_step(d, d.psi_h[par][1][1], d.psi_h[par ^ 1][1][1], wr, 1, i, j, k,
-                                     shy[r], d.ax[1].ah[j], d.ax[1].bh[j], d2);
-          hz[r][v] = u ? h_cell(hzo[r][v], d1, chx[v], d2, chy[r], q1, p1, q2, p2) : hzo[r][v];
+          const bool ux = i < nx && j <= ny - 2 && k <= nz - 2;
+          const bool uy = i <= nx - 2 && k <= nz - 2;
+          const bool uz = i <= nx - 2 && j <= ny - 2;
+          const float dx1 = ezp[v] - ezc[v], dx2 = nyc[v] - eyc[v];
+          const float dy1 = nxc[v] - exc[v], dy2 = ezx - ezc[v];
+          const float dz1 = eyx - eyc[v], dz2 = exp_[v] - exc[v];
+          float px1 = 0.f, px2 = 0.f, py1 = 0.f, py2 = 0.f, pz1 = 0.f, pz2 = 0.f;
+          if (shy >= 0 && ux) px1 = psi_step(d, phi[1][0], pho[1][0], true, 1, i, j, k, shy, d.ax[1].ah[j], d.ax[1].bh[j], dx1);
+          if (zl && ux) px2 = psi_step(d, phi[2][0], pho[2][0], true, 2, i, j, k, shz, d.ax[2].ah[k], d.ax[2].bh[k], dx2);
+          if (zl && uy) py1 = psi_step(d, phi[2][1], pho[2][1], true, 2, i, j, k, shz, d.ax[2].ah[k], d.ax[2].bh[k], dy1);
+          if (xl && uy) py2 = psi_step(d, phi[0][0], pho[0][0], true, 0, i, j, k, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], dy2);
+          if (xl && uz) pz1 = psi_step(d, phi[0][1], pho[0][1], true, 0, i, j, k, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], dz1);
+          if (shy >= 0 && uz) pz2 = psi_step(d, phi[1][1], pho[1][1], true, 1, i, j, k, shy, d.ax[1].ah[j], d.ax[1].bh[j], dz2);
+          hx[v] = ux ? h_cell(hx0[v], dx1, chy, dx2, chz, shy >= 0, px1, zl, px2) : hx0[v];
+          hy[v] = uy ? h_cell(hy0[v], dy1, chz, dy2, chx[v], zl, py1, xl, py2) : hy0[v];
+          hz[v] = uz ? h_cell(hz0[v], dz1, chx[v], dz2, chy, xl, pz1, shy >= 0, pz2) : hz0[v];
         }
-        // Hy (owned rows only)
-        if (own) {
-          float d1 = nex[r][v] - ex[r][v], d2 = ezip - ez[r][v];
-          bool q1 = shz >= 0, q2 = shx[v] >= 0;
-          bool u = i <= nx - 2 && j < ny && k <= nz - 2;
-          float p1 = 0.f, p2 = 0.f;
-          if (q1 && u) p1 = psi_step(d, d.psi_h[par][2][1], d.psi_h[par ^ 1][2][1], wr, 2, i, j, k,
-                                     shz, d.ax[2].ah[k], d.ax[2].bh[k], d1);
-          if (q2 && u) p2 = psi_step(d, d.psi_h[par][0][0], d.psi_h[par ^ 1][0][0], wr, 0, i, j, k,
-                                     shx[v], d.ax[0].ah[i], d.ax[0].bh[i], d2);
-          hy[r][v] = u ? h_cell(hyo[r][v], d1, chz, d2, chx[v], q1, p1, q2, p2) : hyo[r][v];
-        } else {
-          hy[r][v] = 0.f;
-        }
-      }
-    }
-    // store H rows 0..R-1
-#pragma unroll
-    for (int r = 1; r < R + 1; r++) {
-      if (j0 + r - 1 < ny) {
-        st_row<T, VX>(Ho0 + at(r, k), hx[r], on);
-        st_row<T, VX>(Ho1 + at(r, k), hy[r], on);
-        st_row<T, VX>(Ho2 + at(r, k), hz[r], on);
       }
     }
 
-    // ---- E^{n+1}(k): rows 0..R-1
+    // ---- E^{n+1}(k) of row j
+    const float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
+    float oex[VX], oey[VX], oez[VX];
+    if (fast) {
 #pragma unroll
-    for (int r = 1; r < R + 1; r++) {
-      const int j = j0 + r - 1;
-      if (j >= ny) continue;
-      float hzm = __shfl_up(hz[r][VX - 1], 1);
-      float hym = __shfl_up(hy[r][VX - 1], 1);
-      float oex[VX], oey[VX], oez[VX];
+      for (int v = 0; v < VX; v++) {
+        const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+        const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+        oex[v] = fmaf(-cez, hy[v] - hyp[v], fmaf(cey, hz[v] - hzm[v], d.ca * exc[v]));
+        oey[v] = fmaf(-cex[v], hz[v] - hzw, fmaf(cez, hx[v] - hxp[v], d.ca * eyc[v]));
+        oez[v] = fmaf(-cey, hx[v] - hxm[v], fmaf(cex[v], hy[v] - hyw, d.ca * ezc[v]));
+      }
+      if (xfix) {
+#pragma unroll
+        for (int v = 0; v < VX; v++) {
+          const int i = ib + v;
+          if (i >= nx - 1) {
+            oex[v] = exc[v];
+            oey[v] = eyc[v];
+            oez[v] = ezc[v];
+          } else if (i == 0) {
+            oey[v] = eyc[v];
+            oez[v] = ezc[v];
+          } else if (sex[v] >= 0) {
+            const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+            const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+            const float ae = d.ax[0].ae[i], be = d.ax[0].be[i];
+            oey[v] = oey[v] - psi_step(d, d.psi_e[0][0], d.psi_e[0][0], true, 0, i, j, k, sex[v], ae, be, hz[v] - hzw);
+            oez[v] = oez[v] + psi_step(d, d.psi_e[0][1], d.psi_e[0][1], true, 0, i, j, k, sex[v], ae, be, hy[v] - hyw);
+          }
+        }
+      }
+    } else if constexpr (!FAST) {
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         const int i = ib + v;
-        float hzim = (v > 0) ? hz[r][v - 1] : hzm;
-        float hyim = (v > 0) ? hy[r][v - 1] : hym;
-        // Ex
-        {
-          float d1 = hz[r][v] - hz[r - 1][v], d2 = hy[r][v] - hyp[r - 1][v];
-          bool u = i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-          bool q1 = sey[r] >= 0, q2 = sez >= 0;
-          float p1 = 0.f, p2 = 0.f;
-          if (q1 && u) p1 = psi_step(d, d.psi_e[1][0], d.psi_e[1][0], true, 1, i, j, k, sey[r],
-                                     d.ax[1].ae[j], d.ax[1].be[j], d1);
-          if (q2 && u) p2 = psi_step(d, d.psi_e[2][0], d.psi_e[2][0], true, 2, i, j, k, sez,
-                                     d.ax[2].ae[k], d.ax[2].be[k], d2);
-          oex[v] = u ? e_cell(d.ca, ex[r][v], d1, cey[r], d2, cez, q1, p1, q2, p2) : ex[r][v];
-        }
-        // Ey
-        {
-          float d1 = hx[r][v] - hxp[r - 1][v], d2 = hz[r][v] - hzim;
-          bool u = i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-          bool q1 = sez >= 0, q2 = sex[v] >= 0;
-          float p1 = 0.f, p2 = 0.f;
-          if (q1 && u) p1 = psi_step(d, d.psi_e[2][1], d.psi_e[2][1], true, 2, i, j, k, sez,
-                                     d.ax[2].ae[k], d.ax[2].be[k], d1);
-          if (q2 && u) p2 = psi_step(d, d.psi_e[0][0], d.psi_e[0][0], true, 0, i, j, k, sex[v],
-                                     d.ax[0].ae[i], d.ax[0].be[i], d2);
-          oey[v] = u ? e_cell(d.ca, ey[r][v], d1, cez, d2, cex[v], q1, p1, q2, p2) : ey[r][v];
-        }
-        // Ez
-        {
-          float d1 = hy[r][v] - hyim, d2 = hx[r][v] - hx[r - 1][v];
-          bool u = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2;
-          bool q1 = sex[v] >= 0, q2 = sey[r] >= 0;
-          float p1 = 0.f, p2 = 0.f;
-          if (q1 && u) p1 = psi_step(d, d.psi_e[0][1], d.psi_e[0][1], true, 0, i, j, k, sex[v],
-                                     d.ax[0].ae[i], d.ax[0].be[i], d1);
-          if (q2 && u) p2 = psi_step(d, d.psi_e[1][1], d.psi_e[1][1], true, 1, i, j, k, sey[r],
-                                     d.ax[1].ae[j], d.ax[1].be[j], d2);
-          oez[v] = u ? e_cell(d.ca, ez[r][v], d1, cex[v], d2, cey[r], q1, p1, q2, p2) : ez[r][v];
-        }
+        const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+        const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+        const float ax1 = hz[v] - hzm[v], ax2 = hy[v] - hyp[v];  // Ex: y, z
+        const float ay1 = hx[v] - hxp[v], ay2 = hz[v] - hzw;     // Ey: z, x
+        const float az1 = hy[v] - hyw, az2 = hx[v] - hxm[v];     // Ez: x, y
+        const bool wx = i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
+        const bool wy = i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2;
+        const bool wz = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2;
+        float qx1 = 0.f, qx2 = 0.f, qy1 = 0.f, qy2 = 0.f, qz1 = 0.f, qz2 = 0.f;
+        if (sey >= 0 && wx) qx1 = psi_step(d, d.psi_e[1][0], d.psi_e[1][0], true, 1, i, j, k, sey, d.ax[1].ae[j], d.ax[1].be[j], ax1);
+        if (sey >= 0 && wz) qz2 = psi_step(d, d.psi_e[1][1], d.psi_e[1][1], true, 1, i, j, k, sey, d.ax[1].ae[j], d.ax[1].be[j], az2);
+        if (sez >= 0 && wx) qx2 = psi_step(d, d.psi_e[2][0], d.psi_e[2][0], true, 2, i, j, k, sez, d.ax[2].ae[k], d.ax[2].be[k], ax2);
+        if (sez >= 0 && wy) qy1 = psi_step(d, d.psi_e[2][1], d.psi_e[2][1], true, 2, i, j, k, sez, d.ax[2].ae[k], d.ax[2].be[k], ay1);
+        if (sex[v] >= 0 && wy) qy2 = psi_step(d, d.psi_e[0][0], d.psi_e[0][0], true, 0, i, j, k, sex[v], d.ax[0].ae[i], d.ax[0].be[i], ay2);
+        if (sex[v] >= 0 && wz) qz1 = psi_step(d, d.psi_e[0][1], d.psi_e[0][1], true, 0, i, j, k, sex[v], d.ax[0].ae[i], d.ax[0].be[i], az1);
+        oex[v] = wx ? e_cell(d.ca, exc[v], ax1, cey, ax2, cez, sey >= 0, qx1, sez >= 0, qx2) : exc[v];
+        oey[v] = wy ? e_cell(d.ca, eyc[v], ay1, cez, ay2, cex[v], sez >= 0, qy1, sex[v] >= 0, qy2) : eyc[v];
+        oez[v] = wz ? e_cell(d.ca, ezc[v], az1, cex[v], az2, cey, sex[v] >= 0, qz1, sey >= 0, qz2) : ezc[v];
       }
-      st_row<T, VX>(Eo0 + at(r, k), oex, on);
-      st_row<T, VX>(Eo1 + at(r, k), oey, on);
-      st_row<T, VX>(Eo2 + at(r, k), oez, on);
     }
-
-    // ---- march: E(k) <- E(k+1); H(k-1) <- H(k)
+    st_at<T, VX>(Ho0 + pk, o0, hx, on);
+    st_at<T, VX>(Ho1 + pk, o0, hy, on);
+    st_at<T, VX>(Ho2 + pk, o0, hz, on);
+    st_at<T, VX>(Eo0 + pk, o0, oex, on);
+    st_at<T, VX>(Eo1 + pk, o0, oey, on);
+    st_at<T, VX>(Eo2 + pk, o0, oez, on);
 #pragma unroll
-    for (int r = 0; r < R + 2; r++)
-#pragma unroll
-      for (int v = 0; v < VX; v++) {
-        ex[r][v] = nex[r][v];
-        ez[r][v] = nez[r][v];
-        if (r < R + 1) ey[r][v] = ney[r][v];
-      }
-#pragma unroll
-    for (int r = 0; r < R; r++)
-#pragma unroll
-      for (int v = 0; v < VX; v++) {
-        hxp[r][v] = hx[r + 1][v];
-        hyp[r][v] = hy[r + 1][v];
-      }
+    for (int v = 0; v < VX; v++) {
+      hxp[v] = hx[v];
+      hyp[v] = hy[v];
+      exm[v] = nxm[v]; eym[v] = nym[v]; ezm[v] = nzm[v];
+      exc[v] = nxc[v]; eyc[v] = nyc[v]; ezc[v] = nzc[v];
+      exp_[v] = nxp[v]; ezp[v] = nzp[v];
+    }
   }
 }
 
@@ -662,18 +697,22 @@ __global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
 }
 
 // ------------------------------------------------------------------ launch
-template <typename T, int VX, int R>
+template <typename T, int VX, int W>
 static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
-  hipLaunchKernelGGL((k_fused<T, VX, R>), dim3(p.fs.n_blocks), dim3(64 * p.fs.waves), 0, s, d, p.fs, par);
+  if (p.fs.n_fast > 0)
+    hipLaunchKernelGGL((k_fused<T, VX, W, true>), dim3(p.fs.fast_blocks), dim3(64 * W), 0, s, d, p.fs,
+                       (const int *)nullptr, par);
+  if (p.fs.n_slow > 0)
+    hipLaunchKernelGGL((k_fused<T, VX, W, false>), dim3(p.fs.slow_blocks), dim3(64 * W), 0, s, d, p.fs,
+                       d.slow_tiles, par);
   return hipGetLastError();
 }
 
 template <typename T, int VX>
-static hipError_t fused_dispatch_r(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
-  switch (p.fs.rows) {
-    case 1: return fused_launch<T, VX, 1>(p, d, par, s);
-    case 2: return fused_launch<T, VX, 2>(p, d, par, s);
+static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
+  switch (p.fs.waves) {
     case 4: return fused_launch<T, VX, 4>(p, d, par, s);
+    case 8: return fused_launch<T, VX, 8>(p, d, par, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -681,10 +720,10 @@ static hipError_t fused_dispatch_r(const chf_plan &p, const Dev &d, int par, hip
 template <typename T>
 static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
   switch (p.fs.vx) {
-    case 1: return fused_dispatch_r<T, 1>(p, d, par, s);
-    case 2: return fused_dispatch_r<T, 2>(p, d, par, s);
-    case 4: return fused_dispatch_r<T, 4>(p, d, par, s);
-    case 8: return fused_dispatch_r<T, 8>(p, d, par, s);
+    case 1: return fused_dispatch_w<T, 1>(p, d, par, s);
+    case 2: return fused_dispatch_w<T, 2>(p, d, par, s);
+    case 4: return fused_dispatch_w<T, 4>(p, d, par, s);
+    case 8: return fused_dispatch_w<T, 8>(p, d, par, s);
     default: return hipErrorInvalidValue;
   }
 }

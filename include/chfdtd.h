@@ -60,6 +60,7 @@ typedef enum {
   CHF_ESTATE = -8        /* call out of order (e.g. no workspace bound) */
 } chf_status;
 
+/* Field storage (arithmetic is FP32 in every case; BF16 and FP16 round to nearest even). */
 typedef enum { CHF_FP32 = 0, CHF_BF16 = 1, CHF_FP16 = 2 } chf_storage;
 typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
 typedef enum { CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2 } chf_kernel;

@@ -218,9 +218,9 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   const int npml = p->bnd.npml;
   size_t off_f = 0, off_i = 0;
   for (int u = 0; u < 3; u++) {
-    for (int t = 0; t < 6; t++) p->off_tabf[u][t] = off_f + (size_t)t * n3[u];
+    for (int t = 0; t < 10; t++) p->off_tabf[u][t] = off_f + (size_t)t * n3[u];
     for (int t = 0; t < 2; t++) p->off_tabi[u][t] = off_i + (size_t)t * n3[u];
-    off_f += 6 * (size_t)n3[u];
+    off_f += 10 * (size_t)n3[u];
     off_i += 2 * (size_t)n3[u];
   }
   p->tabf.assign(off_f, 0.0f);
@@ -231,9 +231,12 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     float *ae = &p->tabf[p->off_tabf[u][2]], *be = &p->tabf[p->off_tabf[u][3]];
     float *ah = &p->tabf[p->off_tabf[u][4]], *bh = &p->tabf[p->off_tabf[u][5]];
     int *se = &p->tabi[p->off_tabi[u][0]], *sh = &p->tabi[p->off_tabi[u][1]];
+    float *ike = &p->tabf[p->off_tabf[u][6]], *ade = &p->tabf[p->off_tabf[u][7]];
+    float *ikh = &p->tabf[p->off_tabf[u][8]], *adh = &p->tabf[p->off_tabf[u][9]];
     for (int i = 0; i < n; i++) {
       ce[i] = (float)(rse * p->cb / d3[u]);
       ch[i] = (float)(rhs * p->db / d3[u]);
+      ike[i] = ikh[i] = (float)(1.0 / d3[u]);
       be[i] = bh[i] = 1.0f;
       if (npml <= 0) continue;
       const double de = layer_depth((double)i, n, npml);
@@ -243,6 +246,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
         ce[i] = (float)(rse * p->cb / (d3[u] * g.kappa));
         ae[i] = (float)(rse * p->cb * g.a / d3[u]);
         be[i] = (float)g.b;
+        ike[i] = (float)(1.0 / (d3[u] * g.kappa));
+        ade[i] = (float)(g.a / d3[u]);
       }
       if (i <= n - 2) {
         const double dh = layer_depth(i + 0.5, n, npml);
@@ -252,6 +257,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
           ch[i] = (float)(rhs * p->db / (d3[u] * g.kappa));
           ah[i] = (float)(rhs * p->db * g.a / d3[u]);
           bh[i] = (float)g.b;
+          ikh[i] = (float)(1.0 / (d3[u] * g.kappa));
+          adh[i] = (float)(g.a / d3[u]);
         }
       }
     }
@@ -393,6 +400,10 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   D.n_obs = obs->n_obs;
   D.inv_se = 1.0 / p->scale_e;
   D.bc = p->bnd.kind;
+  D.a_cb = (float)p->cb;
+  D.a_db = (float)p->db;
+  D.a_ca = (float)p->ca;
+  D.a_cb_src = p->cb;
   const double vdt = v * G.dt;
   D.mur_kx = (float)((vdt - G.dx) / (vdt + G.dx));
   D.mur_ky = (float)((vdt - G.dy) / (vdt + G.dy));
@@ -444,6 +455,10 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
     A.bh = tf + p->off_tabf[u][5];
     A.se = ti + p->off_tabi[u][0];
     A.sh = ti + p->off_tabi[u][1];
+    A.ike = tf + p->off_tabf[u][6];
+    A.ade = tf + p->off_tabf[u][7];
+    A.ikh = tf + p->off_tabf[u][8];
+    A.adh = tf + p->off_tabf[u][9];
   }
   D.wr = (const double *)(ws + p->off_wr);
   D.q_bins = (const double *)(ws + p->off_q);
@@ -617,11 +632,21 @@ chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
 }
 
 chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev) {
-  (void)stream;
-  (void)dl_dw_dev;
-  (void)dl_dq_dev;
-  if (!p) return fail(CHF_EINVAL, "NULL plan");
-  return fail(CHF_EUNSUPPORTED, "adjoint not built yet");
+  if (!p || !dl_dq_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (p->bnd.kind == CHF_BC_MUR1) return fail(CHF_EUNSUPPORTED, "adjoint of the Mur boundary is not implemented");
+  if (p->storage != CHF_FP32) return fail(CHF_EUNSUPPORTED, "adjoint needs FP32 field storage");
+  hipStream_t s = (hipStream_t)stream;
+  // the workspace now holds the adjoint state: zero fields and psi, then run the transposed
+  // steps from the last to the first
+  hipError_t e = chf::launch_zero(*p, s);
+  if (e == hipSuccess) e = chf::launch_adjoint_init(*p, dl_dq_dev, s);
+  for (int n = p->grid.n_steps - 1; n >= 0 && e == hipSuccess; n--)
+    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  p->parity = 0;
+  p->n_done = 0;
+  return CHF_OK;
 }
 
 chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) {

@@ -23,6 +23,8 @@ struct AxisTab {
   const float *ae, *be;      // CPML psi recursion at integer positions (a prescaled)
   const float *ah, *bh;      // CPML psi recursion at half positions
   const int *se, *sh;        // slab slot (0..2*npml-1) or -1 outside the layer
+  // adjoint (physical units): 1/(delta kappa) and a/delta at integer and half positions
+  const float *ike, *ade, *ikh, *adh;
 };
 
 // Everything a kernel needs, passed by value.
@@ -56,6 +58,9 @@ struct Dev {
   // Mur
   float mur_kx, mur_ky, mur_kz;
   int bc;
+  // adjoint coefficients (physical units)
+  float a_cb, a_db, a_ca;
+  double a_cb_src;           // Cb (unscaled)
 };
 
 struct FusedShape {
@@ -84,7 +89,7 @@ struct chf_plan {
   std::vector<double> wr;      // radial weights
   std::vector<int> obs_idx;
   std::vector<double> obs_t;
-  size_t off_tabf[3][6], off_tabi[3][2];
+  size_t off_tabf[3][10], off_tabi[3][2];
   // workspace layout (byte offsets)
   uint64_t off_e[2][3], off_h[2][3], off_psi_e[3][2], off_psi_h[2][3][2];
   uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, off_tiles, ws_bytes;

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "chf_internal.h"
 
 namespace chf {
@@ -53,6 +55,16 @@ __device__ __forceinline__ void ld_row(const T *p, float (&o)[N], bool on) {
 template <typename T, int N>
 __device__ __forceinline__ void ld_at(const T *base, unsigned boff, float (&o)[N], bool on) {
   ld_row<T, N>(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff), o, on);
+}
+
+// The value a store of x followed by a load returns: the fused sweep feeds H to the E update
+// exactly as stored, as the split sweeps (which reload it) do.
+template <typename T, int N>
+__device__ __forceinline__ void as_stored(float (&o)[N]) {
+  if constexpr (!std::is_same<T, float>::value) {
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = to_f<T>(from_f<T>(o[v]));
+  }
 }
 
 template <typename T, int N>
@@ -231,6 +243,8 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
         hyp[v] = u ? h_cell(hyo[v], d1, chz, d2, chx[v], shz >= 0, p1, shx[v] >= 0, p2) : hyo[v];
       }
     }
+    as_stored<T, VX>(hxp);
+    as_stored<T, VX>(hyp);
   } else {
 #pragma unroll
     for (int v = 0; v < VX; v++) hxp[v] = hyp[v] = 0.f;
@@ -347,6 +361,12 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
         }
       }
     }
+
+    as_stored<T, VX>(hxm);
+    as_stored<T, VX>(hzm);
+    as_stored<T, VX>(hx);
+    as_stored<T, VX>(hy);
+    as_stored<T, VX>(hz);
 
     // ---- E^{n+1}(k) of row j
     const float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
@@ -729,9 +749,10 @@ static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, hipSt
 }
 
 template <typename T>
-static hipError_t step_t(const chf_plan &p, const Dev &d, int par, int step, const double *q,
+static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, const double *q,
                          double *w, int column, int ld, hipStream_t s) {
   hipError_t e;
+  const Dev &d = d_in;
   if (p.kernel == CHF_KERNEL_FUSED) {
     e = fused_dispatch<T>(p, d, par, s);
   } else {

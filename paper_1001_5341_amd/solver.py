@@ -195,3 +195,28 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class CherenkovFDTD(torch.autograd.Function):
+    """Waveforms as a differentiable function of the longitudinal profile bins.
+
+    forward:  w = A q  (the full run from zero fields; FP64 waveforms [n_obs, 3, n_steps])
+    backward: dL/dq = A^T dL/dw by the library's discrete adjoint (exact transpose of the
+              forward recurrence run backward in time).  The map is linear in q, so no forward
+              field state is needed for this gradient."""
+
+    @staticmethod
+    def forward(ctx, q_bins: torch.Tensor, plan: "Plan"):
+        ctx.plan = plan
+        q = q_bins.detach().to(device=plan.device, dtype=torch.float64).contiguous()
+        return plan.run(q_bins=q)
+
+    @staticmethod
+    def backward(ctx, grad_w: torch.Tensor):
+        dq = ctx.plan.adjoint(grad_w.to(torch.float64).contiguous())
+        ctx.plan.sync()
+        return dq, None
+
+
+def waveforms(q_bins: torch.Tensor, plan: "Plan") -> torch.Tensor:
+    return CherenkovFDTD.apply(q_bins, plan)

@@ -272,14 +272,16 @@ def batch_showers(seed: int = 4, count: int = 32, n_steps: int = 2000, n_obs: in
 
 
 def adjoint_problem(seed_target: int = 5, seed_start: int = 6, nx: int = 128, ny: int = 128,
-                    nz: int = 1024, n_steps: int = 3000, n_obs: int = 16, n_bins: int = 128):
+                    nz: int = 1024, n_steps: int = 3000, n_obs: int = 16, n_bins: int = 128,
+                    npml: int = 10):
     """Differentiation workload: 128 hat bins spanning the z extent, target profile q* from one
     seed and the evaluation point q = q* + perturbation from the next.  Returns
     (workload at q, q_target)."""
     d = 0.01
-    base = greisen_shower(seed_target, nx, ny, nz, n_steps, n_obs,
+    half = 0.5 * (min(nx, ny) - 1 - 2 * (npml + 3)) * d
+    base = greisen_shower(seed_target, nx, ny, nz, n_steps, n_obs, npml=npml,
                           zmax_frac=(0.35, 0.55), length_range=(0.1 * nz * d, 0.25 * nz * d),
-                          r_range=(0.3, 2.0), name=f"adjoint-{nx}x{ny}x{nz}")
+                          r_range=(min(0.3, 0.5 * half), 2.0), name=f"adjoint-{nx}x{ny}x{nz}")
     dz_bin = nz * d / n_bins
     zc = np.arange(n_bins) * dz_bin
     # sample the target profile at the bin centres

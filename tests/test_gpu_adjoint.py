@@ -1,0 +1,91 @@
+"""GPU discrete adjoint: against the FP64 oracle adjoint, the dot-product identity, and
+central differences of a quadratic waveform misfit (exact for a quadratic, up to rounding)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1001_5341_amd import _native, solver
+from paper_1001_5341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(msg):
+    print(f"\n[gpu-adjoint] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("bc", ["cpml", "pec"])
+def test_adjoint_matches_oracle(gpu, bc):
+    w = W.small_shower(seed=8, nx=40, ny=36, nz=64, n_steps=120, n_obs=4, bc=bc, npml=6)
+    banner(f"adjoint vs oracle {bc}")
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((w.n_obs, 3, w.n_steps))
+    ref = oracle.adjoint(w, g)
+    plan = solver.Plan(w)
+    got = plan.adjoint(torch.from_numpy(g).to(gpu)).cpu().numpy()
+    plan.sync()
+    plan.close()
+    nz = np.abs(ref) > 0
+    assert nz.sum() > 10
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("rel L2 of the gradient", err)
+    assert err < 1e-4, err
+
+
+def test_adjoint_dot_product_on_gpu(gpu):
+    w = W.small_shower(seed=9, nx=48, ny=40, nz=72, n_steps=150, n_obs=5, npml=6)
+    banner("dot product")
+    rng = np.random.default_rng(4)
+    dq = torch.from_numpy(rng.standard_normal(len(w.q_bins)) * 1e-11).to(gpu)
+    g = torch.from_numpy(rng.standard_normal((w.n_obs, 3, w.n_steps))).to(gpu)
+    plan = solver.Plan(w)
+    a_dq = plan.run(q_bins=dq)
+    lhs = float((g * a_dq).sum())
+    at_g = plan.adjoint(g)
+    plan.sync()
+    rhs = float((at_g * dq).sum())
+    plan.close()
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+
+
+def test_autograd_gradient_central_differences(gpu):
+    w, q_star = W.adjoint_problem(nx=48, ny=48, nz=96, n_steps=160, n_obs=4, n_bins=24, npml=6)
+    banner("autograd vs central differences")
+    plan = solver.Plan(w)
+    target = plan.run(q_bins=torch.from_numpy(q_star).to(gpu)).detach()
+    q = torch.from_numpy(w.q_bins.copy()).to(gpu).requires_grad_(True)
+    loss = ((solver.waveforms(q, plan) - target) ** 2).sum()
+    loss.backward()
+    grad = q.grad.detach().cpu().numpy()
+
+    def loss_at(qq):
+        return float(((plan.run(q_bins=torch.from_numpy(qq).to(gpu)) - target) ** 2).sum())
+
+    q0 = w.q_bins.copy()
+    h = 0.5 * np.abs(q0).max()
+    idx = np.argsort(-np.abs(grad))[:4]
+    for b in idx:
+        e = np.zeros_like(q0)
+        e[b] = h
+        fd = (loss_at(q0 + e) - loss_at(q0 - e)) / (2 * h)
+        assert abs(fd - grad[b]) <= 1e-3 * abs(grad[b]), (b, fd, grad[b])
+    plan.close()
+
+
+def test_adjoint_unsupported_cases(gpu):
+    w = W.gaussian_cube(seed=1, n=24, n_steps=5)
+    plan = solver.Plan(w)
+    with pytest.raises(_native.ChfError) as e:
+        plan.adjoint(torch.zeros((w.n_obs, 3, w.n_steps), dtype=torch.float64, device=gpu))
+    assert e.value.status == "CHF_EUNSUPPORTED"
+    plan.close()
+    ws = W.small_shower(seed=2, nx=30, ny=30, nz=40, n_steps=5, n_obs=2, npml=5)
+    plan = solver.Plan(ws, storage="bf16")
+    with pytest.raises(_native.ChfError) as e:
+        plan.adjoint(torch.zeros((ws.n_obs, 3, ws.n_steps), dtype=torch.float64, device=gpu))
+    assert e.value.status == "CHF_EUNSUPPORTED"
+    plan.close()

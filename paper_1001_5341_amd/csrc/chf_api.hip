@@ -157,26 +157,27 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   fs.n_tiles = fs.nty * fs.nzc;
   fs.n_blocks = (fs.n_tiles + 7) / 8 * 8;
   {
-    // fast rectangle: every row of the tile and the halo row below it lies in [fy0, fy1], every
-    // plane of the chunk and the plane below it in [fz0, fz1], where [f0, f1] are the nodes
-    // with no wall and no layer term (integer and half positions alike)
+    // fast rectangle: every row of the tile and the row below it lie in [fy0, fy1], every plane
+    // of the chunk in [fz0, fz1], where [f0, f1] are the nodes with no wall and no layer term
+    // (integer and half positions alike); all other tiles go to the split sweeps
     const int nl = bnd->kind == CHF_BC_CPML ? bnd->npml : 0;
     const int fy0 = std::max(1, nl), fy1 = G.ny - 2 - nl;
     const int fz0 = std::max(1, nl), fz1 = G.nz - 2 - nl;
-    fs.ty_lo = (fy0 + 1 + fs.waves - 1) / fs.waves;          // j0 - 1 >= fy0 (row below)
-    fs.ty_hi = (fy1 + 1) / fs.waves;                          // j0 + W - 1 <= fy1
-    fs.zc_lo = (fz0 + 1 + fs.zchunk - 1) / fs.zchunk;        // k0 - 1 >= fz0
-    fs.zc_hi = (fz1 + 1) / fs.zchunk;                         // k1 - 1 <= fz1
-    if (fs.ty_hi <= fs.ty_lo || fs.zc_hi <= fs.zc_lo) fs.ty_lo = fs.ty_hi = fs.zc_lo = fs.zc_hi = 0;
+    const int W = fs.waves, Z = fs.zchunk;
+    fs.ty_lo = (fy0 + 1 + W - 1) / W;          // j0 - 1 >= fy0
+    fs.ty_hi = (fy1 + 1) / W;                  // j0 + W - 1 <= fy1
+    fs.zc_lo = (fz0 + Z - 1) / Z;              // k0 >= fz0
+    fs.zc_hi = (fz1 + 1) / Z;                  // k1 - 1 <= fz1
+    if (kernel != CHF_KERNEL_FUSED || fs.ty_hi <= fs.ty_lo || fs.zc_hi <= fs.zc_lo)
+      fs.ty_lo = fs.ty_hi = fs.zc_lo = fs.zc_hi = 0;
     fs.n_fast = (fs.ty_hi - fs.ty_lo) * (fs.zc_hi - fs.zc_lo);
     fs.fast_blocks = (fs.n_fast + 7) / 8 * 8;
+    fs.n_layer = fs.layer_blocks = 0;
     for (int zc = 0; zc < fs.nzc; zc++)
       for (int ty = 0; ty < fs.nty; ty++) {
-        const bool fast = ty >= fs.ty_lo && ty < fs.ty_hi && zc >= fs.zc_lo && zc < fs.zc_hi;
-        if (!fast) {
-          p->slow_tiles.push_back(ty);
-          p->slow_tiles.push_back(zc);
-        }
+        if (ty >= fs.ty_lo && ty < fs.ty_hi && zc >= fs.zc_lo && zc < fs.zc_hi) continue;
+        p->slow_tiles.push_back(ty);
+        p->slow_tiles.push_back(zc);
       }
     fs.n_slow = (int)(p->slow_tiles.size() / 2);
     fs.slow_blocks = (fs.n_slow + 7) / 8 * 8;
@@ -371,6 +372,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   off += 256;
   p->off_tiles = off;
   off += align256(std::max<size_t>(p->slow_tiles.size(), 1) * sizeof(int));
+  p->off_ltiles = off;
+  off += align256(std::max<size_t>(p->layer_tiles.size(), 1) * sizeof(int));
   p->ws_bytes = off;
 
   // kernel parameter block (device pointers are filled at bind time)
@@ -415,6 +418,9 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
 void chf_plan_destroy(chf_plan *plan) {
   if (!plan) return;
   if (plan->graph) (void)hipGraphExecDestroy(plan->graph);
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+  if (plan->aux) (void)hipStreamDestroy(plan->aux);
   delete plan;
 }
 
@@ -466,6 +472,7 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
   D.obs_t = (const double *)(ws + p->off_ot);
   D.nan_flag = (int *)(ws + p->off_nan);
   D.slow_tiles = (const int *)(ws + p->off_tiles);
+  D.layer_tiles = (const int *)(ws + p->off_ltiles);
   struct Up {
     uint64_t off;
     const void *src;
@@ -478,6 +485,7 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
       {p->off_oidx, p->obs_idx.data(), p->obs_idx.size() * sizeof(int)},
       {p->off_ot, p->obs_t.data(), p->obs_t.size() * sizeof(double)},
       {p->off_tiles, p->slow_tiles.data(), p->slow_tiles.size() * sizeof(int)},
+      {p->off_ltiles, p->layer_tiles.data(), p->layer_tiles.size() * sizeof(int)},
   };
   for (const Up &u : ups) {
     if (!u.n) continue;
@@ -487,6 +495,13 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
   if (p->graph) {
     (void)hipGraphExecDestroy(p->graph);
     p->graph = nullptr;
+  }
+  if (!p->aux && p->fs.n_fast > 0 && p->fs.n_slow > 0) {
+    // default-priority side stream and fork/join events for the boundary H sweep
+    hipError_t e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "side stream");
   }
   return chf_plan_reset(p, stream);
 }

@@ -55,6 +55,7 @@ struct Dev {
   double inv_se;             // 1/scale_e for the gather
   int *nan_flag;
   const int *slow_tiles;     // [n_slow][2] (ty, zc) of the tiles taking the general path
+  const int *layer_tiles;    // [n_layer][2] (ty, zc) of the wall-free tiles touching a layer
   // Mur
   float mur_kx, mur_ky, mur_kz;
   int bc;
@@ -65,8 +66,9 @@ struct Dev {
 
 struct FusedShape {
   int vx, rows, waves, zchunk, nty, nzc, n_tiles, n_blocks;
-  // tiles clear of walls and y/z layers form the rectangle [ty_lo,ty_hi) x [zc_lo,zc_hi)
-  int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_slow, slow_blocks;
+  // tiles clear of walls and y/z layers form the rectangle [ty_lo,ty_hi) x [zc_lo,zc_hi); the
+  // other tiles are listed in two tables: clear of walls (layer) and touching a wall (slow)
+  int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_layer, layer_blocks, n_slow, slow_blocks;
 };
 
 }  // namespace chf
@@ -92,8 +94,8 @@ struct chf_plan {
   size_t off_tabf[3][10], off_tabi[3][2];
   // workspace layout (byte offsets)
   uint64_t off_e[2][3], off_h[2][3], off_psi_e[3][2], off_psi_h[2][3][2];
-  uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, off_tiles, ws_bytes;
-  std::vector<int> slow_tiles;
+  uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, off_tiles, off_ltiles, ws_bytes;
+  std::vector<int> slow_tiles, layer_tiles;
   uint64_t field_bytes, psi_bytes, psi_len[3];
   char *ws = nullptr;
   chf::Dev dev;
@@ -101,6 +103,9 @@ struct chf_plan {
   int n_done = 0;   // steps advanced since the last reset (source clock)
   double scale_e = 1.0, scale_h = 1.0;
   double ca, cb, db;
+  // side stream for the boundary H sweep, which runs beside the fused interior sweep
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // graph cache
   hipGraphExec_t graph = nullptr;
   const void *graph_w = nullptr, *graph_q = nullptr;

@@ -4,9 +4,9 @@
 // E^{n+1}); both levels live in HBM, so a single sweep can recompute tile halos from the
 // untouched input level without racing neighbouring workgroups.
 //
-// Per-cell arithmetic (FP32, explicit fmaf, built with -ffp-contract=off) lives in h_cell /
-// e_cell / pml_psi and is shared by every sweep variant, so the fused single sweep and the
-// split E/H sweeps produce identical bits.
+// Per-node arithmetic (FP32, explicit fmaf, built with -ffp-contract=off) lives in h_plain /
+// e_plain / add_layers / pml_psi and is applied in one fixed order by every sweep variant, so
+// the fused single sweep and the split E/H sweeps produce identical bits.
 //
 //   H (Faraday, forward differences of E):
 //     Hx += -chy*(Ez[j+1]-Ez[j]) + chz*(Ey[k+1]-Ey[k])   (- psi_y + psi_z in the CPML)
@@ -85,28 +85,28 @@ __device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on) {
 }
 
 // ------------------------------------------------------------- cell updates
+// Canonical order of one node update: the two central-difference terms (fmaf), then the CPML
+// terms of the node's derivative axes added in the fixed axis order x, y, z, each with its sign
+// folded in (s = +psi or -psi).  Every sweep variant applies exactly this sequence, so the
+// results agree bitwise whichever variant computed a node.
 __device__ __forceinline__ float pml_psi(float psi, float a, float b, float d) {
   return fmaf(b, psi, a * d);
 }
 
-// h' = h - c1 d1 + c2 d2 (- p1 + p2)
-__device__ __forceinline__ float h_cell(float h, float d1, float c1, float d2, float c2, bool q1,
-                                        float p1, bool q2, float p2) {
-  float t = fmaf(-c1, d1, h);
-  t = fmaf(c2, d2, t);
-  if (q1) t = t - p1;
-  if (q2) t = t + p2;
-  return t;
+// h' = h - c1 d1 + c2 d2, then the layer terms
+__device__ __forceinline__ float h_plain(float h, float d1, float c1, float d2, float c2) {
+  return fmaf(c2, d2, fmaf(-c1, d1, h));
 }
 
-// e' = ca e + c1 d1 - c2 d2 (+ p1 - p2)
-__device__ __forceinline__ float e_cell(float ca, float e, float d1, float c1, float d2, float c2,
-                                        bool q1, float p1, bool q2, float p2) {
-  float t = ca * e;
-  t = fmaf(c1, d1, t);
-  t = fmaf(-c2, d2, t);
-  if (q1) t = t + p1;
-  if (q2) t = t - p2;
+// e' = ca e + c1 d1 - c2 d2, then the layer terms
+__device__ __forceinline__ float e_plain(float ca, float e, float d1, float c1, float d2, float c2) {
+  return fmaf(-c2, d2, fmaf(c1, d1, ca * e));
+}
+
+__device__ __forceinline__ float add_layers(float t, bool qx, float sx, bool qy, float sy, bool qz, float sz) {
+  if (qx) t = t + sx;
+  if (qy) t = t + sy;
+  if (qz) t = t + sz;
   return t;
 }
 
@@ -125,6 +125,18 @@ __device__ __forceinline__ float psi_step(const Dev &d, const float *in, float *
   return p;
 }
 
+// psi of an H node term along axis u at position pos (H-update tables, half positions)
+__device__ __forceinline__ float psi_h(const Dev &d, const float *in, float *out, bool wr, int u, int pos,
+                                       int i, int j, int k, int s, float dd) {
+  return psi_step(d, in, out, wr, u, i, j, k, s, d.ax[u].ah[pos], d.ax[u].bh[pos], dd);
+}
+
+// psi of an E node term along axis u (E-update tables, integer positions), updated in place
+__device__ __forceinline__ float psi_e(const Dev &d, float *p, int u, int pos, int i, int j, int k, int s,
+                                       float dd) {
+  return psi_step(d, p, p, true, u, i, j, k, s, d.ax[u].ae[pos], d.ax[u].be[pos], dd);
+}
+
 // --------------------------------------------------------------- fused sweep
 // One wave owns one y row of the full x extent (64 lanes x VX cells, nx <= 64 VX) and marches
 // a z chunk; a workgroup holds W waves over W consecutive rows.  Waves are independent (no LDS,
@@ -134,28 +146,21 @@ __device__ __forceinline__ float psi_step(const Dev &d, const float *in, float *
 // in-plane offsets 32-bit.  Workgroups are ordered so that consecutive logical tiles
 // (neighbours in y, then in z) land on the same XCD and share its L2.
 //
-// FAST: the launch covers only tiles whose rows (and the row below) are clear of the y walls
-// and y layers and whose planes (and the plane below) are clear of the z walls and z layers,
-// so no y/z masks or psi terms are compiled in; lanes holding an x wall, x padding or an
-// x-layer node patch their results, applying the psi terms last exactly as h_cell / e_cell
-// do.  Otherwise tiles come from a table and every node takes the general path.
-template <typename T, int VX, int W, bool FAST>
-__global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const int *tiles, int par) {
+// The launch covers the rectangle of tiles whose rows and planes (and the row and plane below
+// them) lie clear of the walls and of the y/z layers; the other tiles go to the split sweeps
+// (k_split_h / k_split_e over a tile table).  Every node here is updated except at the x walls:
+// nodes take the unmasked update, lanes holding x-layer nodes add the x CPML term, and x-wall /
+// padding nodes keep their old values -- the canonical sequence of the general path.
+template <typename T, int VX, int W>
+__global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, int par) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int b = blockIdx.x;
   const int logical = (b & 7) * (gridDim.x >> 3) + (b >> 3);
-  int ty, zc;
-  if constexpr (FAST) {
-    if (logical >= fs.n_fast) return;
-    const int fw = fs.ty_hi - fs.ty_lo;
-    ty = fs.ty_lo + logical % fw;
-    zc = fs.zc_lo + logical / fw;
-  } else {
-    if (logical >= fs.n_slow) return;
-    ty = tiles[2 * logical];
-    zc = tiles[2 * logical + 1];
-  }
+  if (logical >= fs.n_fast) return;
+  const int fw = fs.ty_hi - fs.ty_lo;
+  const int ty = fs.ty_lo + logical % fw;
+  const int zc = fs.zc_lo + logical / fw;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int j = ty * W + wave;
   if (j >= ny) return;
@@ -172,6 +177,12 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
   const T *Hi0 = (const T *)d.h[par][0], *Hi1 = (const T *)d.h[par][1], *Hi2 = (const T *)d.h[par][2];
   T *Eo0 = (T *)d.e[par ^ 1][0], *Eo1 = (T *)d.e[par ^ 1][1], *Eo2 = (T *)d.e[par ^ 1][2];
   T *Ho0 = (T *)d.h[par ^ 1][0], *Ho1 = (T *)d.h[par ^ 1][1], *Ho2 = (T *)d.h[par ^ 1][2];
+  float *const phi[3][2] = {{d.psi_h[par][0][0], d.psi_h[par][0][1]},
+                            {d.psi_h[par][1][0], d.psi_h[par][1][1]},
+                            {d.psi_h[par][2][0], d.psi_h[par][2][1]}};
+  float *const pho[3][2] = {{d.psi_h[par ^ 1][0][0], d.psi_h[par ^ 1][0][1]},
+                            {d.psi_h[par ^ 1][1][0], d.psi_h[par ^ 1][1][1]},
+                            {d.psi_h[par ^ 1][2][0], d.psi_h[par ^ 1][2][1]}};
 
   float chx[VX], cex[VX];
   int shx[VX], sex[VX];
@@ -189,13 +200,6 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
   const float chy = d.ax[1].ch[j], cey = d.ax[1].ce[j], chym = d.ax[1].ch[jm];
   const int shy = pml ? d.ax[1].sh[j] : -1, sey = pml ? d.ax[1].se[j] : -1;
   const int shym = pml ? d.ax[1].sh[jm] : -1;
-  const bool ylay = shy >= 0 || sey >= 0 || shym >= 0;
-  float *const phi[3][2] = {{d.psi_h[par][0][0], d.psi_h[par][0][1]},
-                            {d.psi_h[par][1][0], d.psi_h[par][1][1]},
-                            {d.psi_h[par][2][0], d.psi_h[par][2][1]}};
-  float *const pho[3][2] = {{d.psi_h[par ^ 1][0][0], d.psi_h[par ^ 1][0][1]},
-                            {d.psi_h[par ^ 1][1][0], d.psi_h[par ^ 1][1][1]},
-                            {d.psi_h[par ^ 1][2][0], d.psi_h[par ^ 1][2][1]}};
 
   // E(k) of rows j-1 (m), j (c), j+1 (p; Ex and Ez only)
   float exm[VX], eym[VX], ezm[VX], exc[VX], eyc[VX], ezc[VX], exp_[VX], ezp[VX];
@@ -229,18 +233,18 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
       {
         const float d1 = ezu[v] - ez_[v], d2 = eyc[v] - ey_[v];
         const bool u = i < nx && j <= ny - 2 && km <= nz - 2;
-        float p1 = 0.f, p2 = 0.f;
-        if (shy >= 0 && u) p1 = psi_step(d, phi[1][0], nullptr, false, 1, i, j, km, shy, d.ax[1].ah[j], d.ax[1].bh[j], d1);
-        if (shz >= 0 && u) p2 = psi_step(d, phi[2][0], nullptr, false, 2, i, j, km, shz, d.ax[2].ah[km], d.ax[2].bh[km], d2);
-        hxp[v] = u ? h_cell(hxo[v], d1, chy, d2, chz, shy >= 0, p1, shz >= 0, p2) : hxo[v];
+        float sy = 0.f, sz = 0.f;
+        if (shy >= 0 && u) sy = -psi_h(d, phi[1][0], nullptr, false, 1, j, i, j, km, shy, d1);
+        if (shz >= 0 && u) sz = psi_h(d, phi[2][0], nullptr, false, 2, km, i, j, km, shz, d2);
+        hxp[v] = u ? add_layers(h_plain(hxo[v], d1, chy, d2, chz), false, 0.f, shy >= 0, sy, shz >= 0, sz) : hxo[v];
       }
       {
         const float d1 = exc[v] - ex_[v], d2 = ezx - ez_[v];
         const bool u = i <= nx - 2 && km <= nz - 2;
-        float p1 = 0.f, p2 = 0.f;
-        if (shz >= 0 && u) p1 = psi_step(d, phi[2][1], nullptr, false, 2, i, j, km, shz, d.ax[2].ah[km], d.ax[2].bh[km], d1);
-        if (shx[v] >= 0 && u) p2 = psi_step(d, phi[0][0], nullptr, false, 0, i, j, km, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], d2);
-        hyp[v] = u ? h_cell(hyo[v], d1, chz, d2, chx[v], shz >= 0, p1, shx[v] >= 0, p2) : hyo[v];
+        float sx = 0.f, sz = 0.f;
+        if (shx[v] >= 0 && u) sx = psi_h(d, phi[0][0], nullptr, false, 0, i, i, j, km, shx[v], d2);
+        if (shz >= 0 && u) sz = -psi_h(d, phi[2][1], nullptr, false, 2, km, i, j, km, shz, d1);
+        hyp[v] = u ? add_layers(h_plain(hyo[v], d1, chz, d2, chx[v]), shx[v] >= 0, sx, false, 0.f, shz >= 0, sz) : hyo[v];
       }
     }
     as_stored<T, VX>(hxp);
@@ -275,93 +279,39 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
     const float eymn = __shfl_down(eym[0], 1);
     const float eyn = __shfl_down(eyc[0], 1), ezn = __shfl_down(ezc[0], 1);
     float hxm[VX], hzm[VX], hx[VX], hy[VX], hz[VX];
-    bool fast;
-    if constexpr (FAST) {
-      fast = true;
-    } else {
-      fast = j >= 2 && j <= ny - 2 && !ylay && k >= 1 && k <= nz - 2 && shz < 0 && sez < 0;
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+      const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
+      const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
+      hxm[v] = h_plain(hxm0[v], ezc[v] - ezm[v], chym, nym[v] - eym[v], chz);
+      hzm[v] = h_plain(hzm0[v], eymx - eym[v], chx[v], exc[v] - exm[v], chym);
+      hx[v] = h_plain(hx0[v], ezp[v] - ezc[v], chy, nyc[v] - eyc[v], chz);
+      hy[v] = h_plain(hy0[v], nxc[v] - exc[v], chz, ezx - ezc[v], chx[v]);
+      hz[v] = h_plain(hz0[v], eyx - eyc[v], chx[v], exp_[v] - exc[v], chy);
     }
-    if (fast) {
-#pragma unroll
-      for (int v = 0; v < VX; v++) {
-        const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
-        const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
-        const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
-        hxm[v] = fmaf(chz, nym[v] - eym[v], fmaf(-chym, ezc[v] - ezm[v], hxm0[v]));
-        hzm[v] = fmaf(chym, exc[v] - exm[v], fmaf(-chx[v], eymx - eym[v], hzm0[v]));
-        hx[v] = fmaf(chz, nyc[v] - eyc[v], fmaf(-chy, ezp[v] - ezc[v], hx0[v]));
-        hy[v] = fmaf(chx[v], ezx - ezc[v], fmaf(-chz, nxc[v] - exc[v], hy0[v]));
-        hz[v] = fmaf(chy, exp_[v] - exc[v], fmaf(-chx[v], eyx - eyc[v], hz0[v]));
-      }
-      if (xfix) {
-#pragma unroll
-        for (int v = 0; v < VX; v++) {
-          const int i = ib + v;
-          if (i >= nx - 1) {
-            hzm[v] = hzm0[v];
-            hy[v] = hy0[v];
-            hz[v] = hz0[v];
-            if (i >= nx) {
-              hxm[v] = hxm0[v];
-              hx[v] = hx0[v];
-            }
-          } else if (shx[v] >= 0) {
-            const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
-            const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
-            const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
-            const float ah = d.ax[0].ah[i], bh = d.ax[0].bh[i];
-            hzm[v] = hzm[v] - psi_step(d, phi[0][1], nullptr, false, 0, i, j - 1, k, shx[v], ah, bh, eymx - eym[v]);
-            hy[v] = hy[v] + psi_step(d, phi[0][0], pho[0][0], true, 0, i, j, k, shx[v], ah, bh, ezx - ezc[v]);
-            hz[v] = hz[v] - psi_step(d, phi[0][1], pho[0][1], true, 0, i, j, k, shx[v], ah, bh, eyx - eyc[v]);
-          }
-        }
-      }
-    } else if constexpr (!FAST) {
-      const bool zl = shz >= 0;
+    if (xfix) {  // x walls and padding keep old values; x-layer terms
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         const int i = ib + v;
-        const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
-        const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
-        const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
-        const bool xl = shx[v] >= 0;
-        // row j-1: Hx, Hz (recomputed, not stored)
-        {
-          const int jj = j - 1;
-          const bool ux = jj >= 0 && i < nx && jj <= ny - 2 && k <= nz - 2;
-          const bool uz = jj >= 0 && i <= nx - 2 && jj <= ny - 2;
-          const float dx1 = ezc[v] - ezm[v], dx2 = nym[v] - eym[v];
-          const float dz1 = eymx - eym[v], dz2 = exc[v] - exm[v];
-          float p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
-          if (shym >= 0 && ux) p1 = psi_step(d, phi[1][0], nullptr, false, 1, i, jj, k, shym, d.ax[1].ah[jj], d.ax[1].bh[jj], dx1);
-          if (zl && ux) p2 = psi_step(d, phi[2][0], nullptr, false, 2, i, jj, k, shz, d.ax[2].ah[k], d.ax[2].bh[k], dx2);
-          if (xl && uz) p3 = psi_step(d, phi[0][1], nullptr, false, 0, i, jj, k, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], dz1);
-          if (shym >= 0 && uz) p4 = psi_step(d, phi[1][1], nullptr, false, 1, i, jj, k, shym, d.ax[1].ah[jj], d.ax[1].bh[jj], dz2);
-          hxm[v] = ux ? h_cell(hxm0[v], dx1, chym, dx2, chz, shym >= 0, p1, zl, p2) : hxm0[v];
-          hzm[v] = uz ? h_cell(hzm0[v], dz1, chx[v], dz2, chym, xl, p3, shym >= 0, p4) : hzm0[v];
-        }
-        // row j: Hx, Hy, Hz
-        {
-          const bool ux = i < nx && j <= ny - 2 && k <= nz - 2;
-          const bool uy = i <= nx - 2 && k <= nz - 2;
-          const bool uz = i <= nx - 2 && j <= ny - 2;
-          const float dx1 = ezp[v] - ezc[v], dx2 = nyc[v] - eyc[v];
-          const float dy1 = nxc[v] - exc[v], dy2 = ezx - ezc[v];
-          const float dz1 = eyx - eyc[v], dz2 = exp_[v] - exc[v];
-          float px1 = 0.f, px2 = 0.f, py1 = 0.f, py2 = 0.f, pz1 = 0.f, pz2 = 0.f;
-          if (shy >= 0 && ux) px1 = psi_step(d, phi[1][0], pho[1][0], true, 1, i, j, k, shy, d.ax[1].ah[j], d.ax[1].bh[j], dx1);
-          if (zl && ux) px2 = psi_step(d, phi[2][0], pho[2][0], true, 2, i, j, k, shz, d.ax[2].ah[k], d.ax[2].bh[k], dx2);
-          if (zl && uy) py1 = psi_step(d, phi[2][1], pho[2][1], true, 2, i, j, k, shz, d.ax[2].ah[k], d.ax[2].bh[k], dy1);
-          if (xl && uy) py2 = psi_step(d, phi[0][0], pho[0][0], true, 0, i, j, k, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], dy2);
-          if (xl && uz) pz1 = psi_step(d, phi[0][1], pho[0][1], true, 0, i, j, k, shx[v], d.ax[0].ah[i], d.ax[0].bh[i], dz1);
-          if (shy >= 0 && uz) pz2 = psi_step(d, phi[1][1], pho[1][1], true, 1, i, j, k, shy, d.ax[1].ah[j], d.ax[1].bh[j], dz2);
-          hx[v] = ux ? h_cell(hx0[v], dx1, chy, dx2, chz, shy >= 0, px1, zl, px2) : hx0[v];
-          hy[v] = uy ? h_cell(hy0[v], dy1, chz, dy2, chx[v], zl, py1, xl, py2) : hy0[v];
-          hz[v] = uz ? h_cell(hz0[v], dz1, chx[v], dz2, chy, xl, pz1, shy >= 0, pz2) : hz0[v];
+        if (i >= nx - 1) {
+          hzm[v] = hzm0[v];
+          hy[v] = hy0[v];
+          hz[v] = hz0[v];
+          if (i >= nx) {
+            hxm[v] = hxm0[v];
+            hx[v] = hx0[v];
+          }
+        } else if (shx[v] >= 0) {
+          const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+          const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
+          const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
+          hzm[v] = hzm[v] + -psi_h(d, phi[0][1], nullptr, false, 0, i, i, j - 1, k, shx[v], eymx - eym[v]);
+          hy[v] = hy[v] + psi_h(d, phi[0][0], pho[0][0], true, 0, i, i, j, k, shx[v], ezx - ezc[v]);
+          hz[v] = hz[v] + -psi_h(d, phi[0][1], pho[0][1], true, 0, i, i, j, k, shx[v], eyx - eyc[v]);
         }
       }
     }
-
     as_stored<T, VX>(hxm);
     as_stored<T, VX>(hzm);
     as_stored<T, VX>(hx);
@@ -371,57 +321,31 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
     // ---- E^{n+1}(k) of row j
     const float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
     float oex[VX], oey[VX], oez[VX];
-    if (fast) {
 #pragma unroll
-      for (int v = 0; v < VX; v++) {
-        const float hzw = (v > 0) ? hz[v - 1] : hzw0;
-        const float hyw = (v > 0) ? hy[v - 1] : hyw0;
-        oex[v] = fmaf(-cez, hy[v] - hyp[v], fmaf(cey, hz[v] - hzm[v], d.ca * exc[v]));
-        oey[v] = fmaf(-cex[v], hz[v] - hzw, fmaf(cez, hx[v] - hxp[v], d.ca * eyc[v]));
-        oez[v] = fmaf(-cey, hx[v] - hxm[v], fmaf(cex[v], hy[v] - hyw, d.ca * ezc[v]));
-      }
-      if (xfix) {
-#pragma unroll
-        for (int v = 0; v < VX; v++) {
-          const int i = ib + v;
-          if (i >= nx - 1) {
-            oex[v] = exc[v];
-            oey[v] = eyc[v];
-            oez[v] = ezc[v];
-          } else if (i == 0) {
-            oey[v] = eyc[v];
-            oez[v] = ezc[v];
-          } else if (sex[v] >= 0) {
-            const float hzw = (v > 0) ? hz[v - 1] : hzw0;
-            const float hyw = (v > 0) ? hy[v - 1] : hyw0;
-            const float ae = d.ax[0].ae[i], be = d.ax[0].be[i];
-            oey[v] = oey[v] - psi_step(d, d.psi_e[0][0], d.psi_e[0][0], true, 0, i, j, k, sex[v], ae, be, hz[v] - hzw);
-            oez[v] = oez[v] + psi_step(d, d.psi_e[0][1], d.psi_e[0][1], true, 0, i, j, k, sex[v], ae, be, hy[v] - hyw);
-          }
-        }
-      }
-    } else if constexpr (!FAST) {
+    for (int v = 0; v < VX; v++) {
+      const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+      const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+      oex[v] = e_plain(d.ca, exc[v], hz[v] - hzm[v], cey, hy[v] - hyp[v], cez);
+      oey[v] = e_plain(d.ca, eyc[v], hx[v] - hxp[v], cez, hz[v] - hzw, cex[v]);
+      oez[v] = e_plain(d.ca, ezc[v], hy[v] - hyw, cex[v], hx[v] - hxm[v], cey);
+    }
+    if (xfix) {
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         const int i = ib + v;
-        const float hzw = (v > 0) ? hz[v - 1] : hzw0;
-        const float hyw = (v > 0) ? hy[v - 1] : hyw0;
-        const float ax1 = hz[v] - hzm[v], ax2 = hy[v] - hyp[v];  // Ex: y, z
-        const float ay1 = hx[v] - hxp[v], ay2 = hz[v] - hzw;     // Ey: z, x
-        const float az1 = hy[v] - hyw, az2 = hx[v] - hxm[v];     // Ez: x, y
-        const bool wx = i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-        const bool wy = i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-        const bool wz = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2;
-        float qx1 = 0.f, qx2 = 0.f, qy1 = 0.f, qy2 = 0.f, qz1 = 0.f, qz2 = 0.f;
-        if (sey >= 0 && wx) qx1 = psi_step(d, d.psi_e[1][0], d.psi_e[1][0], true, 1, i, j, k, sey, d.ax[1].ae[j], d.ax[1].be[j], ax1);
-        if (sey >= 0 && wz) qz2 = psi_step(d, d.psi_e[1][1], d.psi_e[1][1], true, 1, i, j, k, sey, d.ax[1].ae[j], d.ax[1].be[j], az2);
-        if (sez >= 0 && wx) qx2 = psi_step(d, d.psi_e[2][0], d.psi_e[2][0], true, 2, i, j, k, sez, d.ax[2].ae[k], d.ax[2].be[k], ax2);
-        if (sez >= 0 && wy) qy1 = psi_step(d, d.psi_e[2][1], d.psi_e[2][1], true, 2, i, j, k, sez, d.ax[2].ae[k], d.ax[2].be[k], ay1);
-        if (sex[v] >= 0 && wy) qy2 = psi_step(d, d.psi_e[0][0], d.psi_e[0][0], true, 0, i, j, k, sex[v], d.ax[0].ae[i], d.ax[0].be[i], ay2);
-        if (sex[v] >= 0 && wz) qz1 = psi_step(d, d.psi_e[0][1], d.psi_e[0][1], true, 0, i, j, k, sex[v], d.ax[0].ae[i], d.ax[0].be[i], az1);
-        oex[v] = wx ? e_cell(d.ca, exc[v], ax1, cey, ax2, cez, sey >= 0, qx1, sez >= 0, qx2) : exc[v];
-        oey[v] = wy ? e_cell(d.ca, eyc[v], ay1, cez, ay2, cex[v], sez >= 0, qy1, sex[v] >= 0, qy2) : eyc[v];
-        oez[v] = wz ? e_cell(d.ca, ezc[v], az1, cex[v], az2, cey, sex[v] >= 0, qz1, sey >= 0, qz2) : ezc[v];
+        if (i >= nx - 1) {
+          oex[v] = exc[v];
+          oey[v] = eyc[v];
+          oez[v] = ezc[v];
+        } else if (i == 0) {
+          oey[v] = eyc[v];
+          oez[v] = ezc[v];
+        } else if (sex[v] >= 0) {
+          const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+          const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+          oey[v] = oey[v] + -psi_e(d, d.psi_e[0][0], 0, i, i, j, k, sex[v], hz[v] - hzw);
+          oez[v] = oez[v] + psi_e(d, d.psi_e[0][1], 0, i, i, j, k, sex[v], hy[v] - hyw);
+        }
       }
     }
     st_at<T, VX>(Ho0 + pk, o0, hx, on);
@@ -442,24 +366,47 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, const in
 }
 
 // --------------------------------------------------------------- split sweeps
-// General-size fallback: one thread per (i, j) column over a z chunk, H then E in two
-// launches.  Same per-cell arithmetic as the fused sweep.
-constexpr int kSplitZ = 16;
+// Tiles outside the fused rectangle (walls and CPML layers), or every tile when the split
+// sweeps are selected: a workgroup of 64 x W threads covers 64 nodes of the W rows of one tile
+// and marches its z chunk, one thread per (i, j) column; H then E in two launches.  Same
+// canonical per-node arithmetic as the fused sweep.
+struct SplitTile {
+  int i, j, k0, k1;
+};
+
+__device__ __forceinline__ bool split_tile(const Dev &d, const FusedShape &fs, const int *tiles, int n_tiles,
+                                           SplitTile &t) {
+  const int nxb = (d.nx + 63) / 64;
+  const int tile = blockIdx.x / nxb;
+  if (tile >= n_tiles) return false;
+  const int ty = tiles[2 * tile], zc = tiles[2 * tile + 1];
+  t.i = (blockIdx.x % nxb) * 64 + (threadIdx.x & 63);
+  t.j = ty * fs.waves + (threadIdx.x >> 6);
+  t.k0 = zc * fs.zchunk;
+  t.k1 = min(t.k0 + fs.zchunk, d.nz);
+  return t.i < d.nx && t.j < d.ny;
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_split_h(Dev d, int par) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= d.nx || j >= d.ny) return;
-  const int k0 = blockIdx.z * kSplitZ, k1 = min(k0 + kSplitZ, d.nz);
+__global__ void __launch_bounds__(512) k_split_h(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
+  SplitTile st;
+  if (!split_tile(d, fs, tiles, n_tiles, st)) return;
+  const int i = st.i, j = st.j, k0 = st.k0, k1 = st.k1;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const T *E0 = (const T *)d.e[par][0], *E1 = (const T *)d.e[par][1], *E2 = (const T *)d.e[par][2];
   const T *Hi0 = (const T *)d.h[par][0], *Hi1 = (const T *)d.h[par][1], *Hi2 = (const T *)d.h[par][2];
   T *Ho0 = (T *)d.h[par ^ 1][0], *Ho1 = (T *)d.h[par ^ 1][1], *Ho2 = (T *)d.h[par ^ 1][2];
+  float *pi_[3][2], *po_[3][2];
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) {
+      pi_[u][t] = d.psi_h[par][u][t];
+      po_[u][t] = d.psi_h[par ^ 1][u][t];
+    }
   const bool pml = d.np2 > 0;
   const int ip = min(i + 1, nx - 1), jp = min(j + 1, ny - 1);
   const float chx = d.ax[0].ch[i], chy = d.ax[1].ch[j];
   const int shx = pml ? d.ax[0].sh[i] : -1, shy = pml ? d.ax[1].sh[j] : -1;
+  const bool xl = shx >= 0, yl = shy >= 0;
   for (int k = k0; k < k1; k++) {
     const int kp = min(k + 1, nz - 1);
     const long long c = (long long)k * d.plane + (long long)j * d.pitch + i;
@@ -468,52 +415,43 @@ __global__ void __launch_bounds__(256) k_split_h(Dev d, int par) {
     const long long czp = (long long)kp * d.plane + (long long)j * d.pitch + i;
     const float chz = d.ax[2].ch[k];
     const int shz = pml ? d.ax[2].sh[k] : -1;
-    float ex = to_f(E0[c]), ey = to_f(E1[c]), ez = to_f(E2[c]);
-    {
-      float d1 = to_f(E2[cyp]) - ez, d2 = to_f(E1[czp]) - ey;
-      bool u = j <= ny - 2 && k <= nz - 2;
-      bool q1 = shy >= 0, q2 = shz >= 0;
-      float p1 = 0.f, p2 = 0.f;
-      if (q1 && u) p1 = psi_step(d, d.psi_h[par][1][0], d.psi_h[par ^ 1][1][0], true, 1, i, j, k, shy,
-                                 d.ax[1].ah[j], d.ax[1].bh[j], d1);
-      if (q2 && u) p2 = psi_step(d, d.psi_h[par][2][0], d.psi_h[par ^ 1][2][0], true, 2, i, j, k, shz,
-                                 d.ax[2].ah[k], d.ax[2].bh[k], d2);
-      float h = to_f(Hi0[c]);
-      Ho0[c] = from_f<T>(u ? h_cell(h, d1, chy, d2, chz, q1, p1, q2, p2) : h);
+    const bool zl = shz >= 0;
+    const float ex = to_f(E0[c]), ey = to_f(E1[c]), ez = to_f(E2[c]);
+    {  // Hx: y, z
+      const float d1 = to_f(E2[cyp]) - ez, d2 = to_f(E1[czp]) - ey;
+      const bool u = j <= ny - 2 && k <= nz - 2;
+      float sy = 0.f, sz = 0.f;
+      if (yl && u) sy = -psi_h(d, pi_[1][0], po_[1][0], true, 1, j, i, j, k, shy, d1);
+      if (zl && u) sz = psi_h(d, pi_[2][0], po_[2][0], true, 2, k, i, j, k, shz, d2);
+      const float h = to_f(Hi0[c]);
+      Ho0[c] = from_f<T>(u ? add_layers(h_plain(h, d1, chy, d2, chz), false, 0.f, yl, sy, zl, sz) : h);
     }
-    {
-      float d1 = to_f(E0[czp]) - ex, d2 = to_f(E2[cxp]) - ez;
-      bool u = i <= nx - 2 && k <= nz - 2;
-      bool q1 = shz >= 0, q2 = shx >= 0;
-      float p1 = 0.f, p2 = 0.f;
-      if (q1 && u) p1 = psi_step(d, d.psi_h[par][2][1], d.psi_h[par ^ 1][2][1], true, 2, i, j, k, shz,
-                                 d.ax[2].ah[k], d.ax[2].bh[k], d1);
-      if (q2 && u) p2 = psi_step(d, d.psi_h[par][0][0], d.psi_h[par ^ 1][0][0], true, 0, i, j, k, shx,
-                                 d.ax[0].ah[i], d.ax[0].bh[i], d2);
-      float h = to_f(Hi1[c]);
-      Ho1[c] = from_f<T>(u ? h_cell(h, d1, chz, d2, chx, q1, p1, q2, p2) : h);
+    {  // Hy: z, x
+      const float d1 = to_f(E0[czp]) - ex, d2 = to_f(E2[cxp]) - ez;
+      const bool u = i <= nx - 2 && k <= nz - 2;
+      float sx = 0.f, sz = 0.f;
+      if (xl && u) sx = psi_h(d, pi_[0][0], po_[0][0], true, 0, i, i, j, k, shx, d2);
+      if (zl && u) sz = -psi_h(d, pi_[2][1], po_[2][1], true, 2, k, i, j, k, shz, d1);
+      const float h = to_f(Hi1[c]);
+      Ho1[c] = from_f<T>(u ? add_layers(h_plain(h, d1, chz, d2, chx), xl, sx, false, 0.f, zl, sz) : h);
     }
-    {
-      float d1 = to_f(E1[cxp]) - ey, d2 = to_f(E0[cyp]) - ex;
-      bool u = i <= nx - 2 && j <= ny - 2;
-      bool q1 = shx >= 0, q2 = shy >= 0;
-      float p1 = 0.f, p2 = 0.f;
-      if (q1 && u) p1 = psi_step(d, d.psi_h[par][0][1], d.psi_h[par ^ 1][0][1], true, 0, i, j, k, shx,
-                                 d.ax[0].ah[i], d.ax[0].bh[i], d1);
-      if (q2 && u) p2 = psi_step(d, d.psi_h[par][1][1], d.psi_h[par ^ 1][1][1], true, 1, i, j, k, shy,
-                                 d.ax[1].ah[j], d.ax[1].bh[j], d2);
-      float h = to_f(Hi2[c]);
-      Ho2[c] = from_f<T>(u ? h_cell(h, d1, chx, d2, chy, q1, p1, q2, p2) : h);
+    {  // Hz: x, y
+      const float d1 = to_f(E1[cxp]) - ey, d2 = to_f(E0[cyp]) - ex;
+      const bool u = i <= nx - 2 && j <= ny - 2;
+      float sx = 0.f, sy = 0.f;
+      if (xl && u) sx = -psi_h(d, pi_[0][1], po_[0][1], true, 0, i, i, j, k, shx, d1);
+      if (yl && u) sy = psi_h(d, pi_[1][1], po_[1][1], true, 1, j, i, j, k, shy, d2);
+      const float h = to_f(Hi2[c]);
+      Ho2[c] = from_f<T>(u ? add_layers(h_plain(h, d1, chx, d2, chy), xl, sx, yl, sy, false, 0.f) : h);
     }
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_split_e(Dev d, int par) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= d.nx || j >= d.ny) return;
-  const int k0 = blockIdx.z * kSplitZ, k1 = min(k0 + kSplitZ, d.nz);
+__global__ void __launch_bounds__(512) k_split_e(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
+  SplitTile st;
+  if (!split_tile(d, fs, tiles, n_tiles, st)) return;
+  const int i = st.i, j = st.j, k0 = st.k0, k1 = st.k1;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const T *Ei0 = (const T *)d.e[par][0], *Ei1 = (const T *)d.e[par][1], *Ei2 = (const T *)d.e[par][2];
   const T *H0 = (const T *)d.h[par ^ 1][0], *H1 = (const T *)d.h[par ^ 1][1], *H2 = (const T *)d.h[par ^ 1][2];
@@ -522,6 +460,7 @@ __global__ void __launch_bounds__(256) k_split_e(Dev d, int par) {
   const int im = max(i - 1, 0), jm = max(j - 1, 0);
   const float cex = d.ax[0].ce[i], cey = d.ax[1].ce[j];
   const int sex = pml ? d.ax[0].se[i] : -1, sey = pml ? d.ax[1].se[j] : -1;
+  const bool xl = sex >= 0, yl = sey >= 0;
   for (int k = k0; k < k1; k++) {
     const int km = max(k - 1, 0);
     const long long c = (long long)k * d.plane + (long long)j * d.pitch + i;
@@ -530,42 +469,34 @@ __global__ void __launch_bounds__(256) k_split_e(Dev d, int par) {
     const long long czm = (long long)km * d.plane + (long long)j * d.pitch + i;
     const float cez = d.ax[2].ce[k];
     const int sez = pml ? d.ax[2].se[k] : -1;
-    float hx = to_f(H0[c]), hy = to_f(H1[c]), hz = to_f(H2[c]);
-    {
-      float d1 = hz - to_f(H2[cym]), d2 = hy - to_f(H1[czm]);
-      bool u = i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-      bool q1 = sey >= 0, q2 = sez >= 0;
-      float p1 = 0.f, p2 = 0.f;
-      if (q1 && u) p1 = psi_step(d, d.psi_e[1][0], d.psi_e[1][0], true, 1, i, j, k, sey,
-                                 d.ax[1].ae[j], d.ax[1].be[j], d1);
-      if (q2 && u) p2 = psi_step(d, d.psi_e[2][0], d.psi_e[2][0], true, 2, i, j, k, sez,
-                                 d.ax[2].ae[k], d.ax[2].be[k], d2);
-      float e = to_f(Ei0[c]);
-      Eo0[c] = from_f<T>(u ? e_cell(d.ca, e, d1, cey, d2, cez, q1, p1, q2, p2) : e);
+    const bool zl = sez >= 0;
+    const float hx = to_f(H0[c]), hy = to_f(H1[c]), hz = to_f(H2[c]);
+    {  // Ex: y, z
+      const float d1 = hz - to_f(H2[cym]), d2 = hy - to_f(H1[czm]);
+      const bool u = i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
+      float sy = 0.f, sz = 0.f;
+      if (yl && u) sy = psi_e(d, d.psi_e[1][0], 1, j, i, j, k, sey, d1);
+      if (zl && u) sz = -psi_e(d, d.psi_e[2][0], 2, k, i, j, k, sez, d2);
+      const float e = to_f(Ei0[c]);
+      Eo0[c] = from_f<T>(u ? add_layers(e_plain(d.ca, e, d1, cey, d2, cez), false, 0.f, yl, sy, zl, sz) : e);
     }
-    {
-      float d1 = hx - to_f(H0[czm]), d2 = hz - to_f(H2[cxm]);
-      bool u = i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-      bool q1 = sez >= 0, q2 = sex >= 0;
-      float p1 = 0.f, p2 = 0.f;
-      if (q1 && u) p1 = psi_step(d, d.psi_e[2][1], d.psi_e[2][1], true, 2, i, j, k, sez,
-                                 d.ax[2].ae[k], d.ax[2].be[k], d1);
-      if (q2 && u) p2 = psi_step(d, d.psi_e[0][0], d.psi_e[0][0], true, 0, i, j, k, sex,
-                                 d.ax[0].ae[i], d.ax[0].be[i], d2);
-      float e = to_f(Ei1[c]);
-      Eo1[c] = from_f<T>(u ? e_cell(d.ca, e, d1, cez, d2, cex, q1, p1, q2, p2) : e);
+    {  // Ey: z, x
+      const float d1 = hx - to_f(H0[czm]), d2 = hz - to_f(H2[cxm]);
+      const bool u = i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2;
+      float sx = 0.f, sz = 0.f;
+      if (xl && u) sx = -psi_e(d, d.psi_e[0][0], 0, i, i, j, k, sex, d2);
+      if (zl && u) sz = psi_e(d, d.psi_e[2][1], 2, k, i, j, k, sez, d1);
+      const float e = to_f(Ei1[c]);
+      Eo1[c] = from_f<T>(u ? add_layers(e_plain(d.ca, e, d1, cez, d2, cex), xl, sx, false, 0.f, zl, sz) : e);
     }
-    {
-      float d1 = hy - to_f(H1[cxm]), d2 = hx - to_f(H0[cym]);
-      bool u = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2;
-      bool q1 = sex >= 0, q2 = sey >= 0;
-      float p1 = 0.f, p2 = 0.f;
-      if (q1 && u) p1 = psi_step(d, d.psi_e[0][1], d.psi_e[0][1], true, 0, i, j, k, sex,
-                                 d.ax[0].ae[i], d.ax[0].be[i], d1);
-      if (q2 && u) p2 = psi_step(d, d.psi_e[1][1], d.psi_e[1][1], true, 1, i, j, k, sey,
-                                 d.ax[1].ae[j], d.ax[1].be[j], d2);
-      float e = to_f(Ei2[c]);
-      Eo2[c] = from_f<T>(u ? e_cell(d.ca, e, d1, cex, d2, cey, q1, p1, q2, p2) : e);
+    {  // Ez: x, y
+      const float d1 = hy - to_f(H1[cxm]), d2 = hx - to_f(H0[cym]);
+      const bool u = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2;
+      float sx = 0.f, sy = 0.f;
+      if (xl && u) sx = psi_e(d, d.psi_e[0][1], 0, i, i, j, k, sex, d1);
+      if (yl && u) sy = -psi_e(d, d.psi_e[1][1], 1, j, i, j, k, sey, d2);
+      const float e = to_f(Ei2[c]);
+      Eo2[c] = from_f<T>(u ? add_layers(e_plain(d.ca, e, d1, cex, d2, cey), xl, sx, yl, sy, false, 0.f) : e);
     }
   }
 }
@@ -719,12 +650,7 @@ __global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
 // ------------------------------------------------------------------ launch
 template <typename T, int VX, int W>
 static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
-  if (p.fs.n_fast > 0)
-    hipLaunchKernelGGL((k_fused<T, VX, W, true>), dim3(p.fs.fast_blocks), dim3(64 * W), 0, s, d, p.fs,
-                       (const int *)nullptr, par);
-  if (p.fs.n_slow > 0)
-    hipLaunchKernelGGL((k_fused<T, VX, W, false>), dim3(p.fs.slow_blocks), dim3(64 * W), 0, s, d, p.fs,
-                       d.slow_tiles, par);
+  hipLaunchKernelGGL((k_fused<T, VX, W>), dim3(p.fs.fast_blocks), dim3(64 * W), 0, s, d, p.fs, par);
   return hipGetLastError();
 }
 
@@ -751,14 +677,33 @@ static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, hipSt
 template <typename T>
 static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, const double *q,
                          double *w, int column, int ld, hipStream_t s) {
-  hipError_t e;
+  hipError_t e = hipSuccess;
   const Dev &d = d_in;
-  if (p.kernel == CHF_KERNEL_FUSED) {
-    e = fused_dispatch<T>(p, d, par, s);
-  } else {
-    dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, (d.nz + kSplitZ - 1) / kSplitZ);
-    hipLaunchKernelGGL(k_split_h<T>, grid, dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_split_e<T>, grid, dim3(256), 0, s, d, par);
+  // interior rectangle in one fused sweep; the boundary tiles (or all tiles) in split sweeps,
+  // whose E pass reads the fresh H of both
+  // (both read only the input level and write disjoint nodes, so the boundary H sweep runs on a
+  // side stream beside the fused sweep; the boundary E sweep joins them)
+  const int nxb = (d.nx + 63) / 64;
+  const dim3 sgrid(p.fs.n_slow * nxb), sblock(64 * p.fs.waves);
+  const bool fork = p.fs.n_fast > 0 && p.fs.n_slow > 0 && p.aux;
+  if (fork) {
+    e = hipEventRecord(p.ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.ev_fork, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_h<T>, sgrid, sblock, 0, p.aux, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+    e = hipEventRecord(p.ev_join, p.aux);
+    if (e != hipSuccess) return e;
+  }
+  if (p.fs.n_fast > 0) e = fused_dispatch<T>(p, d, par, s);
+  if (e != hipSuccess) return e;
+  if (p.fs.n_slow > 0) {
+    if (fork) {
+      e = hipStreamWaitEvent(s, p.ev_join, 0);
+      if (e != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(k_split_h<T>, sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+    }
+    hipLaunchKernelGGL(k_split_e<T>, sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;

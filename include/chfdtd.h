@@ -182,10 +182,19 @@ typedef struct {
 } chf_plan_info;
 chf_status chf_plan_get_info(const chf_plan *plan, chf_plan_info *info);
 
-/* Batched execution: several plans advanced together, one launch per phase per step for the
-   whole batch.  Plans keep their own workspaces.  waveforms_dev[i] is plan i's output. */
+/* Batched execution (many showers of uneven grids advanced together).  Plans must have their
+   workspaces bound and share storage, waves_per_block and n_steps.  Each step issues one
+   launch per phase for the whole batch (fused interior sweep over every plan's interior tiles,
+   boundary sweeps over every plan's boundary tiles, source, observer gather), and the full run
+   from zero fields is captured once into one hipGraph, replayed by chf_batch_run.  The batch
+   needs its own small DEVICE workspace (plan descriptors, tile tables), caller-owned like the
+   plans'.  waveforms_dev[i] is plan i's DEVICE FP64 output [n_obs_i][3][n_steps]; the graph is
+   re-captured when the set of output pointers changes.  Results equal those of each plan run
+   alone, bit for bit. */
 typedef struct chf_batch chf_batch;
 chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out);
+chf_status chf_batch_workspace_bytes(const chf_batch *batch, uint64_t *bytes);
+chf_status chf_batch_bind_workspace(chf_batch *batch, void *device_ptr, uint64_t bytes, void *stream);
 chf_status chf_batch_run(chf_batch *batch, void *stream, double *const *waveforms_dev);
 void chf_batch_destroy(chf_batch *batch);
 

@@ -22,7 +22,8 @@ EXPORTED = [
     "chf_plan_create", "chf_plan_destroy", "chf_plan_workspace_bytes", "chf_plan_bind_workspace",
     "chf_plan_reset", "chf_forward", "chf_forward_graph", "chf_adjoint", "chf_plan_sync",
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
-    "chf_batch_run", "chf_batch_destroy", "chf_status_str", "chf_last_error", "chf_abi_version",
+    "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_destroy",
+    "chf_status_str", "chf_last_error", "chf_abi_version",
 ]
 
 
@@ -117,6 +118,10 @@ def lib():
         L.chf_plan_get_info.argtypes = [vp, ct.POINTER(PlanInfo)]
         L.chf_batch_create.restype = ct.c_int
         L.chf_batch_create.argtypes = [ct.c_int32, ct.POINTER(vp), ct.POINTER(vp)]
+        L.chf_batch_workspace_bytes.restype = ct.c_int
+        L.chf_batch_workspace_bytes.argtypes = [vp, ct.POINTER(ct.c_uint64)]
+        L.chf_batch_bind_workspace.restype = ct.c_int
+        L.chf_batch_bind_workspace.argtypes = [vp, vp, ct.c_uint64, vp]
         L.chf_batch_run.restype = ct.c_int
         L.chf_batch_run.argtypes = [vp, vp, ct.POINTER(vp)]
         L.chf_batch_destroy.restype = None

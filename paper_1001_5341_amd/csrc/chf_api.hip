@@ -666,28 +666,175 @@ chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, doubl
 
 chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) {
   if (!out || n <= 0 || !plans) return fail(CHF_EINVAL, "bad batch");
+  *out = nullptr;
   chf_batch *b = new (std::nothrow) chf_batch();
   if (!b) return fail(CHF_ENOMEM, "host allocation failed");
   for (int i = 0; i < n; i++) {
-    if (!plans[i]) {
+    chf_plan *p = plans[i];
+    if (!p || !p->ws) {
       delete b;
-      return fail(CHF_EINVAL, "NULL plan in batch");
+      return fail(p ? CHF_ESTATE : CHF_EINVAL, "every plan must exist and have its workspace bound");
     }
-    b->plans.push_back(plans[i]);
+    if (i == 0) {
+      b->storage = p->storage;
+      b->waves = p->fs.waves;
+      b->n_steps = p->grid.n_steps;
+    } else if (p->storage != b->storage || p->fs.waves != b->waves || p->grid.n_steps != b->n_steps) {
+      delete b;
+      return fail(CHF_EINVAL, "plans of a batch share storage, waves_per_block and n_steps");
+    }
+    b->plans.push_back(p);
+    b->vx = std::max(b->vx, p->fs.vx);
+    b->zchunks.push_back(p->fs.zchunk);
+    b->any_mur = b->any_mur || p->bnd.kind == CHF_BC_MUR1;
+    if (p->dev.src_on) b->max_patch = std::max(b->max_patch, p->dev.src_ni * p->dev.src_nj);
+    const chf::FusedShape &fs = p->fs;
+    const int fw = fs.ty_hi - fs.ty_lo;
+    for (int t = 0; t < fs.n_fast; t++) {
+      b->fast_tab.push_back(i);
+      b->fast_tab.push_back(fs.ty_lo + t % fw);
+      b->fast_tab.push_back(fs.zc_lo + t / fw);
+    }
+    const int nxb = (p->grid.nx + 63) / 64;
+    for (int t = 0; t < fs.n_slow; t++)
+      for (int xb = 0; xb < nxb; xb++) {
+        b->slow_tab.push_back(i);
+        b->slow_tab.push_back(p->slow_tiles[2 * t]);
+        b->slow_tab.push_back(p->slow_tiles[2 * t + 1]);
+        b->slow_tab.push_back(xb);
+      }
+    for (int o = 0; o < p->dev.n_obs; o++) {
+      b->obs_tab.push_back(i);
+      b->obs_tab.push_back(o);
+    }
+    chf::Dev d = p->dev;
+    if (!p->ex.nan_watch) d.nan_flag = nullptr;
+    b->devs.push_back(d);
   }
+  b->total_obs = (int)(b->obs_tab.size() / 2);
+  b->wptr.assign(n, nullptr);
+  uint64_t off = 0;
+  b->off_devs = off;
+  off += align256(b->devs.size() * sizeof(chf::Dev));
+  b->off_z = off;
+  off += align256(b->zchunks.size() * sizeof(int));
+  b->off_fast = off;
+  off += align256(std::max<size_t>(b->fast_tab.size(), 1) * sizeof(int));
+  b->off_slow = off;
+  off += align256(std::max<size_t>(b->slow_tab.size(), 1) * sizeof(int));
+  b->off_obs = off;
+  off += align256(std::max<size_t>(b->obs_tab.size(), 1) * sizeof(int));
+  b->off_wptr = off;
+  off += align256((size_t)n * sizeof(double *));
+  b->ws_bytes = off;
   *out = b;
+  return CHF_OK;
+}
+
+chf_status chf_batch_workspace_bytes(const chf_batch *b, uint64_t *bytes) {
+  if (!b || !bytes) return fail(CHF_EINVAL, "NULL argument");
+  *bytes = b->ws_bytes;
+  return CHF_OK;
+}
+
+chf_status chf_batch_bind_workspace(chf_batch *b, void *dev_ptr, uint64_t bytes, void *stream) {
+  if (!b || !dev_ptr) return fail(CHF_EINVAL, "NULL argument");
+  if (bytes < b->ws_bytes) return fail(CHF_ENOMEM, "workspace smaller than chf_batch_workspace_bytes");
+  if ((uintptr_t)dev_ptr % 256) return fail(CHF_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  b->ws = (char *)dev_ptr;
+  struct Up {
+    uint64_t off;
+    const void *src;
+    size_t n;
+  } ups[] = {
+      {b->off_devs, b->devs.data(), b->devs.size() * sizeof(chf::Dev)},
+      {b->off_z, b->zchunks.data(), b->zchunks.size() * sizeof(int)},
+      {b->off_fast, b->fast_tab.data(), b->fast_tab.size() * sizeof(int)},
+      {b->off_slow, b->slow_tab.data(), b->slow_tab.size() * sizeof(int)},
+      {b->off_obs, b->obs_tab.data(), b->obs_tab.size() * sizeof(int)},
+  };
+  for (const Up &u : ups) {
+    if (!u.n) continue;
+    hipError_t e = hipMemcpyAsync(b->ws + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload of batch tables");
+  }
+  if (!b->aux && !b->fast_tab.empty() && !b->slow_tab.empty()) {
+    hipError_t e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "side stream");
+  }
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
   return CHF_OK;
 }
 
 chf_status chf_batch_run(chf_batch *b, void *stream, double *const *w) {
   if (!b || !w) return fail(CHF_EINVAL, "NULL argument");
-  for (size_t i = 0; i < b->plans.size(); i++) {
-    chf_status st = chf_forward_graph(b->plans[i], stream, nullptr, w[i]);
-    if (st != CHF_OK) return st;
+  if (!b->ws) return fail(CHF_ESTATE, "no batch workspace bound");
+  hipStream_t s = (hipStream_t)stream;
+  bool same = b->graph != nullptr;
+  for (size_t i = 0; i < b->plans.size(); i++) same = same && b->wptr[i] == w[i];
+  if (!same) {
+    if (b->graph) {
+      (void)hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    for (size_t i = 0; i < b->plans.size(); i++) b->wptr[i] = w[i];
+    hipError_t e = hipMemcpyAsync(b->ws + b->off_wptr, b->wptr.data(), b->wptr.size() * sizeof(double *),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "upload of waveform pointers");
+    hipStream_t cs;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hip_fail(e, "begin capture");
+    }
+    hipError_t le = hipSuccess;
+    for (chf_plan *p : b->plans)
+      if (le == hipSuccess) le = chf::launch_zero(*p, cs);
+    int par = 0;
+    for (int t = 0; t < b->n_steps && le == hipSuccess; t++) {
+      le = chf::launch_batch_step(*b, par, t, cs);
+      par ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(le, "captured batch launch");
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+  }
+  hipError_t e = hipGraphLaunch(b->graph, s);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  for (chf_plan *p : b->plans) {
+    p->parity = b->n_steps & 1;
+    p->n_done = b->n_steps;
   }
   return CHF_OK;
 }
 
-void chf_batch_destroy(chf_batch *b) { delete b; }
+void chf_batch_destroy(chf_batch *b) {
+  if (!b) return;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->aux) (void)hipStreamDestroy(b->aux);
+  delete b;
+}
 
 }  // extern "C"

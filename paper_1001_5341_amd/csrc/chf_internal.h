@@ -114,6 +114,19 @@ struct chf_plan {
 
 struct chf_batch {
   std::vector<chf_plan *> plans;
+  int storage = 0, vx = 1, waves = 4, n_steps = 0, max_patch = 0, total_obs = 0;
+  bool any_mur = false;
+  std::vector<int> zchunks;   // per plan
+  std::vector<int> fast_tab;  // (plan, ty, zc) over the interior rectangles
+  std::vector<int> slow_tab;  // (plan, ty, zc, x block) over the boundary tiles
+  std::vector<int> obs_tab;   // (plan, observer)
+  uint64_t off_devs = 0, off_z = 0, off_fast = 0, off_slow = 0, off_obs = 0, off_wptr = 0, ws_bytes = 0;
+  char *ws = nullptr;
+  std::vector<chf::Dev> devs;
+  std::vector<double *> wptr;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace chf {
@@ -126,5 +139,6 @@ hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float
 hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step,
                                const double *dl_dw, double *dl_dq, hipStream_t s);
 hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s);
+hipError_t launch_batch_step(const chf_batch &b, int parity, int step, hipStream_t s);
 void set_error(const std::string &msg);
 }  // namespace chf

@@ -151,20 +151,21 @@ __device__ __forceinline__ float psi_e(const Dev &d, float *p, int u, int pos, i
 // (k_split_h / k_split_e over a tile table).  Every node here is updated except at the x walls:
 // nodes take the unmasked update, lanes holding x-layer nodes add the x CPML term, and x-wall /
 // padding nodes keep their old values -- the canonical sequence of the general path.
+// Logical tile of this workgroup: consecutive logical tiles on one XCD (the hardware deals
+// workgroups to the 8 XCDs round-robin).
+__device__ __forceinline__ int xcd_logical() {
+  const int b = blockIdx.x;
+  return (b & 7) * (gridDim.x >> 3) + (b >> 3);
+}
+
 template <typename T, int VX, int W>
-__global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, int par) {
+__device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zchunk, int par) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int b = blockIdx.x;
-  const int logical = (b & 7) * (gridDim.x >> 3) + (b >> 3);
-  if (logical >= fs.n_fast) return;
-  const int fw = fs.ty_hi - fs.ty_lo;
-  const int ty = fs.ty_lo + logical % fw;
-  const int zc = fs.zc_lo + logical / fw;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int j = ty * W + wave;
   if (j >= ny) return;
-  const int k0 = zc * fs.zchunk, k1 = min(k0 + fs.zchunk, nz);
+  const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
   const int ib = lane * VX;
   const bool on = ib < nx;
   const unsigned esz = (unsigned)sizeof(T);
@@ -365,33 +366,37 @@ __global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, int par)
   }
 }
 
+template <typename T, int VX, int W>
+__global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, int par) {
+  const int logical = xcd_logical();
+  if (logical >= fs.n_fast) return;
+  const int fw = fs.ty_hi - fs.ty_lo;
+  fused_body<T, VX, W>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+}
+
+// Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
+template <typename T, int VX, int W>
+__global__ void __launch_bounds__(64 * W) k_fused_batch(const Dev *devs, const int *zchunks, const int *tab,
+                                                       int n, int par) {
+  const int logical = xcd_logical();
+  if (logical >= n) return;
+  const int pl = tab[3 * logical];
+  fused_body<T, VX, W>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
+}
+
 // --------------------------------------------------------------- split sweeps
 // Tiles outside the fused rectangle (walls and CPML layers), or every tile when the split
 // sweeps are selected: a workgroup of 64 x W threads covers 64 nodes of the W rows of one tile
 // and marches its z chunk, one thread per (i, j) column; H then E in two launches.  Same
 // canonical per-node arithmetic as the fused sweep.
-struct SplitTile {
-  int i, j, k0, k1;
-};
-
-__device__ __forceinline__ bool split_tile(const Dev &d, const FusedShape &fs, const int *tiles, int n_tiles,
-                                           SplitTile &t) {
-  const int nxb = (d.nx + 63) / 64;
-  const int tile = blockIdx.x / nxb;
-  if (tile >= n_tiles) return false;
-  const int ty = tiles[2 * tile], zc = tiles[2 * tile + 1];
-  t.i = (blockIdx.x % nxb) * 64 + (threadIdx.x & 63);
-  t.j = ty * fs.waves + (threadIdx.x >> 6);
-  t.k0 = zc * fs.zchunk;
-  t.k1 = min(t.k0 + fs.zchunk, d.nz);
-  return t.i < d.nx && t.j < d.ny;
-}
+template <typename T>
+__device__ __forceinline__ void split_h_body(const Dev &d, int i, int j, int k0, int k1, int par);
+template <typename T>
+__device__ __forceinline__ void split_e_body(const Dev &d, int i, int j, int k0, int k1, int par);
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_split_h(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
-  SplitTile st;
-  if (!split_tile(d, fs, tiles, n_tiles, st)) return;
-  const int i = st.i, j = st.j, k0 = st.k0, k1 = st.k1;
+__device__ __forceinline__ void split_h_body(const Dev &d, int i, int j, int k0, int k1, int par) {
+  if (i >= d.nx || j >= d.ny) return;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const T *E0 = (const T *)d.e[par][0], *E1 = (const T *)d.e[par][1], *E2 = (const T *)d.e[par][2];
   const T *Hi0 = (const T *)d.h[par][0], *Hi1 = (const T *)d.h[par][1], *Hi2 = (const T *)d.h[par][2];
@@ -448,10 +453,8 @@ __global__ void __launch_bounds__(512) k_split_h(Dev d, FusedShape fs, const int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_split_e(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
-  SplitTile st;
-  if (!split_tile(d, fs, tiles, n_tiles, st)) return;
-  const int i = st.i, j = st.j, k0 = st.k0, k1 = st.k1;
+__device__ __forceinline__ void split_e_body(const Dev &d, int i, int j, int k0, int k1, int par) {
+  if (i >= d.nx || j >= d.ny) return;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const T *Ei0 = (const T *)d.e[par][0], *Ei1 = (const T *)d.e[par][1], *Ei2 = (const T *)d.e[par][2];
   const T *H0 = (const T *)d.h[par ^ 1][0], *H1 = (const T *)d.h[par ^ 1][1], *H2 = (const T *)d.h[par ^ 1][2];
@@ -501,6 +504,35 @@ __global__ void __launch_bounds__(512) k_split_e(Dev d, FusedShape fs, const int
   }
 }
 
+// Single plan: workgroup -> (tile from the table, 64-node x block).
+template <typename T, bool H>
+__global__ void __launch_bounds__(512) k_split(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
+  const int nxb = (d.nx + 63) / 64;
+  const int tile = blockIdx.x / nxb;
+  if (tile >= n_tiles) return;
+  const int ty = tiles[2 * tile], zc = tiles[2 * tile + 1];
+  const int i = (blockIdx.x % nxb) * 64 + (threadIdx.x & 63);
+  const int j = ty * fs.waves + (threadIdx.x >> 6);
+  const int k0 = zc * fs.zchunk, k1 = min(k0 + fs.zchunk, d.nz);
+  if constexpr (H) split_h_body<T>(d, i, j, k0, k1, par);
+  else split_e_body<T>(d, i, j, k0, k1, par);
+}
+
+// Batched: entries (plan, ty, zc, x block) over the boundary tiles of every plan.
+template <typename T, bool H>
+__global__ void __launch_bounds__(512) k_split_batch(const Dev *devs, const int *zchunks, const int *tab, int n,
+                                                     int rows, int par) {
+  if ((int)blockIdx.x >= n) return;
+  const int *e = tab + 4 * blockIdx.x;
+  const Dev &d = devs[e[0]];
+  const int zchunk = zchunks[e[0]];
+  const int i = e[3] * 64 + (threadIdx.x & 63);
+  const int j = e[1] * rows + (threadIdx.x >> 6);
+  const int k0 = e[2] * zchunk, k1 = min(k0 + zchunk, d.nz);
+  if constexpr (H) split_h_body<T>(d, i, j, k0, k1, par);
+  else split_e_body<T>(d, i, j, k0, k1, par);
+}
+
 // ------------------------------------------------------------------- source
 // J_z of the moving Gaussian charge snapshot at (n+1/2) dt, subtracted (times scale*Cb)
 // from Ez^{n+1}.  Bookkeeping in FP64: bunch position, Q(z_s) from the hat bins, and the
@@ -525,9 +557,8 @@ __device__ __forceinline__ double source_q(const Dev &d, const double *q, double
 }
 
 template <typename T>
-__global__ void k_source(Dev d, int out_par, int step, const double *q) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.src_ni * d.src_nj) return;
+__device__ __forceinline__ void source_body(const Dev &d, int out_par, int step, const double *q, int t) {
+  if (!d.src_on || t >= d.src_ni * d.src_nj) return;
   const double tt = (step + 0.5) * d.dt;
   if (tt < d.t_entry) return;
   const double wr = d.wr[t];
@@ -552,6 +583,18 @@ __global__ void k_source(Dev d, int out_par, int step, const double *q) {
     const long long c = (long long)k * d.plane + (long long)j * d.pitch + i;
     Ez[c] = from_f<T>(to_f(Ez[c]) - (float)inc);
   }
+}
+
+template <typename T>
+__global__ void k_source(Dev d, int out_par, int step, const double *q) {
+  source_body<T>(d, out_par, step, q, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched: blockIdx.y is the plan; each plan uses its own profile.
+template <typename T>
+__global__ void k_source_batch(const Dev *devs, int out_par, int step) {
+  const Dev &d = devs[blockIdx.y];
+  source_body<T>(d, out_par, step, d.q_bins, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // --------------------------------------------------------------------- Mur-1
@@ -592,8 +635,7 @@ __global__ void k_mur(Dev d, int par) {
 // One wave per observer: lane = 8*component + corner.  Each lane forms weight * E in FP64,
 // then a butterfly over the 8 corners sums each component; lanes 0, 8, 16 write.
 template <typename T>
-__global__ void __launch_bounds__(64) k_gather(Dev d, int par, double *w, int column, int ld) {
-  const int o = blockIdx.x;
+__device__ __forceinline__ void gather_body(const Dev &d, int par, double *w, int column, int ld, int o) {
   const int lane = threadIdx.x;
   const int comp = lane >> 3, corner = lane & 7;
   double val = 0.0;
@@ -614,6 +656,19 @@ __global__ void __launch_bounds__(64) k_gather(Dev d, int par, double *w, int co
     w[((long long)o * 3 + comp) * ld + column] = out;
     if (d.nan_flag && !isfinite(out)) *d.nan_flag = 1;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_gather(Dev d, int par, double *w, int column, int ld) {
+  gather_body<T>(d, par, w, column, ld, blockIdx.x);
+}
+
+// Batched: entries (plan, observer) over every observer of the batch; plan p writes waves[p].
+template <typename T>
+__global__ void __launch_bounds__(64) k_gather_batch(const Dev *devs, double *const *waves, const int *tab,
+                                                    int par, int column, int ld) {
+  const int pl = tab[2 * blockIdx.x];
+  gather_body<T>(devs[pl], par, waves[pl], column, ld, tab[2 * blockIdx.x + 1]);
 }
 
 // ------------------------------------------------------------ fill / copies
@@ -690,7 +745,7 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
     e = hipEventRecord(p.ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.ev_fork, 0);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_h<T>, sgrid, sblock, 0, p.aux, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+    hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, p.aux, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     e = hipEventRecord(p.ev_join, p.aux);
     if (e != hipSuccess) return e;
   }
@@ -701,9 +756,9 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
       e = hipStreamWaitEvent(s, p.ev_join, 0);
       if (e != hipSuccess) return e;
     } else {
-      hipLaunchKernelGGL(k_split_h<T>, sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+      hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     }
-    hipLaunchKernelGGL(k_split_e<T>, sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+    hipLaunchKernelGGL((k_split<T, false>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
@@ -727,6 +782,81 @@ hipError_t launch_step(const chf_plan &p, const Dev &d, int par, int step, const
     case CHF_FP32: return step_t<float>(p, d, par, step, q, w, column, ld, s);
     case CHF_BF16: return step_t<__bf16>(p, d, par, step, q, w, column, ld, s);
     case CHF_FP16: return step_t<_Float16>(p, d, par, step, q, w, column, ld, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int VX, int W>
+static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z, int par, hipStream_t s) {
+  const int n = (int)(b.fast_tab.size() / 3);
+  if (n == 0) return hipSuccess;
+  const int blocks = (n + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_fused_batch<T, VX, W>), dim3(blocks), dim3(64 * W), 0, s, devs, z,
+                     (const int *)(b.ws + b.off_fast), n, par);
+  return hipGetLastError();
+}
+
+template <typename T, int VX>
+static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *z, int par, hipStream_t s) {
+  return b.waves == 8 ? batch_fused<T, VX, 8>(b, devs, z, par, s) : batch_fused<T, VX, 4>(b, devs, z, par, s);
+}
+
+template <typename T>
+static hipError_t batch_step_t(const chf_batch &b, int par, int step, hipStream_t s) {
+  const Dev *devs = (const Dev *)(b.ws + b.off_devs);
+  const int *z = (const int *)(b.ws + b.off_z);
+  hipError_t e = hipSuccess;
+  const int ns = (int)(b.slow_tab.size() / 4);
+  const int *stab = (const int *)(b.ws + b.off_slow);
+  const bool fork = ns > 0 && !b.fast_tab.empty() && b.aux;
+  if (fork) {
+    e = hipEventRecord(b.ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b.aux, b.ev_fork, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_split_batch<T, true>), dim3(ns), dim3(64 * b.waves), 0, b.aux, devs, z, stab, ns,
+                       b.waves, par);
+    e = hipEventRecord(b.ev_join, b.aux);
+    if (e != hipSuccess) return e;
+  }
+  switch (b.vx) {
+    case 1: e = batch_fused_w<T, 1>(b, devs, z, par, s); break;
+    case 2: e = batch_fused_w<T, 2>(b, devs, z, par, s); break;
+    case 4: e = batch_fused_w<T, 4>(b, devs, z, par, s); break;
+    default: e = batch_fused_w<T, 8>(b, devs, z, par, s); break;
+  }
+  if (e != hipSuccess) return e;
+  if (ns > 0) {
+    if (fork) {
+      e = hipStreamWaitEvent(s, b.ev_join, 0);
+      if (e != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL((k_split_batch<T, true>), dim3(ns), dim3(64 * b.waves), 0, s, devs, z, stab, ns,
+                         b.waves, par);
+    }
+    hipLaunchKernelGGL((k_split_batch<T, false>), dim3(ns), dim3(64 * b.waves), 0, s, devs, z, stab, ns,
+                       b.waves, par);
+  }
+  if (b.max_patch > 0)
+    hipLaunchKernelGGL(k_source_batch<T>, dim3((b.max_patch + 255) / 256, (int)b.plans.size()), dim3(256), 0, s,
+                       devs, par ^ 1, step);
+  if (b.any_mur)
+    for (const chf_plan *p : b.plans)
+      if (p->dev.bc == CHF_BC_MUR1) {
+        const int m = max(p->dev.nx, max(p->dev.ny, p->dev.nz));
+        hipLaunchKernelGGL(k_mur<T>, dim3((m + 15) / 16, (m + 15) / 16, 12), dim3(16, 16), 0, s, p->dev, par);
+      }
+  if (b.total_obs > 0)
+    hipLaunchKernelGGL(k_gather_batch<T>, dim3(b.total_obs), dim3(64), 0, s, devs,
+                       (double *const *)(b.ws + b.off_wptr), (const int *)(b.ws + b.off_obs), par ^ 1, step,
+                       b.n_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const chf_batch &b, int par, int step, hipStream_t s) {
+  switch (b.storage) {
+    case CHF_FP32: return batch_step_t<float>(b, par, step, s);
+    case CHF_BF16: return batch_step_t<__bf16>(b, par, step, s);
+    case CHF_FP16: return batch_step_t<_Float16>(b, par, step, s);
   }
   return hipErrorInvalidValue;
 }

@@ -167,18 +167,27 @@ def run(w, **kw) -> torch.Tensor:
 
 
 class Batch:
-    """Several plans advanced by one call (chf_batch_run)."""
+    """Several plans advanced together: one launch per phase per step for the whole batch,
+    the whole run captured once into a hipGraph (chf_batch_run)."""
 
     def __init__(self, plans: Sequence[Plan]):
         self.plans = list(plans)
         arr = (ct.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         self._keep = arr
         self._h = ct.c_void_p()
-        N.check(N.lib().chf_batch_create(len(self.plans), arr, ct.byref(self._h)), "chf_batch_create")
+        L = N.lib()
+        N.check(L.chf_batch_create(len(self.plans), arr, ct.byref(self._h)), "chf_batch_create")
+        nbytes = ct.c_uint64()
+        N.check(L.chf_batch_workspace_bytes(self._h, ct.byref(nbytes)), "chf_batch_workspace_bytes")
+        dev = self.plans[0].device
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        N.check(L.chf_batch_bind_workspace(self._h, ct.c_void_p(self.workspace.data_ptr()), int(nbytes.value),
+                                           _stream_handle()), "chf_batch_bind_workspace")
 
     def run(self, outs=None, stream=None, sync=True):
         outs = outs or [p.new_waveforms() for p in self.plans]
         ptrs = (ct.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        self._ptrs = ptrs
         N.check(N.lib().chf_batch_run(self._h, _stream_handle(stream), ptrs), "chf_batch_run")
         if sync:
             for p in self.plans:

@@ -1,0 +1,60 @@
+"""Batched execution: showers of uneven grids advanced by one launch per phase per step (one
+hipGraph for the run) give exactly the waveforms of each shower run alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_5341_amd import _native, solver
+from paper_1001_5341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def members(steps=110):
+    return [
+        W.small_shower(seed=31, nx=40, ny=40, nz=64, n_steps=steps, n_obs=3, npml=6),
+        W.small_shower(seed=32, nx=72, ny=60, nz=96, n_steps=steps, n_obs=4, npml=8),
+        W.small_shower(seed=33, nx=130, ny=48, nz=80, n_steps=steps, n_obs=2, npml=6),
+        W.small_shower(seed=34, nx=36, ny=44, nz=70, n_steps=steps, n_obs=3, bc="pec"),
+        W.gaussian_cube(seed=35, n=32, n_steps=steps),  # Mur boundary
+    ]
+
+
+def test_batch_equals_single_runs(gpu):
+    ws = members()
+    print("\n[gpu-batch] singles", flush=True)
+    singles = []
+    for w in ws:
+        p = solver.Plan(w)
+        singles.append(p.run().cpu().numpy())
+        p.close()
+    print("[gpu-batch] batch", flush=True)
+    plans = [solver.Plan(w) for w in ws]
+    batch = solver.Batch(plans)
+    for rep in range(2):
+        outs = [o.cpu().numpy() for o in batch.run()]
+        for a, b in zip(outs, singles):
+            assert np.array_equal(a, b), rep
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_batch_member_against_oracle(gpu):
+    ws = members(steps=90)[:3]
+    plans = [solver.Plan(w) for w in ws]
+    batch = solver.Batch(plans)
+    outs = batch.run()
+    ref = oracle.run(ws[1])
+    got = outs[1].cpu().numpy()
+    err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
+    assert np.all(err <= 1e-5), err
+    batch.close()
+
+
+def test_batch_rejects_mismatched_steps(gpu):
+    a = solver.Plan(W.small_shower(seed=1, nx=40, ny=40, nz=60, n_steps=10, n_obs=2, npml=6))
+    b = solver.Plan(W.small_shower(seed=2, nx=40, ny=40, nz=60, n_steps=12, n_obs=2, npml=6))
+    with pytest.raises(_native.ChfError) as e:
+        solver.Batch([a, b])
+    assert e.value.status == "CHF_EINVAL"

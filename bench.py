@@ -1,16 +1,27 @@
 """Throughput of the Yee FDTD hot path on one MI355X.
 
 A bench "step" is one complete run of the single-shower workload (256x256x2048 cells of 1 cm,
-n = 1.78, 10-cell CPML, moving Greisen-like shower, 64 FP64 observers, 4000 Yee steps), from
-zero fields, as one hipGraph launch.  The value is Yee cell-updates per second (all six
-components of one cell, one time step), whole job.
+n = 1.78, 10-cell CPML, moving Greisen-like shower, 64 FP64 observers, 4000 Yee steps) from
+zero fields: every Yee step runs the H/E sweeps (fused interior kernel plus boundary-tile
+kernels), the source injection and the observer gather.  The value is Yee cell-updates per
+second (all six components of one cell over one time step), whole job, inputs resident in HBM.
 
-Prints one JSON line with the roofline of the dominant kernel (the fused E/H sweep) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+The timed runs go through chf_forward_timed: the same launches as chf_forward, with a hipEvent
+pair on the launch stream around every launch of the dominant kernel (the fused interior
+sweep), so the roofline line is that kernel's own average duration over the timed region.
+
+Prints one JSON line.  Besides the FP32 headline it carries the same workload with BF16 and
+FP16 field storage (one timed run each, with their relative L2 error against the FP64
+oracle's stored waveforms), and the FP64 CPU oracle timed on a bounded sample.
+
+Counter summaries: ``--copy-probe`` adds a 256 MiB device copy before the runs (the
+calibration dispatch for FETCH_SIZE / WRITE_SIZE); ``--summarize-pmc FETCH.csv WRITE.csv``
+turns two rocprofv3 --pmc runs of that command into HBM bytes per launch of the sweep.
 """
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -23,6 +34,13 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+COPY_PROBE_BYTES = 256 << 20
+FUSED_KERNEL = "chf::k_fused<"
+DTYPE = {"fp32": "f32", "bf16": "f32 (bf16 storage)", "fp16": "f32 (f16 storage)"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_digest() -> str:
@@ -33,10 +51,14 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, storage: str, bytes_alg_per_launch: float):
-    """HBM bytes per launch of the sweep from the committed rocprofv3 counter summary, if it was
+def traffic_path(workload: str, storage: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_fused_sweep_{workload}_{storage}.json")
+
+
+def measured_traffic(workload: str, storage: str):
+    """HBM bytes per launch of the fused sweep from the committed counter summary, if it was
     taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_fused_sweep_{workload}_{storage}.json")
+    path = traffic_path(workload, storage)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -45,29 +67,137 @@ def measured_traffic(workload: str, storage: str, bytes_alg_per_launch: float):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, seconds_hint: float = 15.0):
-    """The FP64 oracle on a bounded sample of the workload: a 256x256x256 sub-grid (same
-    spacing, CPML and shower source, observers shifted into it) for a few dozen steps."""
+def _dispatches(path: str, counter: str):
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                yield r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, command: str):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the fused sweep, each scaled by what the
+    same counter reads for the 256 MiB calibration copy (read 256 MiB, write 256 MiB)."""
+    out = {}
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = list(_dispatches(path, counter))
+        copies = [v for k, g, v in rows if "copyBuffer" in k]
+        if not copies:
+            raise SystemExit(f"{path}: no calibration copy dispatch (run with --copy-probe)")
+        copy_kib = max(copies)  # the 256 MiB probe is by far the largest copy
+        fused = [v for k, g, v in rows if FUSED_KERNEL in k]
+        if not fused:
+            raise SystemExit(f"{path}: no fused-sweep dispatch")
+        factor = (COPY_PROBE_BYTES / 1024.0) / copy_kib
+        out[name] = {"copy_probe_kib": copy_kib, "scale": factor, "dispatches": len(fused),
+                     "raw_kib_per_launch": float(np.mean(fused)),
+                     "bytes_per_launch": float(np.mean(fused)) * 1024.0 * factor}
+    rec = {"workload": workload, "storage": storage, "kernel": "fused interior sweep (chf::k_fused)",
+           "kernel_digest": kernel_source_digest(), "command": command,
+           "fetch": out["fetch"], "write": out["write"],
+           "bytes_per_launch": out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]}
+    path = traffic_path(workload, storage)
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
+
+
+def cpu_baseline(w, n_steps: int = 600):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: a 256x256x256 sub-grid
+    (same spacing, medium, CPML and shower source; 8 observers placed inside it) for n_steps."""
     import oracle
     from paper_1001_5341_amd import workloads as W
 
     nz = 256
-    sub = W.greisen_shower(w.seed, w.nx, w.ny, nz, 40, 8, zmax_frac=(0.4, 0.5),
+    sub = W.greisen_shower(w.seed, w.nx, w.ny, nz, n_steps, 8, zmax_frac=(0.4, 0.5),
                            length_range=(0.5, 1.0), r_range=(0.3, 1.0), name="cpu-sample")
     t0 = time.perf_counter()
     oracle.run(sub)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rate = sub.n_cells * sub.n_steps / dt / 1e6
-    return {"value": round(rate, 3), "unit": "Mcell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, {sub.nx}x{sub.ny}x{sub.nz} sub-grid of the workload "
-                      f"(CPML-10, shower source, 8 observers), {sub.n_steps} steps, {dt:.1f} s"}
+    return {"value": round(rate, 3), "unit": "Mcell-updates/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"FP64 oracle on a {sub.nx}x{sub.ny}x{sub.nz} sub-grid of the workload "
+                      f"(same medium, CPML-{sub.npml}, shower source, 8 observers), {sub.n_steps} steps, "
+                      f"{dt:.1f} s"}
+
+
+def golden_error(key: str, w, got: np.ndarray):
+    """Relative L2 (per observer, 3 components x all steps) and peak-amplitude error against
+    the FP64 oracle's stored waveforms, when they exist for this exact workload."""
+    from paper_1001_5341_amd.workloads import workload_digest
+
+    gold = os.path.join(ROOT, "tests", "golden", f"{key}_oracle.npz")
+    if not os.path.exists(gold):
+        return None
+    z = np.load(gold)
+    if str(z["digest"]) != workload_digest(w):
+        return None
+    ref = z["waveforms"].astype(np.float64)
+    err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
+    pk_ref = np.abs(ref).max(axis=(1, 2))
+    pk = np.abs(np.abs(got).max(axis=(1, 2)) - pk_ref) / pk_ref
+    return {"rel_l2_max": float(err.max()), "rel_l2_median": float(np.median(err)),
+            "peak_amp_err_max": float(pk.max())}
+
+
+def timed_runs(plan, out, n_runs: int):
+    """n_runs full runs (reset + all Yee steps), each through chf_forward_timed.
+    Returns (wall seconds, event seconds, summed fused-sweep ms, fused launches)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    fused_ms = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(n_runs):
+        plan.reset(stream)
+        fused_ms += plan.forward_timed(plan.n_steps, out, 0, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3, fused_ms, n_runs * plan.n_steps
+
+
+def roofline(info, fused_ms: float, launches: int):
+    alg = info["fused_cells"] * info["fused_bytes_per_cell"]
+    avg_s = fused_ms / 1e3 / launches
+    achieved = alg / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernel": "chf::k_fused (fused interior H/E sweep, one launch per Yee step)",
+            "launch_avg_us": round(avg_s * 1e6, 2), "launches": launches,
+            "cells_per_launch": int(info["fused_cells"]),
+            "bytes_per_cell": round(info["fused_bytes_per_cell"], 3),
+            "alg_bytes_per_launch": int(alg)}
+
+
+def run_variant(w, storage: str, args, n_runs: int, warmup: int):
+    import torch
+
+    from paper_1001_5341_amd import solver
+
+    plan = solver.Plan(w, storage=storage, kernel=args.kernel, rows=args.rows, waves=args.waves,
+                       zchunk=args.zchunk, device=torch.device("cuda:0"))
+    info = plan.info()
+    out = plan.new_waveforms()
+    for i in range(warmup):
+        plan.run(out=out, sync=True)
+        log(f"{storage} warmup {i} done")
+    wall, ev_s, fused_ms, launches = timed_runs(plan, out, n_runs)
+    log(f"{storage}: {n_runs} timed runs, wall {wall:.3f} s, events {ev_s:.3f} s, "
+        f"fused sweep {fused_ms / launches * 1e3:.1f} us/launch")
+    got = out.cpu().numpy()
+    plan.close()
+    return info, wall, ev_s, fused_ms, launches, got
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=2, help="timed full runs")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single-shower")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
@@ -77,64 +207,51 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--time-steps", type=int, default=0, help="override the Yee steps per run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the BF16/FP16 storage runs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 256 MiB device copy first (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--pmc-command", default="", help="command recorded in the counter summary")
     args = ap.parse_args()
 
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.storage,
+                      args.pmc_command)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU z-slab decomposition is design-only)"}))
         sys.exit(2)
 
     import torch
 
-    from paper_1001_5341_amd import solver
     from paper_1001_5341_amd import workloads as W
 
     w = W.workload_by_name(args.workload)
     if args.time_steps:
         w = w.replace(n_steps=args.time_steps)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    print(f"[bench] workload {w.name}: {w.nx}x{w.ny}x{w.nz}, {w.n_steps} steps, "
-          f"storage {args.storage}", file=sys.stderr, flush=True)
-    plan = solver.Plan(w, storage=args.storage, kernel=args.kernel, rows=args.rows,
-                       waves=args.waves, zchunk=args.zchunk, device=dev)
-    info = plan.info()
-    out = plan.new_waveforms()
-    stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        plan.run(out=out, graph=True, sync=True)
-        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nz}, {w.n_steps} steps, storage {args.storage}")
+    if args.copy_probe:
+        a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        plan.run(out=out, graph=True, sync=False)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    plan.sync()
-    gpu_ms = ev0.elapsed_time(ev1)
-    print(f"[bench] timed {args.steps} runs: wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s",
-          file=sys.stderr, flush=True)
-
+    info, wall, ev_s, fused_ms, launches, got = run_variant(w, args.storage, args, args.steps, args.warmup)
     cells = w.nx * w.ny * w.nz
     updates = cells * w.n_steps * args.steps
-    value = updates / wall / 1e6
-    # dominant kernel: the sweep, one launch per Yee step; the event time per Yee step also
-    # contains the small source and observer kernels (a few microseconds), so this is a bound
-    # from below on the sweep's own rate
-    step_s = gpu_ms / 1e3 / (args.steps * w.n_steps)
-    b_cell = info["bytes_per_cell_update"]
-    alg_bytes_launch = b_cell * cells
-    achieved = alg_bytes_launch / step_s / 1e9
-    traffic = measured_traffic(w.name, args.storage, alg_bytes_launch)
+    roof = roofline(info, fused_ms, launches)
+    roof["traffic"] = measured_traffic(args.workload, args.storage) if not args.time_steps else None
+    # whole Yee step (all kernels) against the whole-grid algorithmic bytes, for context
+    step_s = ev_s / (args.steps * w.n_steps)
+    roof["whole_step"] = {"bytes_per_cell": round(info["bytes_per_cell_update"], 3),
+                          "achieved": round(info["bytes_per_cell_update"] * cells / step_s / 1e9, 1),
+                          "us_per_yee_step": round(step_s * 1e6, 2)}
     rec = {
         "metric": "Yee Mcell-updates/s and % HBM roofline, FP32 vs BF16-storage at stated L2 error",
-        "value": round(value, 1),
+        "value": round(updates / wall / 1e6, 1),
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -143,33 +260,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16-storage/f32-math", "fp16": "f16-storage/f32-math"}[args.storage],
-        "data": "synthetic (seeded Greisen-like shower, no datasets)",
+        "dtype": DTYPE[args.storage],
+        "data": "synthetic (seeded Greisen-like shower profile and observers; no datasets)",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "yee_steps_per_run": w.n_steps,
                    "boundary": f"{w.bc}{w.npml}", "observers": w.n_obs, "storage": args.storage,
-                   "kernel": {1: "split", 2: "fused"}[info["kernel"]],
-                   "tile": {"vx": info["vx"], "rows_per_wave": info["rows_per_wave"],
-                            "waves_per_block": info["waves_per_block"], "z_chunk": info["z_chunk"]},
+                   "kernel": {1: "split", 2: "fused+split boundary tiles"}[info["kernel"]],
+                   "tile": {"vx": info["vx"], "waves_per_block": info["waves_per_block"],
+                            "z_chunk": info["z_chunk"]},
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "bytes_per_cell_update": round(b_cell, 3),
-                     "kernel": "k_fused (one launch per Yee step)",
-                     "launch_avg_us": round(step_s * 1e6, 2)},
+        "roofline": roof,
     }
-    if not args.no_accuracy and w.name.startswith("single-shower") and not args.time_steps:
-        gold = os.path.join(ROOT, "tests", "golden", "single-shower_oracle.npz")
-        if os.path.exists(gold):
-            ref = np.load(gold)["waveforms"].astype(np.float64)
-            got = out.cpu().numpy()
-            err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
-            rec["accuracy_vs_fp64_oracle"] = {"rel_l2_max": float(err.max()),
-                                              "rel_l2_median": float(np.median(err))}
+    acc = golden_error(args.workload, w, got)
+    if acc is not None:
+        rec["accuracy_vs_fp64_oracle"] = acc
+    if not args.no_variants and not args.time_steps:
+        variants = {}
+        for st in ("bf16", "fp16"):
+            if st == args.storage:
+                continue
+            vinfo, vwall, _, vms, vl, vgot = run_variant(w, st, args, 1, 0)
+            v = {"value": round(cells * w.n_steps / vwall / 1e6, 1), "unit": "Mcell-updates/s",
+                 "roofline_frac": roofline(vinfo, vms, vl)["frac"],
+                 "fused_launch_avg_us": round(vms / vl * 1e3, 2),
+                 "fused_bytes_per_cell": round(vinfo["fused_bytes_per_cell"], 3),
+                 "scale_e": vinfo["scale_e"], "scale_h": vinfo["scale_h"]}
+            e = golden_error(args.workload, w, vgot)
+            if e is not None:
+                v["accuracy_vs_fp64_oracle"] = e
+            variants[st] = v
+        rec["storage_variants"] = variants
     if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on a CPU sample", file=sys.stderr, flush=True)
+        log("timing the FP64 oracle on a CPU sample")
         rec["cpu_baseline"] = cpu_baseline(w)
-    plan.close()
     print(json.dumps(rec), flush=True)
 
 

@@ -151,6 +151,13 @@ chf_status chf_plan_reset(chf_plan *plan, void *stream);
 chf_status chf_forward(chf_plan *plan, void *stream, const double *q_bins_dev, double *waveforms_dev,
                        int32_t n_steps, int32_t first_column, int32_t ld_steps);
 
+/* Instrumented chf_forward for measurement: identical work, plus a hipEvent pair on `stream`
+   around the launch of the fused interior sweep in every step.  Waits for `stream` before
+   returning; *fused_ms receives the summed duration of those launches (0 when the plan has no
+   fused interior tiles). */
+chf_status chf_forward_timed(chf_plan *plan, void *stream, const double *q_bins_dev, double *waveforms_dev,
+                             int32_t n_steps, int32_t first_column, int32_t ld_steps, double *fused_ms);
+
 /* Same as chf_forward over the plan's n_steps, captured once into a hipGraph per
    (waveform pointer, profile pointer) and replayed on later calls. */
 chf_status chf_forward_graph(chf_plan *plan, void *stream, const double *q_bins_dev,
@@ -178,7 +185,9 @@ typedef struct {
   int32_t kernel, storage, vx, rows_per_wave, waves_per_block, z_chunk, pitch, n_blocks;
   double scale_e, scale_h;
   uint64_t field_bytes, psi_bytes, workspace_bytes;
-  double bytes_per_cell_update; /* algorithmic HBM bytes of one cell-update */
+  double bytes_per_cell_update; /* algorithmic HBM bytes of one cell-update (whole grid) */
+  uint64_t fused_cells;         /* nodes covered by one launch of the fused interior sweep */
+  double fused_bytes_per_cell;  /* its algorithmic HBM bytes per node (fields + x-layer psi) */
 } chf_plan_info;
 chf_status chf_plan_get_info(const chf_plan *plan, chf_plan_info *info);
 

@@ -79,6 +79,7 @@ def lib():
             L.orc_run.argtypes = [ct.POINTER(OrcCfg), P]
             L.orc_adjoint.restype = ct.c_int
             L.orc_adjoint.argtypes = [ct.POINTER(OrcCfg), P, P]
+            L.orc_threads.restype = ct.c_int
             for f in ("orc_c0", "orc_mu0", "orc_eps0"):
                 getattr(L, f).restype = ct.c_double
             _lib = L
@@ -88,6 +89,10 @@ def lib():
 def constants():
     L = lib()
     return {"c0": L.orc_c0(), "mu0": L.orc_mu0(), "eps0": L.orc_eps0()}
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def _dp(a: np.ndarray):

@@ -10,6 +10,9 @@
 #include "yee_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -21,6 +24,13 @@ static double eps0(void) { return 1.0 / (MU0 * C0 * C0); }
 double orc_c0(void) { return C0; }
 double orc_mu0(void) { return MU0; }
 double orc_eps0(void) { return eps0(); }
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 static __thread char g_err[256];
 const char *orc_last_error(void) { return g_err; }

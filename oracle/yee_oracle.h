@@ -84,6 +84,8 @@ int orc_adjoint(const orc_cfg *cfg, const double *dl_dw, double *dl_dq);
 double orc_c0(void);
 double orc_mu0(void);
 double orc_eps0(void);
+/* OpenMP threads the loops above run on (1 without OpenMP). */
+int orc_threads(void);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ KERNEL = {"auto": 0, "split": 1, "fused": 2}
 
 EXPORTED = [
     "chf_plan_create", "chf_plan_destroy", "chf_plan_workspace_bytes", "chf_plan_bind_workspace",
-    "chf_plan_reset", "chf_forward", "chf_forward_graph", "chf_adjoint", "chf_plan_sync",
+    "chf_plan_reset", "chf_forward", "chf_forward_timed", "chf_forward_graph", "chf_adjoint", "chf_plan_sync",
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
     "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_destroy",
     "chf_status_str", "chf_last_error", "chf_abi_version",
@@ -65,7 +65,8 @@ class PlanInfo(ct.Structure):
                 ("z_chunk", ct.c_int32), ("pitch", ct.c_int32), ("n_blocks", ct.c_int32),
                 ("scale_e", ct.c_double), ("scale_h", ct.c_double), ("field_bytes", ct.c_uint64),
                 ("psi_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
-                ("bytes_per_cell_update", ct.c_double)]
+                ("bytes_per_cell_update", ct.c_double), ("fused_cells", ct.c_uint64),
+                ("fused_bytes_per_cell", ct.c_double)]
 
 
 class ChfError(RuntimeError):
@@ -104,6 +105,9 @@ def lib():
         L.chf_plan_reset.argtypes = [vp, vp]
         L.chf_forward.restype = ct.c_int
         L.chf_forward.argtypes = [vp, vp, vp, vp, ct.c_int32, ct.c_int32, ct.c_int32]
+        L.chf_forward_timed.restype = ct.c_int
+        L.chf_forward_timed.argtypes = [vp, vp, vp, vp, ct.c_int32, ct.c_int32, ct.c_int32,
+                                        ct.POINTER(ct.c_double)]
         L.chf_forward_graph.restype = ct.c_int
         L.chf_forward_graph.argtypes = [vp, vp, vp, vp]
         L.chf_adjoint.restype = ct.c_int

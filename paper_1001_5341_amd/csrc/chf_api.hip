@@ -538,6 +538,40 @@ chf_status chf_forward(chf_plan *p, void *stream, const double *q_bins_dev, doub
   return CHF_OK;
 }
 
+chf_status chf_forward_timed(chf_plan *p, void *stream, const double *q_bins_dev, double *w_dev, int32_t n_steps,
+                             int32_t first_column, int32_t ld_steps, double *fused_ms) {
+  if (!p || !fused_ms) return fail(CHF_EINVAL, "NULL argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
+  if (p->dev.n_obs > 0 && w_dev && (ld_steps < first_column + n_steps))
+    return fail(CHF_EINVAL, "ld_steps too small for first_column + n_steps");
+  *fused_ms = 0.0;
+  std::vector<hipEvent_t> ev(2 * (size_t)n_steps, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t t = 0; t < ev.size() && e == hipSuccess; t++) e = hipEventCreate(&ev[t]);
+  chf::Dev d = p->dev;
+  if (!p->ex.nan_watch) d.nan_flag = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  for (int t = 0; t < n_steps && e == hipSuccess; t++) {
+    e = chf::launch_step(*p, d, p->parity, p->n_done, q_bins_dev, w_dev, first_column + t, ld_steps, s,
+                         ev[2 * t], ev[2 * t + 1]);
+    p->parity ^= 1;
+    p->n_done++;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  double total = 0.0;
+  for (int t = 0; t < n_steps && e == hipSuccess && p->fs.n_fast > 0; t++) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]);
+    total += ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(e, "timed forward");
+  *fused_ms = total;
+  return CHF_OK;
+}
+
 chf_status chf_forward_graph(chf_plan *p, void *stream, const double *q_bins_dev, double *w_dev) {
   if (!p) return fail(CHF_EINVAL, "NULL plan");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
@@ -643,6 +677,12 @@ chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
   }
   info->bytes_per_cell_update = 12.0 * p->elem_bytes + psi_rw;
   (void)cells;
+  // fused interior sweep: rows and planes clear of y/z layers, so only the x-layer psi
+  const uint64_t rows = (uint64_t)std::max(0, (p->fs.ty_hi - p->fs.ty_lo) * p->fs.waves);
+  const uint64_t planes = (uint64_t)std::max(0, (p->fs.zc_hi - p->fs.zc_lo) * p->fs.zchunk);
+  info->fused_cells = rows * planes * (uint64_t)p->grid.nx;
+  info->fused_bytes_per_cell =
+      12.0 * p->elem_bytes + (p->bnd.npml > 0 ? (2.0 * p->bnd.npml / p->grid.nx) * 4 * 2 * 4.0 : 0.0);
   return CHF_OK;
 }
 

@@ -132,7 +132,8 @@ struct chf_batch {
 namespace chf {
 // kernel launchers (chf_kernels.hip)
 hipError_t launch_step(const chf_plan &p, const Dev &d, int parity, int step, const double *q_dev,
-                       double *w_dev, int column, int ld, hipStream_t s);
+                       double *w_dev, int column, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
+                       hipEvent_t ev_b = nullptr);
 hipError_t launch_zero(const chf_plan &p, hipStream_t s);
 hipError_t launch_get_field(const chf_plan &p, int parity, int comp, float *out, hipStream_t s);
 hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float *in, hipStream_t s);

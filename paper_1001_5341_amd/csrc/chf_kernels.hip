@@ -731,7 +731,7 @@ static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, hipSt
 
 template <typename T>
 static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, const double *q,
-                         double *w, int column, int ld, hipStream_t s) {
+                         double *w, int column, int ld, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
   hipError_t e = hipSuccess;
   const Dev &d = d_in;
   // interior rectangle in one fused sweep; the boundary tiles (or all tiles) in split sweeps,
@@ -749,7 +749,11 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
     e = hipEventRecord(p.ev_join, p.aux);
     if (e != hipSuccess) return e;
   }
-  if (p.fs.n_fast > 0) e = fused_dispatch<T>(p, d, par, s);
+  if (p.fs.n_fast > 0) {
+    if (ev_a) e = hipEventRecord(ev_a, s);
+    if (e == hipSuccess) e = fused_dispatch<T>(p, d, par, s);
+    if (e == hipSuccess && ev_b) e = hipEventRecord(ev_b, s);
+  }
   if (e != hipSuccess) return e;
   if (p.fs.n_slow > 0) {
     if (fork) {
@@ -777,11 +781,11 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
 }
 
 hipError_t launch_step(const chf_plan &p, const Dev &d, int par, int step, const double *q, double *w,
-                       int column, int ld, hipStream_t s) {
+                       int column, int ld, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
   switch (p.storage) {
-    case CHF_FP32: return step_t<float>(p, d, par, step, q, w, column, ld, s);
-    case CHF_BF16: return step_t<__bf16>(p, d, par, step, q, w, column, ld, s);
-    case CHF_FP16: return step_t<_Float16>(p, d, par, step, q, w, column, ld, s);
+    case CHF_FP32: return step_t<float>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
+    case CHF_BF16: return step_t<__bf16>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
+    case CHF_FP16: return step_t<_Float16>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
   }
   return hipErrorInvalidValue;
 }

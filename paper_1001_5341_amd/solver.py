@@ -116,6 +116,16 @@ class Plan:
         N.check(N.lib().chf_forward(self._h, _stream_handle(stream), qp, wp, n_steps, first_column, ld),
                 "chf_forward")
 
+    def forward_timed(self, n_steps: int, out: Optional[torch.Tensor] = None, first_column: int = 0,
+                      stream=None) -> float:
+        """chf_forward plus hipEvents around every fused-sweep launch; returns their summed ms."""
+        ld = out.shape[2] if out is not None else 0
+        wp = ct.c_void_p(out.data_ptr()) if out is not None else ct.c_void_p()
+        ms = ct.c_double()
+        N.check(N.lib().chf_forward_timed(self._h, _stream_handle(stream), ct.c_void_p(), wp, n_steps,
+                                          first_column, ld, ct.byref(ms)), "chf_forward_timed")
+        return float(ms.value)
+
     def run(self, q_bins: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
             graph: bool = False, stream=None, sync: bool = True) -> torch.Tensor:
         """Full run from zero fields; returns [n_obs, 3, n_steps] FP64 waveforms."""

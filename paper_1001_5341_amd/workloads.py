@@ -19,6 +19,8 @@ Every random quantity comes from ``numpy.random.default_rng(seed)``.
 from __future__ import annotations
 
 import dataclasses
+import hashlib
+import json
 import math
 from typing import List, Optional
 
@@ -312,3 +314,14 @@ def workload_by_name(name: str, seed: Optional[int] = None) -> Workload:
         "small": lambda s: small_shower(11 if s is None else s),
     }
     return table[name](seed)
+
+
+def workload_digest(w) -> str:
+    """SHA-256 of everything that defines a workload's inputs (stored expected values carry it)."""
+    h = hashlib.sha256()
+    h.update(json.dumps(w.describe(), sort_keys=True).encode())
+    for arr in (w.q_bins, w.obs_xyz):
+        h.update(np.ascontiguousarray(arr, dtype=np.float64).tobytes())
+    for v in (w.dt, w.dx, w.x_axis, w.y_axis, w.z_entry, w.sigma_r, w.sigma_z, w.pml_alpha_max):
+        h.update(np.float64(v).tobytes())
+    return h.hexdigest()

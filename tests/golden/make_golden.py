@@ -3,7 +3,6 @@
 Calls only the FP64 oracle (``oracle/``) and the seeded workload generator; no value here
 comes from the HIP path.  Usage:  python tests/golden/make_golden.py single-shower
 """
-import hashlib
 import json
 import os
 import sys
@@ -16,18 +15,9 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 from paper_1001_5341_amd import workloads as W  # noqa: E402
+from paper_1001_5341_amd.workloads import workload_digest  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-def workload_digest(w) -> str:
-    h = hashlib.sha256()
-    h.update(json.dumps(w.describe(), sort_keys=True).encode())
-    for arr in (w.q_bins, w.obs_xyz):
-        h.update(np.ascontiguousarray(arr, dtype=np.float64).tobytes())
-    for v in (w.dt, w.dx, w.x_axis, w.y_axis, w.z_entry, w.sigma_r, w.sigma_z, w.pml_alpha_max):
-        h.update(np.float64(v).tobytes())
-    return h.hexdigest()
 
 
 def main(name: str):

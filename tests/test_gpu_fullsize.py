@@ -2,7 +2,6 @@
 64 observers) on the GPU, in the configuration the benchmark times, against the FP64 oracle's
 waveforms stored by tests/golden/make_golden.py (which calls only the oracle)."""
 import os
-import sys
 
 import numpy as np
 import pytest
@@ -17,8 +16,7 @@ GOLD = os.path.join(HERE, "golden", "single-shower_oracle.npz")
 
 
 def test_single_shower_full_size_against_stored_oracle(gpu):
-    sys.path.insert(0, os.path.join(HERE, "golden"))
-    from make_golden import workload_digest
+    from paper_1001_5341_amd.workloads import workload_digest
 
     if not os.path.exists(GOLD):
         pytest.skip("stored oracle waveforms not generated")

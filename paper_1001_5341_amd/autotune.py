@@ -1,0 +1,128 @@
+"""Tile-shape autotuner for the fused sweep, with a JSON cache.
+
+For one workload shape it times every candidate (waves per workgroup x z chunk) over a short
+run of the real step (interior and boundary sweeps, source, gather) and keeps the fastest.
+Every candidate must reproduce the first candidate's observer waveforms bit for bit: the
+per-node arithmetic is the same in every tile shape, so a difference means a bug and the
+tuner raises instead of picking it.
+
+Cache: a JSON object keyed by device architecture, storage type, boundary and grid shape,
+stored at ``$CHFDTD_TUNE_CACHE`` or ``~/.cache/chfdtd/tune.json``.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+import torch
+
+from . import _native as N
+from . import solver
+
+CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((w, z) for w in (4, 8) for z in (8, 12, 16, 24, 32))
+
+
+def default_cache_path() -> str:
+    return os.environ.get("CHFDTD_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "chfdtd", "tune.json"))
+
+
+def shape_key(w, storage: str, device=None) -> str:
+    arch = torch.cuda.get_device_properties(device or torch.cuda.current_device()).gcnArchName.split(":")[0]
+    npml = w.npml if w.bc == "cpml" else 0
+    return f"{arch}/{storage}/{w.bc}{npml}/{w.nx}x{w.ny}x{w.nz}"
+
+
+def _load(path: str) -> dict:
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, table: dict) -> None:
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time_candidate(w, storage: str, waves: int, zchunk: int, steps: int, device):
+    plan = solver.Plan(w.replace(n_steps=steps), storage=storage, kernel="fused", waves=waves,
+                       zchunk=zchunk, device=device)
+    try:
+        out = plan.new_waveforms()
+        stream = torch.cuda.current_stream(device)
+        plan.reset(stream)
+        plan.forward(steps, out, 0, stream=stream)  # warm-up, also the bitwise reference run
+        ref = out.clone()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        plan.reset(stream)
+        out.zero_()
+        ev0.record(stream)
+        plan.forward(steps, out, 0, stream=stream)
+        ev1.record(stream)
+        plan.sync(stream)
+        ms = ev0.elapsed_time(ev1) / steps
+        if not torch.equal(out, ref):
+            raise RuntimeError(f"tile shape waves={waves} z_chunk={zchunk}: run-to-run waveforms differ")
+        return ms, out.cpu(), plan.info()
+    finally:
+        plan.close()
+
+
+def tune(w, storage: str = "fp32", steps: int = 48, cache_path: Optional[str] = None,
+         candidates: Optional[Sequence[Tuple[int, int]]] = None, use_cache: bool = True,
+         device=None) -> dict:
+    """Best (waves_per_block, z_chunk) for this workload shape; cached by shape_key()."""
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    path = cache_path or default_cache_path()
+    key = shape_key(w, storage, device)
+    cands = list(candidates or CANDIDATES)
+    if use_cache:
+        hit = _load(path).get(key)
+        if hit and (hit["waves"], hit["z_chunk"]) in [tuple(c) for c in cands]:
+            return dict(hit, cached=True)
+    steps = max(2, min(steps, w.n_steps))
+    trials, ref = [], None
+    for waves, zchunk in cands:
+        try:
+            ms, wave, info = _time_candidate(w, storage, waves, zchunk, steps, device)
+        except N.ChfError as exc:  # shape not valid for this grid (e.g. 8 waves on wide rows)
+            trials.append({"waves": waves, "z_chunk": zchunk, "error": exc.status})
+            continue
+        if ref is None:
+            ref = wave
+        elif not torch.equal(wave, ref):
+            raise RuntimeError(f"tile shape waves={waves} z_chunk={zchunk} changes the waveforms")
+        trials.append({"waves": waves, "z_chunk": zchunk, "ms_per_step": ms,
+                       "vx": info["vx"], "bitwise_equal": True})
+    timed = [t for t in trials if "ms_per_step" in t]
+    if not timed:
+        raise RuntimeError(f"no valid tile shape for {key}")
+    best = min(timed, key=lambda t: t["ms_per_step"])
+    rec = {"waves": best["waves"], "z_chunk": best["z_chunk"], "ms_per_step": best["ms_per_step"],
+           "steps": steps, "trials": trials}
+    table = _load(path)
+    table[key] = rec
+    _store(path, table)
+    return dict(rec, cached=False)
+
+
+def tuned_plan(w, storage: str = "fp32", **kw) -> "solver.Plan":
+    """A Plan whose fused-sweep tile shape comes from tune()."""
+    t = tune(w, storage, **kw)
+    return solver.Plan(w, storage=storage, kernel="fused", waves=t["waves"], zchunk=t["z_chunk"],
+                       device=kw.get("device"))
+
+
+def tune_batch(workloads: Iterable, storage: str = "fp32", **kw) -> list:
+    """Per-member z chunks for a batch (one waves_per_block for all members: the most common
+    best value)."""
+    res = [tune(w, storage, **kw) for w in workloads]
+    waves = max({r["waves"] for r in res}, key=lambda v: sum(r["waves"] == v for r in res))
+    return [{"waves": waves, "z_chunk": r["z_chunk"]} for r in res]

@@ -142,11 +142,15 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   fs.vx = 1;
   while (64 * fs.vx < G.nx) fs.vx *= 2;
   fs.rows = 1;
-  fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 4;
+  fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : (fs.vx <= 4 ? 8 : 4);
   fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 16;
   if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) || !(fs.waves == 4 || fs.waves == 8)) {
     delete p;
     return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4 or 8");
+  }
+  if (kernel == CHF_KERNEL_FUSED && fs.vx > 4 && fs.waves != 4) {
+    delete p;
+    return fail(CHF_EINVAL, "the fused sweep over rows wider than 256 nodes takes waves_per_block 4");
   }
   if ((int64_t)((G.nx + 15) / 16 * 16) * G.ny >= ((int64_t)1 << 31)) {
     delete p;
@@ -168,7 +172,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     fs.ty_hi = (fy1 + 1) / W;                  // j0 + W - 1 <= fy1
     fs.zc_lo = (fz0 + Z - 1) / Z;              // k0 >= fz0
     fs.zc_hi = (fz1 + 1) / Z;                  // k1 - 1 <= fz1
-    if (kernel != CHF_KERNEL_FUSED || fs.ty_hi <= fs.ty_lo || fs.zc_hi <= fs.zc_lo)
+    if (kernel != CHF_KERNEL_FUSED || fs.ty_hi <= fs.ty_lo || fs.zc_hi <= fs.zc_lo ||
+        2 * nl > chf::kMaxFusedLayer)
       fs.ty_lo = fs.ty_hi = fs.zc_lo = fs.zc_hi = 0;
     fs.n_fast = (fs.ty_hi - fs.ty_lo) * (fs.zc_hi - fs.zc_lo);
     fs.fast_blocks = (fs.n_fast + 7) / 8 * 8;

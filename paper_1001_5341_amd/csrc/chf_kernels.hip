@@ -158,64 +158,93 @@ __device__ __forceinline__ int xcd_logical() {
   return (b & 7) * (gridDim.x >> 3) + (b >> 3);
 }
 
-template <typename T, int VX, int W>
+// G = false: the interior rectangle (no wall and no y/z layer in reach; x walls and the x layer
+// are per-lane fix-ups).  G = true: any tile (the boundary tiles), with the wall masks of every
+// component and the y/z CPML terms, which are uniform per row and per plane.
+template <typename T, int VX, int W, bool G>
 __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zchunk, int par) {
+  // Wave r of the workgroup owns row j = j0 - 1 + r: r = 1..W are the tile's rows, r = 0 is
+  // the row below the tile, whose H the E update of row j0 needs (it computes H only and
+  // stores nothing; the tile below owns that row).  Rows exchange through LDS:
+  //   sEx/sEz slot s: Ex, Ez(k) of row j0 - 1 + s (s = 1..W+1; the top wave also loads row
+  //   j0 + W), read by the row below for its H update;
+  //   sHx/sHz slot s: Hx, Hz^{n+1/2}(k) of row j0 - 1 + s (s = 0..W-1), read by the row above
+  //   for its E update.
+  // Two barriers per plane.  Per plane a wave loads only its own row (6 vector loads), so the
+  // registers that wait on HBM hold no duplicated data.
+  constexpr int NL = 64 * VX;
+  __shared__ float sEx[W + 2][NL], sEz[W + 2][NL], sHx[W][NL], sHz[W][NL];
+  __shared__ float sTab[8][NL];  // per x node: ch, ce, ah, bh, ae, be, x-slab index (H, E)
+  // x-slab psi of the own row (H: Hy, Hz terms; E: Ey, Ez terms), staged so that both the
+  // loads and the stores of a row's slab are one contiguous value per lane; the node that owns
+  // slab index s replaces its value in place
+  __shared__ float sPsi[W + 1][4][kMaxFusedLayer];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int r = threadIdx.x >> 6;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const int j = ty * W + wave;
-  if (j >= ny) return;
+  const int j0 = ty * W;
+  const int j = j0 - 1 + r;
+  const bool act = !G || (j >= 0 && j < ny);  // row exists (always, in the interior rectangle)
+  const int jc = G ? min(max(j, 0), ny - 1) : j;
+  const bool own = r > 0 && act, top = r == W;
+  const bool top_ld = top && (!G || j + 1 < ny);
   const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
   const int ib = lane * VX;
-  const bool on = ib < nx;
+  const bool on = ib < nx && act;
   const unsigned esz = (unsigned)sizeof(T);
-  const unsigned o0 = ((unsigned)j * (unsigned)d.pitch + (unsigned)ib) * esz;               // row j
-  const unsigned om = ((unsigned)max(j - 1, 0) * (unsigned)d.pitch + (unsigned)ib) * esz;   // row j-1
-  const unsigned op = ((unsigned)min(j + 1, ny - 1) * (unsigned)d.pitch + (unsigned)ib) * esz;  // row j+1
+  const unsigned o0 = ((unsigned)jc * (unsigned)d.pitch + (unsigned)ib) * esz;  // own row
+  const unsigned op = ((unsigned)min(jc + 1, ny - 1) * (unsigned)d.pitch + (unsigned)ib) * esz;  // row above
   const long long plane = d.plane;
-  const bool pml = d.np2 > 0;
+  const int np2 = d.np2;
   const T *Ei0 = (const T *)d.e[par][0], *Ei1 = (const T *)d.e[par][1], *Ei2 = (const T *)d.e[par][2];
   const T *Hi0 = (const T *)d.h[par][0], *Hi1 = (const T *)d.h[par][1], *Hi2 = (const T *)d.h[par][2];
   T *Eo0 = (T *)d.e[par ^ 1][0], *Eo1 = (T *)d.e[par ^ 1][1], *Eo2 = (T *)d.e[par ^ 1][2];
   T *Ho0 = (T *)d.h[par ^ 1][0], *Ho1 = (T *)d.h[par ^ 1][1], *Ho2 = (T *)d.h[par ^ 1][2];
-  float *const phi[3][2] = {{d.psi_h[par][0][0], d.psi_h[par][0][1]},
-                            {d.psi_h[par][1][0], d.psi_h[par][1][1]},
-                            {d.psi_h[par][2][0], d.psi_h[par][2][1]}};
-  float *const pho[3][2] = {{d.psi_h[par ^ 1][0][0], d.psi_h[par ^ 1][0][1]},
-                            {d.psi_h[par ^ 1][1][0], d.psi_h[par ^ 1][1][1]},
-                            {d.psi_h[par ^ 1][2][0], d.psi_h[par ^ 1][2][1]}};
+  const float *phi0 = d.psi_h[par][0][0], *phi1 = d.psi_h[par][0][1];
+  float *pho0 = d.psi_h[par ^ 1][0][0], *pho1 = d.psi_h[par ^ 1][0][1];
+  float *pe0 = d.psi_e[0][0], *pe1 = d.psi_e[0][1];
 
-  float chx[VX], cex[VX];
-  int shx[VX], sex[VX];
-  bool xfix = false;
-#pragma unroll
-  for (int v = 0; v < VX; v++) {
-    const int i = ib + v, ic = min(i, nx - 1);
-    chx[v] = d.ax[0].ch[ic];
-    cex[v] = d.ax[0].ce[ic];
-    shx[v] = (pml && i < nx) ? d.ax[0].sh[i] : -1;
-    sex[v] = (pml && i < nx) ? d.ax[0].se[i] : -1;
-    xfix = xfix || i == 0 || i >= nx - 1 || shx[v] >= 0 || sex[v] >= 0;
+  for (int i = threadIdx.x; i < NL; i += 64 * (W + 1)) {
+    const int ic = min(i, nx - 1);
+    const bool lay = np2 > 0 && i < nx;
+    sTab[0][i] = d.ax[0].ch[ic];
+    sTab[1][i] = d.ax[0].ce[ic];
+    sTab[2][i] = lay ? d.ax[0].ah[i] : 0.f;
+    sTab[3][i] = lay ? d.ax[0].bh[i] : 0.f;
+    sTab[4][i] = lay ? d.ax[0].ae[i] : 0.f;
+    sTab[5][i] = lay ? d.ax[0].be[i] : 0.f;
+    sTab[6][i] = __int_as_float(lay ? d.ax[0].sh[i] : -1);
+    sTab[7][i] = __int_as_float(lay ? d.ax[0].se[i] : -1);
   }
-  const int jm = max(j - 1, 0);
-  const float chy = d.ax[1].ch[j], cey = d.ax[1].ce[j], chym = d.ax[1].ch[jm];
-  const int shy = pml ? d.ax[1].sh[j] : -1, sey = pml ? d.ax[1].se[j] : -1;
-  const int shym = pml ? d.ax[1].sh[jm] : -1;
+  // lanes holding x walls, padding or x-layer nodes take the fix-up paths below
+  bool xfix = ib == 0 || ib + VX - 1 >= nx - 1;
+  if (np2 > 0) {
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      const int i = ib + v;
+      xfix = xfix || (i < nx && (d.ax[0].sh[i] >= 0 || d.ax[0].se[i] >= 0));
+    }
+  }
+  const float chy = d.ax[1].ch[jc], cey = d.ax[1].ce[jc];
+  // y layer and wall masks of the own row (uniform per wave)
+  const int shy = G && np2 > 0 ? d.ax[1].sh[jc] : -1, sey = G && np2 > 0 ? d.ax[1].se[jc] : -1;
+  const float ahy = shy >= 0 ? d.ax[1].ah[jc] : 0.f, bhy = shy >= 0 ? d.ax[1].bh[jc] : 0.f;
+  const float aey = sey >= 0 ? d.ax[1].ae[jc] : 0.f, bey = sey >= 0 ? d.ax[1].be[jc] : 0.f;
+  const bool jh = !G || j <= ny - 2;               // Hx, Hz have their y difference
+  const bool je = !G || (j >= 1 && j <= ny - 2);   // Ex, Ez are not tangential to a y wall
+  __syncthreads();  // sTab
 
-  // E(k) of rows j-1 (m), j (c), j+1 (p; Ex and Ez only)
-  float exm[VX], eym[VX], ezm[VX], exc[VX], eyc[VX], ezc[VX], exp_[VX], ezp[VX];
-  ld_at<T, VX>(Ei0 + k0 * plane, om, exm, on);
-  ld_at<T, VX>(Ei1 + k0 * plane, om, eym, on);
-  ld_at<T, VX>(Ei2 + k0 * plane, om, ezm, on);
+  // E(k0) of the own row (and, for the top wave, Ex, Ez of the row above the tile)
+  float exc[VX], eyc[VX], ezc[VX], etx[VX], etz[VX];
   ld_at<T, VX>(Ei0 + k0 * plane, o0, exc, on);
   ld_at<T, VX>(Ei1 + k0 * plane, o0, eyc, on);
   ld_at<T, VX>(Ei2 + k0 * plane, o0, ezc, on);
-  ld_at<T, VX>(Ei0 + k0 * plane, op, exp_, on);
-  ld_at<T, VX>(Ei2 + k0 * plane, op, ezp, on);
+  ld_at<T, VX>(Ei0 + k0 * plane, op, etx, on && top_ld);
+  ld_at<T, VX>(Ei2 + k0 * plane, op, etz, on && top_ld);
 
-  // H^{n+1/2}(k0-1), Hx and Hy of row j, for the backward z differences of the first plane
+  // Hx, Hy^{n+1/2}(k0-1) of the own row, for the backward z differences of the first plane
   float hxp[VX], hyp[VX];
-  if (k0 > 0) {
+  if (k0 > 0 && own) {
     const int km = k0 - 1;
     float ex_[VX], ey_[VX], ez_[VX], ezu[VX], hxo[VX], hyo[VX];
     ld_at<T, VX>(Ei0 + km * plane, o0, ex_, on);
@@ -225,27 +254,28 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     ld_at<T, VX>(Hi0 + km * plane, o0, hxo, on);
     ld_at<T, VX>(Hi1 + km * plane, o0, hyo, on);
     const float chz = d.ax[2].ch[km];
-    const int shz = pml ? d.ax[2].sh[km] : -1;
+    const int shz = np2 > 0 ? d.ax[2].sh[km] : -1;
     const float ezn = __shfl_down(ez_[0], 1);
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       const int i = ib + v;
+      const int shx = __float_as_int(sTab[6][i]);
       const float ezx = (v + 1 < VX) ? ez_[v + 1] : ezn;
       {
         const float d1 = ezu[v] - ez_[v], d2 = eyc[v] - ey_[v];
         const bool u = i < nx && j <= ny - 2 && km <= nz - 2;
         float sy = 0.f, sz = 0.f;
-        if (shy >= 0 && u) sy = -psi_h(d, phi[1][0], nullptr, false, 1, j, i, j, km, shy, d1);
-        if (shz >= 0 && u) sz = psi_h(d, phi[2][0], nullptr, false, 2, km, i, j, km, shz, d2);
+        if (shy >= 0 && u) sy = -psi_h(d, d.psi_h[par][1][0], nullptr, false, 1, j, i, j, km, shy, d1);
+        if (shz >= 0 && u) sz = psi_h(d, d.psi_h[par][2][0], nullptr, false, 2, km, i, j, km, shz, d2);
         hxp[v] = u ? add_layers(h_plain(hxo[v], d1, chy, d2, chz), false, 0.f, shy >= 0, sy, shz >= 0, sz) : hxo[v];
       }
       {
         const float d1 = exc[v] - ex_[v], d2 = ezx - ez_[v];
         const bool u = i <= nx - 2 && km <= nz - 2;
         float sx = 0.f, sz = 0.f;
-        if (shx[v] >= 0 && u) sx = psi_h(d, phi[0][0], nullptr, false, 0, i, i, j, km, shx[v], d2);
-        if (shz >= 0 && u) sz = -psi_h(d, phi[2][1], nullptr, false, 2, km, i, j, km, shz, d1);
-        hyp[v] = u ? add_layers(h_plain(hyo[v], d1, chz, d2, chx[v]), shx[v] >= 0, sx, false, 0.f, shz >= 0, sz) : hyo[v];
+        if (shx >= 0 && u) sx = psi_h(d, d.psi_h[par][0][0], nullptr, false, 0, i, i, j, km, shx, d2);
+        if (shz >= 0 && u) sz = -psi_h(d, d.psi_h[par][2][1], nullptr, false, 2, km, i, j, km, shz, d1);
+        hyp[v] = u ? add_layers(h_plain(hyo[v], d1, chz, d2, sTab[0][i]), shx >= 0, sx, false, 0.f, shz >= 0, sz) : hyo[v];
       }
     }
     as_stored<T, VX>(hxp);
@@ -258,130 +288,315 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   for (int k = k0; k < k1; k++) {
     const int kp = min(k + 1, nz - 1);
     const long long pk = k * plane, pn = kp * plane;
-    // E(k+1) of rows j-1, j, j+1 and H^{n-1/2}(k) of rows j-1 (Hx, Hz) and j
-    float nxm[VX], nym[VX], nzm[VX], nxc[VX], nyc[VX], nzc[VX], nxp[VX], nzp[VX];
-    float hxm0[VX], hzm0[VX], hx0[VX], hy0[VX], hz0[VX];
-    ld_at<T, VX>(Ei0 + pn, om, nxm, on);
-    ld_at<T, VX>(Ei1 + pn, om, nym, on);
-    ld_at<T, VX>(Ei2 + pn, om, nzm, on);
+    // publish E(k) of the own row (slot r) and of the row above the tile (slot W+1)
+    if (own) {
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        sEx[r][ib + v] = exc[v];
+        sEz[r][ib + v] = ezc[v];
+      }
+    }
+    if (top) {
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        sEx[W + 1][ib + v] = etx[v];
+        sEz[W + 1][ib + v] = etz[v];
+      }
+    }
+    // loads: E(k+1) and H^{n-1/2}(k) of the own row, Ex, Ez(k+1) of the row above the tile
+    // (top wave), the own row's x-slab psi (one value per lane) and y/z-slab psi rows
+    float nxc[VX], nyc[VX], nzc[VX], hx0[VX], hy0[VX], hz0[VX];
     ld_at<T, VX>(Ei0 + pn, o0, nxc, on);
     ld_at<T, VX>(Ei1 + pn, o0, nyc, on);
     ld_at<T, VX>(Ei2 + pn, o0, nzc, on);
-    ld_at<T, VX>(Ei0 + pn, op, nxp, on);
-    ld_at<T, VX>(Ei2 + pn, op, nzp, on);
-    ld_at<T, VX>(Hi0 + pk, om, hxm0, on);
-    ld_at<T, VX>(Hi2 + pk, om, hzm0, on);
     ld_at<T, VX>(Hi0 + pk, o0, hx0, on);
     ld_at<T, VX>(Hi1 + pk, o0, hy0, on);
     ld_at<T, VX>(Hi2 + pk, o0, hz0, on);
-
+    ld_at<T, VX>(Ei0 + pn, op, etx, on && top_ld);
+    ld_at<T, VX>(Ei2 + pn, op, etz, on && top_ld);
+    const long long prow = ((long long)k * ny + jc) * np2;
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+    if (lane < np2 && act) {
+      q0 = phi0[prow + lane];
+      q1 = phi1[prow + lane];
+      if (own) {
+        q2 = pe0[prow + lane];
+        q3 = pe1[prow + lane];
+      }
+    }
     const float chz = d.ax[2].ch[k], cez = d.ax[2].ce[k];
-    const int shz = pml ? d.ax[2].sh[k] : -1, sez = pml ? d.ax[2].se[k] : -1;
-    const float eymn = __shfl_down(eym[0], 1);
-    const float eyn = __shfl_down(eyc[0], 1), ezn = __shfl_down(ezc[0], 1);
-    float hxm[VX], hzm[VX], hx[VX], hy[VX], hz[VX];
+    // z layer and wall masks of this plane (uniform)
+    const int shz = G && np2 > 0 ? d.ax[2].sh[k] : -1, sez = G && np2 > 0 ? d.ax[2].se[k] : -1;
+    const bool kh = !G || k <= nz - 2;              // Hx, Hy have their z difference
+    const bool ke = !G || (k >= 1 && k <= nz - 2);  // Ex, Ey are not tangential to a z wall
+    // y/z slab rows: H terms Hx(y), Hz(y), Hx(z), Hy(z); E terms Ex(y), Ez(y), Ex(z), Ey(z)
+    float qhxy[VX], qhzy[VX], qhxz[VX], qhyz[VX], qexy[VX], qezy[VX], qexz[VX], qeyz[VX];
+    long long iyh = 0, iye = 0, izh = 0, ize = 0;
+    if constexpr (G) {
+      iyh = ((long long)k * np2 + max(shy, 0)) * d.pitch + ib;
+      iye = ((long long)k * np2 + max(sey, 0)) * d.pitch + ib;
+      izh = ((long long)max(shz, 0) * ny + jc) * d.pitch + ib;
+      ize = ((long long)max(sez, 0) * ny + jc) * d.pitch + ib;
+      ld_row<float, VX>(d.psi_h[par][1][0] + iyh, qhxy, on && shy >= 0);
+      ld_row<float, VX>(d.psi_h[par][1][1] + iyh, qhzy, on && shy >= 0);
+      ld_row<float, VX>(d.psi_h[par][2][0] + izh, qhxz, on && shz >= 0);
+      ld_row<float, VX>(d.psi_h[par][2][1] + izh, qhyz, on && shz >= 0);
+      ld_row<float, VX>(d.psi_e[1][0] + iye, qexy, own && on && sey >= 0);
+      ld_row<float, VX>(d.psi_e[1][1] + iye, qezy, own && on && sey >= 0);
+      ld_row<float, VX>(d.psi_e[2][0] + ize, qexz, own && on && sez >= 0);
+      ld_row<float, VX>(d.psi_e[2][1] + ize, qeyz, own && on && sez >= 0);
+    }
+    __syncthreads();
+
+    // ---- H^{n+1/2}(k) of the own row
+    if (lane < np2) {
+      sPsi[r][0][lane] = q0;
+      sPsi[r][1][lane] = q1;
+      sPsi[r][2][lane] = q2;
+      sPsi[r][3][lane] = q3;
+    }
+    float eux[VX], euz[VX], chx[VX];
 #pragma unroll
     for (int v = 0; v < VX; v++) {
-      const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+      eux[v] = sEx[r + 1][ib + v];
+      euz[v] = sEz[r + 1][ib + v];
+      chx[v] = sTab[0][ib + v];
+    }
+    const float eyn = __shfl_down(eyc[0], 1), ezn = __shfl_down(ezc[0], 1);
+    float hx[VX], hy[VX], hz[VX];
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
       const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
       const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
-      hxm[v] = h_plain(hxm0[v], ezc[v] - ezm[v], chym, nym[v] - eym[v], chz);
-      hzm[v] = h_plain(hzm0[v], eymx - eym[v], chx[v], exc[v] - exm[v], chym);
-      hx[v] = h_plain(hx0[v], ezp[v] - ezc[v], chy, nyc[v] - eyc[v], chz);
+      hx[v] = h_plain(hx0[v], euz[v] - ezc[v], chy, nyc[v] - eyc[v], chz);
       hy[v] = h_plain(hy0[v], nxc[v] - exc[v], chz, ezx - ezc[v], chx[v]);
-      hz[v] = h_plain(hz0[v], eyx - eyc[v], chx[v], exp_[v] - exc[v], chy);
+      hz[v] = h_plain(hz0[v], eyx - eyc[v], chx[v], eux[v] - exc[v], chy);
     }
     if (xfix) {  // x walls and padding keep old values; x-layer terms
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         const int i = ib + v;
+        const int sh = __float_as_int(sTab[6][i]);
         if (i >= nx - 1) {
-          hzm[v] = hzm0[v];
           hy[v] = hy0[v];
           hz[v] = hz0[v];
-          if (i >= nx) {
-            hxm[v] = hxm0[v];
-            hx[v] = hx0[v];
-          }
-        } else if (shx[v] >= 0) {
-          const float eymx = (v + 1 < VX) ? eym[v + 1] : eymn;
+          if (i >= nx) hx[v] = hx0[v];
+        } else if (sh >= 0) {
           const float eyx = (v + 1 < VX) ? eyc[v + 1] : eyn;
           const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
-          hzm[v] = hzm[v] + -psi_h(d, phi[0][1], nullptr, false, 0, i, i, j - 1, k, shx[v], eymx - eym[v]);
-          hy[v] = hy[v] + psi_h(d, phi[0][0], pho[0][0], true, 0, i, i, j, k, shx[v], ezx - ezc[v]);
-          hz[v] = hz[v] + -psi_h(d, phi[0][1], pho[0][1], true, 0, i, i, j, k, shx[v], eyx - eyc[v]);
+          const float ah = sTab[2][i], bh = sTab[3][i];
+          if (kh) {
+            const float py = pml_psi(sPsi[r][0][sh], ah, bh, ezx - ezc[v]);
+            hy[v] = hy[v] + py;
+            sPsi[r][0][sh] = py;
+          }
+          if (jh) {
+            const float pz = pml_psi(sPsi[r][1][sh], ah, bh, eyx - eyc[v]);
+            hz[v] = hz[v] + -pz;
+            sPsi[r][1][sh] = pz;
+          }
         }
       }
     }
-    as_stored<T, VX>(hxm);
-    as_stored<T, VX>(hzm);
+    if constexpr (G) {  // y and z layer terms (after the x term), then the wall masks
+      const float ahz = shz >= 0 ? d.ax[2].ah[k] : 0.f, bhz = shz >= 0 ? d.ax[2].bh[k] : 0.f;
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        const int i = ib + v;
+        const bool ux = i < nx && jh && kh, uy = i <= nx - 2 && kh, uz = i <= nx - 2 && jh;
+        if (shy >= 0) {
+          if (ux) {
+            const float p = pml_psi(qhxy[v], ahy, bhy, euz[v] - ezc[v]);
+            qhxy[v] = p;
+            hx[v] = hx[v] + -p;
+          }
+          if (uz) {
+            const float p = pml_psi(qhzy[v], ahy, bhy, eux[v] - exc[v]);
+            qhzy[v] = p;
+            hz[v] = hz[v] + p;
+          }
+        }
+        if (shz >= 0) {
+          if (ux) {
+            const float p = pml_psi(qhxz[v], ahz, bhz, nyc[v] - eyc[v]);
+            qhxz[v] = p;
+            hx[v] = hx[v] + p;
+          }
+          if (uy) {
+            const float p = pml_psi(qhyz[v], ahz, bhz, nxc[v] - exc[v]);
+            qhyz[v] = p;
+            hy[v] = hy[v] + -p;
+          }
+        }
+        if (!ux) hx[v] = hx0[v];
+        if (!uy) hy[v] = hy0[v];
+        if (!uz) hz[v] = hz0[v];
+      }
+    }
     as_stored<T, VX>(hx);
     as_stored<T, VX>(hy);
     as_stored<T, VX>(hz);
 
-    // ---- E^{n+1}(k) of row j
-    const float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
-    float oex[VX], oey[VX], oez[VX];
-#pragma unroll
-    for (int v = 0; v < VX; v++) {
-      const float hzw = (v > 0) ? hz[v - 1] : hzw0;
-      const float hyw = (v > 0) ? hy[v - 1] : hyw0;
-      oex[v] = e_plain(d.ca, exc[v], hz[v] - hzm[v], cey, hy[v] - hyp[v], cez);
-      oey[v] = e_plain(d.ca, eyc[v], hx[v] - hxp[v], cez, hz[v] - hzw, cex[v]);
-      oez[v] = e_plain(d.ca, ezc[v], hy[v] - hyw, cex[v], hx[v] - hxm[v], cey);
-    }
-    if (xfix) {
+    // publish Hx, Hz(k) of the own row for the row above
+    if (r < W) {
 #pragma unroll
       for (int v = 0; v < VX; v++) {
-        const int i = ib + v;
-        if (i >= nx - 1) {
-          oex[v] = exc[v];
-          oey[v] = eyc[v];
-          oez[v] = ezc[v];
-        } else if (i == 0) {
-          oey[v] = eyc[v];
-          oez[v] = ezc[v];
-        } else if (sex[v] >= 0) {
-          const float hzw = (v > 0) ? hz[v - 1] : hzw0;
-          const float hyw = (v > 0) ? hy[v - 1] : hyw0;
-          oey[v] = oey[v] + -psi_e(d, d.psi_e[0][0], 0, i, i, j, k, sex[v], hz[v] - hzw);
-          oez[v] = oez[v] + psi_e(d, d.psi_e[0][1], 0, i, i, j, k, sex[v], hy[v] - hyw);
+        sHx[r][ib + v] = hx[v];
+        sHz[r][ib + v] = hz[v];
+      }
+    }
+    __syncthreads();
+
+    if (own) {
+      // ---- E^{n+1}(k) of the own row
+      float hxm[VX], hzm[VX], cex[VX];
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        hxm[v] = sHx[r - 1][ib + v];
+        hzm[v] = sHz[r - 1][ib + v];
+        cex[v] = sTab[1][ib + v];
+      }
+      const float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
+      float oex[VX], oey[VX], oez[VX];
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+        const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+        oex[v] = e_plain(d.ca, exc[v], hz[v] - hzm[v], cey, hy[v] - hyp[v], cez);
+        oey[v] = e_plain(d.ca, eyc[v], hx[v] - hxp[v], cez, hz[v] - hzw, cex[v]);
+        oez[v] = e_plain(d.ca, ezc[v], hy[v] - hyw, cex[v], hx[v] - hxm[v], cey);
+      }
+      if (xfix) {
+#pragma unroll
+        for (int v = 0; v < VX; v++) {
+          const int i = ib + v;
+          const int se = __float_as_int(sTab[7][i]);
+          if (i >= nx - 1) {
+            oex[v] = exc[v];
+            oey[v] = eyc[v];
+            oez[v] = ezc[v];
+          } else if (i == 0) {
+            oey[v] = eyc[v];
+            oez[v] = ezc[v];
+          } else if (se >= 0) {
+            const float hzw = (v > 0) ? hz[v - 1] : hzw0;
+            const float hyw = (v > 0) ? hy[v - 1] : hyw0;
+            const float ae = sTab[4][i], be = sTab[5][i];
+            if (jh && ke) {
+              const float py = pml_psi(sPsi[r][2][se], ae, be, hz[v] - hzw);
+              oey[v] = oey[v] + -py;
+              sPsi[r][2][se] = py;
+            }
+            if (je && kh) {
+              const float pz = pml_psi(sPsi[r][3][se], ae, be, hy[v] - hyw);
+              oez[v] = oez[v] + pz;
+              sPsi[r][3][se] = pz;
+            }
+          }
+        }
+      }
+      if constexpr (G) {
+        const float aez = sez >= 0 ? d.ax[2].ae[k] : 0.f, bez = sez >= 0 ? d.ax[2].be[k] : 0.f;
+#pragma unroll
+        for (int v = 0; v < VX; v++) {
+          const int i = ib + v;
+          const bool ux = i <= nx - 2 && je && ke;
+          const bool uy = i >= 1 && i <= nx - 2 && jh && ke;
+          const bool uz = i >= 1 && i <= nx - 2 && je && kh;
+          if (sey >= 0) {
+            if (ux) {
+              const float p = pml_psi(qexy[v], aey, bey, hz[v] - hzm[v]);
+              qexy[v] = p;
+              oex[v] = oex[v] + p;
+            }
+            if (uz) {
+              const float p = pml_psi(qezy[v], aey, bey, hx[v] - hxm[v]);
+              qezy[v] = p;
+              oez[v] = oez[v] + -p;
+            }
+          }
+          if (sez >= 0) {
+            if (ux) {
+              const float p = pml_psi(qexz[v], aez, bez, hy[v] - hyp[v]);
+              qexz[v] = p;
+              oex[v] = oex[v] + -p;
+            }
+            if (uy) {
+              const float p = pml_psi(qeyz[v], aez, bez, hx[v] - hxp[v]);
+              qeyz[v] = p;
+              oey[v] = oey[v] + p;
+            }
+          }
+          if (!ux) oex[v] = exc[v];
+          if (!uy) oey[v] = eyc[v];
+          if (!uz) oez[v] = ezc[v];
+        }
+      }
+      st_at<T, VX>(Ho0 + pk, o0, hx, on);
+      st_at<T, VX>(Ho1 + pk, o0, hy, on);
+      st_at<T, VX>(Ho2 + pk, o0, hz, on);
+      st_at<T, VX>(Eo0 + pk, o0, oex, on);
+      st_at<T, VX>(Eo1 + pk, o0, oey, on);
+      st_at<T, VX>(Eo2 + pk, o0, oez, on);
+      // the row's x-slab psi back to memory (slab indices of wall nodes keep their values)
+      if (lane < np2) {
+        pho0[prow + lane] = sPsi[r][0][lane];
+        pho1[prow + lane] = sPsi[r][1][lane];
+        pe0[prow + lane] = sPsi[r][2][lane];
+        pe1[prow + lane] = sPsi[r][3][lane];
+      }
+      if constexpr (G) {
+        if (shy >= 0) {
+          st_row<float, VX>(d.psi_h[par ^ 1][1][0] + iyh, qhxy, on);
+          st_row<float, VX>(d.psi_h[par ^ 1][1][1] + iyh, qhzy, on);
+        }
+        if (shz >= 0) {
+          st_row<float, VX>(d.psi_h[par ^ 1][2][0] + izh, qhxz, on);
+          st_row<float, VX>(d.psi_h[par ^ 1][2][1] + izh, qhyz, on);
+        }
+        if (sey >= 0) {
+          st_row<float, VX>(d.psi_e[1][0] + iye, qexy, on);
+          st_row<float, VX>(d.psi_e[1][1] + iye, qezy, on);
+        }
+        if (sez >= 0) {
+          st_row<float, VX>(d.psi_e[2][0] + ize, qexz, on);
+          st_row<float, VX>(d.psi_e[2][1] + ize, qeyz, on);
         }
       }
     }
-    st_at<T, VX>(Ho0 + pk, o0, hx, on);
-    st_at<T, VX>(Ho1 + pk, o0, hy, on);
-    st_at<T, VX>(Ho2 + pk, o0, hz, on);
-    st_at<T, VX>(Eo0 + pk, o0, oex, on);
-    st_at<T, VX>(Eo1 + pk, o0, oey, on);
-    st_at<T, VX>(Eo2 + pk, o0, oez, on);
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       hxp[v] = hx[v];
       hyp[v] = hy[v];
-      exm[v] = nxm[v]; eym[v] = nym[v]; ezm[v] = nzm[v];
-      exc[v] = nxc[v]; eyc[v] = nyc[v]; ezc[v] = nzc[v];
-      exp_[v] = nxp[v]; ezp[v] = nzp[v];
+      exc[v] = nxc[v];
+      eyc[v] = nyc[v];
+      ezc[v] = nzc[v];
     }
   }
 }
-
 template <typename T, int VX, int W>
-__global__ void __launch_bounds__(64 * W) k_fused(Dev d, FusedShape fs, int par) {
+__global__ void __launch_bounds__(64 * (W + 1)) k_fused(Dev d, FusedShape fs, int par) {
   const int logical = xcd_logical();
   if (logical >= fs.n_fast) return;
   const int fw = fs.ty_hi - fs.ty_lo;
-  fused_body<T, VX, W>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+  fused_body<T, VX, W, false>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+}
+// Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep.
+template <typename T, int VX, int W>
+__global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen(Dev d, FusedShape fs, const int *tiles, int n, int par) {
+  const int logical = xcd_logical();
+  if (logical >= n) return;
+  fused_body<T, VX, W, true>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
 }
 
 // Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
 template <typename T, int VX, int W>
-__global__ void __launch_bounds__(64 * W) k_fused_batch(const Dev *devs, const int *zchunks, const int *tab,
+__global__ void __launch_bounds__(64 * (W + 1)) k_fused_batch(const Dev *devs, const int *zchunks, const int *tab,
                                                        int n, int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int pl = tab[3 * logical];
-  fused_body<T, VX, W>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
+  fused_body<T, VX, W, false>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
 }
 
 // --------------------------------------------------------------- split sweeps
@@ -704,27 +919,35 @@ __global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
 
 // ------------------------------------------------------------------ launch
 template <typename T, int VX, int W>
-static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
-  hipLaunchKernelGGL((k_fused<T, VX, W>), dim3(p.fs.fast_blocks), dim3(64 * W), 0, s, d, p.fs, par);
+static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+  if (general) {
+    if constexpr (VX <= kMaxGeneralVX)
+      hipLaunchKernelGGL((k_fused_gen<T, VX, W>), dim3(p.fs.slow_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs,
+                         d.slow_tiles, p.fs.n_slow, par);
+    else
+      return hipErrorInvalidValue;
+  } else
+    hipLaunchKernelGGL((k_fused<T, VX, W>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
   return hipGetLastError();
 }
 
 template <typename T, int VX>
-static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
+static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   switch (p.fs.waves) {
-    case 4: return fused_launch<T, VX, 4>(p, d, par, s);
-    case 8: return fused_launch<T, VX, 8>(p, d, par, s);
+    case 4: return fused_launch<T, VX, 4>(p, d, par, general, s);
+    case 8: return fused_launch<T, VX, 8>(p, d, par, general, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+// general = false: the interior rectangle; true: the boundary tiles of the tile table
 template <typename T>
-static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, hipStream_t s) {
+static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   switch (p.fs.vx) {
-    case 1: return fused_dispatch_w<T, 1>(p, d, par, s);
-    case 2: return fused_dispatch_w<T, 2>(p, d, par, s);
-    case 4: return fused_dispatch_w<T, 4>(p, d, par, s);
-    case 8: return fused_dispatch_w<T, 8>(p, d, par, s);
+    case 1: return fused_dispatch_w<T, 1>(p, d, par, general, s);
+    case 2: return fused_dispatch_w<T, 2>(p, d, par, general, s);
+    case 4: return fused_dispatch_w<T, 4>(p, d, par, general, s);
+    case 8: return fused_dispatch_w<T, 8>(p, d, par, general, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -734,34 +957,50 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
                          double *w, int column, int ld, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
   hipError_t e = hipSuccess;
   const Dev &d = d_in;
-  // interior rectangle in one fused sweep; the boundary tiles (or all tiles) in split sweeps,
-  // whose E pass reads the fresh H of both
-  // (both read only the input level and write disjoint nodes, so the boundary H sweep runs on a
-  // side stream beside the fused sweep; the boundary E sweep joins them)
   const int nxb = (d.nx + 63) / 64;
   const dim3 sgrid(p.fs.n_slow * nxb), sblock(64 * p.fs.waves);
-  const bool fork = p.fs.n_fast > 0 && p.fs.n_slow > 0 && p.aux;
-  if (fork) {
-    e = hipEventRecord(p.ev_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.ev_fork, 0);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, p.aux, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
-    e = hipEventRecord(p.ev_join, p.aux);
-    if (e != hipSuccess) return e;
-  }
-  if (p.fs.n_fast > 0) {
-    if (ev_a) e = hipEventRecord(ev_a, s);
-    if (e == hipSuccess) e = fused_dispatch<T>(p, d, par, s);
-    if (e == hipSuccess && ev_b) e = hipEventRecord(ev_b, s);
-  }
-  if (e != hipSuccess) return e;
-  if (p.fs.n_slow > 0) {
+  if (p.kernel == CHF_KERNEL_FUSED) {
+    // The interior rectangle in one fused sweep; the boundary tiles in the general fused sweep
+    // (or, for rows wider than 256 nodes, in split H and E sweeps).  Both read only the input
+    // level and write disjoint nodes, so the boundary sweep (its H half, when split) runs on
+    // the side stream beside the interior one.
+    const bool gen = p.fs.vx <= kMaxGeneralVX;
+    const bool fork = p.fs.n_fast > 0 && p.fs.n_slow > 0 && p.aux;
     if (fork) {
-      e = hipStreamWaitEvent(s, p.ev_join, 0);
+      e = hipEventRecord(p.ev_fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.ev_fork, 0);
+      if (e == hipSuccess) {
+        if (gen) {
+          e = fused_dispatch<T>(p, d, par, true, p.aux);
+        } else {
+          hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, p.aux, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+          e = hipGetLastError();
+        }
+      }
+      if (e == hipSuccess) e = hipEventRecord(p.ev_join, p.aux);
       if (e != hipSuccess) return e;
-    } else {
-      hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     }
+    if (p.fs.n_fast > 0) {
+      if (ev_a) e = hipEventRecord(ev_a, s);
+      if (e == hipSuccess) e = fused_dispatch<T>(p, d, par, false, s);
+      if (e == hipSuccess && ev_b) e = hipEventRecord(ev_b, s);
+      if (e != hipSuccess) return e;
+    }
+    if (p.fs.n_slow > 0) {
+      if (fork) {
+        e = hipStreamWaitEvent(s, p.ev_join, 0);
+      } else if (gen) {
+        e = fused_dispatch<T>(p, d, par, true, s);
+      } else {
+        hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+      }
+      if (e == hipSuccess && !gen)
+        hipLaunchKernelGGL((k_split<T, false>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
+      if (e == hipSuccess) e = hipGetLastError();
+    }
+  } else if (p.fs.n_slow > 0) {
+    // split sweeps over every tile: H, then E reading the fresh H
+    hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     hipLaunchKernelGGL((k_split<T, false>), sgrid, sblock, 0, s, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
     e = hipGetLastError();
   }
@@ -795,7 +1034,7 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
   const int n = (int)(b.fast_tab.size() / 3);
   if (n == 0) return hipSuccess;
   const int blocks = (n + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused_batch<T, VX, W>), dim3(blocks), dim3(64 * W), 0, s, devs, z,
+  hipLaunchKernelGGL((k_fused_batch<T, VX, W>), dim3(blocks), dim3(64 * (W + 1)), 0, s, devs, z,
                      (const int *)(b.ws + b.off_fast), n, par);
   return hipGetLastError();
 }

@@ -1,0 +1,31 @@
+"""Tile-shape autotuner: every candidate reproduces the same waveforms bit for bit, the fastest
+is cached by shape, and a tuned plan still matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_5341_amd import autotune
+from paper_1001_5341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CANDS = [(4, 8), (8, 16), (4, 150), (8, 5)]
+
+
+def test_autotune_verifies_caches_and_matches_oracle(gpu, tmp_path):
+    w = W.small_shower()
+    path = str(tmp_path / "tune.json")
+    print(f"\n[gpu-autotune] {w.name}", flush=True)
+    first = autotune.tune(w, "fp32", steps=40, cache_path=path, candidates=CANDS)
+    assert not first["cached"]
+    timed = [t for t in first["trials"] if "ms_per_step" in t]
+    assert len(timed) == len(CANDS) and all(t["bitwise_equal"] for t in timed)
+    assert (first["waves"], first["z_chunk"]) in CANDS
+    again = autotune.tune(w, "fp32", steps=40, cache_path=path, candidates=CANDS)
+    assert again["cached"] and (again["waves"], again["z_chunk"]) == (first["waves"], first["z_chunk"])
+    plan = autotune.tuned_plan(w, "fp32", cache_path=path, candidates=CANDS)
+    got = plan.run().cpu().numpy()
+    plan.close()
+    ref = oracle.run(w)
+    err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
+    assert np.all(err <= 1e-5), err

@@ -167,11 +167,23 @@ def roofline(info, fused_ms: float, launches: int):
     achieved = alg / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "kernel": "chf::k_fused (fused interior H/E sweep, one launch per Yee step)",
+            "kernel": "chf::k_fused (fused H/E sweep of the interior rectangle, one launch per Yee step)",
             "launch_avg_us": round(avg_s * 1e6, 2), "launches": launches,
             "cells_per_launch": int(info["fused_cells"]),
             "bytes_per_cell": round(info["fused_bytes_per_cell"], 3),
             "alg_bytes_per_launch": int(alg)}
+
+
+def tile_shape(w, storage: str, args):
+    """(waves, z_chunk): given on the command line, else from the autotuner (cached by shape)."""
+    if args.waves or args.zchunk or args.kernel == "split" or args.no_tune:
+        return args.waves, args.zchunk, False
+    from paper_1001_5341_amd import autotune
+
+    t = autotune.tune(w, storage)
+    log(f"{storage}: tuned tile waves={t['waves']} z_chunk={t['z_chunk']} "
+        f"({'cached' if t['cached'] else 'measured'}, {t['ms_per_step']:.3f} ms/step)")
+    return t["waves"], t["z_chunk"], True
 
 
 def run_variant(w, storage: str, args, n_runs: int, warmup: int):
@@ -179,8 +191,9 @@ def run_variant(w, storage: str, args, n_runs: int, warmup: int):
 
     from paper_1001_5341_amd import solver
 
-    plan = solver.Plan(w, storage=storage, kernel=args.kernel, rows=args.rows, waves=args.waves,
-                       zchunk=args.zchunk, device=torch.device("cuda:0"))
+    waves, zchunk, tuned = tile_shape(w, storage, args)
+    plan = solver.Plan(w, storage=storage, kernel=args.kernel, rows=args.rows, waves=waves,
+                       zchunk=zchunk, device=torch.device("cuda:0"))
     info = plan.info()
     out = plan.new_waveforms()
     for i in range(warmup):
@@ -191,6 +204,7 @@ def run_variant(w, storage: str, args, n_runs: int, warmup: int):
         f"fused sweep {fused_ms / launches * 1e3:.1f} us/launch")
     got = out.cpu().numpy()
     plan.close()
+    info["tuned"] = tuned
     return info, wall, ev_s, fused_ms, launches, got
 
 
@@ -206,6 +220,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--time-steps", type=int, default=0, help="override the Yee steps per run")
+    ap.add_argument("--no-tune", action="store_true", help="default tile shape instead of the autotuner's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/FP16 storage runs")
     ap.add_argument("--copy-probe", action="store_true",
@@ -264,9 +279,9 @@ def main():
         "data": "synthetic (seeded Greisen-like shower profile and observers; no datasets)",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "yee_steps_per_run": w.n_steps,
                    "boundary": f"{w.bc}{w.npml}", "observers": w.n_obs, "storage": args.storage,
-                   "kernel": {1: "split", 2: "fused+split boundary tiles"}[info["kernel"]],
+                   "kernel": {1: "split H/E sweeps", 2: "fused sweep (interior + boundary tiles)"}[info["kernel"]],
                    "tile": {"vx": info["vx"], "waves_per_block": info["waves_per_block"],
-                            "z_chunk": info["z_chunk"]},
+                            "z_chunk": info["z_chunk"], "autotuned": info["tuned"]},
                    "parallelism": "single GPU"},
         "roofline": roof,
     }

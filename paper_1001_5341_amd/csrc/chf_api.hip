@@ -516,9 +516,6 @@ chf_status chf_plan_reset(chf_plan *p, void *stream) {
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
   hipError_t e = chf::launch_zero(*p, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reset");
-  int zero = 0;
-  e = hipMemcpyAsync(p->dev.nan_flag, &zero, sizeof(int), hipMemcpyHostToDevice, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "reset of the watchdog flag");
   p->parity = 0;
   p->n_done = 0;
   return CHF_OK;

@@ -138,19 +138,22 @@ __device__ __forceinline__ float psi_e(const Dev &d, float *p, int u, int pos, i
 }
 
 // --------------------------------------------------------------- fused sweep
-// One wave owns one y row of the full x extent (64 lanes x VX cells, nx <= 64 VX) and marches
-// a z chunk; a workgroup holds W waves over W consecutive rows.  Waves are independent (no LDS,
-// no barriers): each recomputes the H row below its own (the E update needs H^{n+1/2}(j-1))
-// and reads the E row above it, so neighbouring rows are read by two waves, mostly from L2.
-// x neighbours move between lanes with shuffles.  Plane base pointers are wave-uniform and
-// in-plane offsets 32-bit.  Workgroups are ordered so that consecutive logical tiles
-// (neighbours in y, then in z) land on the same XCD and share its L2.
+// One Yee step in a single pass over the fields: a workgroup owns W consecutive y rows of the
+// full x extent (64 lanes x VX nodes per row, nx <= 64 VX) and marches a z chunk, updating H
+// then E plane by plane.  Each wave loads only its own row (E at k+1, H at k: 6 vector loads
+// per plane); the y neighbours it needs -- Ex, Ez of the row above for H, Hx, Hz of the row
+// below for E -- come from the neighbouring waves through LDS, with two barriers per plane.
+// One extra wave per workgroup computes the H row below the tile (read by the tile's first
+// row) and stores nothing.  x neighbours move between lanes with shuffles.  Plane base
+// pointers are wave-uniform and in-plane offsets 32-bit.  Workgroups are ordered so that
+// consecutive logical tiles (neighbours in y, then in z) land on the same XCD and share its L2.
 //
-// The launch covers the rectangle of tiles whose rows and planes (and the row and plane below
-// them) lie clear of the walls and of the y/z layers; the other tiles go to the split sweeps
-// (k_split_h / k_split_e over a tile table).  Every node here is updated except at the x walls:
-// nodes take the unmasked update, lanes holding x-layer nodes add the x CPML term, and x-wall /
-// padding nodes keep their old values -- the canonical sequence of the general path.
+// k_fused covers the rectangle of tiles whose rows and planes (and the row and plane below
+// them) lie clear of the walls and of the y/z layers: every node takes the unmasked update,
+// lanes holding x-layer nodes add the x CPML term, x-wall / padding nodes keep their old
+// values.  k_fused_gen covers the remaining tiles from a table, with the wall masks of every
+// component and the y/z CPML terms (uniform per row and per plane).  Both apply the canonical
+// per-node sequence, as the split sweeps do.
 // Logical tile of this workgroup: consecutive logical tiles on one XCD (the hardware deals
 // workgroups to the 8 XCDs round-robin).
 __device__ __forceinline__ int xcd_logical() {
@@ -600,10 +603,10 @@ __global__ void __launch_bounds__(64 * (W + 1)) k_fused_batch(const Dev *devs, c
 }
 
 // --------------------------------------------------------------- split sweeps
-// Tiles outside the fused rectangle (walls and CPML layers), or every tile when the split
-// sweeps are selected: a workgroup of 64 x W threads covers 64 nodes of the W rows of one tile
-// and marches its z chunk, one thread per (i, j) column; H then E in two launches.  Same
-// canonical per-node arithmetic as the fused sweep.
+// Every tile when the split sweeps are selected (and the boundary tiles of fused plans whose
+// rows are wider than 256 nodes): a workgroup of 64 x W threads covers 64 nodes of the W rows
+// of one tile and marches its z chunk, one thread per (i, j) column; H then E in two launches.
+// Same canonical per-node arithmetic as the fused sweeps.
 template <typename T>
 __device__ __forceinline__ void split_h_body(const Dev &d, int i, int j, int k0, int k1, int par);
 template <typename T>
@@ -1108,6 +1111,8 @@ hipError_t launch_zero(const chf_plan &p, hipStream_t s) {
   // fields and psi occupy [0, off_tf) of the workspace (16-byte multiples)
   const long long n16 = (long long)(p.off_tf / 16);
   hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, (uint4 *)p.ws, n16);
+  // and the watchdog flag (a kernel, not a memset/copy, so that graphs may capture it)
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, s, (uint4 *)(p.ws + p.off_nan), 16LL);
   return hipGetLastError();
 }
 

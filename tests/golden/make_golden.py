@@ -1,7 +1,10 @@
 """Writes stored oracle waveforms for the full-size parity tests.
 
 Calls only the FP64 oracle (``oracle/``) and the seeded workload generator; no value here
-comes from the HIP path.  Usage:  python tests/golden/make_golden.py single-shower
+comes from the HIP path.  Usage:
+    python tests/golden/make_golden.py single-shower   # 256x256x2048, 4000 steps
+    python tests/golden/make_golden.py adjoint         # 128x128x1024, 3000 steps: w*, dL/dq
+    python tests/golden/make_golden.py batch           # sampled members of the 32-shower batch
 """
 import json
 import os
@@ -32,5 +35,43 @@ def main(name: str):
                       "cell_updates_per_s": w.n_cells * w.n_steps / wall}))
 
 
+# members of the 32-shower batch whose waveforms are stored (the oracle cannot afford all 32)
+BATCH_SAMPLE = (2, 5, 20)
+
+
+def adjoint_golden():
+    """Target waveforms w* = A q* and the FP64 adjoint gradient of L = sum (A q - w*)^2 at the
+    perturbed profile q, for the differentiation workload."""
+    w, q_target = W.adjoint_problem()
+    t0 = time.time()
+    w_star = oracle.run(w, q_bins=q_target)
+    w_q = oracle.run(w)
+    grad = oracle.adjoint(w, 2.0 * (w_q - w_star))
+    wall = time.time() - t0
+    path = os.path.join(HERE, "adjoint_oracle.npz")
+    np.savez_compressed(path, w_star=w_star.astype(np.float32), w_q=w_q.astype(np.float32),
+                        dl_dq=grad, q_target=q_target, digest=workload_digest(w), wall_s=wall)
+    print(json.dumps({"written": path, "wall_s": wall, "grad_norm": float(np.linalg.norm(grad))}))
+
+
+def batch_golden():
+    ws = W.batch_showers()
+    out = {}
+    t0 = time.time()
+    for m in BATCH_SAMPLE:
+        out[f"member{m}"] = oracle.run(ws[m]).astype(np.float32)
+        out[f"digest{m}"] = workload_digest(ws[m])
+        print(json.dumps({"member": m, "name": ws[m].name, "elapsed_s": time.time() - t0}), flush=True)
+    path = os.path.join(HERE, "batch_oracle.npz")
+    np.savez_compressed(path, members=np.array(BATCH_SAMPLE), wall_s=time.time() - t0, **out)
+    print(json.dumps({"written": path}))
+
+
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "single-shower")
+    what = sys.argv[1] if len(sys.argv) > 1 else "single-shower"
+    if what == "adjoint":
+        adjoint_golden()
+    elif what == "batch":
+        batch_golden()
+    else:
+        main(what)

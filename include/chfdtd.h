@@ -169,6 +169,25 @@ chf_status chf_forward_graph(chf_plan *plan, void *stream, const double *q_bins_
    is destroyed (the workspace holds the adjoint state). */
 chf_status chf_adjoint(chf_plan *plan, void *stream, const double *dl_dw_dev, double *dl_dq_dev);
 
+/* The same adjoint in pieces, for checkpointed schedules: chf_adjoint_begin zeroes the adjoint
+   state and dL/dq; chf_adjoint_steps then applies the transposed steps t_hi-1 down to t_lo
+   (0 <= t_lo <= t_hi <= n_steps), accumulating into dL/dq.  Successive calls must continue
+   where the previous one stopped (t_hi of a call = t_lo of the previous; the first call after
+   begin has t_hi = n_steps), else CHF_ESTATE.  begin + steps(0, n_steps) = chf_adjoint. */
+chf_status chf_adjoint_begin(chf_plan *plan, void *stream, double *dl_dq_dev);
+chf_status chf_adjoint_steps(chf_plan *plan, void *stream, const double *dl_dw_dev, double *dl_dq_dev,
+                             int32_t t_lo, int32_t t_hi);
+
+/* Forward-state snapshots (checkpoints, resume).  A snapshot is the plan's whole field and
+   CPML state -- both time levels of E and H and every psi array -- as a DEVICE byte image of
+   chf_plan_state_bytes bytes owned by the caller.  save copies it out (stream-ordered) and
+   reports the step it belongs to; load copies it back and sets the step (and with it the
+   source clock and the current time level).  Restarting from a snapshot reproduces the run
+   bit for bit. */
+chf_status chf_plan_state_bytes(const chf_plan *plan, uint64_t *bytes);
+chf_status chf_plan_save_state(chf_plan *plan, void *stream, void *dst_dev, int32_t *step);
+chf_status chf_plan_load_state(chf_plan *plan, void *stream, const void *src_dev, int32_t step);
+
 /* Wait for `stream` and report a kernel fault (CHF_EHIP) or the watchdog (CHF_ENAN). */
 chf_status chf_plan_sync(chf_plan *plan, void *stream);
 

@@ -518,6 +518,7 @@ chf_status chf_plan_reset(chf_plan *p, void *stream) {
   if (e != hipSuccess) return hip_fail(e, "reset");
   p->parity = 0;
   p->n_done = 0;
+  p->adj_next = -1;
   return CHF_OK;
 }
 
@@ -525,6 +526,7 @@ chf_status chf_forward(chf_plan *p, void *stream, const double *q_bins_dev, doub
                        int32_t first_column, int32_t ld_steps) {
   if (!p) return fail(CHF_EINVAL, "NULL plan");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  p->adj_next = -1;
   if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
   if (p->dev.n_obs > 0 && w_dev && (ld_steps < first_column + n_steps))
     return fail(CHF_EINVAL, "ld_steps too small for first_column + n_steps");
@@ -544,6 +546,7 @@ chf_status chf_forward_timed(chf_plan *p, void *stream, const double *q_bins_dev
                              int32_t first_column, int32_t ld_steps, double *fused_ms) {
   if (!p || !fused_ms) return fail(CHF_EINVAL, "NULL argument");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  p->adj_next = -1;
   if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
   if (p->dev.n_obs > 0 && w_dev && (ld_steps < first_column + n_steps))
     return fail(CHF_EINVAL, "ld_steps too small for first_column + n_steps");
@@ -577,6 +580,7 @@ chf_status chf_forward_timed(chf_plan *p, void *stream, const double *q_bins_dev
 chf_status chf_forward_graph(chf_plan *p, void *stream, const double *q_bins_dev, double *w_dev) {
   if (!p) return fail(CHF_EINVAL, "NULL plan");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  p->adj_next = -1;
   hipStream_t s = (hipStream_t)stream;
   const int T = p->grid.n_steps;
   if (!p->graph || p->graph_w != w_dev || p->graph_q != q_bins_dev) {
@@ -688,21 +692,68 @@ chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
   return CHF_OK;
 }
 
-chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev) {
-  if (!p || !dl_dq_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
+chf_status chf_adjoint_begin(chf_plan *p, void *stream, double *dl_dq_dev) {
+  if (!p || !dl_dq_dev) return fail(CHF_EINVAL, "NULL argument");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
   if (p->bnd.kind == CHF_BC_MUR1) return fail(CHF_EUNSUPPORTED, "adjoint of the Mur boundary is not implemented");
   if (p->storage != CHF_FP32) return fail(CHF_EUNSUPPORTED, "adjoint needs FP32 field storage");
   hipStream_t s = (hipStream_t)stream;
-  // the workspace now holds the adjoint state: zero fields and psi, then run the transposed
-  // steps from the last to the first
+  // the workspace now holds the adjoint state: zero fields and psi
   hipError_t e = chf::launch_zero(*p, s);
   if (e == hipSuccess) e = chf::launch_adjoint_init(*p, dl_dq_dev, s);
-  for (int n = p->grid.n_steps - 1; n >= 0 && e == hipSuccess; n--)
-    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, s);
-  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  if (e != hipSuccess) return hip_fail(e, "adjoint start");
   p->parity = 0;
   p->n_done = 0;
+  p->adj_next = p->grid.n_steps;
+  return CHF_OK;
+}
+
+chf_status chf_adjoint_steps(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev, int32_t t_lo,
+                             int32_t t_hi) {
+  if (!p || !dl_dq_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (t_lo < 0 || t_lo > t_hi || t_hi > p->grid.n_steps) return fail(CHF_EINVAL, "bad step range");
+  if (p->adj_next < 0 || t_hi != p->adj_next)
+    return fail(CHF_ESTATE, "adjoint steps must continue where the previous call stopped");
+  hipError_t e = hipSuccess;
+  for (int n = t_hi - 1; n >= t_lo && e == hipSuccess; n--)
+    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  p->adj_next = t_lo;
+  return CHF_OK;
+}
+
+chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev) {
+  if (!p || !dl_dq_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
+  chf_status st = chf_adjoint_begin(p, stream, dl_dq_dev);
+  if (st != CHF_OK) return st;
+  return chf_adjoint_steps(p, stream, dl_dw_dev, dl_dq_dev, 0, p->grid.n_steps);
+}
+
+chf_status chf_plan_state_bytes(const chf_plan *p, uint64_t *bytes) {
+  if (!p || !bytes) return fail(CHF_EINVAL, "NULL argument");
+  *bytes = p->off_tf;  // fields and psi lead the workspace
+  return CHF_OK;
+}
+
+chf_status chf_plan_save_state(chf_plan *p, void *stream, void *dst_dev, int32_t *step) {
+  if (!p || !dst_dev || !step) return fail(CHF_EINVAL, "NULL argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipError_t e = hipMemcpyAsync(dst_dev, p->ws, p->off_tf, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "save state");
+  *step = p->n_done;
+  return CHF_OK;
+}
+
+chf_status chf_plan_load_state(chf_plan *p, void *stream, const void *src_dev, int32_t step) {
+  if (!p || !src_dev) return fail(CHF_EINVAL, "NULL argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (step < 0) return fail(CHF_EINVAL, "negative step");
+  hipError_t e = hipMemcpyAsync(p->ws, src_dev, p->off_tf, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "load state");
+  p->n_done = step;
+  p->parity = step & 1;
+  p->adj_next = -1;
   return CHF_OK;
 }
 

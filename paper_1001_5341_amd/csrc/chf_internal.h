@@ -103,6 +103,7 @@ struct chf_plan {
   chf::Dev dev;
   int parity = 0;   // time level holding the current state
   int n_done = 0;   // steps advanced since the last reset (source clock)
+  int adj_next = -1;  // next adjoint step range ends here (-1: no adjoint in progress)
   double scale_e = 1.0, scale_h = 1.0;
   double ca, cb, db;
   // side stream for the boundary H sweep, which runs beside the fused interior sweep

@@ -6,6 +6,7 @@ allocates the caller-owned workspace and output tensors, and picks the stream.
 from __future__ import annotations
 
 import ctypes as ct
+import math
 from typing import Optional, Sequence
 
 import numpy as np
@@ -152,6 +153,32 @@ class Plan:
                                     ct.c_void_p(out.data_ptr())), "chf_adjoint")
         return out
 
+    def adjoint_begin(self, dl_dq: torch.Tensor, stream=None):
+        N.check(N.lib().chf_adjoint_begin(self._h, _stream_handle(stream), ct.c_void_p(dl_dq.data_ptr())),
+                "chf_adjoint_begin")
+
+    def adjoint_steps(self, dl_dw: torch.Tensor, dl_dq: torch.Tensor, t_lo: int, t_hi: int, stream=None):
+        N.check(N.lib().chf_adjoint_steps(self._h, _stream_handle(stream), ct.c_void_p(dl_dw.data_ptr()),
+                                          ct.c_void_p(dl_dq.data_ptr()), t_lo, t_hi), "chf_adjoint_steps")
+
+    # -- snapshots of the whole field + CPML state
+    def state_bytes(self) -> int:
+        n = ct.c_uint64()
+        N.check(N.lib().chf_plan_state_bytes(self._h, ct.byref(n)), "chf_plan_state_bytes")
+        return int(n.value)
+
+    def save_state(self, dst: torch.Tensor, stream=None) -> int:
+        assert dst.dtype == torch.uint8 and dst.is_contiguous() and dst.numel() >= self.state_bytes()
+        step = ct.c_int32()
+        N.check(N.lib().chf_plan_save_state(self._h, _stream_handle(stream), ct.c_void_p(dst.data_ptr()),
+                                            ct.byref(step)), "chf_plan_save_state")
+        return int(step.value)
+
+    def load_state(self, src: torch.Tensor, step: int, stream=None):
+        assert src.dtype == torch.uint8 and src.is_contiguous() and src.numel() >= self.state_bytes()
+        N.check(N.lib().chf_plan_load_state(self._h, _stream_handle(stream), ct.c_void_p(src.data_ptr()), step),
+                "chf_plan_load_state")
+
     # -- field access (physical units, [nz, ny, nx] FP32)
     def get_field(self, comp: int, stream=None) -> torch.Tensor:
         out = torch.empty((self.w.nz, self.w.ny, self.w.nx), dtype=torch.float32, device=self.device)
@@ -216,26 +243,74 @@ class Batch:
             pass
 
 
+def checkpointed_adjoint(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int] = None,
+                         verify: bool = True, q_bins: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """dL/dq by checkpointed recomputation: a forward run on a second workspace keeps a
+    snapshot every `every` steps (default ceil(sqrt(T))); the reverse sweep then takes the
+    segments last to first, restores each segment's snapshot, recomputes its forward steps
+    (with the profile q_bins the forward run used, default the plan's)
+    and applies the transposed steps of that segment to the adjoint state.  With verify, every
+    recomputed segment must end on the next snapshot bit for bit (a determinism check).
+
+    The profile map is linear with zero initial fields, so the transposed steps do not read
+    the recomputed forward states: the result is bitwise that of Plan.adjoint.  The schedule
+    is the one gradients with respect to non-linear parameters need."""
+    T = plan.n_steps
+    K = max(1, every or math.ceil(math.sqrt(T)))
+    n_seg = (T + K - 1) // K
+    fwd = Plan(plan.w, storage=plan.storage, device=plan.device)
+    try:
+        nbytes = fwd.state_bytes()
+        snaps = torch.empty((n_seg, nbytes), dtype=torch.uint8, device=plan.device)
+        fwd.reset(stream)
+        for s_ in range(n_seg):
+            fwd.save_state(snaps[s_], stream)
+            fwd.forward(min(K, T - s_ * K), None, 0, q_bins, stream)
+        dl_dw = dl_dw.to(torch.float64).contiguous()
+        dq = torch.zeros(len(plan.w.q_bins), dtype=torch.float64, device=plan.device)
+        tail = torch.empty(nbytes, dtype=torch.uint8, device=plan.device) if verify else None
+        plan.adjoint_begin(dq, stream)
+        for s_ in reversed(range(n_seg)):
+            t0, t1 = s_ * K, min((s_ + 1) * K, T)
+            fwd.load_state(snaps[s_], t0, stream)
+            fwd.forward(t1 - t0, None, 0, q_bins, stream)
+            if verify and s_ + 1 < n_seg:
+                fwd.save_state(tail, stream)
+                if not torch.equal(tail, snaps[s_ + 1]):
+                    raise RuntimeError(f"recomputed segment {s_} does not reproduce its snapshot")
+            plan.adjoint_steps(dl_dw, dq, t0, t1, stream)
+        plan.sync(stream)
+        return dq
+    finally:
+        fwd.close()
+
+
 class CherenkovFDTD(torch.autograd.Function):
     """Waveforms as a differentiable function of the longitudinal profile bins.
 
     forward:  w = A q  (the full run from zero fields; FP64 waveforms [n_obs, 3, n_steps])
     backward: dL/dq = A^T dL/dw by the library's discrete adjoint (exact transpose of the
-              forward recurrence run backward in time).  The map is linear in q, so no forward
-              field state is needed for this gradient."""
+              forward recurrence run backward in time), either in one reverse sweep or, with
+              checkpoint_every, by checkpointed recomputation (checkpointed_adjoint)."""
 
     @staticmethod
-    def forward(ctx, q_bins: torch.Tensor, plan: "Plan"):
+    def forward(ctx, q_bins: torch.Tensor, plan: "Plan", checkpoint_every: Optional[int] = None):
         ctx.plan = plan
+        ctx.every = checkpoint_every
         q = q_bins.detach().to(device=plan.device, dtype=torch.float64).contiguous()
+        ctx.q = q
         return plan.run(q_bins=q)
 
     @staticmethod
     def backward(ctx, grad_w: torch.Tensor):
-        dq = ctx.plan.adjoint(grad_w.to(torch.float64).contiguous())
-        ctx.plan.sync()
-        return dq, None
+        g = grad_w.to(torch.float64).contiguous()
+        if ctx.every:
+            dq = checkpointed_adjoint(ctx.plan, g, every=ctx.every, q_bins=ctx.q)
+        else:
+            dq = ctx.plan.adjoint(g)
+            ctx.plan.sync()
+        return dq, None, None
 
 
-def waveforms(q_bins: torch.Tensor, plan: "Plan") -> torch.Tensor:
-    return CherenkovFDTD.apply(q_bins, plan)
+def waveforms(q_bins: torch.Tensor, plan: "Plan", checkpoint_every: Optional[int] = None) -> torch.Tensor:
+    return CherenkovFDTD.apply(q_bins, plan, checkpoint_every)

@@ -122,3 +122,21 @@ def test_plan_info_layout():
         assert info.scale_h == 256.0 and info.scale_e == 1.0
     finally:
         N.lib().chf_plan_destroy(h)
+
+
+def test_snapshot_size_and_adjoint_state_checks():
+    """Host-side checks of the checkpoint entry points (no device call is made)."""
+    h = solver.create_plan_handle(W.small_shower())
+    try:
+        info = N.PlanInfo()
+        assert N.lib().chf_plan_get_info(h, ct.byref(info)) == 0
+        n = ct.c_uint64()
+        assert N.lib().chf_plan_state_bytes(h, ct.byref(n)) == 0
+        # a snapshot is both field levels plus every psi array
+        assert n.value == info.field_bytes + info.psi_bytes
+        step = ct.c_int32()
+        assert N.STATUS[N.lib().chf_plan_save_state(h, None, ct.c_void_p(1), ct.byref(step))] == "CHF_ESTATE"
+        assert N.STATUS[N.lib().chf_adjoint_steps(h, None, ct.c_void_p(1), ct.c_void_p(1), 0, 5)] == "CHF_ESTATE"
+        assert N.STATUS[N.lib().chf_plan_load_state(h, None, None, 0)] == "CHF_EINVAL"
+    finally:
+        N.lib().chf_plan_destroy(h)

@@ -5,7 +5,8 @@ oracle):
 - single shower 256x256x2048, CPML-10, 4000 steps, 64 observers: every waveform;
 - the 32-shower batch (uneven grids up to 256x256x1024, 2000 steps, 16 observers each), run
   as one batch: the sampled members the oracle can afford;
-- differentiation 128x128x1024, 3000 steps, 128 profile bins: waveforms and dL/dq.
+- differentiation 128x128x1024, 3000 steps, 128 profile bins: waveforms and dL/dq, by the
+  one-sweep and the checkpointed (every 55 steps) adjoint.
 
 The precision grid (512x512x4096) is beyond the oracle here (10 h and ~60 GB of host memory);
 it is checked through properties that hold at any size: tile-shape and sweep-variant
@@ -83,8 +84,15 @@ def test_adjoint_full_size_against_stored_oracle(gpu):
     print("waveforms rel L2 max", err.max(), flush=True)
     assert np.all(err <= 1e-5), err
     w_star = torch.from_numpy(rec["w_star"].astype(np.float64)).to(w_q.device)
-    grad = plan.adjoint(2.0 * (w_q - w_star)).cpu().numpy()
+    dl_dw = 2.0 * (w_q - w_star)
+    grad = plan.adjoint(dl_dw)
+    plan.sync()
+    # the checkpointed schedule (a snapshot every 55 steps, segments recomputed in reverse)
+    # gives the same bits
+    grad_ck = solver.checkpointed_adjoint(plan, dl_dw, every=55)
     plan.close()
+    assert torch.equal(grad_ck, grad)
+    grad = grad.cpu().numpy()
     ref = rec["dl_dq"]
     gerr = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
     print("dL/dq rel L2", gerr, flush=True)

@@ -111,9 +111,11 @@ typedef struct {
 
 /* Execution choices.  storage: field storage type (arithmetic is always FP32; waveforms are
    accumulated in FP64).  scale_e / scale_h: power-of-two storage scales (0 = automatic).
-   kernel: split E/H sweeps or the fused single sweep.  rows_per_wave, waves_per_block and
-   z_chunk shape the fused sweep (0 = default).  nan_watch: check waveforms for
-   non-finite values every step. */
+   kernel: split E/H sweeps or the fused single sweep.  waves_per_block is the number of y
+   rows per tile (4, 7, 8 or 15; 4 or 7 for rows wider than 256 nodes; a fused workgroup has
+   one more wave for the row below the tile) and z_chunk the planes per tile (0 = defaults:
+   7 rows, 12 planes); rows_per_wave must be 0 or 1.  None of these changes
+   a result bit.  nan_watch: check waveforms for non-finite values every step. */
 typedef struct {
   int32_t storage, kernel;
   int32_t rows_per_wave, waves_per_block, z_chunk, nan_watch;

@@ -20,7 +20,7 @@ import torch
 from . import _native as N
 from . import solver
 
-CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((w, z) for w in (4, 8) for z in (8, 12, 16, 24, 32))
+CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((w, z) for w in (4, 7, 8, 15) for z in (8, 12, 16, 24, 32))
 
 
 def default_cache_path() -> str:

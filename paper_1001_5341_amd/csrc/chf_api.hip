@@ -142,15 +142,17 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   fs.vx = 1;
   while (64 * fs.vx < G.nx) fs.vx *= 2;
   fs.rows = 1;
-  fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : (fs.vx <= 4 ? 8 : 4);
-  fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 16;
-  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) || !(fs.waves == 4 || fs.waves == 8)) {
+  // defaults: 7 rows (8 waves: two workgroups fill a CU at 4 waves per SIMD), 12 planes
+  fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 7;
+  fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 12;
+  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) ||
+      !(fs.waves == 4 || fs.waves == 7 || fs.waves == 8 || fs.waves == 15)) {
     delete p;
-    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4 or 8");
+    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 7, 8 or 15");
   }
-  if (kernel == CHF_KERNEL_FUSED && fs.vx > 4 && fs.waves != 4) {
+  if (kernel == CHF_KERNEL_FUSED && fs.vx > 4 && fs.waves != 4 && fs.waves != 7) {
     delete p;
-    return fail(CHF_EINVAL, "the fused sweep over rows wider than 256 nodes takes waves_per_block 4");
+    return fail(CHF_EINVAL, "the fused sweep over rows wider than 256 nodes takes waves_per_block 4 or 7");
   }
   if ((int64_t)((G.nx + 15) / 16 * 16) * G.ny >= ((int64_t)1 << 31)) {
     delete p;
@@ -178,12 +180,18 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     fs.n_fast = (fs.ty_hi - fs.ty_lo) * (fs.zc_hi - fs.zc_lo);
     fs.fast_blocks = (fs.n_fast + 7) / 8 * 8;
     fs.n_layer = fs.layer_blocks = 0;
-    for (int zc = 0; zc < fs.nzc; zc++)
-      for (int ty = 0; ty < fs.nty; ty++) {
-        if (ty >= fs.ty_lo && ty < fs.ty_hi && zc >= fs.zc_lo && zc < fs.zc_hi) continue;
-        p->slow_tiles.push_back(ty);
-        p->slow_tiles.push_back(zc);
-      }
+    // boundary tiles: first those whose chunk lies in the interior z range (y walls and layers
+    // only), then the rest
+    for (int pass = 0; pass < 2; pass++) {
+      for (int zc = 0; zc < fs.nzc; zc++)
+        for (int ty = 0; ty < fs.nty; ty++) {
+          const bool zin = zc >= fs.zc_lo && zc < fs.zc_hi;
+          if ((ty >= fs.ty_lo && ty < fs.ty_hi && zin) || zin != (pass == 0)) continue;
+          p->slow_tiles.push_back(ty);
+          p->slow_tiles.push_back(zc);
+        }
+      if (pass == 0) fs.n_slow_y = (int)(p->slow_tiles.size() / 2);
+    }
     fs.n_slow = (int)(p->slow_tiles.size() / 2);
     fs.slow_blocks = (fs.n_slow + 7) / 8 * 8;
   }

@@ -14,6 +14,7 @@ namespace chf {
 constexpr int kMaxVX = 8;        // cells per lane along x in the fused sweep (nx <= 64*8)
 constexpr int kMaxFusedLayer = 64;  // 2*npml the fused sweep handles (x-slab psi, one per lane)
 constexpr int kMaxGeneralVX = 4;    // widest rows (64*VX nodes) of the general fused sweep
+constexpr int kMaxGeneralW = 8;     // and most rows per workgroup
 constexpr int kMaxObsPerPlan = 4096;
 constexpr int kMaxWz = 64;       // longitudinal source support in cells
 
@@ -71,6 +72,7 @@ struct FusedShape {
   // tiles clear of walls and y/z layers form the rectangle [ty_lo,ty_hi) x [zc_lo,zc_hi); the
   // other tiles are listed in two tables: clear of walls (layer) and touching a wall (slow)
   int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_layer, layer_blocks, n_slow, slow_blocks;
+  int n_slow_y;  // leading entries of the tile table whose planes lie in [zc_lo, zc_hi) chunks
 };
 
 }  // namespace chf

@@ -161,10 +161,11 @@ __device__ __forceinline__ int xcd_logical() {
   return (b & 7) * (gridDim.x >> 3) + (b >> 3);
 }
 
-// G = false: the interior rectangle (no wall and no y/z layer in reach; x walls and the x layer
-// are per-lane fix-ups).  G = true: any tile (the boundary tiles), with the wall masks of every
-// component and the y/z CPML terms, which are uniform per row and per plane.
-template <typename T, int VX, int W, bool G>
+// G = 0: the interior rectangle (no wall and no y/z layer in reach; x walls and the x layer are
+// per-lane fix-ups).  G = 1: boundary tiles whose planes lie in the interior z range (y walls
+// and y layers: masks and terms uniform per row).  G = 2: any tile, adding the z walls and the
+// z layers (uniform per plane).
+template <typename T, int VX, int W, int G>
 __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zchunk, int par) {
   // Wave r of the workgroup owns row j = j0 - 1 + r: r = 1..W are the tile's rows, r = 0 is
   // the row below the tile, whose H the E update of row j0 needs (it computes H only and
@@ -187,10 +188,11 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int j0 = ty * W;
   const int j = j0 - 1 + r;
-  const bool act = !G || (j >= 0 && j < ny);  // row exists (always, in the interior rectangle)
+  constexpr bool GY = G >= 1, GZ = G >= 2;
+  const bool act = !GY || (j >= 0 && j < ny);  // row exists (always, in the interior rectangle)
   const int jc = G ? min(max(j, 0), ny - 1) : j;
   const bool own = r > 0 && act, top = r == W;
-  const bool top_ld = top && (!G || j + 1 < ny);
+  const bool top_ld = top && (!GY || j + 1 < ny);
   const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
   const int ib = lane * VX;
   const bool on = ib < nx && act;
@@ -230,11 +232,11 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   }
   const float chy = d.ax[1].ch[jc], cey = d.ax[1].ce[jc];
   // y layer and wall masks of the own row (uniform per wave)
-  const int shy = G && np2 > 0 ? d.ax[1].sh[jc] : -1, sey = G && np2 > 0 ? d.ax[1].se[jc] : -1;
+  const int shy = GY && np2 > 0 ? d.ax[1].sh[jc] : -1, sey = GY && np2 > 0 ? d.ax[1].se[jc] : -1;
   const float ahy = shy >= 0 ? d.ax[1].ah[jc] : 0.f, bhy = shy >= 0 ? d.ax[1].bh[jc] : 0.f;
   const float aey = sey >= 0 ? d.ax[1].ae[jc] : 0.f, bey = sey >= 0 ? d.ax[1].be[jc] : 0.f;
-  const bool jh = !G || j <= ny - 2;               // Hx, Hz have their y difference
-  const bool je = !G || (j >= 1 && j <= ny - 2);   // Ex, Ez are not tangential to a y wall
+  const bool jh = !GY || j <= ny - 2;               // Hx, Hz have their y difference
+  const bool je = !GY || (j >= 1 && j <= ny - 2);   // Ex, Ez are not tangential to a y wall
   __syncthreads();  // sTab
 
   // E(k0) of the own row (and, for the top wave, Ex, Ez of the row above the tile)
@@ -329,13 +331,13 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     }
     const float chz = d.ax[2].ch[k], cez = d.ax[2].ce[k];
     // z layer and wall masks of this plane (uniform)
-    const int shz = G && np2 > 0 ? d.ax[2].sh[k] : -1, sez = G && np2 > 0 ? d.ax[2].se[k] : -1;
-    const bool kh = !G || k <= nz - 2;              // Hx, Hy have their z difference
-    const bool ke = !G || (k >= 1 && k <= nz - 2);  // Ex, Ey are not tangential to a z wall
+    const int shz = GZ && np2 > 0 ? d.ax[2].sh[k] : -1, sez = GZ && np2 > 0 ? d.ax[2].se[k] : -1;
+    const bool kh = !GZ || k <= nz - 2;              // Hx, Hy have their z difference
+    const bool ke = !GZ || (k >= 1 && k <= nz - 2);  // Ex, Ey are not tangential to a z wall
     // y/z slab rows: H terms Hx(y), Hz(y), Hx(z), Hy(z); E terms Ex(y), Ez(y), Ex(z), Ey(z)
     float qhxy[VX], qhzy[VX], qhxz[VX], qhyz[VX], qexy[VX], qezy[VX], qexz[VX], qeyz[VX];
     long long iyh = 0, iye = 0, izh = 0, ize = 0;
-    if constexpr (G) {
+    if constexpr (GY) {
       iyh = ((long long)k * np2 + max(shy, 0)) * d.pitch + ib;
       iye = ((long long)k * np2 + max(sey, 0)) * d.pitch + ib;
       izh = ((long long)max(shz, 0) * ny + jc) * d.pitch + ib;
@@ -401,7 +403,7 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
         }
       }
     }
-    if constexpr (G) {  // y and z layer terms (after the x term), then the wall masks
+    if constexpr (GY) {  // y and z layer terms (after the x term), then the wall masks
       const float ahz = shz >= 0 ? d.ax[2].ah[k] : 0.f, bhz = shz >= 0 ? d.ax[2].bh[k] : 0.f;
 #pragma unroll
       for (int v = 0; v < VX; v++) {
@@ -498,7 +500,7 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
           }
         }
       }
-      if constexpr (G) {
+      if constexpr (GY) {
         const float aez = sez >= 0 ? d.ax[2].ae[k] : 0.f, bez = sez >= 0 ? d.ax[2].be[k] : 0.f;
 #pragma unroll
         for (int v = 0; v < VX; v++) {
@@ -548,7 +550,7 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
         pe0[prow + lane] = sPsi[r][2][lane];
         pe1[prow + lane] = sPsi[r][3][lane];
       }
-      if constexpr (G) {
+      if constexpr (GY) {
         if (shy >= 0) {
           st_row<float, VX>(d.psi_h[par ^ 1][1][0] + iyh, qhxy, on);
           st_row<float, VX>(d.psi_h[par ^ 1][1][1] + iyh, qhzy, on);
@@ -582,14 +584,15 @@ __global__ void __launch_bounds__(64 * (W + 1)) k_fused(Dev d, FusedShape fs, in
   const int logical = xcd_logical();
   if (logical >= fs.n_fast) return;
   const int fw = fs.ty_hi - fs.ty_lo;
-  fused_body<T, VX, W, false>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+  fused_body<T, VX, W, 0>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
 }
-// Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep.
-template <typename T, int VX, int W>
+// Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep: G = 1
+// over the table's first n_slow_y entries (interior z range), G = 2 over the rest.
+template <typename T, int VX, int W, int G>
 __global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen(Dev d, FusedShape fs, const int *tiles, int n, int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
-  fused_body<T, VX, W, true>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
+  fused_body<T, VX, W, G>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
 }
 
 // Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
@@ -599,7 +602,7 @@ __global__ void __launch_bounds__(64 * (W + 1)) k_fused_batch(const Dev *devs, c
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int pl = tab[3 * logical];
-  fused_body<T, VX, W, false>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
+  fused_body<T, VX, W, 0>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
 }
 
 // --------------------------------------------------------------- split sweeps
@@ -724,7 +727,7 @@ __device__ __forceinline__ void split_e_body(const Dev &d, int i, int j, int k0,
 
 // Single plan: workgroup -> (tile from the table, 64-node x block).
 template <typename T, bool H>
-__global__ void __launch_bounds__(512) k_split(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
+__global__ void __launch_bounds__(1024) k_split(Dev d, FusedShape fs, const int *tiles, int n_tiles, int par) {
   const int nxb = (d.nx + 63) / 64;
   const int tile = blockIdx.x / nxb;
   if (tile >= n_tiles) return;
@@ -738,7 +741,7 @@ __global__ void __launch_bounds__(512) k_split(Dev d, FusedShape fs, const int *
 
 // Batched: entries (plan, ty, zc, x block) over the boundary tiles of every plan.
 template <typename T, bool H>
-__global__ void __launch_bounds__(512) k_split_batch(const Dev *devs, const int *zchunks, const int *tab, int n,
+__global__ void __launch_bounds__(1024) k_split_batch(const Dev *devs, const int *zchunks, const int *tab, int n,
                                                      int rows, int par) {
   if ((int)blockIdx.x >= n) return;
   const int *e = tab + 4 * blockIdx.x;
@@ -924,10 +927,15 @@ __global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
 template <typename T, int VX, int W>
 static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   if (general) {
-    if constexpr (VX <= kMaxGeneralVX)
-      hipLaunchKernelGGL((k_fused_gen<T, VX, W>), dim3(p.fs.slow_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs,
-                         d.slow_tiles, p.fs.n_slow, par);
-    else
+    if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
+      const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
+      if (ny_ > 0)
+        hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+                           p.fs, d.slow_tiles, ny_, par);
+      if (nr > 0)
+        hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+                           p.fs, d.slow_tiles + 2 * ny_, nr, par);
+    } else
       return hipErrorInvalidValue;
   } else
     hipLaunchKernelGGL((k_fused<T, VX, W>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
@@ -938,7 +946,13 @@ template <typename T, int VX>
 static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   switch (p.fs.waves) {
     case 4: return fused_launch<T, VX, 4>(p, d, par, general, s);
-    case 8: return fused_launch<T, VX, 8>(p, d, par, general, s);
+    case 7: return fused_launch<T, VX, 7>(p, d, par, general, s);
+    case 8:
+      if constexpr (VX <= 4) return fused_launch<T, VX, 8>(p, d, par, general, s);
+      return hipErrorInvalidValue;
+    case 15:
+      if constexpr (VX <= 4) return fused_launch<T, VX, 15>(p, d, par, general, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -964,10 +978,11 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
   const dim3 sgrid(p.fs.n_slow * nxb), sblock(64 * p.fs.waves);
   if (p.kernel == CHF_KERNEL_FUSED) {
     // The interior rectangle in one fused sweep; the boundary tiles in the general fused sweep
-    // (or, for rows wider than 256 nodes, in split H and E sweeps).  Both read only the input
+    // (or, for rows wider than 256 nodes and for 15-row tiles, whose general sweep would not
+    // fit its registers, in split H and E sweeps).  Both read only the input
     // level and write disjoint nodes, so the boundary sweep (its H half, when split) runs on
     // the side stream beside the interior one.
-    const bool gen = p.fs.vx <= kMaxGeneralVX;
+    const bool gen = p.fs.vx <= kMaxGeneralVX && p.fs.waves <= kMaxGeneralW;
     const bool fork = p.fs.n_fast > 0 && p.fs.n_slow > 0 && p.aux;
     if (fork) {
       e = hipEventRecord(p.ev_fork, s);
@@ -1044,7 +1059,17 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
 
 template <typename T, int VX>
 static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *z, int par, hipStream_t s) {
-  return b.waves == 8 ? batch_fused<T, VX, 8>(b, devs, z, par, s) : batch_fused<T, VX, 4>(b, devs, z, par, s);
+  switch (b.waves) {
+    case 4: return batch_fused<T, VX, 4>(b, devs, z, par, s);
+    case 7: return batch_fused<T, VX, 7>(b, devs, z, par, s);
+    case 8:
+      if constexpr (VX <= 4) return batch_fused<T, VX, 8>(b, devs, z, par, s);
+      return hipErrorInvalidValue;
+    case 15:
+      if constexpr (VX <= 4) return batch_fused<T, VX, 15>(b, devs, z, par, s);
+      return hipErrorInvalidValue;
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>

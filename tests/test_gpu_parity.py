@@ -74,7 +74,7 @@ def test_small_shower_cpml_fused_and_split(gpu, shower):
     assert np.array_equal(fused, split)
 
 
-@pytest.mark.parametrize("waves,zchunk", [(4, 7), (8, 32), (4, 16), (8, 150), (8, 1)])
+@pytest.mark.parametrize("waves,zchunk", [(4, 7), (8, 32), (4, 16), (8, 150), (8, 1), (7, 12), (15, 9)])
 def test_tile_shape_invariance_bitwise(gpu, shower, waves, zchunk):
     w, _ = shower
     banner(f"tile shape waves={waves} zchunk={zchunk}")

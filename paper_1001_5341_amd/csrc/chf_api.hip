@@ -796,6 +796,12 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) 
       b->fast_tab.push_back(fs.ty_lo + t % fw);
       b->fast_tab.push_back(fs.zc_lo + t / fw);
     }
+    for (int t = 0; t < fs.n_slow; t++) {
+      std::vector<int> &g = b->gen_tab[t < fs.n_slow_y ? 0 : 1];
+      g.push_back(i);
+      g.push_back(p->slow_tiles[2 * t]);
+      g.push_back(p->slow_tiles[2 * t + 1]);
+    }
     const int nxb = (p->grid.nx + 63) / 64;
     for (int t = 0; t < fs.n_slow; t++)
       for (int xb = 0; xb < nxb; xb++) {
@@ -814,6 +820,8 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) 
   }
   b->total_obs = (int)(b->obs_tab.size() / 2);
   b->wptr.assign(n, nullptr);
+  // boundary tiles in the general fused sweep where it fits (as for single plans)
+  b->gen = b->vx <= chf::kMaxGeneralVX && b->waves <= chf::kMaxGeneralW;
   uint64_t off = 0;
   b->off_devs = off;
   off += align256(b->devs.size() * sizeof(chf::Dev));
@@ -823,6 +831,10 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) 
   off += align256(std::max<size_t>(b->fast_tab.size(), 1) * sizeof(int));
   b->off_slow = off;
   off += align256(std::max<size_t>(b->slow_tab.size(), 1) * sizeof(int));
+  for (int c = 0; c < 2; c++) {
+    b->off_gen[c] = off;
+    off += align256(std::max<size_t>(b->gen_tab[c].size(), 1) * sizeof(int));
+  }
   b->off_obs = off;
   off += align256(std::max<size_t>(b->obs_tab.size(), 1) * sizeof(int));
   b->off_wptr = off;
@@ -853,6 +865,8 @@ chf_status chf_batch_bind_workspace(chf_batch *b, void *dev_ptr, uint64_t bytes,
       {b->off_z, b->zchunks.data(), b->zchunks.size() * sizeof(int)},
       {b->off_fast, b->fast_tab.data(), b->fast_tab.size() * sizeof(int)},
       {b->off_slow, b->slow_tab.data(), b->slow_tab.size() * sizeof(int)},
+      {b->off_gen[0], b->gen_tab[0].data(), b->gen_tab[0].size() * sizeof(int)},
+      {b->off_gen[1], b->gen_tab[1].data(), b->gen_tab[1].size() * sizeof(int)},
       {b->off_obs, b->obs_tab.data(), b->obs_tab.size() * sizeof(int)},
   };
   for (const Up &u : ups) {

@@ -123,9 +123,13 @@ struct chf_batch {
   bool any_mur = false;
   std::vector<int> zchunks;   // per plan
   std::vector<int> fast_tab;  // (plan, ty, zc) over the interior rectangles
-  std::vector<int> slow_tab;  // (plan, ty, zc, x block) over the boundary tiles
+  std::vector<int> slow_tab;  // (plan, ty, zc, x block) over the boundary tiles (split sweeps)
+  // (plan, ty, zc) over the boundary tiles in the general fused sweep: interior z range, rest
+  bool gen = false;
+  std::vector<int> gen_tab[2];
   std::vector<int> obs_tab;   // (plan, observer)
   uint64_t off_devs = 0, off_z = 0, off_fast = 0, off_slow = 0, off_obs = 0, off_wptr = 0, ws_bytes = 0;
+  uint64_t off_gen[2] = {0, 0};
   char *ws = nullptr;
   std::vector<chf::Dev> devs;
   std::vector<double *> wptr;

@@ -604,6 +604,15 @@ __global__ void __launch_bounds__(64 * (W + 1)) k_fused_batch(const Dev *devs, c
   const int pl = tab[3 * logical];
   fused_body<T, VX, W, 0>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
 }
+// Batched boundary tiles in the general fused sweep: entries (plan, ty, zc) of one class.
+template <typename T, int VX, int W, int G>
+__global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen_batch(const Dev *devs, const int *zchunks, const int *tab,
+                                                                 int n, int par) {
+  const int logical = xcd_logical();
+  if (logical >= n) return;
+  const int pl = tab[3 * logical];
+  fused_body<T, VX, W, G>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
+}
 
 // --------------------------------------------------------------- split sweeps
 // Every tile when the split sweeps are selected (and the boundary tiles of fused plans whose
@@ -1047,8 +1056,23 @@ hipError_t launch_step(const chf_plan &p, const Dev &d, int par, int step, const
   return hipErrorInvalidValue;
 }
 
+// general = false: the interior tiles of every member; true: their boundary tiles
 template <typename T, int VX, int W>
-static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z, int par, hipStream_t s) {
+static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z, int par, bool general,
+                              hipStream_t s) {
+  if (general) {
+    if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
+      const int n1 = (int)(b.gen_tab[0].size() / 3), n2 = (int)(b.gen_tab[1].size() / 3);
+      if (n1 > 0)
+        hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 1>), dim3((n1 + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s,
+                           devs, z, (const int *)(b.ws + b.off_gen[0]), n1, par);
+      if (n2 > 0)
+        hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 2>), dim3((n2 + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s,
+                           devs, z, (const int *)(b.ws + b.off_gen[1]), n2, par);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   const int n = (int)(b.fast_tab.size() / 3);
   if (n == 0) return hipSuccess;
   const int blocks = (n + 7) / 8 * 8;
@@ -1058,18 +1082,30 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
 }
 
 template <typename T, int VX>
-static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *z, int par, hipStream_t s) {
+static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *z, int par, bool general,
+                                hipStream_t s) {
   switch (b.waves) {
-    case 4: return batch_fused<T, VX, 4>(b, devs, z, par, s);
-    case 7: return batch_fused<T, VX, 7>(b, devs, z, par, s);
+    case 4: return batch_fused<T, VX, 4>(b, devs, z, par, general, s);
+    case 7: return batch_fused<T, VX, 7>(b, devs, z, par, general, s);
     case 8:
-      if constexpr (VX <= 4) return batch_fused<T, VX, 8>(b, devs, z, par, s);
+      if constexpr (VX <= 4) return batch_fused<T, VX, 8>(b, devs, z, par, general, s);
       return hipErrorInvalidValue;
     case 15:
-      if constexpr (VX <= 4) return batch_fused<T, VX, 15>(b, devs, z, par, s);
+      if constexpr (VX <= 4) return batch_fused<T, VX, 15>(b, devs, z, par, general, s);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t batch_fused_v(const chf_batch &b, const Dev *devs, const int *z, int par, bool general,
+                                hipStream_t s) {
+  switch (b.vx) {
+    case 1: return batch_fused_w<T, 1>(b, devs, z, par, general, s);
+    case 2: return batch_fused_w<T, 2>(b, devs, z, par, general, s);
+    case 4: return batch_fused_w<T, 4>(b, devs, z, par, general, s);
+    default: return batch_fused_w<T, 8>(b, devs, z, par, general, s);
+  }
 }
 
 template <typename T>
@@ -1079,34 +1115,34 @@ static hipError_t batch_step_t(const chf_batch &b, int par, int step, hipStream_
   hipError_t e = hipSuccess;
   const int ns = (int)(b.slow_tab.size() / 4);
   const int *stab = (const int *)(b.ws + b.off_slow);
+  // boundary tiles (general fused sweep, or split H then E) on the side stream beside the
+  // interior tiles; the source injection joins them
   const bool fork = ns > 0 && !b.fast_tab.empty() && b.aux;
+  hipStream_t sb = fork ? b.aux : s;
   if (fork) {
     e = hipEventRecord(b.ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(b.aux, b.ev_fork, 0);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_split_batch<T, true>), dim3(ns), dim3(64 * b.waves), 0, b.aux, devs, z, stab, ns,
-                       b.waves, par);
-    e = hipEventRecord(b.ev_join, b.aux);
+  }
+  if (ns > 0) {
+    if (b.gen) {
+      e = batch_fused_v<T>(b, devs, z, par, true, sb);
+    } else {
+      hipLaunchKernelGGL((k_split_batch<T, true>), dim3(ns), dim3(64 * b.waves), 0, sb, devs, z, stab, ns,
+                         b.waves, par);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && fork) e = hipEventRecord(b.ev_join, b.aux);
     if (e != hipSuccess) return e;
   }
-  switch (b.vx) {
-    case 1: e = batch_fused_w<T, 1>(b, devs, z, par, s); break;
-    case 2: e = batch_fused_w<T, 2>(b, devs, z, par, s); break;
-    case 4: e = batch_fused_w<T, 4>(b, devs, z, par, s); break;
-    default: e = batch_fused_w<T, 8>(b, devs, z, par, s); break;
-  }
+  e = batch_fused_v<T>(b, devs, z, par, false, s);
   if (e != hipSuccess) return e;
-  if (ns > 0) {
-    if (fork) {
-      e = hipStreamWaitEvent(s, b.ev_join, 0);
-      if (e != hipSuccess) return e;
-    } else {
-      hipLaunchKernelGGL((k_split_batch<T, true>), dim3(ns), dim3(64 * b.waves), 0, s, devs, z, stab, ns,
-                         b.waves, par);
-    }
+  if (fork) e = hipStreamWaitEvent(s, b.ev_join, 0);
+  if (e != hipSuccess) return e;
+  // the split E sweep reads the fresh H of the interior tiles next to the boundary ones
+  if (ns > 0 && !b.gen)
     hipLaunchKernelGGL((k_split_batch<T, false>), dim3(ns), dim3(64 * b.waves), 0, s, devs, z, stab, ns,
                        b.waves, par);
-  }
   if (b.max_patch > 0)
     hipLaunchKernelGGL(k_source_batch<T>, dim3((b.max_patch + 255) / 256, (int)b.plans.size()), dim3(256), 0, s,
                        devs, par ^ 1, step);

@@ -115,10 +115,22 @@ def cpu_baseline(w, n_steps: int = 600):
     oracle.run(sub)
     dt = time.perf_counter() - t0
     rate = sub.n_cells * sub.n_steps / dt / 1e6
-    return {"value": round(rate, 3), "unit": "Mcell-updates/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    # one thread, as the paper's sequential CPU code ran (a shorter sample of the same grid)
+    one = sub.replace(n_steps=20)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.run(one)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    return {"value": round(rate, 3), "unit": "Mcell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle on a {sub.nx}x{sub.ny}x{sub.nz} sub-grid of the workload "
                       f"(same medium, CPML-{sub.npml}, shower source, 8 observers), {sub.n_steps} steps, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "value_1core": round(one.n_cells * one.n_steps / dt1 / 1e6, 3),
+            "sample_1core": f"same sub-grid, {one.n_steps} steps on one thread, {dt1:.1f} s"}
 
 
 def golden_error(key: str, w, got: np.ndarray):

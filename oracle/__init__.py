@@ -80,6 +80,7 @@ def lib():
             L.orc_adjoint.restype = ct.c_int
             L.orc_adjoint.argtypes = [ct.POINTER(OrcCfg), P, P]
             L.orc_threads.restype = ct.c_int
+            L.orc_set_threads.argtypes = [ct.c_int]
             for f in ("orc_c0", "orc_mu0", "orc_eps0"):
                 getattr(L, f).restype = ct.c_double
             _lib = L
@@ -93,6 +94,10 @@ def constants():
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 def _dp(a: np.ndarray):

@@ -31,6 +31,13 @@ int orc_threads(void) {
   return 1;
 #endif
 }
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 
 static __thread char g_err[256];
 const char *orc_last_error(void) { return g_err; }

@@ -86,6 +86,8 @@ double orc_mu0(void);
 double orc_eps0(void);
 /* OpenMP threads the loops above run on (1 without OpenMP). */
 int orc_threads(void);
+/* Threads for the following calls (n > 0). */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

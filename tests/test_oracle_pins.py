@@ -413,3 +413,29 @@ def test_fraunhofer_sum_matches_gaussian_closed_form():
     ths = np.radians(np.linspace(30, 80, 501))
     amp = [abs(ph.gaussian_profile_far_field([2 * math.pi * 1e9], t, R, qmax, l, n)[0]) for t in ths]
     assert abs(ths[int(np.argmax(amp))] - ph.cherenkov_angle(n)) < math.radians(1.0)
+
+
+@pytest.mark.parametrize("bc,npml,kappa_max,alpha_on", [("pec", 0, 1.0, True), ("mur1", 0, 1.0, True),
+                                                       ("cpml", 4, 1.0, True), ("cpml", 5, 3.0, False)])
+def test_independent_numpy_implementation_agrees(bc, npml, kappa_max, alpha_on):
+    """A second FP64 implementation of the scheme (whole-array NumPy, full-size CPML arrays,
+    its own source and observer code) reproduces the oracle's waveforms and final fields to
+    rounding: a slip in an index, sign or coefficient in either would show here."""
+    from oracle import numpy_yee
+
+    base = W.small_shower(seed=31, nx=26, ny=24, nz=40, n_steps=60, n_obs=3, bc="pec")
+    obs = np.array([[0.10, 0.12, 0.20], [0.16, 0.09, 0.25], [0.13, 0.15, 0.30]])
+    w = base.replace(bc=bc, npml=npml, obs_xyz=obs, pml_kappa_max=kappa_max,
+                     pml_alpha_max=base.pml_alpha_max if alpha_on else 0.0)
+    a = oracle.run(w)
+    b = numpy_yee.run(w)
+    assert np.abs(a).max() > 0
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+    st_c, st_n = oracle.State(w), numpy_yee.NumpyYee(w)
+    for _ in range(w.n_steps):
+        st_c.step()
+        st_n.step()
+    for fam_c, fam_n in ((st_c.fields[:3], st_n.E), (st_c.fields[3:], st_n.H)):
+        scale = max(np.abs(f).max() for f in fam_c)
+        for fc, fn in zip(fam_c, fam_n):
+            assert np.abs(fc - fn).max() <= 1e-12 * scale

@@ -325,3 +325,142 @@ def workload_digest(w) -> str:
     for v in (w.dt, w.dx, w.x_axis, w.y_axis, w.z_entry, w.sigma_r, w.sigma_z, w.pml_alpha_max):
         h.update(np.float64(v).tobytes())
     return h.hexdigest()
+
+
+# ------------------------------------------------------------ axisymmetric (r, z) workloads
+@dataclasses.dataclass
+class RZWorkload:
+    """Inputs of the axisymmetric scheme: nr x nz nodes (node i at r = i dr, node k at
+    z = k dz; the axis is node column 0 and the outer wall is column nr-1), the same moving
+    shower source as in 3-D (centred on the axis), observers given as (r, z) pairs."""
+    name: str
+    nr: int
+    nz: int
+    n_steps: int
+    dr: float
+    dz: float
+    dt: float
+    eps_r: float = N_ICE ** 2
+    mu_r: float = 1.0
+    sigma: float = 0.0
+    bc: str = "mur1"  # "pec" | "mur1"
+    src_on: bool = True
+    z_entry: float = 0.0
+    t_entry: float = 0.0
+    beta: float = 1.0
+    sigma_r: float = 0.02
+    sigma_z: float = 0.01
+    cut_sigmas: float = 4.0
+    z_bin0: float = 0.0
+    dz_bin: float = 0.01
+    q_bins: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(2))
+    obs_rz: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 2)))
+    seed: int = 0
+    notes: str = ""
+
+    @property
+    def n_cells(self) -> int:
+        return self.nr * self.nz
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_rz.shape[0])
+
+    def replace(self, **kw) -> "RZWorkload":
+        return dataclasses.replace(self, **kw)
+
+    def describe(self) -> dict:
+        return {
+            "workload": self.name, "grid": [self.nr, self.nz], "steps": self.n_steps,
+            "dr_m": self.dr, "dz_m": self.dz, "dt_s": self.dt, "bc": self.bc,
+            "n_obs": self.n_obs, "n_bins": int(len(self.q_bins)), "seed": self.seed,
+        }
+
+
+def place_observers_rz(rng: np.random.Generator, n_obs: int, z_origin: float, r_hi: float,
+                       z_lo: float, z_hi: float, r_min: float, r_max: float, r_lo: float,
+                       theta_deg=(40.0, 70.0)) -> np.ndarray:
+    """(R, theta) about the point (0, z_origin): theta ~ U[theta_deg], R ~ U[r_min, min(r_max,
+    R_fit)], where R_fit keeps r in [r_lo, r_hi] and z in [z_lo, z_hi]."""
+    out = []
+    tries = 0
+    while len(out) < n_obs:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("cannot place observers in this grid")
+        th = math.radians(rng.uniform(*theta_deg))
+        s, c = math.sin(th), math.cos(th)
+        r_fit = r_hi / s
+        if c > 1e-12:
+            r_fit = min(r_fit, (z_hi - z_origin) / c)
+        elif c < -1e-12:
+            r_fit = min(r_fit, (z_lo - z_origin) / c)
+        top = min(r_max, r_fit)
+        bot = max(r_min, r_lo / s)
+        if top < bot:
+            continue
+        R = rng.uniform(bot, top)
+        out.append((R * s, z_origin + R * c))
+    return np.array(out, dtype=np.float64)
+
+
+def rz_shower(seed: int, nr: int, nz: int, n_steps: int, n_obs: int, d: float = 0.01,
+              bc: str = "mur1", sigma_r: float = 0.03, zmax_frac=(0.2, 0.35),
+              length_range=(3.0, 8.0), r_range=(1.0, 64.0), margin: int = 4,
+              name: str = "") -> RZWorkload:
+    """Greisen-like shower on an (r, z) grid of square cells: the axisymmetric counterpart of
+    greisen_shower.  The shower enters near the lower z wall and is switched off near the upper
+    one; observers at theta 40-70 deg about the shower maximum with R drawn in r_range (clipped
+    to what fits the grid), at least `margin` cells from the walls and the axis."""
+    rng = np.random.default_rng(seed)
+    Lz = (nz - 1) * d
+    z_max = rng.uniform(*zmax_frac) * Lz
+    length = min(rng.uniform(*length_range), 0.25 * Lz)
+    q0 = draw_q0(rng)
+    z_entry = (margin + 5) * d
+    z_off = (nz - 1 - margin - 5) * d
+    ramp = min(0.3, 0.25 * (z_off - z_entry))
+    zb = np.arange(z_entry, z_off + 0.5 * d, d)
+    q = greisen_profile_bins(zb, z_max, length, q0, z_entry, z_off, ramp)
+    obs = place_observers_rz(rng, n_obs, z_max, (nr - 1 - margin) * d, margin * d,
+                             (nz - 1 - margin) * d, r_range[0], r_range[1], margin * d)
+    return RZWorkload(name=name or f"rz-{nr}x{nz}", nr=nr, nz=nz, n_steps=n_steps, dr=d, dz=d,
+                      dt=courant_dt(d, d, d), bc=bc, z_entry=z_entry, t_entry=0.0, beta=1.0,
+                      sigma_r=sigma_r, sigma_z=0.01, z_bin0=float(zb[0]), dz_bin=d, q_bins=q,
+                      obs_rz=obs, seed=seed,
+                      notes=f"z_max={z_max:.3f} m, length={length:.3f} m, Q0={q0:.3e} C")
+
+
+def rz_small(seed: int = 21, nr: int = 300, nz: int = 520, n_steps: int = 700, n_obs: int = 12,
+             bc: str = "mur1") -> RZWorkload:
+    """Reduced (r, z) shower for parity tests: several tiles in r and z with ragged tails."""
+    return rz_shower(seed, nr, nz, n_steps, n_obs, bc=bc, sigma_r=0.02, zmax_frac=(0.15, 0.25),
+                     length_range=(0.3, 0.6), r_range=(0.2, 1.2), name=f"rz-small-{nr}x{nz}-{bc}")
+
+
+def rz_paper_grid(n: int, seed: int = 22, n_steps: Optional[int] = None, n_obs: int = 64) -> RZWorkload:
+    """The paper's (r, z) grid sizes (N^2 for N = 256 ... 8192, 1 cm cells), Mur walls, the
+    Greisen shower, 64 observers with R up to 64 m where the grid allows; n_steps defaults to N
+    (the paper's total work grows as N^3)."""
+    return rz_shower(seed, n, n, n if n_steps is None else n_steps, n_obs,
+                     zmax_frac=(0.2, 0.3) if n >= 2048 else (0.3, 0.45),
+                     length_range=(3.0, 8.0) if n >= 2048 else (0.3, 0.6),
+                     r_range=(min(1.0, 0.05 * n * 0.01), 64.0), name=f"rz-{n}x{n}")
+
+
+def rz_workload_by_name(name: str, seed: Optional[int] = None) -> RZWorkload:
+    if name == "rz-small":
+        return rz_small(21 if seed is None else seed)
+    if name.startswith("rz-") and name[3:].isdigit():
+        return rz_paper_grid(int(name[3:]), 22 if seed is None else seed)
+    raise KeyError(name)
+
+
+def rz_workload_digest(w: RZWorkload) -> str:
+    h = hashlib.sha256()
+    h.update(json.dumps(w.describe(), sort_keys=True).encode())
+    for arr in (w.q_bins, w.obs_rz):
+        h.update(np.ascontiguousarray(arr, dtype=np.float64).tobytes())
+    for v in (w.dt, w.dr, w.dz, w.z_entry, w.sigma_r, w.sigma_z, w.eps_r, w.sigma):
+        h.update(np.float64(v).tobytes())
+    return h.hexdigest()

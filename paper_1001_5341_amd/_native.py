@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/chfdtd.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/chfdtd.h and include/chfdtd_rz.h (argument
+marshalling only).
 
 Loading fails loudly when libchfdtd.so is missing: there is no fallback path.
 """
@@ -26,6 +27,9 @@ EXPORTED = [
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
     "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_destroy",
     "chf_status_str", "chf_last_error", "chf_abi_version",
+    "chf_rz_plan_create", "chf_rz_plan_destroy", "chf_rz_workspace_bytes", "chf_rz_bind_workspace",
+    "chf_rz_reset", "chf_rz_forward", "chf_rz_forward_timed", "chf_rz_forward_graph", "chf_rz_sync",
+    "chf_rz_get_field", "chf_rz_set_field", "chf_rz_get_info",
 ]
 
 
@@ -69,6 +73,34 @@ class PlanInfo(ct.Structure):
                 ("psi_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
                 ("bytes_per_cell_update", ct.c_double), ("fused_cells", ct.c_uint64),
                 ("fused_bytes_per_cell", ct.c_double)]
+
+
+class RZGrid(ct.Structure):
+    _fields_ = [("nr", ct.c_int32), ("nz", ct.c_int32), ("n_steps", ct.c_int32), ("pad0", ct.c_int32),
+                ("dr", ct.c_double), ("dz", ct.c_double), ("dt", ct.c_double)]
+
+
+class RZSource(ct.Structure):
+    _fields_ = [("z_entry", ct.c_double), ("t_entry", ct.c_double), ("beta", ct.c_double),
+                ("sigma_r", ct.c_double), ("sigma_z", ct.c_double), ("cut_sigmas", ct.c_double),
+                ("n_bins", ct.c_int32), ("pad0", ct.c_int32), ("z_bin0", ct.c_double),
+                ("dz_bin", ct.c_double), ("q_bins", ct.POINTER(ct.c_double))]
+
+
+class RZObservers(ct.Structure):
+    _fields_ = [("n_obs", ct.c_int32), ("pad0", ct.c_int32), ("rz", ct.POINTER(ct.c_double))]
+
+
+class RZExec(ct.Structure):
+    _fields_ = [("bc", ct.c_int32), ("vx", ct.c_int32), ("waves_per_block", ct.c_int32),
+                ("z_chunk", ct.c_int32), ("nan_watch", ct.c_int32), ("pad0", ct.c_int32)]
+
+
+class RZInfo(ct.Structure):
+    _fields_ = [("vx", ct.c_int32), ("waves_per_block", ct.c_int32), ("z_chunk", ct.c_int32),
+                ("pitch", ct.c_int32), ("n_blocks", ct.c_int32), ("n_src", ct.c_int32),
+                ("field_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
+                ("bytes_per_cell_update", ct.c_double)]
 
 
 class ChfError(RuntimeError):
@@ -148,6 +180,32 @@ def lib():
         L.chf_last_error.argtypes = []
         L.chf_abi_version.restype = ct.c_int32
         L.chf_abi_version.argtypes = []
+        L.chf_rz_plan_create.restype = ct.c_int
+        L.chf_rz_plan_create.argtypes = [ct.POINTER(RZGrid), ct.POINTER(Medium), ct.POINTER(RZSource),
+                                         ct.POINTER(RZObservers), ct.POINTER(RZExec), ct.POINTER(vp)]
+        L.chf_rz_plan_destroy.restype = None
+        L.chf_rz_plan_destroy.argtypes = [vp]
+        L.chf_rz_workspace_bytes.restype = ct.c_int
+        L.chf_rz_workspace_bytes.argtypes = [vp, ct.POINTER(ct.c_uint64)]
+        L.chf_rz_bind_workspace.restype = ct.c_int
+        L.chf_rz_bind_workspace.argtypes = [vp, vp, ct.c_uint64, vp]
+        L.chf_rz_reset.restype = ct.c_int
+        L.chf_rz_reset.argtypes = [vp, vp]
+        L.chf_rz_forward.restype = ct.c_int
+        L.chf_rz_forward.argtypes = [vp, vp, vp, vp, ct.c_int32, ct.c_int32, ct.c_int32]
+        L.chf_rz_forward_timed.restype = ct.c_int
+        L.chf_rz_forward_timed.argtypes = [vp, vp, vp, vp, ct.c_int32, ct.c_int32, ct.c_int32,
+                                           ct.POINTER(ct.c_double)]
+        L.chf_rz_forward_graph.restype = ct.c_int
+        L.chf_rz_forward_graph.argtypes = [vp, vp, vp, vp]
+        L.chf_rz_sync.restype = ct.c_int
+        L.chf_rz_sync.argtypes = [vp, vp]
+        L.chf_rz_get_field.restype = ct.c_int
+        L.chf_rz_get_field.argtypes = [vp, vp, ct.c_int32, vp]
+        L.chf_rz_set_field.restype = ct.c_int
+        L.chf_rz_set_field.argtypes = [vp, vp, ct.c_int32, vp]
+        L.chf_rz_get_info.restype = ct.c_int
+        L.chf_rz_get_info.argtypes = [vp, ct.POINTER(RZInfo)]
         _lib = L
         return L
 

@@ -1,0 +1,771 @@
+// Axisymmetric (r, z) solver of libchfdtd for gfx950: E_r, E_z, H_phi on the (r, z) restriction
+// of the Yee lattice (eqs. fdtd_Er, fdtd_Ez, fdtd_Hphi of the Numerical Method section), the
+// entry points declared in include/chfdtd_rz.h.
+//
+// Data layout: each component is a row-major [nz][pitch] FP32 array (r fastest, pitch a
+// multiple of 64 nodes, padding columns zero), in two time levels.  Step n reads level `par`
+// (E^n, H^{n-1/2}) and writes level par^1, so one sweep can recompute the H values its tile
+// borrows from neighbouring tiles without racing them.
+//
+// The sweep: a wave owns 64*VX consecutive radial nodes (VX per lane, 16-byte loads) and
+// marches up a chunk of z rows.  Per row it loads E_r(k+1), E_z(k) and H(k) once, forms
+// H^{n+1/2}(k) (the E_z(i+1) of the last node of a lane comes from the next lane by a
+// shuffle, or for lane 63 from the next wave's first node), then E_r^{n+1}(k) from H(k) and
+// the H(k-1) kept in registers, and E_z^{n+1}(k) from H(i) and H(i-1) (H(i-1) of the first
+// node of a lane by shuffle; lane 0 recomputes it from the input level).  A chunk starts by
+// recomputing H of the row below it.  Every variant and tile shape evaluates each node with
+// the same expression in the same order, so results do not depend on the tiling.
+//
+//   H   += db/dr (E_z(i+1) - E_z(i)) - db/dz (E_r(k+1) - E_r(k))
+//   E_r  = ca E_r - cb/dz (H(k) - H(k-1))
+//   E_z  = ca E_z + cp_i H(i) - cm_i H(i-1),  cp_i = cb r_{i+1/2}/(a_i dr), cm_i = cb r_{i-1/2}/(a_i dr)
+// with a_i = r_i (a_0 = dr/8, the disc of radius dr/2 on the axis).  Afterwards the source
+// kernel subtracts cb J_z, the Mur kernel sets the wall values and the gather kernel samples
+// E^{n+1} at the observers in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/chfdtd_rz.h"
+#include "chf_internal.h"
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kMu0 = 1.25663706212e-6;  // CODATA 2018
+constexpr double kPi = 3.14159265358979323846;
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+constexpr int kRzMaxWz = 64;          // longitudinal source support in rows
+constexpr int kRzMaxObs = 1 << 16;
+// Largest eigenvalue of the radial operator times dr^2 (4 on a Cartesian line; the axis cell
+// raises it to 4.8419...), rounded up.
+constexpr double kRadialEig = 4.85;
+
+struct RDev {
+  int nr, nz, pitch, zchunk, nrb, n_blocks, wv;
+  float ca, db_dr, db_dz, cb_dz;
+  float *f[2][3];          // [level][E_r, E_z, H_phi]
+  const float *cp, *cm;    // [pitch]
+  // source
+  int src_on, n_bins, n_src;
+  double z_entry, t_entry, v_src, sigma_z, cut_sigmas, z_bin0, dz_bin, dz, dt, cb;
+  const double *q_bins, *wr;
+  // Mur
+  int mur;
+  float mur_kr, mur_kz;
+  // observers
+  int n_obs;
+  const int *obs_idx;      // [n_obs][2][2] (i0, k0) per component
+  const double *obs_t;     // [n_obs][2][2] (tr, tz)
+  int *nan_flag;
+};
+
+chf_status fail(chf_status s, const std::string &m) {
+  chf::set_error(m);
+  return s;
+}
+
+chf_status hip_fail(hipError_t e, const char *what) {
+  chf::set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return CHF_EHIP;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+}  // namespace
+
+struct chf_rz_plan {
+  chf_rz_grid g;
+  chf_medium med;
+  chf_rz_source src;
+  chf_rz_exec ex;
+  std::vector<double> q_bins;
+  int vx = 4, wv = 4, zchunk = 32, pitch = 0, nrb = 0, nzc = 0, n_blocks = 0, n_src = 0;
+  double ca = 1, cb = 0, db = 0;
+  std::vector<float> cp, cm;
+  std::vector<double> wr;
+  std::vector<int> oidx;
+  std::vector<double> ot;
+  uint64_t off_f[2][3] = {}, off_cp = 0, off_cm = 0, off_wr = 0, off_q = 0, off_oidx = 0, off_ot = 0,
+           off_nan = 0, field_bytes = 0, ws_bytes = 0;
+  char *ws = nullptr;
+  RDev dev{};
+  int parity = 0, n_done = 0;
+  hipGraphExec_t graph = nullptr;
+  const void *graph_w = nullptr, *graph_q = nullptr;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ kernels
+template <int N>
+struct alignas(4 * N) F {
+  float v[N];
+};
+
+template <int N>
+__device__ __forceinline__ void ld(const float *p, float (&o)[N], bool on) {
+  if (on) {
+    const F<N> x = *reinterpret_cast<const F<N> *>(p);
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = x.v[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = 0.f;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void st(float *p, const float (&o)[N], bool on) {
+  if (!on) return;
+  F<N> x;
+#pragma unroll
+  for (int v = 0; v < N; v++) x.v[v] = o[v];
+  *reinterpret_cast<F<N> *>(p) = x;
+}
+
+// H' = H - db/dz dEr + db/dr dEz (the order every sweep uses)
+__device__ __forceinline__ float h_node(float h, float d_er, float d_ez, const RDev &d) {
+  return fmaf(d.db_dr, d_ez, fmaf(-d.db_dz, d_er, h));
+}
+
+template <int VX>
+__global__ void __launch_bounds__(512) k_rz_sweep(RDev d, int par) {
+  const int per = (d.n_blocks + 7) >> 3;  // hardware block b runs on XCD b % 8
+  const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (logical >= d.n_blocks) return;
+  const int rb = logical % d.nrb, zc = logical / d.nrb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int w0 = (rb * d.wv + wv) * 64 * VX;  // first node of the wave
+  if (w0 >= d.nr) return;                     // whole wave beyond the last node
+  const int c0 = w0 + lane * VX;
+  const bool on = c0 < d.nr;
+  const int k0 = zc * d.zchunk, k1 = min(k0 + d.zchunk, d.nz);
+  const int nr = d.nr, nz = d.nz;
+  const long long P = d.pitch;
+  const float *Er = d.f[par][0], *Ez = d.f[par][1], *Hp = d.f[par][2];
+  float *Ero = d.f[par ^ 1][0], *Ezo = d.f[par ^ 1][1], *Hpo = d.f[par ^ 1][2];
+  const bool halo_l = lane == 0 && c0 > 0;          // lane 0 recomputes H(c0-1)
+  const bool halo_r = lane == 63 && c0 + VX < nr;   // lane 63 reads E_z(c0+VX)
+
+  float cp[VX], cm[VX];
+  ld<VX>(d.cp + c0, cp, on);
+  ld<VX>(d.cm + c0, cm, on);
+  bool live[VX];
+#pragma unroll
+  for (int v = 0; v < VX; v++) live[v] = c0 + v <= nr - 2;
+
+  float er_k[VX], hn_b[VX];  // E_r(k) of the input level, H^{n+1/2}(k-1)
+  float erl_k = 0.f;         // lane 0: E_r(c0-1, k)
+  if (k0 > 0) {
+    const int kb = k0 - 1;
+    float erb[VX], ezb[VX], hb[VX];
+    ld<VX>(Er + kb * P + c0, erb, on);
+    ld<VX>(Er + k0 * P + c0, er_k, on);
+    ld<VX>(Ez + kb * P + c0, ezb, on);
+    ld<VX>(Hp + kb * P + c0, hb, on);
+    float ezr = __shfl_down(ezb[0], 1);
+    if (lane == 63) ezr = halo_r ? Ez[kb * P + c0 + VX] : 0.f;
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      const float e1 = v + 1 < VX ? ezb[v + 1] : ezr;
+      hn_b[v] = live[v] ? h_node(hb[v], er_k[v] - erb[v], e1 - ezb[v], d) : hb[v];
+    }
+  } else {
+    ld<VX>(Er + c0, er_k, on);
+#pragma unroll
+    for (int v = 0; v < VX; v++) hn_b[v] = 0.f;
+  }
+  if (halo_l) erl_k = Er[k0 * P + c0 - 1];
+
+  for (int k = k0; k < k1; k++) {
+    const bool top = k + 1 < nz;
+    float er1[VX], ez[VX], h[VX];
+    ld<VX>(Er + (k + 1) * P + c0, er1, on && top);
+    ld<VX>(Ez + k * P + c0, ez, on);
+    ld<VX>(Hp + k * P + c0, h, on);
+    float ezr = __shfl_down(ez[0], 1);
+    if (lane == 63) ezr = halo_r ? Ez[k * P + c0 + VX] : 0.f;
+    const bool hrow = k <= nz - 2;
+    float hn[VX];
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      const float e1 = v + 1 < VX ? ez[v + 1] : ezr;
+      hn[v] = live[v] && hrow ? h_node(h[v], er1[v] - er_k[v], e1 - ez[v], d) : h[v];
+    }
+    // H(c0-1, k): from the lane below, or recomputed by lane 0 from the input level
+    float hl = __shfl_up(hn[VX - 1], 1);
+    if (lane == 0) {
+      hl = 0.f;
+      if (halo_l) {
+        const long long c = k * P + c0 - 1;
+        const float h_l = Hp[c], ez_l = Ez[c];
+        const float er1_l = top ? Er[c + P] : 0.f;
+        hl = hrow ? h_node(h_l, er1_l - erl_k, ez[0] - ez_l, d) : h_l;
+        erl_k = er1_l;
+      }
+    }
+    const bool erow = k >= 1 && k <= nz - 2;
+    float ero[VX], ezo[VX];
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      ero[v] = live[v] && erow ? fmaf(-d.cb_dz, hn[v] - hn_b[v], d.ca * er_k[v]) : er_k[v];
+      const float hm = v > 0 ? hn[v - 1] : hl;
+      ezo[v] = live[v] && hrow ? fmaf(-cm[v], hm, fmaf(cp[v], hn[v], d.ca * ez[v])) : ez[v];
+    }
+    st<VX>(Hpo + k * P + c0, hn, on);
+    st<VX>(Ero + k * P + c0, ero, on);
+    st<VX>(Ezo + k * P + c0, ezo, on);
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      er_k[v] = er1[v];
+      hn_b[v] = hn[v];
+    }
+  }
+}
+
+// J_z of the moving Gaussian charge at (n+1/2) dt, subtracted (times Cb) from E_z^{n+1}; one
+// thread per radial node of the source patch.  FP64 bookkeeping: bunch position, Q(z_s) from
+// the hat bins, lattice-normalised longitudinal weights.
+__global__ void k_rz_source(RDev d, int out_par, int step, const double *q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!d.src_on || i >= d.n_src) return;
+  const double tt = (step + 0.5) * d.dt;
+  if (tt < d.t_entry) return;
+  const double wr = d.wr[i];
+  if (wr == 0.0) return;
+  const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
+  const double u = (zs - d.z_bin0) / d.dz_bin;
+  const double fl = floor(u);
+  const int b0 = (int)fl;
+  const double t = u - fl;
+  double qz = 0.0;
+  if (b0 >= 0 && b0 < d.n_bins) qz += (1.0 - t) * q[b0];
+  if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) qz += t * q[b0 + 1];
+  const double half = d.cut_sigmas * d.sigma_z;
+  const int lo = (int)ceil((zs - half) / d.dz - 0.5);
+  const int hi = (int)floor((zs + half) / d.dz - 0.5);
+  const int m = min(hi - lo + 1, kRzMaxWz);
+  double norm = 0.0;
+  for (int s = 0; s < m; s++) {
+    const double dd = (lo + s + 0.5) * d.dz - zs;
+    norm += exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z));
+  }
+  norm *= d.dz;
+  float *Ez = d.f[out_par][1];
+  for (int s = 0; s < m; s++) {
+    const int k = lo + s;
+    if (k < 0 || k > d.nz - 2) continue;
+    const double dd = (k + 0.5) * d.dz - zs;
+    const double wz = exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) / norm;
+    const long long c = (long long)k * d.pitch + i;
+    Ez[c] = Ez[c] - (float)(d.cb * d.v_src * qz * wr * wz);
+  }
+}
+
+// First-order Mur: wall value^{n+1} = inner^n + K (inner^{n+1} - wall^n), on E_z at r_max
+// (rows 0..nz-2) and on E_r at the z walls (nodes 0..nr-2).
+__global__ void k_rz_mur(RDev d, int par) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long P = d.pitch;
+  long long c0, c1;
+  float K;
+  int comp;
+  if (t < d.nz - 1) {
+    c0 = t * P + d.nr - 1;
+    c1 = c0 - 1;
+    K = d.mur_kr;
+    comp = 1;
+  } else {
+    t -= d.nz - 1;
+    if (t >= 2 * (d.nr - 1)) return;
+    const bool hi = t >= d.nr - 1;
+    const int i = hi ? t - (d.nr - 1) : t;
+    c0 = (hi ? (d.nz - 1) * P : 0) + i;
+    c1 = c0 + (hi ? -P : P);
+    K = d.mur_kz;
+    comp = 0;
+  }
+  const float *Ein = d.f[par][comp];
+  float *Eout = d.f[par ^ 1][comp];
+  Eout[c0] = fmaf(K, Eout[c1] - Ein[c0], Ein[c1]);
+}
+
+// Eight observers per 64-lane block: lane = 8*observer + 4*component + corner; each lane forms
+// weight * E in FP64 and two butterflies sum the corners.
+__global__ void __launch_bounds__(64) k_rz_gather(RDev d, int par, double *w, int column, int ld) {
+  const int lane = threadIdx.x;
+  const int o = blockIdx.x * 8 + (lane >> 3);
+  const int comp = (lane >> 2) & 1, a = lane & 1, b = (lane >> 1) & 1;
+  double val = 0.0;
+  if (o < d.n_obs) {
+    const int *ix = d.obs_idx + (o * 2 + comp) * 2;
+    const double *tf = d.obs_t + (o * 2 + comp) * 2;
+    const double wgt = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]);
+    const long long node = (long long)(ix[1] + b) * d.pitch + ix[0] + a;
+    val = wgt * (double)d.f[par][comp][node];
+  }
+  val += __shfl_xor(val, 1);
+  val += __shfl_xor(val, 2);
+  if (o < d.n_obs && (lane & 3) == 0) {
+    w[((long long)o * 2 + comp) * ld + column] = val;
+    if (d.nan_flag && !isfinite(val)) *d.nan_flag = 1;
+  }
+}
+
+__global__ void k_rz_zero(uint4 *p, long long n) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    p[t] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_rz_copy(const float *src, float *dst, int nr, int nz, int pitch, int to_dense) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)nr * nz) return;
+  const int i = (int)(t % nr);
+  const long long k = t / nr;
+  if (to_dense) dst[t] = src[k * pitch + i];
+  else dst[k * pitch + i] = src[t];
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_sweep(const chf_rz_plan &p, const RDev &d, int par, hipStream_t s) {
+  const dim3 grid(8 * ((p.n_blocks + 7) / 8)), block(64 * p.wv);
+  switch (p.vx) {
+    case 1: k_rz_sweep<1><<<grid, block, 0, s>>>(d, par); break;
+    case 2: k_rz_sweep<2><<<grid, block, 0, s>>>(d, par); break;
+    case 4: k_rz_sweep<4><<<grid, block, 0, s>>>(d, par); break;
+    default: k_rz_sweep<8><<<grid, block, 0, s>>>(d, par); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rz_step(const chf_rz_plan &p, const RDev &d, int par, int step, const double *q,
+                          double *w, int column, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
+                          hipEvent_t ev_b = nullptr) {
+  hipError_t e = hipSuccess;
+  if (ev_a) e = hipEventRecord(ev_a, s);
+  if (e == hipSuccess) e = launch_sweep(p, d, par, s);
+  if (e == hipSuccess && ev_b) e = hipEventRecord(ev_b, s);
+  if (e != hipSuccess) return e;
+  if (d.src_on && d.n_src > 0) {
+    k_rz_source<<<(d.n_src + 63) / 64, 64, 0, s>>>(d, par ^ 1, step, q ? q : d.q_bins);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (d.mur) {
+    const int n = (d.nz - 1) + 2 * (d.nr - 1);
+    k_rz_mur<<<(n + 255) / 256, 256, 0, s>>>(d, par);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (d.n_obs > 0 && w) {
+    k_rz_gather<<<(d.n_obs + 7) / 8, 64, 0, s>>>(d, par ^ 1, w, column, ld);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_rz_zero(const chf_rz_plan &p, hipStream_t s) {
+  // both levels of all three fields are contiguous from offset 0, plus the watchdog flag
+  const long long n16 = (long long)(p.off_cp / 16);
+  k_rz_zero<<<2048, 256, 0, s>>>((uint4 *)p.ws, n16);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_rz_zero<<<1, 64, 0, s>>>((uint4 *)(p.ws + p.off_nan), 16);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium, const chf_rz_source *src,
+                              const chf_rz_observers *obs, const chf_rz_exec *ex, chf_rz_plan **out) {
+  if (!grid || !medium || !src || !obs || !ex || !out) return fail(CHF_EINVAL, "NULL descriptor");
+  *out = nullptr;
+  const chf_rz_grid &g = *grid;
+  if (g.nr < 4 || g.nz < 4 || g.n_steps < 0) return fail(CHF_EINVAL, "need nr, nz >= 4 and n_steps >= 0");
+  if (!(g.dr > 0) || !(g.dz > 0) || !(g.dt > 0) || !std::isfinite(g.dr) || !std::isfinite(g.dz) ||
+      !std::isfinite(g.dt))
+    return fail(CHF_EINVAL, "spacings and time step must be positive and finite");
+  if (!(medium->eps_r > 0) || !(medium->mu_r > 0) || !(medium->sigma >= 0))
+    return fail(CHF_EINVAL, "medium needs eps_r > 0, mu_r > 0, sigma >= 0");
+  const double v = kC0 / std::sqrt(medium->eps_r * medium->mu_r);
+  const double dt_max = 2.0 / (v * std::sqrt(kRadialEig / (g.dr * g.dr) + 4.0 / (g.dz * g.dz)));
+  if (g.dt > dt_max) return fail(CHF_ECFL, "dt above the stability limit of the (r, z) lattice");
+  if (ex->bc == CHF_BC_CPML) return fail(CHF_EUNSUPPORTED, "the (r, z) solver offers PEC and Mur walls");
+  if (ex->bc != CHF_BC_PEC && ex->bc != CHF_BC_MUR1) return fail(CHF_EINVAL, "unknown boundary kind");
+  const int vx = ex->vx ? ex->vx : 4, wv = ex->waves_per_block ? ex->waves_per_block : 4;
+  const int zchunk = ex->z_chunk ? ex->z_chunk : 32;
+  if (vx != 1 && vx != 2 && vx != 4 && vx != 8) return fail(CHF_EINVAL, "vx must be 1, 2, 4 or 8");
+  if (wv != 1 && wv != 2 && wv != 4 && wv != 8) return fail(CHF_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
+  if (zchunk < 1) return fail(CHF_EINVAL, "z_chunk must be >= 1");
+  const bool src_on = src->n_bins > 0;
+  if (src->n_bins < 0) return fail(CHF_EINVAL, "n_bins < 0");
+  if (src_on) {
+    if (!src->q_bins) return fail(CHF_EINVAL, "q_bins is NULL");
+    if (!(src->sigma_r > 0) || !(src->sigma_z > 0) || !(src->cut_sigmas > 0) || !(src->dz_bin > 0) ||
+        !(src->beta > 0))
+      return fail(CHF_EINVAL, "source widths, cut, bin width and beta must be positive");
+    if (2.0 * src->cut_sigmas * src->sigma_z / g.dz + 2.0 > kRzMaxWz)
+      return fail(CHF_EUNSUPPORTED, "longitudinal source support above 64 rows");
+  }
+  if (obs->n_obs < 0 || obs->n_obs > kRzMaxObs || (obs->n_obs > 0 && !obs->rz))
+    return fail(CHF_EINVAL, "bad observer list");
+
+  chf_rz_plan *p = new (std::nothrow) chf_rz_plan();
+  if (!p) return fail(CHF_ENOMEM, "host allocation");
+  p->g = g;
+  p->med = *medium;
+  p->src = *src;
+  p->ex = *ex;
+  p->vx = vx;
+  p->wv = wv;
+  p->zchunk = std::min(zchunk, g.nz);
+  p->pitch = (g.nr + 63) / 64 * 64;
+  const uint64_t elems = (uint64_t)p->pitch * (uint64_t)g.nz;
+  if (elems > (uint64_t(1) << 40)) {
+    delete p;
+    return fail(CHF_ENOMEM, "grid too large");
+  }
+  p->nrb = (g.nr + 64 * vx * wv - 1) / (64 * vx * wv);
+  p->nzc = (g.nz + p->zchunk - 1) / p->zchunk;
+  if ((uint64_t)p->nrb * p->nzc > (uint64_t)0x7fffffff / 8) {
+    delete p;
+    return fail(CHF_EINVAL, "too many workgroups for this tile shape");
+  }
+  p->n_blocks = p->nrb * p->nzc;
+  if (src_on) p->q_bins.assign(src->q_bins, src->q_bins + src->n_bins);
+  else p->q_bins.assign(1, 0.0);
+
+  // coefficients (FP64, rounded once)
+  const double eps = kEps0 * medium->eps_r, mu = kMu0 * medium->mu_r;
+  const double loss = medium->sigma * g.dt / (2.0 * eps);
+  p->ca = (1.0 - loss) / (1.0 + loss);
+  p->cb = (g.dt / eps) / (1.0 + loss);
+  p->db = g.dt / mu;
+  p->cp.assign(p->pitch, 0.f);
+  p->cm.assign(p->pitch, 0.f);
+  for (int i = 0; i <= g.nr - 2; i++) {
+    const double a = i == 0 ? g.dr / 8.0 : i * g.dr;
+    p->cp[i] = (float)(p->cb * (i + 0.5) * g.dr / (a * g.dr));
+    p->cm[i] = i == 0 ? 0.f : (float)(p->cb * (i - 0.5) * g.dr / (a * g.dr));
+  }
+  // radial source weights on the E_z nodes 0..nr-2, normalised with the ring areas
+  if (src_on) {
+    std::vector<double> gr;
+    double norm = 0.0;
+    for (int i = 0; i <= g.nr - 2; i++) {
+      const double r = i * g.dr;
+      if (r > src->cut_sigmas * src->sigma_r) break;
+      const double x = std::exp(-0.5 * (r / src->sigma_r) * (r / src->sigma_r));
+      const double a = i == 0 ? g.dr / 8.0 : r;
+      gr.push_back(x);
+      norm += x * 2.0 * kPi * a * g.dr;
+    }
+    for (double &x : gr) x /= norm;
+    p->wr = gr;
+    p->n_src = (int)gr.size();
+  }
+  if (p->wr.empty()) p->wr.assign(1, 0.0);
+
+  // observers: base node and fractions of the bilinear stencils
+  p->oidx.assign(std::max(1, obs->n_obs) * 4, 0);
+  p->ot.assign(std::max(1, obs->n_obs) * 4, 0.0);
+  for (int o = 0; o < obs->n_obs; o++) {
+    const double r = obs->rz[2 * o], z = obs->rz[2 * o + 1];
+    if (!std::isfinite(r) || !std::isfinite(z)) {
+      delete p;
+      return fail(CHF_EINVAL, "non-finite observer position");
+    }
+    for (int c = 0; c < 2; c++) {
+      const double fr = r / g.dr - (c == 0 ? 0.5 : 0.0);
+      const double fz = z / g.dz - (c == 1 ? 0.5 : 0.0);
+      const double i0 = std::floor(fr), k0 = std::floor(fz);
+      // E_r lives on nodes i <= nr-2, rows 0..nz-1; E_z on nodes 0..nr-1, rows 0..nz-2
+      const double imax = c == 0 ? g.nr - 3 : g.nr - 2, kmax = c == 0 ? g.nz - 2 : g.nz - 3;
+      if (!(i0 >= 0 && i0 <= imax && k0 >= 0 && k0 <= kmax)) {
+        delete p;
+        return fail(CHF_EDOMAIN, "observer stencil outside the (r, z) lattice");
+      }
+      p->oidx[(o * 2 + c) * 2] = (int)i0;
+      p->oidx[(o * 2 + c) * 2 + 1] = (int)k0;
+      p->ot[(o * 2 + c) * 2] = fr - i0;
+      p->ot[(o * 2 + c) * 2 + 1] = fz - k0;
+    }
+  }
+
+  // workspace layout: 6 field arrays first (zeroed together), then the tables
+  const uint64_t fbytes = align256(elems * sizeof(float));
+  uint64_t off = 0;
+  for (int l = 0; l < 2; l++)
+    for (int c = 0; c < 3; c++) {
+      p->off_f[l][c] = off;
+      off += fbytes;
+    }
+  p->field_bytes = off;
+  p->off_cp = off;
+  off = align256(off + p->cp.size() * sizeof(float));
+  p->off_cm = off;
+  off = align256(off + p->cm.size() * sizeof(float));
+  p->off_wr = off;
+  off = align256(off + p->wr.size() * sizeof(double));
+  p->off_q = off;
+  off = align256(off + p->q_bins.size() * sizeof(double));
+  p->off_oidx = off;
+  off = align256(off + p->oidx.size() * sizeof(int));
+  p->off_ot = off;
+  off = align256(off + p->ot.size() * sizeof(double));
+  p->off_nan = off;
+  off = align256(off + 256);
+  p->ws_bytes = off;
+
+  RDev &D = p->dev;
+  D.nr = g.nr;
+  D.nz = g.nz;
+  D.pitch = p->pitch;
+  D.zchunk = p->zchunk;
+  D.nrb = p->nrb;
+  D.n_blocks = p->n_blocks;
+  D.wv = wv;
+  D.ca = (float)p->ca;
+  D.db_dr = (float)(p->db / g.dr);
+  D.db_dz = (float)(p->db / g.dz);
+  D.cb_dz = (float)(p->cb / g.dz);
+  D.src_on = src_on ? 1 : 0;
+  D.n_bins = src_on ? src->n_bins : 0;
+  D.n_src = p->n_src;
+  D.z_entry = src->z_entry;
+  D.t_entry = src->t_entry;
+  D.v_src = src->beta * kC0;
+  D.sigma_z = src->sigma_z;
+  D.cut_sigmas = src->cut_sigmas;
+  D.z_bin0 = src->z_bin0;
+  D.dz_bin = src->dz_bin;
+  D.dz = g.dz;
+  D.dt = g.dt;
+  D.cb = p->cb;
+  D.mur = ex->bc == CHF_BC_MUR1;
+  D.mur_kr = (float)((v * g.dt - g.dr) / (v * g.dt + g.dr));
+  D.mur_kz = (float)((v * g.dt - g.dz) / (v * g.dt + g.dz));
+  D.n_obs = obs->n_obs;
+  *out = p;
+  return CHF_OK;
+}
+
+void chf_rz_plan_destroy(chf_rz_plan *p) {
+  if (!p) return;
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  delete p;
+}
+
+chf_status chf_rz_workspace_bytes(const chf_rz_plan *p, uint64_t *bytes) {
+  if (!p || !bytes) return fail(CHF_EINVAL, "NULL argument");
+  *bytes = p->ws_bytes;
+  return CHF_OK;
+}
+
+chf_status chf_rz_reset(chf_rz_plan *p, void *stream) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipError_t e = launch_rz_zero(*p, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "reset");
+  p->parity = 0;
+  p->n_done = 0;
+  return CHF_OK;
+}
+
+chf_status chf_rz_bind_workspace(chf_rz_plan *p, void *dev_ptr, uint64_t bytes, void *stream) {
+  if (!p || !dev_ptr) return fail(CHF_EINVAL, "NULL argument");
+  if (bytes < p->ws_bytes) return fail(CHF_ENOMEM, "workspace smaller than chf_rz_workspace_bytes");
+  if ((uintptr_t)dev_ptr % 256) return fail(CHF_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)dev_ptr;
+  p->ws = ws;
+  RDev &D = p->dev;
+  for (int l = 0; l < 2; l++)
+    for (int c = 0; c < 3; c++) D.f[l][c] = (float *)(ws + p->off_f[l][c]);
+  D.cp = (const float *)(ws + p->off_cp);
+  D.cm = (const float *)(ws + p->off_cm);
+  D.wr = (const double *)(ws + p->off_wr);
+  D.q_bins = (const double *)(ws + p->off_q);
+  D.obs_idx = (const int *)(ws + p->off_oidx);
+  D.obs_t = (const double *)(ws + p->off_ot);
+  D.nan_flag = (int *)(ws + p->off_nan);
+  struct Up {
+    uint64_t off;
+    const void *src;
+    size_t n;
+  } ups[] = {
+      {p->off_cp, p->cp.data(), p->cp.size() * sizeof(float)},
+      {p->off_cm, p->cm.data(), p->cm.size() * sizeof(float)},
+      {p->off_wr, p->wr.data(), p->wr.size() * sizeof(double)},
+      {p->off_q, p->q_bins.data(), p->q_bins.size() * sizeof(double)},
+      {p->off_oidx, p->oidx.data(), p->oidx.size() * sizeof(int)},
+      {p->off_ot, p->ot.data(), p->ot.size() * sizeof(double)},
+  };
+  for (const Up &u : ups) {
+    hipError_t e = hipMemcpyAsync(ws + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload of plan tables");
+  }
+  if (p->graph) {
+    (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  return chf_rz_reset(p, stream);
+}
+
+static chf_status rz_forward(chf_rz_plan *p, void *stream, const double *q, double *w, int32_t n_steps,
+                             int32_t first_column, int32_t ld, std::vector<hipEvent_t> *ev) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
+  if (p->dev.n_obs > 0 && w && ld < first_column + n_steps)
+    return fail(CHF_EINVAL, "ld_steps too small for first_column + n_steps");
+  RDev d = p->dev;
+  if (!p->ex.nan_watch) d.nan_flag = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  for (int t = 0; t < n_steps; t++) {
+    hipError_t e = launch_rz_step(*p, d, p->parity, p->n_done, q, w, first_column + t, ld, s,
+                                  ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    p->parity ^= 1;
+    p->n_done++;
+  }
+  return CHF_OK;
+}
+
+chf_status chf_rz_forward(chf_rz_plan *p, void *stream, const double *q, double *w, int32_t n_steps,
+                          int32_t first_column, int32_t ld) {
+  return rz_forward(p, stream, q, w, n_steps, first_column, ld, nullptr);
+}
+
+chf_status chf_rz_forward_timed(chf_rz_plan *p, void *stream, const double *q, double *w, int32_t n_steps,
+                                int32_t first_column, int32_t ld, double *sweep_ms) {
+  if (!p || !sweep_ms) return fail(CHF_EINVAL, "NULL argument");
+  if (n_steps < 0) return fail(CHF_EINVAL, "negative step count");
+  *sweep_ms = 0.0;
+  std::vector<hipEvent_t> ev(2 * (size_t)n_steps, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t t = 0; t < ev.size() && e == hipSuccess; t++) e = hipEventCreate(&ev[t]);
+  chf_status st = CHF_OK;
+  if (e == hipSuccess) st = rz_forward(p, stream, q, w, n_steps, first_column, ld, &ev);
+  if (e == hipSuccess && st == CHF_OK) e = hipStreamSynchronize((hipStream_t)stream);
+  double total = 0.0;
+  for (int t = 0; t < n_steps && e == hipSuccess && st == CHF_OK; t++) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]);
+    total += ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (st != CHF_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "timed forward");
+  *sweep_ms = total;
+  return CHF_OK;
+}
+
+chf_status chf_rz_forward_graph(chf_rz_plan *p, void *stream, const double *q, double *w) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  hipStream_t s = (hipStream_t)stream;
+  const int T = p->g.n_steps;
+  if (!p->graph || p->graph_w != w || p->graph_q != q) {
+    if (p->graph) {
+      (void)hipGraphExecDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hip_fail(e, "begin capture");
+    }
+    RDev d = p->dev;
+    if (!p->ex.nan_watch) d.nan_flag = nullptr;
+    hipError_t le = launch_rz_zero(*p, cs);
+    int par = 0;
+    for (int t = 0; t < T && le == hipSuccess; t++) {
+      le = launch_rz_step(*p, d, par, t, q, w, t, T, cs);
+      par ^= 1;
+    }
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(cs, &gr);
+    (void)hipStreamDestroy(cs);
+    if (le != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return hip_fail(le, "captured launch");
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      p->graph = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    p->graph_w = w;
+    p->graph_q = q;
+  }
+  hipError_t e = hipGraphLaunch(p->graph, s);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  p->parity = T & 1;
+  p->n_done = T;
+  return CHF_OK;
+}
+
+chf_status chf_rz_sync(chf_rz_plan *p, void *stream) {
+  if (!p) return fail(CHF_EINVAL, "NULL plan");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "pending error");
+  if (p->ws && p->ex.nan_watch) {
+    int flag = 0;
+    e = hipMemcpy(&flag, p->dev.nan_flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read watchdog flag");
+    if (flag) return fail(CHF_ENAN, "non-finite waveform value");
+  }
+  return CHF_OK;
+}
+
+static chf_status rz_copy(chf_rz_plan *p, void *stream, int comp, const float *src, float *dst, int to_dense) {
+  if (!p || comp < 0 || comp > 2 || !(to_dense ? (const void *)dst : (const void *)src))
+    return fail(CHF_EINVAL, "bad argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  float *f = p->dev.f[p->parity][comp];
+  const long long n = (long long)p->g.nr * p->g.nz;
+  if ((n + 255) / 256 > 0x7fffffffLL) return fail(CHF_EUNSUPPORTED, "field too large to copy in one launch");
+  k_rz_copy<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(to_dense ? f : src, to_dense ? dst : f,
+                                                                         p->g.nr, p->g.nz, p->pitch, to_dense);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CHF_OK : hip_fail(e, "field copy");
+}
+
+chf_status chf_rz_get_field(chf_rz_plan *p, void *stream, int32_t comp, float *out_dev) {
+  return rz_copy(p, stream, comp, nullptr, out_dev, 1);
+}
+
+chf_status chf_rz_set_field(chf_rz_plan *p, void *stream, int32_t comp, const float *in_dev) {
+  return rz_copy(p, stream, comp, in_dev, nullptr, 0);
+}
+
+chf_status chf_rz_get_info(const chf_rz_plan *p, chf_rz_info *info) {
+  if (!p || !info) return fail(CHF_EINVAL, "NULL argument");
+  info->vx = p->vx;
+  info->waves_per_block = p->wv;
+  info->z_chunk = p->zchunk;
+  info->pitch = p->pitch;
+  info->n_blocks = p->n_blocks;
+  info->n_src = p->n_src;
+  info->field_bytes = p->field_bytes;
+  info->workspace_bytes = p->ws_bytes;
+  info->bytes_per_cell_update = 6.0 * sizeof(float);  // read E_r, E_z, H; write all three
+  return CHF_OK;
+}
+
+}  // extern "C"

@@ -314,3 +314,132 @@ class CherenkovFDTD(torch.autograd.Function):
 
 def waveforms(q_bins: torch.Tensor, plan: "Plan", checkpoint_every: Optional[int] = None) -> torch.Tensor:
     return CherenkovFDTD.apply(q_bins, plan, checkpoint_every)
+
+
+# ---------------------------------------------------------------- axisymmetric (r, z) solver
+def rz_descriptors(w, vx=0, waves=0, zchunk=0, nan_watch=False, q_bins=None):
+    """C descriptor structs for an RZWorkload.  Returns (structs, keepalive)."""
+    q = np.ascontiguousarray(w.q_bins if q_bins is None else q_bins, dtype=np.float64)
+    obs = np.ascontiguousarray(w.obs_rz, dtype=np.float64).reshape(-1, 2)
+    g = N.RZGrid(w.nr, w.nz, w.n_steps, 0, w.dr, w.dz, w.dt)
+    m = N.Medium(w.eps_r, w.mu_r, w.sigma)
+    s = N.RZSource(w.z_entry, w.t_entry, w.beta, w.sigma_r, w.sigma_z, w.cut_sigmas,
+                   len(q) if w.src_on else 0, 0, w.z_bin0, w.dz_bin, _dp(q))
+    o = N.RZObservers(obs.shape[0], 0, _dp(obs))
+    e = N.RZExec(N.BC[w.bc], vx, waves, zchunk, 1 if nan_watch else 0, 0)
+    return (g, m, s, o, e), (q, obs)
+
+
+def create_rz_plan_handle(w, **kw) -> ct.c_void_p:
+    """chf_rz_plan_create only (host-side validation and tables; no device call)."""
+    (g, m, s, o, e), keep = rz_descriptors(w, **kw)
+    h = ct.c_void_p()
+    N.check(N.lib().chf_rz_plan_create(ct.byref(g), ct.byref(m), ct.byref(s), ct.byref(o), ct.byref(e),
+                                       ct.byref(h)), "chf_rz_plan_create")
+    return h
+
+
+class RZPlan:
+    """The axisymmetric solver on one (r, z) grid, with its caller-owned device workspace.
+
+    >>> plan = RZPlan(rz_workload)
+    >>> w = plan.run()                  # FP64 waveforms [n_obs, 2 (E_r, E_z), n_steps]
+    """
+
+    def __init__(self, w, vx: int = 0, waves: int = 0, zchunk: int = 0, nan_watch: bool = False,
+                 device=None):
+        self.w = w
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._h = create_rz_plan_handle(w, vx=vx, waves=waves, zchunk=zchunk, nan_watch=nan_watch)
+        L = N.lib()
+        nbytes = ct.c_uint64()
+        N.check(L.chf_rz_workspace_bytes(self._h, ct.byref(nbytes)), "chf_rz_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            N.check(L.chf_rz_bind_workspace(self._h, ct.c_void_p(self.workspace.data_ptr()),
+                                            self.workspace_bytes, _stream_handle()), "chf_rz_bind_workspace")
+        self.n_obs = w.n_obs
+        self.n_steps = w.n_steps
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            N.lib().chf_rz_plan_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        ri = N.RZInfo()
+        N.check(N.lib().chf_rz_get_info(self._h, ct.byref(ri)), "chf_rz_get_info")
+        return {f: getattr(ri, f) for f, _ in N.RZInfo._fields_}
+
+    def new_waveforms(self) -> torch.Tensor:
+        return torch.zeros((self.n_obs, 2, self.n_steps), dtype=torch.float64, device=self.device)
+
+    def reset(self, stream=None):
+        N.check(N.lib().chf_rz_reset(self._h, _stream_handle(stream)), "chf_rz_reset")
+
+    @staticmethod
+    def _ptr(t: Optional[torch.Tensor]) -> ct.c_void_p:
+        return ct.c_void_p(t.data_ptr()) if t is not None else ct.c_void_p()
+
+    def _check_io(self, out, q_bins):
+        if out is not None:
+            assert out.dtype == torch.float64 and out.is_contiguous() and out.device == self.device
+            assert out.shape[:2] == (self.n_obs, 2)
+        if q_bins is not None:
+            assert q_bins.dtype == torch.float64 and q_bins.numel() == len(self.w.q_bins)
+
+    def forward(self, n_steps: int, out: Optional[torch.Tensor] = None, first_column: int = 0,
+                q_bins: Optional[torch.Tensor] = None, stream=None):
+        self._check_io(out, q_bins)
+        ld = out.shape[2] if out is not None else 0
+        N.check(N.lib().chf_rz_forward(self._h, _stream_handle(stream), self._ptr(q_bins), self._ptr(out),
+                                       n_steps, first_column, ld), "chf_rz_forward")
+
+    def forward_timed(self, n_steps: int, out: Optional[torch.Tensor] = None, first_column: int = 0,
+                      stream=None) -> float:
+        """chf_rz_forward plus hipEvents around every sweep launch; returns their summed ms."""
+        self._check_io(out, None)
+        ld = out.shape[2] if out is not None else 0
+        ms = ct.c_double()
+        N.check(N.lib().chf_rz_forward_timed(self._h, _stream_handle(stream), ct.c_void_p(), self._ptr(out),
+                                             n_steps, first_column, ld, ct.byref(ms)), "chf_rz_forward_timed")
+        return float(ms.value)
+
+    def run(self, q_bins: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+            graph: bool = False, stream=None, sync: bool = True) -> torch.Tensor:
+        """Full run from zero fields; returns [n_obs, 2, n_steps] FP64 waveforms."""
+        out = self.new_waveforms() if out is None else out
+        self._check_io(out, q_bins)
+        if graph:
+            N.check(N.lib().chf_rz_forward_graph(self._h, _stream_handle(stream), self._ptr(q_bins),
+                                                 self._ptr(out)), "chf_rz_forward_graph")
+        else:
+            self.reset(stream)
+            self.forward(self.n_steps, out, 0, q_bins, stream)
+        if sync:
+            self.sync(stream)
+        return out
+
+    def sync(self, stream=None):
+        N.check(N.lib().chf_rz_sync(self._h, _stream_handle(stream)), "chf_rz_sync")
+
+    def get_field(self, comp: int, stream=None) -> torch.Tensor:
+        """Component 0 = E_r, 1 = E_z, 2 = H_phi of the current level as [nz, nr] FP32."""
+        out = torch.empty((self.w.nz, self.w.nr), dtype=torch.float32, device=self.device)
+        N.check(N.lib().chf_rz_get_field(self._h, _stream_handle(stream), comp, ct.c_void_p(out.data_ptr())),
+                "chf_rz_get_field")
+        return out
+
+    def set_field(self, comp: int, value: torch.Tensor, stream=None):
+        v = value.to(device=self.device, dtype=torch.float32).contiguous()
+        assert v.shape == (self.w.nz, self.w.nr)
+        N.check(N.lib().chf_rz_set_field(self._h, _stream_handle(stream), comp, ct.c_void_p(v.data_ptr())),
+                "chf_rz_set_field")
+        torch.cuda.current_stream().synchronize()

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "chfdtd.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(chf_[a-z_]+)\s*\(", text)))
 
@@ -23,7 +24,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     L = N.lib()
     names = declared_symbols()
-    assert "chf_plan_create" in names and "chf_forward" in names
+    assert "chf_plan_create" in names and "chf_forward" in names and "chf_rz_forward" in names
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(N.EXPORTED)
@@ -140,3 +141,43 @@ def test_snapshot_size_and_adjoint_state_checks():
         assert N.STATUS[N.lib().chf_plan_load_state(h, None, None, 0)] == "CHF_EINVAL"
     finally:
         N.lib().chf_plan_destroy(h)
+
+
+def _rz_status(w, **kw):
+    try:
+        h = solver.create_rz_plan_handle(w, **kw)
+    except N.ChfError as e:
+        return e.status
+    N.lib().chf_rz_plan_destroy(h)
+    return "CHF_OK"
+
+
+def test_rz_plan_validation():
+    w = W.rz_small()
+    assert _rz_status(w) == "CHF_OK"
+    assert _rz_status(W.rz_paper_grid(8192)) == "CHF_OK"
+    assert _rz_status(w.replace(bc="cpml")) == "CHF_EUNSUPPORTED"
+    assert _rz_status(w, vx=3) == "CHF_EINVAL"
+    assert _rz_status(w, waves=16) == "CHF_EINVAL"
+    assert _rz_status(w.replace(nr=3)) == "CHF_EINVAL"
+    # stability limit of the (r, z) lattice: the axis raises the radial eigenvalue to 4.85/dr^2
+    v = W.C0 / W.N_ICE
+    lim = 2.0 / (v * np.sqrt(4.85 / w.dr ** 2 + 4.0 / w.dz ** 2))
+    assert _rz_status(w.replace(dt=lim * 0.999)) == "CHF_OK"
+    assert _rz_status(w.replace(dt=lim * 1.001)) == "CHF_ECFL"
+    for r, z in ((0.3 * w.dr, 1.0), (1.0, (w.nz - 1.2) * w.dz), ((w.nr - 1.2) * w.dr, 1.0)):
+        obs = w.obs_rz.copy()
+        obs[0] = (r, z)
+        assert _rz_status(w.replace(obs_rz=obs)) == "CHF_EDOMAIN"
+
+
+def test_rz_radial_stability_constant():
+    """The largest eigenvalue of the radial operator (E_z -> H_phi -> E_z with the axis disc)
+    stays below the 4.85/dr^2 the plan's stability check assumes, for any nr."""
+    for nr in (4, 9, 64, 700):
+        i = np.arange(nr - 1)
+        a = np.where(i == 0, 1.0 / 8.0, i.astype(float))
+        D = np.eye(nr - 1, k=1) - np.eye(nr - 1)
+        C = np.diag((i + 0.5) / a) - np.diag(((i - 0.5) / a)[1:], k=-1)
+        lam = np.max(np.linalg.eigvals(-C @ D).real)
+        assert 4.0 < lam < 4.85

@@ -17,6 +17,11 @@ oracle's stored waveforms), and the FP64 CPU oracle timed on a bounded sample.
 Counter summaries: ``--copy-probe`` adds a 256 MiB device copy before the runs (the
 calibration dispatch for FETCH_SIZE / WRITE_SIZE); ``--summarize-pmc FETCH.csv WRITE.csv``
 turns two rocprofv3 --pmc runs of that command into HBM bytes per launch of the sweep.
+
+``--workload rz-8192`` (or rz-N) measures the paper's own axisymmetric (r, z) scheme instead:
+a bench step is one full run of the N x N lattice (1 cm cells, Mur walls, the moving shower,
+64 observers, N Yee steps) from zero fields, one kernel launch per Yee step; the default line
+also carries a short summary of that path under "axisymmetric".
 """
 from __future__ import annotations
 
@@ -36,6 +41,8 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20
 FUSED_KERNEL = "chf::k_fused<"
+RZ_KERNEL = "k_rz_step<"
+RZ_BYTES_PER_NODE = 24.0  # read E_r, E_z, H_phi once and write them once (FP32)
 DTYPE = {"fp32": "f32", "bf16": "f32 (bf16 storage)", "fp16": "f32 (f16 storage)"}
 
 
@@ -43,26 +50,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(files=("chf_kernels.hip", "chf_internal.h")) -> str:
     h = hashlib.sha256()
-    for f in ("chf_kernels.hip", "chf_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1001_5341_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
+def is_rz(workload: str) -> bool:
+    return workload.startswith("rz-")
+
+
+def kernel_digest_for(workload: str) -> str:
+    return kernel_source_digest(("chf_rz.hip",) if is_rz(workload) else ("chf_kernels.hip", "chf_internal.h"))
+
+
 def traffic_path(workload: str, storage: str) -> str:
-    return os.path.join(ROOT, "profiles", f"traffic_fused_sweep_{workload}_{storage}.json")
+    kern = "rz_step" if is_rz(workload) else "fused_sweep"
+    return os.path.join(ROOT, "profiles", f"traffic_{kern}_{workload}_{storage}.json")
 
 
 def measured_traffic(workload: str, storage: str):
-    """HBM bytes per launch of the fused sweep from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
     path = traffic_path(workload, storage)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_digest") != kernel_source_digest():
+    if rec.get("kernel_digest") != kernel_digest_for(workload):
         return None
     return rec.get("bytes_per_launch")
 
@@ -78,21 +94,23 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the fused sweep, each scaled by what the
     same counter reads for the 256 MiB calibration copy (read 256 MiB, write 256 MiB)."""
     out = {}
+    kname = RZ_KERNEL if is_rz(workload) else FUSED_KERNEL
     for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = list(_dispatches(path, counter))
         copies = [v for k, g, v in rows if "copyBuffer" in k]
         if not copies:
             raise SystemExit(f"{path}: no calibration copy dispatch (run with --copy-probe)")
         copy_kib = max(copies)  # the 256 MiB probe is by far the largest copy
-        fused = [v for k, g, v in rows if FUSED_KERNEL in k]
+        fused = [v for k, g, v in rows if kname in k]
         if not fused:
-            raise SystemExit(f"{path}: no fused-sweep dispatch")
+            raise SystemExit(f"{path}: no {kname} dispatch")
         factor = (COPY_PROBE_BYTES / 1024.0) / copy_kib
         out[name] = {"copy_probe_kib": copy_kib, "scale": factor, "dispatches": len(fused),
                      "raw_kib_per_launch": float(np.mean(fused)),
                      "bytes_per_launch": float(np.mean(fused)) * 1024.0 * factor}
-    rec = {"workload": workload, "storage": storage, "kernel": "fused interior sweep (chf::k_fused)",
-           "kernel_digest": kernel_source_digest(), "command": command,
+    kdesc = ("axisymmetric step (k_rz_step)" if is_rz(workload) else "fused interior sweep (chf::k_fused)")
+    rec = {"workload": workload, "storage": storage, "kernel": kdesc,
+           "kernel_digest": kernel_digest_for(workload), "command": command,
            "fetch": out["fetch"], "write": out["write"],
            "bytes_per_launch": out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]}
     path = traffic_path(workload, storage)
@@ -220,6 +238,110 @@ def run_variant(w, storage: str, args, n_runs: int, warmup: int):
     return info, wall, ev_s, fused_ms, launches, got
 
 
+def rz_cpu_baseline(w, n_steps: int = 4):
+    """The axisymmetric FP64 oracle (NumPy, one thread), as it stands, on the workload's own
+    lattice for a few Yee steps from zero fields (its cost per step does not depend on the
+    field values)."""
+    from oracle import rz_oracle as R
+
+    st = R.RZState(w)
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        st.step()
+    dt = time.perf_counter() - t0
+    return {"value": round(w.nr * w.nz * n_steps / dt / 1e6, 3), "unit": "Mcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"NumPy FP64 oracle of the (r, z) scheme on the full {w.nr}x{w.nz} lattice, "
+                      f"{n_steps} steps, {dt:.1f} s"}
+
+
+def rz_measure(w, n_runs: int, warmup: int, vx=0, waves=0, zchunk=0):
+    """n_runs full runs through chf_rz_forward_timed; returns (info, wall s, event s,
+    summed step-kernel ms, launches, waveforms)."""
+    import torch
+
+    from paper_1001_5341_amd import solver
+
+    plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zchunk, device=torch.device("cuda:0"))
+    info = plan.info()
+    out = plan.new_waveforms()
+    for i in range(warmup):
+        plan.run(out=out)
+        log(f"rz warmup {i} done")
+    wall, ev_s, ms, launches = timed_runs(plan, out, n_runs)
+    got = out.cpu().numpy()
+    plan.close()
+    return info, wall, ev_s, ms, launches, got
+
+
+def rz_roofline(w, ms: float, launches: int):
+    nodes = w.nr * (w.nz - 1)  # rows 0..nz-2 are marched over every radial node
+    alg = nodes * RZ_BYTES_PER_NODE
+    avg_s = ms / 1e3 / launches
+    achieved = alg / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernel": "k_rz_step (H, E_r, E_z, source, walls and the previous step's sampling; one launch per Yee step)",
+            "launch_avg_us": round(avg_s * 1e6, 2), "launches": launches, "nodes_per_launch": nodes,
+            "bytes_per_node": RZ_BYTES_PER_NODE, "alg_bytes_per_launch": int(alg)}
+
+
+def rz_main(args):
+    import torch
+
+    from paper_1001_5341_amd import workloads as W
+
+    w = W.rz_workload_by_name(args.workload)
+    if args.time_steps:
+        w = w.replace(n_steps=args.time_steps)
+    torch.cuda.set_device(0)
+    log(f"workload {w.name}: {w.nr}x{w.nz}, {w.n_steps} steps")
+    if args.copy_probe:
+        a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    info, wall, ev_s, ms, launches, got = rz_measure(w, args.steps, args.warmup, args.vx, args.waves,
+                                                     args.zchunk)
+    log(f"rz: {args.steps} timed runs, wall {wall:.3f} s, step kernel {ms / launches * 1e3:.1f} us/launch")
+    roof = rz_roofline(w, ms, launches)
+    roof["traffic"] = measured_traffic(args.workload, "fp32") if not args.time_steps else None
+    rec = {
+        "metric": "Yee Mcell-updates/s and % HBM roofline of the axisymmetric (r, z) scheme, FP32",
+        "value": round(w.nr * w.nz * w.n_steps * args.steps / wall / 1e6, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Greisen-like shower profile and observers; no datasets)",
+        "config": {"workload": w.name, "grid_rz": [w.nr, w.nz], "yee_steps_per_run": w.n_steps,
+                   "boundary": w.bc, "observers": w.n_obs,
+                   "tile": {"vx": info["vx"], "waves_per_block": info["waves_per_block"],
+                            "z_chunk": info["z_chunk"]},
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "waveforms_finite": bool(np.isfinite(got).all()),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the (r, z) oracle on the host")
+        rec["cpu_baseline"] = rz_cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+def rz_summary(n: int = 8192, n_steps: int = 2048):
+    """Short measurement of the axisymmetric path for the default line."""
+    from paper_1001_5341_amd import workloads as W
+
+    w = W.rz_paper_grid(n, n_steps=n_steps)
+    info, wall, ev_s, ms, launches, got = rz_measure(w, 1, 1)
+    roof = rz_roofline(w, ms, launches)
+    return {"workload": w.name, "yee_steps": n_steps, "value": round(w.nr * w.nz * n_steps / wall / 1e6, 1),
+            "unit": "Mcell-updates/s", "roofline_frac": roof["frac"], "achieved_gbs": roof["achieved"],
+            "step_kernel_avg_us": roof["launch_avg_us"],
+            "note": "python bench.py --workload rz-8192 gives the full line"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +353,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--vx", type=int, default=0, help="(r, z) path: radial nodes per lane")
     ap.add_argument("--time-steps", type=int, default=0, help="override the Yee steps per run")
     ap.add_argument("--no-tune", action="store_true", help="default tile shape instead of the autotuner's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -249,6 +372,10 @@ def main():
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU z-slab decomposition is design-only)"}))
         sys.exit(2)
+
+    if is_rz(args.workload):
+        rz_main(args)
+        return
 
     import torch
 
@@ -316,6 +443,9 @@ def main():
                 v["accuracy_vs_fp64_oracle"] = e
             variants[st] = v
         rec["storage_variants"] = variants
+    if not args.no_variants and not args.time_steps:
+        log("axisymmetric (r, z) summary")
+        rec["axisymmetric"] = rz_summary()
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -19,9 +19,11 @@
 //   H   += db/dr (E_z(i+1) - E_z(i)) - db/dz (E_r(k+1) - E_r(k))
 //   E_r  = ca E_r - cb/dz (H(k) - H(k-1))
 //   E_z  = ca E_z + cp_i H(i) - cm_i H(i-1),  cp_i = cb r_{i+1/2}/(a_i dr), cm_i = cb r_{i-1/2}/(a_i dr)
-// with a_i = r_i (a_0 = dr/8, the disc of radius dr/2 on the axis).  Afterwards the source
-// kernel subtracts cb J_z, the Mur kernel sets the wall values and the gather kernel samples
-// E^{n+1} at the observers in FP64.
+// with a_i = r_i (a_0 = dr/8, the disc of radius dr/2 on the axis).  The same launch subtracts
+// cb J_z of the moving source on the nodes it covers, writes the Mur (or PEC) wall values, and
+// samples the previous step's E at the observers in FP64 (that level is this launch's input, so
+// the sampling races nothing); a small gather kernel samples the last step of each call.  A step
+// is thus one kernel launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,7 +49,7 @@ constexpr int kRzMaxObs = 1 << 16;
 constexpr double kRadialEig = 4.85;
 
 struct RDev {
-  int nr, nz, pitch, zchunk, nrb, n_blocks, wv;
+  int nr, nz, pitch, zchunk, nrb, n_blocks, n_gblocks, wv;
   float ca, db_dr, db_dz, cb_dz;
   float *f[2][3];          // [level][E_r, E_z, H_phi]
   const float *cp, *cm;    // [pitch]
@@ -86,6 +88,7 @@ struct chf_rz_plan {
   chf_rz_exec ex;
   std::vector<double> q_bins;
   int vx = 4, wv = 4, zchunk = 32, pitch = 0, nrb = 0, nzc = 0, n_blocks = 0, n_src = 0;
+  bool mur_r_kernel = false;  // the r-wall node starts a wave: its Mur value takes a kernel of its own
   double ca = 1, cb = 0, db = 0;
   std::vector<float> cp, cm;
   std::vector<double> wr;
@@ -129,24 +132,60 @@ __device__ __forceinline__ void st(float *p, const float (&o)[N], bool on) {
   *reinterpret_cast<F<N> *>(p) = x;
 }
 
-// H' = H - db/dz dEr + db/dr dEz (the order every sweep uses)
+// H' = H - db/dz dEr + db/dr dEz (the order every tile shape uses)
 __device__ __forceinline__ float h_node(float h, float d_er, float d_ez, const RDev &d) {
   return fmaf(d.db_dr, d_ez, fmaf(-d.db_dz, d_er, h));
 }
 
+// Observer sampling of level `par` into waveform column `column`: eight observers per wave,
+// lane = 8*observer + 4*component + corner; each lane forms weight * E in FP64 and two
+// butterflies sum the corners.
+__device__ __forceinline__ void gather_wave(const RDev &d, int par, double *w, int column, int ld, int o0,
+                                            int lane) {
+  const int o = o0 + (lane >> 3);
+  const int comp = (lane >> 2) & 1, a = lane & 1, b = (lane >> 1) & 1;
+  double val = 0.0;
+  if (o < d.n_obs) {
+    const int *ix = d.obs_idx + (o * 2 + comp) * 2;
+    const double *tf = d.obs_t + (o * 2 + comp) * 2;
+    const double wgt = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]);
+    const long long node = (long long)(ix[1] + b) * d.pitch + ix[0] + a;
+    val = wgt * (double)d.f[par][comp][node];
+  }
+  val += __shfl_xor(val, 1);
+  val += __shfl_xor(val, 2);
+  if (o < d.n_obs && (lane & 3) == 0) {
+    w[((long long)o * 2 + comp) * ld + column] = val;
+    if (d.nan_flag && !isfinite(val)) *d.nan_flag = 1;
+  }
+}
+
+// One whole step in one launch.  Workgroups [0, n_blocks) sweep tiles (a tile = wv waves side by
+// side in r, each 64*VX nodes wide, times a chunk of z rows); the n_gblocks workgroups after
+// them sample level `par` (E^n, the previous step's result, which this launch only reads) into
+// waveform column gcol.  Rows 0..nz-2 are marched; the E_r rows on the z walls are written from
+// rows 1 and nz-2 (copied, or the Mur value).  The moving source is subtracted from E_z by the
+// lanes that own its nodes, and the Mur value of E_z on the r wall by the lane that owns the
+// wall (the host adds k_rz_mur_r when the wall is the first node of a wave).
 template <int VX>
-__global__ void __launch_bounds__(512) k_rz_sweep(RDev d, int par) {
-  const int per = (d.n_blocks + 7) >> 3;  // hardware block b runs on XCD b % 8
+__global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, const double *q, double *w,
+                                                 int gcol, int ldw) {
+  const int n_all = d.n_blocks + d.n_gblocks;
+  const int per = (n_all + 7) >> 3;  // hardware block b runs on XCD b % 8
   const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (logical >= d.n_blocks) return;
-  const int rb = logical % d.nrb, zc = logical / d.nrb;
+  if (logical >= n_all) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (logical >= d.n_blocks) {
+    if (gcol >= 0) gather_wave(d, par, w, gcol, ldw, ((logical - d.n_blocks) * d.wv + wv) * 8, lane);
+    return;
+  }
+  const int rb = logical % d.nrb, zc = logical / d.nrb;
   const int w0 = (rb * d.wv + wv) * 64 * VX;  // first node of the wave
   if (w0 >= d.nr) return;                     // whole wave beyond the last node
   const int c0 = w0 + lane * VX;
   const bool on = c0 < d.nr;
-  const int k0 = zc * d.zchunk, k1 = min(k0 + d.zchunk, d.nz);
   const int nr = d.nr, nz = d.nz;
+  const int k0 = zc * d.zchunk, k1 = min(k0 + d.zchunk, nz - 1);
   const long long P = d.pitch;
   const float *Er = d.f[par][0], *Ez = d.f[par][1], *Hp = d.f[par][2];
   float *Ero = d.f[par ^ 1][0], *Ezo = d.f[par ^ 1][1], *Hpo = d.f[par ^ 1][2];
@@ -160,8 +199,42 @@ __global__ void __launch_bounds__(512) k_rz_sweep(RDev d, int par) {
 #pragma unroll
   for (int v = 0; v < VX; v++) live[v] = c0 + v <= nr - 2;
 
+  // source rows of this step (FP64 bookkeeping: bunch position, Q(z_s) from the hat bins, the
+  // longitudinal weights normalised over the window; lane j holds the weight of row lo + j)
+  int s_lo = 0, s_m = 0;
+  double s_amp = 0.0, s_w = 0.0;
+  if (d.src_on && w0 < d.n_src) {
+    const double tt = (step + 0.5) * d.dt;
+    if (tt >= d.t_entry) {
+      const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
+      const double u = (zs - d.z_bin0) / d.dz_bin;
+      const double fl = floor(u);
+      const int b0 = (int)fl;
+      const double t = u - fl;
+      const double *qb = q ? q : d.q_bins;
+      double qz = 0.0;
+      if (b0 >= 0 && b0 < d.n_bins) qz += (1.0 - t) * qb[b0];
+      if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) qz += t * qb[b0 + 1];
+      const double half = d.cut_sigmas * d.sigma_z;
+      s_lo = (int)ceil((zs - half) / d.dz - 0.5);
+      const int hi = (int)floor((zs + half) / d.dz - 0.5);
+      s_m = max(0, min(hi - s_lo + 1, 64));
+      const double dd = (s_lo + lane + 0.5) * d.dz - zs;
+      s_w = lane < s_m ? exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) : 0.0;
+      double norm = s_w;
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) norm += __shfl_xor(norm, m);
+      s_w = s_w / (norm * d.dz);
+      s_amp = d.cb * d.v_src * qz;
+    }
+  }
+  // Mur on the r wall: position of node nr-1 in this lane (the wave-start case is the host's)
+  const int vw = nr - 1 - c0;
+  const bool wall_here = d.mur && vw >= 0 && vw < VX && !(vw == 0 && lane == 0);
+  const bool wall_wave = d.mur && nr - 1 > w0 && nr - 1 < w0 + 64 * VX;  // some lane > 0 or v > 0
+
   float er_k[VX], hn_b[VX];  // E_r(k) of the input level, H^{n+1/2}(k-1)
-  float erl_k = 0.f;         // lane 0: E_r(c0-1, k)
+  float erl_k = 0.f;                   // lane 0: E_r(c0-1, k)
   if (k0 > 0) {
     const int kb = k0 - 1;
     float erb[VX], ezb[VX], hb[VX];
@@ -183,20 +256,18 @@ __global__ void __launch_bounds__(512) k_rz_sweep(RDev d, int par) {
   }
   if (halo_l) erl_k = Er[k0 * P + c0 - 1];
 
-  for (int k = k0; k < k1; k++) {
-    const bool top = k + 1 < nz;
+  for (int k = k0; k < k1; k++) {  // k <= nz-2
     float er1[VX], ez[VX], h[VX];
-    ld<VX>(Er + (k + 1) * P + c0, er1, on && top);
+    ld<VX>(Er + (k + 1) * P + c0, er1, on);
     ld<VX>(Ez + k * P + c0, ez, on);
     ld<VX>(Hp + k * P + c0, h, on);
     float ezr = __shfl_down(ez[0], 1);
     if (lane == 63) ezr = halo_r ? Ez[k * P + c0 + VX] : 0.f;
-    const bool hrow = k <= nz - 2;
     float hn[VX];
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       const float e1 = v + 1 < VX ? ez[v + 1] : ezr;
-      hn[v] = live[v] && hrow ? h_node(h[v], er1[v] - er_k[v], e1 - ez[v], d) : h[v];
+      hn[v] = live[v] ? h_node(h[v], er1[v] - er_k[v], e1 - ez[v], d) : h[v];
     }
     // H(c0-1, k): from the lane below, or recomputed by lane 0 from the input level
     float hl = __shfl_up(hn[VX - 1], 1);
@@ -204,23 +275,55 @@ __global__ void __launch_bounds__(512) k_rz_sweep(RDev d, int par) {
       hl = 0.f;
       if (halo_l) {
         const long long c = k * P + c0 - 1;
-        const float h_l = Hp[c], ez_l = Ez[c];
-        const float er1_l = top ? Er[c + P] : 0.f;
-        hl = hrow ? h_node(h_l, er1_l - erl_k, ez[0] - ez_l, d) : h_l;
+        const float h_l = Hp[c], ez_l = Ez[c], er1_l = Er[c + P];
+        hl = h_node(h_l, er1_l - erl_k, ez[0] - ez_l, d);
         erl_k = er1_l;
       }
     }
-    const bool erow = k >= 1 && k <= nz - 2;
+    const bool erow = k >= 1;
     float ero[VX], ezo[VX];
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       ero[v] = live[v] && erow ? fmaf(-d.cb_dz, hn[v] - hn_b[v], d.ca * er_k[v]) : er_k[v];
       const float hm = v > 0 ? hn[v - 1] : hl;
-      ezo[v] = live[v] && hrow ? fmaf(-cm[v], hm, fmaf(cp[v], hn[v], d.ca * ez[v])) : ez[v];
+      ezo[v] = live[v] ? fmaf(-cm[v], hm, fmaf(cp[v], hn[v], d.ca * ez[v])) : ez[v];
+    }
+    if (s_m > 0 && k - s_lo >= 0 && k - s_lo < s_m) {  // wave-uniform
+      const double wz = __shfl(s_w, k - s_lo);
+#pragma unroll
+      for (int v = 0; v < VX; v++)
+        if (c0 + v < d.n_src) ezo[v] = ezo[v] - (float)(s_amp * d.wr[c0 + v] * wz);
+    }
+    if (wall_wave) {  // E_z on r = r_max: inner^n + K (inner^{n+1} - wall^n)
+      const float en = __shfl_up(ezo[VX - 1], 1), ei = __shfl_up(ez[VX - 1], 1);
+      if (wall_here) {
+#pragma unroll
+        for (int v = 0; v < VX; v++)
+          if (v == vw) {
+            const float inner_new = v > 0 ? ezo[v > 0 ? v - 1 : 0] : en;
+            const float inner_old = v > 0 ? ez[v > 0 ? v - 1 : 0] : ei;
+            ezo[v] = fmaf(d.mur_kr, inner_new - ez[v], inner_old);
+          }
+      }
     }
     st<VX>(Hpo + k * P + c0, hn, on);
-    st<VX>(Ero + k * P + c0, ero, on);
+    if (k >= 1) st<VX>(Ero + k * P + c0, ero, on);
     st<VX>(Ezo + k * P + c0, ezo, on);
+    if (k == 1) {  // z = 0 wall from row 1
+      float w0v[VX];
+      ld<VX>(Er + c0, w0v, on);
+#pragma unroll
+      for (int v = 0; v < VX; v++)
+        if (d.mur && live[v]) w0v[v] = fmaf(d.mur_kz, ero[v] - w0v[v], er_k[v]);
+      st<VX>(Ero + c0, w0v, on);
+    }
+    if (k == nz - 2) {  // z = z_max wall from row nz-2
+      float w1v[VX];
+#pragma unroll
+      for (int v = 0; v < VX; v++)
+        w1v[v] = d.mur && live[v] ? fmaf(d.mur_kz, ero[v] - er1[v], er_k[v]) : er1[v];
+      st<VX>(Ero + (k + 1) * P + c0, w1v, on);
+    }
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       er_k[v] = er1[v];
@@ -229,93 +332,19 @@ __global__ void __launch_bounds__(512) k_rz_sweep(RDev d, int par) {
   }
 }
 
-// J_z of the moving Gaussian charge at (n+1/2) dt, subtracted (times Cb) from E_z^{n+1}; one
-// thread per radial node of the source patch.  FP64 bookkeeping: bunch position, Q(z_s) from
-// the hat bins, lattice-normalised longitudinal weights.
-__global__ void k_rz_source(RDev d, int out_par, int step, const double *q) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!d.src_on || i >= d.n_src) return;
-  const double tt = (step + 0.5) * d.dt;
-  if (tt < d.t_entry) return;
-  const double wr = d.wr[i];
-  if (wr == 0.0) return;
-  const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
-  const double u = (zs - d.z_bin0) / d.dz_bin;
-  const double fl = floor(u);
-  const int b0 = (int)fl;
-  const double t = u - fl;
-  double qz = 0.0;
-  if (b0 >= 0 && b0 < d.n_bins) qz += (1.0 - t) * q[b0];
-  if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) qz += t * q[b0 + 1];
-  const double half = d.cut_sigmas * d.sigma_z;
-  const int lo = (int)ceil((zs - half) / d.dz - 0.5);
-  const int hi = (int)floor((zs + half) / d.dz - 0.5);
-  const int m = min(hi - lo + 1, kRzMaxWz);
-  double norm = 0.0;
-  for (int s = 0; s < m; s++) {
-    const double dd = (lo + s + 0.5) * d.dz - zs;
-    norm += exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z));
-  }
-  norm *= d.dz;
-  float *Ez = d.f[out_par][1];
-  for (int s = 0; s < m; s++) {
-    const int k = lo + s;
-    if (k < 0 || k > d.nz - 2) continue;
-    const double dd = (k + 0.5) * d.dz - zs;
-    const double wz = exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) / norm;
-    const long long c = (long long)k * d.pitch + i;
-    Ez[c] = Ez[c] - (float)(d.cb * d.v_src * qz * wr * wz);
-  }
+// Mur value of E_z on the r wall (rows 0..nz-2) for tilings whose wall node starts a wave.
+__global__ void k_rz_mur_r(RDev d, int par) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nz - 1) return;
+  const long long c0 = k * (long long)d.pitch + d.nr - 1, c1 = c0 - 1;
+  const float *Ein = d.f[par][1];
+  float *Eout = d.f[par ^ 1][1];
+  Eout[c0] = fmaf(d.mur_kr, Eout[c1] - Ein[c0], Ein[c1]);
 }
 
-// First-order Mur: wall value^{n+1} = inner^n + K (inner^{n+1} - wall^n), on E_z at r_max
-// (rows 0..nz-2) and on E_r at the z walls (nodes 0..nr-2).
-__global__ void k_rz_mur(RDev d, int par) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const long long P = d.pitch;
-  long long c0, c1;
-  float K;
-  int comp;
-  if (t < d.nz - 1) {
-    c0 = t * P + d.nr - 1;
-    c1 = c0 - 1;
-    K = d.mur_kr;
-    comp = 1;
-  } else {
-    t -= d.nz - 1;
-    if (t >= 2 * (d.nr - 1)) return;
-    const bool hi = t >= d.nr - 1;
-    const int i = hi ? t - (d.nr - 1) : t;
-    c0 = (hi ? (d.nz - 1) * P : 0) + i;
-    c1 = c0 + (hi ? -P : P);
-    K = d.mur_kz;
-    comp = 0;
-  }
-  const float *Ein = d.f[par][comp];
-  float *Eout = d.f[par ^ 1][comp];
-  Eout[c0] = fmaf(K, Eout[c1] - Ein[c0], Ein[c1]);
-}
-
-// Eight observers per 64-lane block: lane = 8*observer + 4*component + corner; each lane forms
-// weight * E in FP64 and two butterflies sum the corners.
+// Sampling of the final level after the last step of a call.
 __global__ void __launch_bounds__(64) k_rz_gather(RDev d, int par, double *w, int column, int ld) {
-  const int lane = threadIdx.x;
-  const int o = blockIdx.x * 8 + (lane >> 3);
-  const int comp = (lane >> 2) & 1, a = lane & 1, b = (lane >> 1) & 1;
-  double val = 0.0;
-  if (o < d.n_obs) {
-    const int *ix = d.obs_idx + (o * 2 + comp) * 2;
-    const double *tf = d.obs_t + (o * 2 + comp) * 2;
-    const double wgt = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]);
-    const long long node = (long long)(ix[1] + b) * d.pitch + ix[0] + a;
-    val = wgt * (double)d.f[par][comp][node];
-  }
-  val += __shfl_xor(val, 1);
-  val += __shfl_xor(val, 2);
-  if (o < d.n_obs && (lane & 3) == 0) {
-    w[((long long)o * 2 + comp) * ld + column] = val;
-    if (d.nan_flag && !isfinite(val)) *d.nan_flag = 1;
-  }
+  gather_wave(d, par, w, column, ld, blockIdx.x * 8, threadIdx.x);
 }
 
 __global__ void k_rz_zero(uint4 *p, long long n) {
@@ -333,39 +362,37 @@ __global__ void k_rz_copy(const float *src, float *dst, int nr, int nz, int pitc
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_sweep(const chf_rz_plan &p, const RDev &d, int par, hipStream_t s) {
-  const dim3 grid(8 * ((p.n_blocks + 7) / 8)), block(64 * p.wv);
-  switch (p.vx) {
-    case 1: k_rz_sweep<1><<<grid, block, 0, s>>>(d, par); break;
-    case 2: k_rz_sweep<2><<<grid, block, 0, s>>>(d, par); break;
-    case 4: k_rz_sweep<4><<<grid, block, 0, s>>>(d, par); break;
-    default: k_rz_sweep<8><<<grid, block, 0, s>>>(d, par); break;
-  }
-  return hipGetLastError();
-}
-
+// One step: the fused kernel (which also samples the previous step into column gcol when
+// gcol >= 0), plus the r-wall Mur kernel in the wave-start tiling.
 hipError_t launch_rz_step(const chf_rz_plan &p, const RDev &d, int par, int step, const double *q,
-                          double *w, int column, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
+                          double *w, int gcol, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
                           hipEvent_t ev_b = nullptr) {
   hipError_t e = hipSuccess;
   if (ev_a) e = hipEventRecord(ev_a, s);
-  if (e == hipSuccess) e = launch_sweep(p, d, par, s);
-  if (e == hipSuccess && ev_b) e = hipEventRecord(ev_b, s);
   if (e != hipSuccess) return e;
-  if (d.src_on && d.n_src > 0) {
-    k_rz_source<<<(d.n_src + 63) / 64, 64, 0, s>>>(d, par ^ 1, step, q ? q : d.q_bins);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int n_all = p.n_blocks + d.n_gblocks;
+  const dim3 grid(8 * ((n_all + 7) / 8)), block(64 * p.wv);
+  if (!w) gcol = -1;
+  switch (p.vx) {
+    case 1: k_rz_step<1><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
+    case 2: k_rz_step<2><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
+    case 4: k_rz_step<4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
+    default: k_rz_step<8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
   }
-  if (d.mur) {
-    const int n = (d.nz - 1) + 2 * (d.nr - 1);
-    k_rz_mur<<<(n + 255) / 256, 256, 0, s>>>(d, par);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  if (d.n_obs > 0 && w) {
-    k_rz_gather<<<(d.n_obs + 7) / 8, 64, 0, s>>>(d, par ^ 1, w, column, ld);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev_b) e = hipEventRecord(ev_b, s);
+  if (e != hipSuccess) return e;
+  if (d.mur && p.mur_r_kernel) {
+    k_rz_mur_r<<<(d.nz - 1 + 255) / 256, 256, 0, s>>>(d, par);
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_rz_gather(const RDev &d, int par, double *w, int column, int ld, hipStream_t s) {
+  if (d.n_obs <= 0 || !w) return hipSuccess;
+  k_rz_gather<<<(d.n_obs + 7) / 8, 64, 0, s>>>(d, par, w, column, ld);
+  return hipGetLastError();
 }
 
 hipError_t launch_rz_zero(const chf_rz_plan &p, hipStream_t s) {
@@ -424,7 +451,7 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   p->ex = *ex;
   p->vx = vx;
   p->wv = wv;
-  p->zchunk = std::min(zchunk, g.nz);
+  p->zchunk = std::min(zchunk, g.nz - 1);
   p->pitch = (g.nr + 63) / 64 * 64;
   const uint64_t elems = (uint64_t)p->pitch * (uint64_t)g.nz;
   if (elems > (uint64_t(1) << 40)) {
@@ -432,7 +459,7 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
     return fail(CHF_ENOMEM, "grid too large");
   }
   p->nrb = (g.nr + 64 * vx * wv - 1) / (64 * vx * wv);
-  p->nzc = (g.nz + p->zchunk - 1) / p->zchunk;
+  p->nzc = (g.nz - 1 + p->zchunk - 1) / p->zchunk;  // rows 0..nz-2 are marched
   if ((uint64_t)p->nrb * p->nzc > (uint64_t)0x7fffffff / 8) {
     delete p;
     return fail(CHF_EINVAL, "too many workgroups for this tile shape");
@@ -531,6 +558,8 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   D.nrb = p->nrb;
   D.n_blocks = p->n_blocks;
   D.wv = wv;
+  D.n_gblocks = (obs->n_obs + 8 * wv - 1) / (8 * wv);
+  p->mur_r_kernel = ex->bc == CHF_BC_MUR1 && (g.nr - 1) % (64 * vx) == 0;
   D.ca = (float)p->ca;
   D.db_dr = (float)(p->db / g.dr);
   D.db_dz = (float)(p->db / g.dz);
@@ -628,12 +657,16 @@ static chf_status rz_forward(chf_rz_plan *p, void *stream, const double *q, doub
   RDev d = p->dev;
   if (!p->ex.nan_watch) d.nan_flag = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  for (int t = 0; t < n_steps; t++) {
-    hipError_t e = launch_rz_step(*p, d, p->parity, p->n_done, q, w, first_column + t, ld, s,
+  for (int t = 0; t < n_steps; t++) {  // step t samples step t-1's result
+    hipError_t e = launch_rz_step(*p, d, p->parity, p->n_done, q, w, t > 0 ? first_column + t - 1 : -1, ld, s,
                                   ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     p->parity ^= 1;
     p->n_done++;
+  }
+  if (n_steps > 0) {
+    hipError_t e = launch_rz_gather(d, p->parity, w, first_column + n_steps - 1, ld, s);
+    if (e != hipSuccess) return hip_fail(e, "gather launch");
   }
   return CHF_OK;
 }
@@ -691,9 +724,10 @@ chf_status chf_rz_forward_graph(chf_rz_plan *p, void *stream, const double *q, d
     hipError_t le = launch_rz_zero(*p, cs);
     int par = 0;
     for (int t = 0; t < T && le == hipSuccess; t++) {
-      le = launch_rz_step(*p, d, par, t, q, w, t, T, cs);
+      le = launch_rz_step(*p, d, par, t, q, w, t - 1, T, cs);
       par ^= 1;
     }
+    if (le == hipSuccess && T > 0) le = launch_rz_gather(d, par, w, T - 1, T, cs);
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(cs, &gr);
     (void)hipStreamDestroy(cs);

@@ -71,7 +71,7 @@ def test_waveforms_and_fields_match_oracle(fixture, request):
         plan.close()
 
 
-SHAPES = [(1, 1, 1), (1, 2, 7), (2, 8, 5), (4, 4, 32), (4, 1, 600), (8, 1, 13), (8, 2, 64)]
+SHAPES = [(1, 1, 1), (1, 2, 2), (1, 2, 7), (2, 8, 5), (4, 4, 32), (4, 1, 600), (8, 1, 13), (8, 2, 64)]
 
 
 def test_tile_shapes_bitwise_equal(small_mur):
@@ -204,3 +204,27 @@ def test_fullsize_8192_dependency_cone():
         outside = f.clone()
         outside[:nz_c - 1, :nr_c - 1] = 0
         assert int(torch.count_nonzero(outside)) == 0, c
+
+
+@pytest.mark.parametrize("nr,vx,sigma_r", [(65, 1, 0.02), (129, 2, 0.02), (257, 4, 0.05), (14, 4, 0.04)])
+def test_wall_at_wave_start_and_source_at_wall(nr, vx, sigma_r):
+    """The r wall as the first node of a wave (its Mur value then comes from a kernel of its
+    own), and a source patch reaching the node next to the wall, against the oracle."""
+    d = 0.01
+    nz = 160
+    zb = np.arange(0.0, 2.0, d)
+    q = -1e-10 * np.exp(-0.5 * ((zb - 0.5) / 0.1) ** 2)
+    rr = min(0.5 * (nr - 1) * d, 0.3)
+    obs = np.array([[rr, 0.6], [0.5 * rr, 0.9], [0.8 * rr, 1.2]])
+    w = W.RZWorkload(name=f"rz-wall-{nr}-{vx}", nr=nr, nz=nz, n_steps=220, dr=d, dz=d,
+                     dt=W.courant_dt(d, d, d), bc="mur1", z_entry=0.05, sigma_r=sigma_r, sigma_z=0.01,
+                     z_bin0=0.0, dz_bin=d, q_bins=q, obs_rz=obs)
+    ref, er, ez, hp = oracle_run(w)
+    plan = solver.RZPlan(w, vx=vx, waves=2, zchunk=9)
+    try:
+        got = plan.run().cpu().numpy()
+        assert rel_l2(got, ref) <= TOL
+        for comp, want in ((0, er), (1, ez), (2, hp)):
+            assert rel_l2(plan.get_field(comp).cpu().numpy(), want) <= TOL, comp
+    finally:
+        plan.close()

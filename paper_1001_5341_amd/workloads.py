@@ -65,6 +65,7 @@ class Workload:
     obs_xyz: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3)))
     seed: int = 0
     notes: str = ""
+    z_origin: float = 0.0  # axis point the observers' (R, theta) are measured from (shower maximum)
 
     @property
     def n_cells(self) -> int:
@@ -234,7 +235,7 @@ def greisen_shower(seed: int, nx: int, ny: int, nz: int, n_steps: int, n_obs: in
                     dx=d, dy=d, dz=d, dt=courant_dt(d, d, d), bc=bc, npml=npml if bc == "cpml" else 0,
                     pml_alpha_max=alpha_max, x_axis=x_axis, y_axis=y_axis, z_entry=z_entry,
                     t_entry=0.0, beta=1.0, sigma_r=sigma_r, sigma_z=0.01, z_bin0=float(zb[0]),
-                    dz_bin=d, q_bins=q, obs_xyz=obs, seed=seed,
+                    dz_bin=d, q_bins=q, obs_xyz=obs, seed=seed, z_origin=z_max,
                     notes=f"z_max={z_max:.3f} m, length={length:.3f} m, Q0={q0:.3e} C")
 
 
@@ -254,7 +255,7 @@ def precision_shower(seed: int = 2) -> Workload:
     obs = off + np.array([big.x_axis, big.y_axis, 0.0])
     zb = np.arange(w.z_bin0, w.z_bin0 + w.dz_bin * len(w.q_bins) - 0.5 * w.dz_bin, w.dz_bin)
     return big.replace(q_bins=w.q_bins.copy(), z_bin0=w.z_bin0, dz_bin=w.dz_bin, obs_xyz=obs,
-                       z_entry=w.z_entry, notes=w.notes + f"; {len(zb)} bins")
+                       z_entry=w.z_entry, z_origin=w.z_origin, notes=w.notes + f"; {len(zb)} bins")
 
 
 def batch_showers(seed: int = 4, count: int = 32, n_steps: int = 2000, n_obs: int = 16) -> List[Workload]:
@@ -357,6 +358,7 @@ class RZWorkload:
     obs_rz: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 2)))
     seed: int = 0
     notes: str = ""
+    z_origin: float = 0.0  # axis point the observers' (R, theta) are measured from (shower maximum)
 
     @property
     def n_cells(self) -> int:
@@ -427,7 +429,7 @@ def rz_shower(seed: int, nr: int, nz: int, n_steps: int, n_obs: int, d: float = 
     return RZWorkload(name=name or f"rz-{nr}x{nz}", nr=nr, nz=nz, n_steps=n_steps, dr=d, dz=d,
                       dt=courant_dt(d, d, d), bc=bc, z_entry=z_entry, t_entry=0.0, beta=1.0,
                       sigma_r=sigma_r, sigma_z=0.01, z_bin0=float(zb[0]), dz_bin=d, q_bins=q,
-                      obs_rz=obs, seed=seed,
+                      obs_rz=obs, seed=seed, z_origin=z_max,
                       notes=f"z_max={z_max:.3f} m, length={length:.3f} m, Q0={q0:.3e} C")
 
 

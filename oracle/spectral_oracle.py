@@ -91,7 +91,8 @@ def profile_transform(q_bins, z_bin0: float, dz_bin: float, p: np.ndarray, sub: 
 
 
 def far_field_theta(q_bins, z_bin0: float, dz_bin: float, R, theta, n_index: float, beta: float,
-                    omega, z_entry: float = 0.0, t_entry: float = 0.0, z_origin: float = 0.0) -> np.ndarray:
+                    omega, z_entry: float = 0.0, t_entry: float = 0.0, z_origin: float = 0.0,
+                    sub: int = 64) -> np.ndarray:
     """E_theta(omega) of the far-field formula for each (R, theta) pair: [n_obs, n_freq]."""
     R = np.atleast_1d(np.asarray(R, dtype=np.float64))
     theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
@@ -102,7 +103,7 @@ def far_field_theta(q_bins, z_bin0: float, dz_bin: float, R, theta, n_index: flo
     out = np.zeros((len(R), len(omega)), dtype=np.complex128)
     for o in range(len(R)):
         p = omega / v - k * math.cos(theta[o])
-        F = profile_transform(q_bins, z_bin0, dz_bin, p)
+        F = profile_transform(q_bins, z_bin0, dz_bin, p, sub)
         A = MU0 / (4.0 * math.pi) * np.exp(1j * k * R[o]) / R[o] * np.exp(1j * omega * t_off) \
             * np.exp(1j * k * math.cos(theta[o]) * z_origin) * F
         out[o] = -1j * omega * math.sin(theta[o]) * A

@@ -30,6 +30,7 @@ EXPORTED = [
     "chf_rz_plan_create", "chf_rz_plan_destroy", "chf_rz_workspace_bytes", "chf_rz_bind_workspace",
     "chf_rz_reset", "chf_rz_forward", "chf_rz_forward_timed", "chf_rz_forward_graph", "chf_rz_sync",
     "chf_rz_get_field", "chf_rz_set_field", "chf_rz_get_info",
+    "chf_spectrum", "chf_spectrum_project", "chf_geometry_rz", "chf_geometry_xyz", "chf_far_field_1d",
 ]
 
 
@@ -101,6 +102,11 @@ class RZInfo(ct.Structure):
                 ("pitch", ct.c_int32), ("n_blocks", ct.c_int32), ("n_src", ct.c_int32),
                 ("field_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
                 ("bytes_per_cell_update", ct.c_double)]
+
+
+class FarFieldParams(ct.Structure):
+    _fields_ = [("n_index", ct.c_double), ("beta", ct.c_double), ("z_entry", ct.c_double),
+                ("t_entry", ct.c_double), ("z_origin", ct.c_double)]
 
 
 class ChfError(RuntimeError):
@@ -206,6 +212,18 @@ def lib():
         L.chf_rz_set_field.argtypes = [vp, vp, ct.c_int32, vp]
         L.chf_rz_get_info.restype = ct.c_int
         L.chf_rz_get_info.argtypes = [vp, ct.POINTER(RZInfo)]
+        L.chf_spectrum.restype = ct.c_int
+        L.chf_spectrum.argtypes = [vp, vp, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, ct.c_double, vp,
+                                   ct.c_int32, vp]
+        L.chf_spectrum_project.restype = ct.c_int
+        L.chf_spectrum_project.argtypes = [vp, vp, ct.c_int32, ct.c_int32, ct.c_int32, vp, vp, vp]
+        L.chf_geometry_rz.restype = ct.c_int
+        L.chf_geometry_rz.argtypes = [ct.c_int32, dp, ct.c_double, dp, dp]
+        L.chf_geometry_xyz.restype = ct.c_int
+        L.chf_geometry_xyz.argtypes = [ct.c_int32, dp, ct.c_double, ct.c_double, ct.c_double, dp, dp]
+        L.chf_far_field_1d.restype = ct.c_int
+        L.chf_far_field_1d.argtypes = [vp, vp, ct.c_int32, ct.c_double, ct.c_double, vp, ct.c_int32,
+                                       ct.POINTER(FarFieldParams), vp, ct.c_int32, vp]
         _lib = L
         return L
 

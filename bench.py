@@ -41,7 +41,7 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20
 FUSED_KERNEL = "chf::k_fused<"
-RZ_KERNEL = "k_rz_step<"
+RZ_KERNEL = "k_rz_step2<"
 RZ_BYTES_PER_NODE = 24.0  # read E_r, E_z, H_phi once and write them once (FP32)
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 DFT_FLOPS_PER_TERM = 10.0  # 2 FMA into the sums + one complex rotation of the phase (4 mul, 2 add)
@@ -110,7 +110,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
         out[name] = {"copy_probe_kib": copy_kib, "scale": factor, "dispatches": len(fused),
                      "raw_kib_per_launch": float(np.mean(fused)),
                      "bytes_per_launch": float(np.mean(fused)) * 1024.0 * factor}
-    kdesc = ("axisymmetric step (k_rz_step)" if is_rz(workload) else "fused interior sweep (chf::k_fused)")
+    kdesc = ("axisymmetric two-step launch (k_rz_step2)" if is_rz(workload) else "fused interior sweep (chf::k_fused)")
     rec = {"workload": workload, "storage": storage, "kernel": kdesc,
            "kernel_digest": kernel_digest_for(workload), "command": command,
            "fetch": out["fetch"], "write": out["write"],
@@ -257,35 +257,44 @@ def rz_cpu_baseline(w, n_steps: int = 4):
                       f"{n_steps} steps, {dt:.1f} s"}
 
 
-def rz_measure(w, n_runs: int, warmup: int, vx=0, waves=0, zchunk=0):
+def rz_measure(w, n_runs: int, warmup: int, vx=0, waves=0, zchunk=0, spl=0):
     """n_runs full runs through chf_rz_forward_timed; returns (info, wall s, event s,
     summed step-kernel ms, launches, waveforms)."""
     import torch
 
     from paper_1001_5341_amd import solver
 
-    plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zchunk, device=torch.device("cuda:0"))
+    plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zchunk, steps_per_launch=spl, device=torch.device("cuda:0"))
     info = plan.info()
     out = plan.new_waveforms()
     for i in range(warmup):
         plan.run(out=out)
         log(f"rz warmup {i} done")
-    wall, ev_s, ms, launches = timed_runs(plan, out, n_runs)
+    wall, ev_s, ms, _ = timed_runs(plan, out, n_runs)
+    spl = info["steps_per_launch"]
+    launches = n_runs * (w.n_steps // spl + w.n_steps % spl)
     got = out.cpu().numpy()
     plan.close()
     return info, wall, ev_s, ms, launches, got
 
 
-def rz_roofline(w, ms: float, launches: int):
+def rz_roofline(w, ms: float, launches: int, spl: int):
+    """Algorithmic bytes of one launch: every marched node's E_r, E_z, H_phi read once and written
+    once (24 B in FP32), whether the launch advances one Yee step or two; `effective` counts the
+    bytes the same steps would move one step per pass."""
     nodes = w.nr * (w.nz - 1)  # rows 0..nz-2 are marched over every radial node
     alg = nodes * RZ_BYTES_PER_NODE
     avg_s = ms / 1e3 / launches
     achieved = alg / avg_s / 1e9
+    name = ("k_rz_step2 (two Yee steps per launch: H, E_r, E_z, source and walls of both, the intermediate "
+            "level in registers, and the previous launch's sampling)" if spl == 2 else
+            "k_rz_step (H, E_r, E_z, source, walls and the previous step's sampling; one launch per Yee step)")
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "kernel": "k_rz_step (H, E_r, E_z, source, walls and the previous step's sampling; one launch per Yee step)",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": name, "steps_per_launch": spl,
             "launch_avg_us": round(avg_s * 1e6, 2), "launches": launches, "nodes_per_launch": nodes,
-            "bytes_per_node": RZ_BYTES_PER_NODE, "alg_bytes_per_launch": int(alg)}
+            "bytes_per_node": RZ_BYTES_PER_NODE, "alg_bytes_per_launch": int(alg),
+            "effective_single_step_gbs": round(achieved * spl, 1),
+            "effective_frac": round(achieved * spl / HBM_PEAK_GBS, 4)}
 
 
 def rz_main(args):
@@ -305,9 +314,9 @@ def rz_main(args):
         torch.cuda.synchronize()
         del a, b
     info, wall, ev_s, ms, launches, got = rz_measure(w, args.steps, args.warmup, args.vx, args.waves,
-                                                     args.zchunk)
+                                                     args.zchunk, args.steps_per_launch)
     log(f"rz: {args.steps} timed runs, wall {wall:.3f} s, step kernel {ms / launches * 1e3:.1f} us/launch")
-    roof = rz_roofline(w, ms, launches)
+    roof = rz_roofline(w, ms, launches, info["steps_per_launch"])
     roof["traffic"] = measured_traffic(args.workload, "fp32") if not args.time_steps else None
     rec = {
         "metric": "Yee Mcell-updates/s and % HBM roofline of the axisymmetric (r, z) scheme, FP32",
@@ -320,7 +329,7 @@ def rz_main(args):
         "config": {"workload": w.name, "grid_rz": [w.nr, w.nz], "yee_steps_per_run": w.n_steps,
                    "boundary": w.bc, "observers": w.n_obs,
                    "tile": {"vx": info["vx"], "waves_per_block": info["waves_per_block"],
-                            "z_chunk": info["z_chunk"]},
+                            "z_chunk": info["z_chunk"], "steps_per_launch": info["steps_per_launch"]},
                    "parallelism": "single GPU"},
         "roofline": roof,
         "waveforms_finite": bool(np.isfinite(got).all()),
@@ -373,10 +382,11 @@ def rz_summary(n: int = 8192, n_steps: int = 2048):
 
     w = W.rz_paper_grid(n, n_steps=n_steps)
     info, wall, ev_s, ms, launches, got = rz_measure(w, 1, 1)
-    roof = rz_roofline(w, ms, launches)
+    roof = rz_roofline(w, ms, launches, info["steps_per_launch"])
     return {"workload": w.name, "yee_steps": n_steps, "value": round(w.nr * w.nz * n_steps / wall / 1e6, 1),
             "unit": "Mcell-updates/s", "roofline_frac": roof["frac"], "achieved_gbs": roof["achieved"],
-            "step_kernel_avg_us": roof["launch_avg_us"],
+            "launch_avg_us": roof["launch_avg_us"], "steps_per_launch": info["steps_per_launch"],
+            "effective_frac": roof["effective_frac"],
             "note": "python bench.py --workload rz-8192 gives the full line"}
 
 
@@ -392,6 +402,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--vx", type=int, default=0, help="(r, z) path: radial nodes per lane")
+    ap.add_argument("--steps-per-launch", type=int, default=0, help="(r, z) path: 1, or 2 (temporal blocking)")
     ap.add_argument("--time-steps", type=int, default=0, help="override the Yee steps per run")
     ap.add_argument("--no-tune", action="store_true", help="default tile shape instead of the autotuner's")
     ap.add_argument("--no-cpu-baseline", action="store_true")

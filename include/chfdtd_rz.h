@@ -65,10 +65,12 @@ typedef struct {
 /* Execution: bc is CHF_BC_PEC or CHF_BC_MUR1 (CHF_BC_CPML: CHF_EUNSUPPORTED).  The sweep tiles
    the lattice into workgroups of waves_per_block waves (1, 2, 4 or 8), each wave owning 64*vx
    consecutive radial nodes (vx = 1, 2, 4 or 8) of z_chunk rows (>= 1); 0 picks the defaults
-   (vx 4, 4 waves, 32 rows).  No choice changes a result bit.  nan_watch: check waveforms for
+   (vx 4, 4 waves, 32 rows).  steps_per_launch: 1, or 2 to advance two Yee steps per pass over
+   the fields (temporal blocking; needs vx 4 or 8; an odd remainder takes a one-step pass);
+   0 = 2 when vx >= 4, else 1.  No choice changes a result bit.  nan_watch: check waveforms for
    non-finite values every step (reported by chf_rz_sync). */
 typedef struct {
-  int32_t bc, vx, waves_per_block, z_chunk, nan_watch, pad0;
+  int32_t bc, vx, waves_per_block, z_chunk, nan_watch, steps_per_launch;
 } chf_rz_exec;
 
 typedef struct chf_rz_plan chf_rz_plan;
@@ -120,9 +122,9 @@ chf_status chf_rz_get_field(chf_rz_plan *plan, void *stream, int32_t comp, float
 chf_status chf_rz_set_field(chf_rz_plan *plan, void *stream, int32_t comp, const float *in_dev);
 
 typedef struct {
-  int32_t vx, waves_per_block, z_chunk, pitch, n_blocks, n_src;
+  int32_t vx, waves_per_block, z_chunk, pitch, n_blocks, n_src, steps_per_launch, pad0;
   uint64_t field_bytes, workspace_bytes;
-  double bytes_per_cell_update; /* algorithmic HBM bytes of one node update of the sweep */
+  double bytes_per_cell_update; /* algorithmic HBM bytes per node of one pass (one launch) */
 } chf_rz_info;
 chf_status chf_rz_get_info(const chf_rz_plan *plan, chf_rz_info *info);
 

@@ -50,6 +50,7 @@ constexpr double kRadialEig = 4.85;
 
 struct RDev {
   int nr, nz, pitch, zchunk, nrb, n_blocks, n_gblocks, wv;
+  int nrb2, n_waves2, n_blocks2;  // two-step launches: overlapped waves of 62*VX stored nodes
   float ca, db_dr, db_dz, cb_dz;
   float *f[2][3];          // [level][E_r, E_z, H_phi]
   const float *cp, *cm;    // [pitch]
@@ -65,6 +66,11 @@ struct RDev {
   const int *obs_idx;      // [n_obs][2][2] (i0, k0) per component
   const double *obs_t;     // [n_obs][2][2] (tr, tz)
   int *nan_flag;
+  // observer stencil nodes by row, for the intermediate level of two-step launches
+  const int *row_ptr;      // [nz+1]
+  const int2 *ent;         // (node i, slot | component << 30), slot = (obs*2 + comp)*4 + corner
+  const double *ent_w;     // bilinear weights
+  double *samp;            // [2][8 n_obs] weight * E^{n+1}
 };
 
 chf_status fail(chf_status s, const std::string &m) {
@@ -88,14 +94,19 @@ struct chf_rz_plan {
   chf_rz_exec ex;
   std::vector<double> q_bins;
   int vx = 4, wv = 4, zchunk = 32, pitch = 0, nrb = 0, nzc = 0, n_blocks = 0, n_src = 0;
+  int spl = 1;                // Yee steps per launch (2: temporally blocked)
+  int nrb2 = 0, n_waves2 = 0, n_blocks2 = 0;
+  int samp_par = 0;           // sample buffer the last two-step launch wrote
   bool mur_r_kernel = false;  // the r-wall node starts a wave: its Mur value takes a kernel of its own
   double ca = 1, cb = 0, db = 0;
   std::vector<float> cp, cm;
   std::vector<double> wr;
   std::vector<int> oidx;
   std::vector<double> ot;
+  std::vector<int> row_ptr, ent;  // observer stencil nodes by row: (node, slot | comp << 30)
+  std::vector<double> ent_w;
   uint64_t off_f[2][3] = {}, off_cp = 0, off_cm = 0, off_wr = 0, off_q = 0, off_oidx = 0, off_ot = 0,
-           off_nan = 0, field_bytes = 0, ws_bytes = 0;
+           off_nan = 0, off_rowptr = 0, off_ent = 0, off_entw = 0, off_samp = 0, field_bytes = 0, ws_bytes = 0;
   char *ws = nullptr;
   RDev dev{};
   int parity = 0, n_done = 0;
@@ -132,7 +143,7 @@ __device__ __forceinline__ void st(float *p, const float (&o)[N], bool on) {
   *reinterpret_cast<F<N> *>(p) = x;
 }
 
-// H' = H - db/dz dEr + db/dr dEz (the order every tile shape uses)
+// H' = H - db/dz dEr + db/dr dEz (the order every kernel and tile shape uses)
 __device__ __forceinline__ float h_node(float h, float d_er, float d_ez, const RDev &d) {
   return fmaf(d.db_dr, d_ez, fmaf(-d.db_dz, d_er, h));
 }
@@ -160,23 +171,109 @@ __device__ __forceinline__ void gather_wave(const RDev &d, int par, double *w, i
   }
 }
 
+// The work a launch does for its predecessor: sample the level it starts from into column gcol,
+// and sum the stencil samples a two-step launch took of its intermediate level (buffer sb) into
+// column scol, corners added in the order the gather uses.
+__device__ __forceinline__ void pending_wave(const RDev &d, int par, double *w, int ld, int gcol, int scol, int sb,
+                                             int o0, int lane) {
+  if (gcol >= 0) gather_wave(d, par, w, gcol, ld, o0, lane);
+  if (scol >= 0) {
+    const int o = o0 + (lane >> 1), comp = lane & 1;
+    if (lane < 16 && o < d.n_obs) {
+      const double *s = d.samp + (long long)sb * 8 * d.n_obs + (o * 2 + comp) * 4;
+      const double val = (s[0] + s[1]) + (s[2] + s[3]);
+      w[((long long)o * 2 + comp) * ld + scol] = val;
+      if (d.nan_flag && !isfinite(val)) *d.nan_flag = 1;
+    }
+  }
+}
+
+// Source rows of one step for a wave (FP64 bookkeeping: bunch position, Q(z_s) from the hat
+// bins, longitudinal weights normalised over the window; lane j holds the weight of row lo + j).
+struct SrcRows {
+  int lo, m;
+  double amp, w;
+};
+
+__device__ __forceinline__ SrcRows source_rows(const RDev &d, int step, const double *q, int w0, int lane) {
+  SrcRows s{0, 0, 0.0, 0.0};
+  if (!d.src_on || w0 >= d.n_src) return s;
+  const double tt = (step + 0.5) * d.dt;
+  if (tt < d.t_entry) return s;
+  const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
+  const double u = (zs - d.z_bin0) / d.dz_bin;
+  const double fl = floor(u);
+  const int b0 = (int)fl;
+  const double t = u - fl;
+  const double *qb = q ? q : d.q_bins;
+  double qz = 0.0;
+  if (b0 >= 0 && b0 < d.n_bins) qz += (1.0 - t) * qb[b0];
+  if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) qz += t * qb[b0 + 1];
+  const double half = d.cut_sigmas * d.sigma_z;
+  s.lo = (int)ceil((zs - half) / d.dz - 0.5);
+  const int hi = (int)floor((zs + half) / d.dz - 0.5);
+  s.m = max(0, min(hi - s.lo + 1, 64));
+  const double dd = (s.lo + lane + 0.5) * d.dz - zs;
+  double e = lane < s.m ? exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) : 0.0;
+  double norm = e;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) norm += __shfl_xor(norm, m);
+  s.w = e / (norm * d.dz);
+  s.amp = d.cb * d.v_src * qz;
+  return s;
+}
+
+// E_z -= Cb J_z on row k for the nodes of this lane (wave-uniform branch and shuffle)
+template <int VX>
+__device__ __forceinline__ void sub_source(const RDev &d, const SrcRows &s, int k, int c0, float (&ez)[VX]) {
+  if (s.m > 0 && k - s.lo >= 0 && k - s.lo < s.m) {
+    const double wz = __shfl(s.w, k - s.lo);
+#pragma unroll
+    for (int v = 0; v < VX; v++)
+      if (c0 + v >= 0 && c0 + v < d.n_src) ez[v] = ez[v] - (float)(s.amp * d.wr[c0 + v] * wz);
+  }
+}
+
+// E_z on r = r_max: inner^n + K (inner^{n+1} - wall^n), by the lane that owns the wall node
+// (a wall node in lane 0 takes the value shuffled from no lane: callers never keep it)
+template <int VX>
+__device__ __forceinline__ void mur_r(const RDev &d, int vw, bool wall_here, float (&ezo)[VX], const float (&ez)[VX]) {
+  const float en = __shfl_up(ezo[VX - 1], 1), ei = __shfl_up(ez[VX - 1], 1);
+  if (wall_here) {
+#pragma unroll
+    for (int v = 0; v < VX; v++)
+      if (v == vw) {
+        const float inner_new = v > 0 ? ezo[v > 0 ? v - 1 : 0] : en;
+        const float inner_old = v > 0 ? ez[v > 0 ? v - 1 : 0] : ei;
+        ezo[v] = fmaf(d.mur_kr, inner_new - ez[v], inner_old);
+      }
+  }
+}
+
+template <int VX>
+__device__ __forceinline__ void right_of(const float (&a)[VX], float (&r)[VX]) {
+  const float t = __shfl_down(a[0], 1);
+#pragma unroll
+  for (int v = 0; v < VX; v++) r[v] = v + 1 < VX ? a[v + 1 < VX ? v + 1 : 0] : t;
+}
+
 // One whole step in one launch.  Workgroups [0, n_blocks) sweep tiles (a tile = wv waves side by
 // side in r, each 64*VX nodes wide, times a chunk of z rows); the n_gblocks workgroups after
-// them sample level `par` (E^n, the previous step's result, which this launch only reads) into
-// waveform column gcol.  Rows 0..nz-2 are marched; the E_r rows on the z walls are written from
-// rows 1 and nz-2 (copied, or the Mur value).  The moving source is subtracted from E_z by the
-// lanes that own its nodes, and the Mur value of E_z on the r wall by the lane that owns the
-// wall (the host adds k_rz_mur_r when the wall is the first node of a wave).
+// them do the pending work of the previous launch (pending_wave).  Rows 0..nz-2 are marched;
+// the E_r rows on the z walls are written from rows 1 and nz-2 (copied, or the Mur value).  The
+// moving source is subtracted from E_z by the lanes that own its nodes, and the Mur value of E_z
+// on the r wall by the lane that owns the wall (the host adds k_rz_mur_r when the wall is the
+// first node of a wave).
 template <int VX>
 __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, const double *q, double *w,
-                                                 int gcol, int ldw) {
+                                                 int gcol, int scol, int sb, int ldw) {
   const int n_all = d.n_blocks + d.n_gblocks;
   const int per = (n_all + 7) >> 3;  // hardware block b runs on XCD b % 8
   const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (logical >= n_all) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (logical >= d.n_blocks) {
-    if (gcol >= 0) gather_wave(d, par, w, gcol, ldw, ((logical - d.n_blocks) * d.wv + wv) * 8, lane);
+    pending_wave(d, par, w, ldw, gcol, scol, sb, ((logical - d.n_blocks) * d.wv + wv) * 8, lane);
     return;
   }
   const int rb = logical % d.nrb, zc = logical / d.nrb;
@@ -198,43 +295,13 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
   bool live[VX];
 #pragma unroll
   for (int v = 0; v < VX; v++) live[v] = c0 + v <= nr - 2;
-
-  // source rows of this step (FP64 bookkeeping: bunch position, Q(z_s) from the hat bins, the
-  // longitudinal weights normalised over the window; lane j holds the weight of row lo + j)
-  int s_lo = 0, s_m = 0;
-  double s_amp = 0.0, s_w = 0.0;
-  if (d.src_on && w0 < d.n_src) {
-    const double tt = (step + 0.5) * d.dt;
-    if (tt >= d.t_entry) {
-      const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
-      const double u = (zs - d.z_bin0) / d.dz_bin;
-      const double fl = floor(u);
-      const int b0 = (int)fl;
-      const double t = u - fl;
-      const double *qb = q ? q : d.q_bins;
-      double qz = 0.0;
-      if (b0 >= 0 && b0 < d.n_bins) qz += (1.0 - t) * qb[b0];
-      if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) qz += t * qb[b0 + 1];
-      const double half = d.cut_sigmas * d.sigma_z;
-      s_lo = (int)ceil((zs - half) / d.dz - 0.5);
-      const int hi = (int)floor((zs + half) / d.dz - 0.5);
-      s_m = max(0, min(hi - s_lo + 1, 64));
-      const double dd = (s_lo + lane + 0.5) * d.dz - zs;
-      s_w = lane < s_m ? exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) : 0.0;
-      double norm = s_w;
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) norm += __shfl_xor(norm, m);
-      s_w = s_w / (norm * d.dz);
-      s_amp = d.cb * d.v_src * qz;
-    }
-  }
-  // Mur on the r wall: position of node nr-1 in this lane (the wave-start case is the host's)
+  const SrcRows S = source_rows(d, step, q, w0, lane);
   const int vw = nr - 1 - c0;
   const bool wall_here = d.mur && vw >= 0 && vw < VX && !(vw == 0 && lane == 0);
   const bool wall_wave = d.mur && nr - 1 > w0 && nr - 1 < w0 + 64 * VX;  // some lane > 0 or v > 0
 
   float er_k[VX], hn_b[VX];  // E_r(k) of the input level, H^{n+1/2}(k-1)
-  float erl_k = 0.f;                   // lane 0: E_r(c0-1, k)
+  float erl_k = 0.f;         // lane 0: E_r(c0-1, k)
   if (k0 > 0) {
     const int kb = k0 - 1;
     float erb[VX], ezb[VX], hb[VX];
@@ -288,24 +355,8 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
       const float hm = v > 0 ? hn[v - 1] : hl;
       ezo[v] = live[v] ? fmaf(-cm[v], hm, fmaf(cp[v], hn[v], d.ca * ez[v])) : ez[v];
     }
-    if (s_m > 0 && k - s_lo >= 0 && k - s_lo < s_m) {  // wave-uniform
-      const double wz = __shfl(s_w, k - s_lo);
-#pragma unroll
-      for (int v = 0; v < VX; v++)
-        if (c0 + v < d.n_src) ezo[v] = ezo[v] - (float)(s_amp * d.wr[c0 + v] * wz);
-    }
-    if (wall_wave) {  // E_z on r = r_max: inner^n + K (inner^{n+1} - wall^n)
-      const float en = __shfl_up(ezo[VX - 1], 1), ei = __shfl_up(ez[VX - 1], 1);
-      if (wall_here) {
-#pragma unroll
-        for (int v = 0; v < VX; v++)
-          if (v == vw) {
-            const float inner_new = v > 0 ? ezo[v > 0 ? v - 1 : 0] : en;
-            const float inner_old = v > 0 ? ez[v > 0 ? v - 1 : 0] : ei;
-            ezo[v] = fmaf(d.mur_kr, inner_new - ez[v], inner_old);
-          }
-      }
-    }
+    sub_source<VX>(d, S, k, c0, ezo);
+    if (wall_wave) mur_r<VX>(d, vw, wall_here, ezo, ez);
     st<VX>(Hpo + k * P + c0, hn, on);
     if (k >= 1) st<VX>(Ero + k * P + c0, ero, on);
     st<VX>(Ezo + k * P + c0, ezo, on);
@@ -332,7 +383,173 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
   }
 }
 
-// Mur value of E_z on the r wall (rows 0..nz-2) for tilings whose wall node starts a wave.
+// Two steps in one launch (temporal blocking).  Waves overlap: wave g covers the 64*VX nodes from
+// g*62*VX - VX, and only lanes 1..62 store, so every H and E a stored node needs is formed inside
+// the wave from the input level (VX >= 4 keeps the lanes' own halo cells exact): step n+1 (stage
+// 1) for row m, then step n+2 (stage 2) for row m-1 from stage-1 values held in registers.  The
+// intermediate level never reaches HBM: its observer-stencil values are written, weighted, to
+// the sample buffer sb (summed by the next launch).  Per node and step the arithmetic is that of
+// k_rz_step, so the two kernels give the same bits.
+template <int VX>
+__global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, const double *q, double *w,
+                                                  int gcol, int scol, int sb_in, int sb_out, int ldw) {
+  const int n_all = d.n_blocks2 + d.n_gblocks;
+  const int per = (n_all + 7) >> 3;
+  const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (logical >= n_all) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (logical >= d.n_blocks2) {
+    pending_wave(d, par, w, ldw, gcol, scol, sb_in, ((logical - d.n_blocks2) * d.wv + wv) * 8, lane);
+    return;
+  }
+  const int rb = logical % d.nrb2, zc = logical / d.nrb2;
+  const int g = rb * d.wv + wv;
+  if (g >= d.n_waves2) return;
+  const int nr = d.nr, nz = d.nz;
+  const int w0 = g * 62 * VX - VX;  // node of lane 0, cell 0
+  const int c0 = w0 + lane * VX;
+  const bool on = c0 >= 0 && c0 < nr;
+  const bool outl = on && lane >= 1 && lane <= 62;
+  const int k0 = zc * d.zchunk, k1 = min(k0 + d.zchunk, nz - 1);  // stage-2 rows [k0, k1)
+  const int m0 = max(0, k0 - 2);
+  const long long P = d.pitch;
+  const float *Er = d.f[par][0], *Ez = d.f[par][1], *Hp = d.f[par][2];
+  float *Ero = d.f[par ^ 1][0], *Ezo = d.f[par ^ 1][1], *Hpo = d.f[par ^ 1][2];
+
+  float cp[VX], cm[VX];
+  ld<VX>(d.cp + c0, cp, on);
+  ld<VX>(d.cm + c0, cm, on);
+  bool live[VX];
+#pragma unroll
+  for (int v = 0; v < VX; v++) live[v] = on && c0 + v <= nr - 2;
+  const SrcRows S1 = source_rows(d, step, q, w0, lane);
+  const SrcRows S2 = source_rows(d, step + 1, q, w0, lane);
+  const int vw = nr - 1 - c0;
+  const bool wall_here = d.mur && on && vw >= 0 && vw < VX;
+  const bool wall_wave = d.mur && nr - 1 >= w0 && nr - 1 < w0 + 64 * VX;
+  double *samp = d.samp + (long long)sb_out * 8 * d.n_obs;
+
+  float er_in[VX];                     // E_r^n(m)
+  float er1_b[VX], ez1_b[VX], h1_b[VX];  // stage 1 of row m-1
+  float h2_b[VX];                      // stage 2 H of row j-1
+  ld<VX>(Er + m0 * P + c0, er_in, on);
+#pragma unroll
+  for (int v = 0; v < VX; v++) {
+    er1_b[v] = 0.f;
+    ez1_b[v] = 0.f;
+    h1_b[v] = 0.f;
+    h2_b[v] = 0.f;
+  }
+
+  for (int m = m0; m <= k1; m++) {
+    // ---- stage 1 (step n -> n+1), row m
+    float er1[VX], ez1[VX], h1[VX], er1n[VX];
+    if (m <= nz - 2) {
+      float ez[VX], h[VX], e1[VX];
+      ld<VX>(Er + (m + 1) * P + c0, er1n, on);
+      ld<VX>(Ez + m * P + c0, ez, on);
+      ld<VX>(Hp + m * P + c0, h, on);
+      right_of<VX>(ez, e1);
+#pragma unroll
+      for (int v = 0; v < VX; v++) h1[v] = live[v] ? h_node(h[v], er1n[v] - er_in[v], e1[v] - ez[v], d) : h[v];
+      const float hl = __shfl_up(h1[VX - 1], 1);
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        er1[v] = live[v] && m >= 1 ? fmaf(-d.cb_dz, h1[v] - h1_b[v], d.ca * er_in[v]) : er_in[v];
+        const float hm = v > 0 ? h1[v - 1] : hl;
+        ez1[v] = live[v] ? fmaf(-cm[v], hm, fmaf(cp[v], h1[v], d.ca * ez[v])) : ez[v];
+      }
+      sub_source<VX>(d, S1, m, c0, ez1);
+      if (wall_wave) mur_r<VX>(d, vw, wall_here, ez1, ez);
+    } else {  // m == nz-1: only the E_r wall row, from row nz-2
+      float ein_b[VX];
+      ld<VX>(Er + (nz - 2) * P + c0, ein_b, on);
+#pragma unroll
+      for (int v = 0; v < VX; v++) {
+        er1[v] = d.mur && live[v] ? fmaf(d.mur_kz, er1_b[v] - er_in[v], ein_b[v]) : er_in[v];
+        ez1[v] = 0.f;
+        h1[v] = 0.f;
+        er1n[v] = 0.f;
+      }
+    }
+    if (m == 1 && m0 == 0) {  // stage-1 z = 0 wall from row 1 (er1_b holds E_r^n(0) copied)
+#pragma unroll
+      for (int v = 0; v < VX; v++)
+        if (d.mur && live[v]) er1_b[v] = fmaf(d.mur_kz, er1[v] - er1_b[v], er_in[v]);
+    }
+    // ---- stage 2 (step n+1 -> n+2), row j = m-1
+    const int j = m - 1;
+    if (j >= max(0, k0 - 1)) {
+      float e1[VX], h2[VX];
+      right_of<VX>(ez1_b, e1);
+#pragma unroll
+      for (int v = 0; v < VX; v++) h2[v] = live[v] ? h_node(h1_b[v], er1[v] - er1_b[v], e1[v] - ez1_b[v], d) : h1_b[v];
+      if (j >= k0) {
+        const float hl = __shfl_up(h2[VX - 1], 1);
+        float er2[VX], ez2[VX];
+#pragma unroll
+        for (int v = 0; v < VX; v++) {
+          er2[v] = live[v] && j >= 1 ? fmaf(-d.cb_dz, h2[v] - h2_b[v], d.ca * er1_b[v]) : er1_b[v];
+          const float hm = v > 0 ? h2[v - 1] : hl;
+          ez2[v] = live[v] ? fmaf(-cm[v], hm, fmaf(cp[v], h2[v], d.ca * ez1_b[v])) : ez1_b[v];
+        }
+        sub_source<VX>(d, S2, j, c0, ez2);
+        if (wall_wave) mur_r<VX>(d, vw, wall_here, ez2, ez1_b);
+        st<VX>(Hpo + j * P + c0, h2, outl);
+        if (j >= 1) st<VX>(Ero + j * P + c0, er2, outl);
+        st<VX>(Ezo + j * P + c0, ez2, outl);
+        if (j == 1) {  // stage-2 z = 0 wall: E_r^{n+1}(0) again from the input level
+          float ein0[VX], ein1[VX], wv0[VX];
+          ld<VX>(Er + c0, ein0, on);
+          ld<VX>(Er + P + c0, ein1, on);
+#pragma unroll
+          for (int v = 0; v < VX; v++) {
+            const float e10 = d.mur && live[v] ? fmaf(d.mur_kz, er1_b[v] - ein0[v], ein1[v]) : ein0[v];
+            wv0[v] = d.mur && live[v] ? fmaf(d.mur_kz, er2[v] - e10, er1_b[v]) : e10;
+          }
+          st<VX>(Ero + c0, wv0, outl);
+        }
+        if (j == nz - 2) {  // stage-2 z = z_max wall
+          float wv1[VX];
+#pragma unroll
+          for (int v = 0; v < VX; v++) wv1[v] = d.mur && live[v] ? fmaf(d.mur_kz, er2[v] - er1[v], er1_b[v]) : er1[v];
+          st<VX>(Ero + (j + 1) * P + c0, wv1, outl);
+        }
+        // observer stencil nodes of the intermediate level on row j (and on row nz-1 with it)
+        for (int pass = 0; pass < (j == nz - 2 ? 2 : 1); pass++) {
+          const int row = pass ? nz - 1 : j;
+          const int e_lo = d.row_ptr[row], e_hi = d.row_ptr[row + 1];
+          for (int e = e_lo; e < e_hi; e++) {
+            const int2 en = d.ent[e];  // (node, slot | comp << 30)
+            const int rel = en.x - w0;
+            const int L = rel / VX, cell = rel - L * VX;
+            if (rel >= 0 && L == lane && outl) {
+              const int comp = (unsigned)en.y >> 30;
+              float val = 0.f;
+#pragma unroll
+              for (int v = 0; v < VX; v++)
+                if (v == cell) val = comp ? ez1_b[v] : (pass ? er1[v] : er1_b[v]);
+              samp[en.y & 0x3fffffff] = d.ent_w[e] * (double)val;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < VX; v++) h2_b[v] = h2[v];
+    }
+    // ---- shift
+#pragma unroll
+    for (int v = 0; v < VX; v++) {
+      if (m <= nz - 2) er_in[v] = er1n[v];
+      er1_b[v] = er1[v];
+      ez1_b[v] = ez1[v];
+      h1_b[v] = h1[v];
+    }
+  }
+}
+
+// Mur value of E_z on the r wall (rows 0..nz-2) for single-step tilings whose wall node starts a
+// wave.
 __global__ void k_rz_mur_r(RDev d, int par) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.nz - 1) return;
@@ -342,9 +559,9 @@ __global__ void k_rz_mur_r(RDev d, int par) {
   Eout[c0] = fmaf(d.mur_kr, Eout[c1] - Ein[c0], Ein[c1]);
 }
 
-// Sampling of the final level after the last step of a call.
-__global__ void __launch_bounds__(64) k_rz_gather(RDev d, int par, double *w, int column, int ld) {
-  gather_wave(d, par, w, column, ld, blockIdx.x * 8, threadIdx.x);
+// The last launch's pending work, after the last step of a call.
+__global__ void __launch_bounds__(64) k_rz_finish(RDev d, int par, double *w, int gcol, int scol, int sb, int ld) {
+  pending_wave(d, par, w, ld, gcol, scol, sb, blockIdx.x * 8, threadIdx.x);
 }
 
 __global__ void k_rz_zero(uint4 *p, long long n) {
@@ -362,36 +579,55 @@ __global__ void k_rz_copy(const float *src, float *dst, int nr, int nz, int pitc
 }
 
 // ------------------------------------------------------------------ launchers
-// One step: the fused kernel (which also samples the previous step into column gcol when
-// gcol >= 0), plus the r-wall Mur kernel in the wave-start tiling.
-hipError_t launch_rz_step(const chf_rz_plan &p, const RDev &d, int par, int step, const double *q,
-                          double *w, int gcol, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
-                          hipEvent_t ev_b = nullptr) {
+// Pending work a launch leaves for the next one: the level it wrote sampled into gcol, and the
+// stencil samples of its intermediate level (buffer sb) summed into scol.
+struct Pending {
+  int gcol = -1, scol = -1, sb = 0;
+};
+
+// One launch: `two` steps (k_rz_step2) or one (k_rz_step, plus the r-wall Mur kernel in the
+// wave-start tiling).  Updates `pend` to what this launch leaves.
+hipError_t launch_rz(const chf_rz_plan &p, const RDev &d, int par, int step, bool two, const double *q, double *w,
+                     int col, int ld, Pending &pend, int &samp_par, hipStream_t s, hipEvent_t ev_a = nullptr,
+                     hipEvent_t ev_b = nullptr) {
   hipError_t e = hipSuccess;
   if (ev_a) e = hipEventRecord(ev_a, s);
   if (e != hipSuccess) return e;
-  const int n_all = p.n_blocks + d.n_gblocks;
-  const dim3 grid(8 * ((n_all + 7) / 8)), block(64 * p.wv);
-  if (!w) gcol = -1;
-  switch (p.vx) {
-    case 1: k_rz_step<1><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
-    case 2: k_rz_step<2><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
-    case 4: k_rz_step<4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
-    default: k_rz_step<8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, ld); break;
+  const int gcol = w ? pend.gcol : -1, scol = w ? pend.scol : -1;
+  const dim3 block(64 * p.wv);
+  if (two) {
+    const int sb_out = samp_par ^ 1;
+    const dim3 grid(8 * ((p.n_blocks2 + d.n_gblocks + 7) / 8));
+    if (p.vx == 4) k_rz_step2<4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, sb_out, ld);
+    else k_rz_step2<8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, sb_out, ld);
+    samp_par = sb_out;
+    pend.scol = col;
+    pend.sb = sb_out;
+    pend.gcol = col + 1;
+  } else {
+    const dim3 grid(8 * ((p.n_blocks + d.n_gblocks + 7) / 8));
+    switch (p.vx) {
+      case 1: k_rz_step<1><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
+      case 2: k_rz_step<2><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
+      case 4: k_rz_step<4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
+      default: k_rz_step<8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
+    }
+    pend.scol = -1;
+    pend.gcol = col;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev_b) e = hipEventRecord(ev_b, s);
   if (e != hipSuccess) return e;
-  if (d.mur && p.mur_r_kernel) {
+  if (!two && d.mur && p.mur_r_kernel) {
     k_rz_mur_r<<<(d.nz - 1 + 255) / 256, 256, 0, s>>>(d, par);
     e = hipGetLastError();
   }
   return e;
 }
 
-hipError_t launch_rz_gather(const RDev &d, int par, double *w, int column, int ld, hipStream_t s) {
-  if (d.n_obs <= 0 || !w) return hipSuccess;
-  k_rz_gather<<<(d.n_obs + 7) / 8, 64, 0, s>>>(d, par, w, column, ld);
+hipError_t launch_rz_finish(const RDev &d, int par, double *w, const Pending &pend, int ld, hipStream_t s) {
+  if (d.n_obs <= 0 || !w || (pend.gcol < 0 && pend.scol < 0)) return hipSuccess;
+  k_rz_finish<<<(d.n_obs + 7) / 8, 64, 0, s>>>(d, par, w, pend.gcol, pend.scol, pend.sb, ld);
   return hipGetLastError();
 }
 
@@ -430,6 +666,9 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   if (vx != 1 && vx != 2 && vx != 4 && vx != 8) return fail(CHF_EINVAL, "vx must be 1, 2, 4 or 8");
   if (wv != 1 && wv != 2 && wv != 4 && wv != 8) return fail(CHF_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
   if (zchunk < 1) return fail(CHF_EINVAL, "z_chunk must be >= 1");
+  const int spl = ex->steps_per_launch ? ex->steps_per_launch : (vx >= 4 ? 2 : 1);
+  if (spl != 1 && spl != 2) return fail(CHF_EINVAL, "steps_per_launch must be 1 or 2");
+  if (spl == 2 && vx < 4) return fail(CHF_EINVAL, "two steps per launch need vx 4 or 8");
   const bool src_on = src->n_bins > 0;
   if (src->n_bins < 0) return fail(CHF_EINVAL, "n_bins < 0");
   if (src_on) {
@@ -465,6 +704,14 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
     return fail(CHF_EINVAL, "too many workgroups for this tile shape");
   }
   p->n_blocks = p->nrb * p->nzc;
+  p->spl = spl;
+  p->n_waves2 = (g.nr + 62 * vx - 1) / (62 * vx);
+  p->nrb2 = (p->n_waves2 + wv - 1) / wv;
+  p->n_blocks2 = p->nrb2 * p->nzc;
+  if ((uint64_t)p->n_blocks2 > (uint64_t)0x7fffffff / 8) {
+    delete p;
+    return fail(CHF_EINVAL, "too many workgroups for this tile shape");
+  }
   if (src_on) p->q_bins.assign(src->q_bins, src->q_bins + src->n_bins);
   else p->q_bins.assign(1, 0.0);
 
@@ -525,6 +772,36 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
     }
   }
 
+  // observer stencil nodes by row (slot = (o*2 + comp)*4 + corner, corner = a + 2b, the order in
+  // which the gather adds them), for the intermediate level of two-step launches
+  {
+    std::vector<std::vector<int>> rows_i(g.nz), rows_s(g.nz);
+    std::vector<std::vector<double>> rows_w(g.nz);
+    for (int o = 0; o < obs->n_obs; o++)
+      for (int c = 0; c < 2; c++)
+        for (int corner = 0; corner < 4; corner++) {
+          const int a = corner & 1, b = corner >> 1;
+          const double tr = p->ot[(o * 2 + c) * 2], tz = p->ot[(o * 2 + c) * 2 + 1];
+          const int k = p->oidx[(o * 2 + c) * 2 + 1] + b;
+          rows_i[k].push_back(p->oidx[(o * 2 + c) * 2] + a);
+          rows_s[k].push_back(((o * 2 + c) * 4 + corner) | (c << 30));
+          rows_w[k].push_back((a ? tr : 1.0 - tr) * (b ? tz : 1.0 - tz));
+        }
+    p->row_ptr.assign(g.nz + 1, 0);
+    for (int k = 0; k < g.nz; k++) {
+      p->row_ptr[k + 1] = p->row_ptr[k] + (int)rows_i[k].size();
+      for (size_t e = 0; e < rows_i[k].size(); e++) {
+        p->ent.push_back(rows_i[k][e]);
+        p->ent.push_back(rows_s[k][e]);
+        p->ent_w.push_back(rows_w[k][e]);
+      }
+    }
+    if (p->ent.empty()) {
+      p->ent.assign(2, 0);
+      p->ent_w.assign(1, 0.0);
+    }
+  }
+
   // workspace layout: 6 field arrays first (zeroed together), then the tables
   const uint64_t fbytes = align256(elems * sizeof(float));
   uint64_t off = 0;
@@ -548,6 +825,14 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   off = align256(off + p->ot.size() * sizeof(double));
   p->off_nan = off;
   off = align256(off + 256);
+  p->off_rowptr = off;
+  off = align256(off + p->row_ptr.size() * sizeof(int));
+  p->off_ent = off;
+  off = align256(off + p->ent.size() * sizeof(int));
+  p->off_entw = off;
+  off = align256(off + p->ent_w.size() * sizeof(double));
+  p->off_samp = off;
+  off = align256(off + 2 * 8 * (size_t)std::max(1, obs->n_obs) * sizeof(double));
   p->ws_bytes = off;
 
   RDev &D = p->dev;
@@ -559,6 +844,9 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   D.n_blocks = p->n_blocks;
   D.wv = wv;
   D.n_gblocks = (obs->n_obs + 8 * wv - 1) / (8 * wv);
+  D.nrb2 = p->nrb2;
+  D.n_waves2 = p->n_waves2;
+  D.n_blocks2 = p->n_blocks2;
   p->mur_r_kernel = ex->bc == CHF_BC_MUR1 && (g.nr - 1) % (64 * vx) == 0;
   D.ca = (float)p->ca;
   D.db_dr = (float)(p->db / g.dr);
@@ -624,6 +912,10 @@ chf_status chf_rz_bind_workspace(chf_rz_plan *p, void *dev_ptr, uint64_t bytes, 
   D.obs_idx = (const int *)(ws + p->off_oidx);
   D.obs_t = (const double *)(ws + p->off_ot);
   D.nan_flag = (int *)(ws + p->off_nan);
+  D.row_ptr = (const int *)(ws + p->off_rowptr);
+  D.ent = (const int2 *)(ws + p->off_ent);
+  D.ent_w = (const double *)(ws + p->off_entw);
+  D.samp = (double *)(ws + p->off_samp);
   struct Up {
     uint64_t off;
     const void *src;
@@ -635,6 +927,9 @@ chf_status chf_rz_bind_workspace(chf_rz_plan *p, void *dev_ptr, uint64_t bytes, 
       {p->off_q, p->q_bins.data(), p->q_bins.size() * sizeof(double)},
       {p->off_oidx, p->oidx.data(), p->oidx.size() * sizeof(int)},
       {p->off_ot, p->ot.data(), p->ot.size() * sizeof(double)},
+      {p->off_rowptr, p->row_ptr.data(), p->row_ptr.size() * sizeof(int)},
+      {p->off_ent, p->ent.data(), p->ent.size() * sizeof(int)},
+      {p->off_entw, p->ent_w.data(), p->ent_w.size() * sizeof(double)},
   };
   for (const Up &u : ups) {
     hipError_t e = hipMemcpyAsync(ws + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
@@ -648,7 +943,7 @@ chf_status chf_rz_bind_workspace(chf_rz_plan *p, void *dev_ptr, uint64_t bytes, 
 }
 
 static chf_status rz_forward(chf_rz_plan *p, void *stream, const double *q, double *w, int32_t n_steps,
-                             int32_t first_column, int32_t ld, std::vector<hipEvent_t> *ev) {
+                             int32_t first_column, int32_t ld, std::vector<hipEvent_t> *ev, int *n_launches = nullptr) {
   if (!p) return fail(CHF_EINVAL, "NULL plan");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
   if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
@@ -657,17 +952,19 @@ static chf_status rz_forward(chf_rz_plan *p, void *stream, const double *q, doub
   RDev d = p->dev;
   if (!p->ex.nan_watch) d.nan_flag = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  for (int t = 0; t < n_steps; t++) {  // step t samples step t-1's result
-    hipError_t e = launch_rz_step(*p, d, p->parity, p->n_done, q, w, t > 0 ? first_column + t - 1 : -1, ld, s,
-                                  ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
+  Pending pend;  // each launch samples its predecessor's results
+  for (int t = 0, li = 0; t < n_steps; li++) {
+    const bool two = p->spl == 2 && t + 1 < n_steps;
+    hipError_t e = launch_rz(*p, d, p->parity, p->n_done, two, q, w, first_column + t, ld, pend, p->samp_par, s,
+                             ev ? (*ev)[2 * li] : nullptr, ev ? (*ev)[2 * li + 1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     p->parity ^= 1;
-    p->n_done++;
+    p->n_done += two ? 2 : 1;
+    t += two ? 2 : 1;
+    if (n_launches) *n_launches = li + 1;
   }
-  if (n_steps > 0) {
-    hipError_t e = launch_rz_gather(d, p->parity, w, first_column + n_steps - 1, ld, s);
-    if (e != hipSuccess) return hip_fail(e, "gather launch");
-  }
+  hipError_t e = launch_rz_finish(d, p->parity, w, pend, ld, s);
+  if (e != hipSuccess) return hip_fail(e, "gather launch");
   return CHF_OK;
 }
 
@@ -685,10 +982,11 @@ chf_status chf_rz_forward_timed(chf_rz_plan *p, void *stream, const double *q, d
   hipError_t e = hipSuccess;
   for (size_t t = 0; t < ev.size() && e == hipSuccess; t++) e = hipEventCreate(&ev[t]);
   chf_status st = CHF_OK;
-  if (e == hipSuccess) st = rz_forward(p, stream, q, w, n_steps, first_column, ld, &ev);
+  int launches = 0;
+  if (e == hipSuccess) st = rz_forward(p, stream, q, w, n_steps, first_column, ld, &ev, &launches);
   if (e == hipSuccess && st == CHF_OK) e = hipStreamSynchronize((hipStream_t)stream);
   double total = 0.0;
-  for (int t = 0; t < n_steps && e == hipSuccess && st == CHF_OK; t++) {
+  for (int t = 0; t < launches && e == hipSuccess && st == CHF_OK; t++) {
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]);
     total += ms;
@@ -722,12 +1020,15 @@ chf_status chf_rz_forward_graph(chf_rz_plan *p, void *stream, const double *q, d
     RDev d = p->dev;
     if (!p->ex.nan_watch) d.nan_flag = nullptr;
     hipError_t le = launch_rz_zero(*p, cs);
-    int par = 0;
-    for (int t = 0; t < T && le == hipSuccess; t++) {
-      le = launch_rz_step(*p, d, par, t, q, w, t - 1, T, cs);
+    int par = 0, sp = p->samp_par;
+    Pending pend;
+    for (int t = 0; t < T && le == hipSuccess;) {
+      const bool two = p->spl == 2 && t + 1 < T;
+      le = launch_rz(*p, d, par, t, two, q, w, t, T, pend, sp, cs);
       par ^= 1;
+      t += two ? 2 : 1;
     }
-    if (le == hipSuccess && T > 0) le = launch_rz_gather(d, par, w, T - 1, T, cs);
+    if (le == hipSuccess) le = launch_rz_finish(d, par, w, pend, T, cs);
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(cs, &gr);
     (void)hipStreamDestroy(cs);
@@ -747,7 +1048,8 @@ chf_status chf_rz_forward_graph(chf_rz_plan *p, void *stream, const double *q, d
   }
   hipError_t e = hipGraphLaunch(p->graph, s);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
-  p->parity = T & 1;
+  const int launches = p->spl == 2 ? T / 2 + (T & 1) : T;
+  p->parity = launches & 1;
   p->n_done = T;
   return CHF_OK;
 }
@@ -796,6 +1098,8 @@ chf_status chf_rz_get_info(const chf_rz_plan *p, chf_rz_info *info) {
   info->pitch = p->pitch;
   info->n_blocks = p->n_blocks;
   info->n_src = p->n_src;
+  info->steps_per_launch = p->spl;
+  info->pad0 = 0;
   info->field_bytes = p->field_bytes;
   info->workspace_bytes = p->ws_bytes;
   info->bytes_per_cell_update = 6.0 * sizeof(float);  // read E_r, E_z, H; write all three

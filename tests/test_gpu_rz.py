@@ -71,15 +71,20 @@ def test_waveforms_and_fields_match_oracle(fixture, request):
         plan.close()
 
 
-SHAPES = [(1, 1, 1), (1, 2, 2), (1, 2, 7), (2, 8, 5), (4, 4, 32), (4, 1, 600), (8, 1, 13), (8, 2, 64)]
+# (vx, waves per workgroup, z chunk, Yee steps per launch)
+SHAPES = [(1, 1, 1, 1), (1, 2, 2, 1), (1, 2, 7, 1), (2, 8, 5, 1), (4, 4, 32, 1), (4, 4, 32, 2), (4, 1, 600, 2),
+          (4, 2, 1, 2), (4, 8, 2, 2), (8, 1, 13, 1), (8, 1, 13, 2), (8, 2, 64, 2)]
 
 
-def test_tile_shapes_bitwise_equal(small_mur):
-    w = small_mur.replace(n_steps=260)
+@pytest.mark.parametrize("n_steps", [260, 261])
+def test_tile_shapes_bitwise_equal(small_mur, n_steps):
+    """Every tile shape, with one or two Yee steps per launch (an odd count ends on a one-step
+    launch), gives the same waveforms and fields bit for bit."""
+    w = small_mur.replace(n_steps=n_steps)
     outs, fields = [], []
-    for vx, waves, zc in SHAPES:
-        print(f"rz shape vx={vx} waves={waves} z_chunk={zc}", flush=True)
-        plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zc)
+    for vx, waves, zc, spl in SHAPES:
+        print(f"rz shape vx={vx} waves={waves} z_chunk={zc} steps/launch={spl}", flush=True)
+        plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zc, steps_per_launch=spl)
         try:
             outs.append(plan.run().cpu())
             fields.append(torch.stack([plan.get_field(c) for c in range(3)]).cpu())

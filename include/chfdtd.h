@@ -180,6 +180,18 @@ chf_status chf_adjoint_begin(chf_plan *plan, void *stream, double *dl_dq_dev);
 chf_status chf_adjoint_steps(chf_plan *plan, void *stream, const double *dl_dw_dev, double *dl_dq_dev,
                              int32_t t_lo, int32_t t_hi);
 
+/* Gradients with respect to the source's non-linear parameters (the radial width sigma_r and the
+   trajectory offset z_entry of the Simulation Setup section's moving charge snapshot), with the
+   profile gradient, from one reverse sweep: J_z enters the E update linearly, so
+   dL/dtheta = sum_n <Eb_z, -Cb dJ_z^n/dtheta> needs the adjoint state only, not the forward
+   states.  q_bins_dev: DEVICE profile the forward run used (NULL = plan's); dl_dq_dev: DEVICE
+   [n_bins]; dl_dtheta_dev: DEVICE FP64 [2] = (dL/dsigma_r, dL/dz_entry), per metre.  The
+   derivative holds the source's discrete support (nodes inside the cut disc, rows of the z
+   window) fixed, i.e. it is exact wherever that support does not change.  PEC and CPML only;
+   CHF_EINVAL without a source.  The forward field state is destroyed. */
+chf_status chf_adjoint_source_params(chf_plan *plan, void *stream, const double *dl_dw_dev,
+                                     const double *q_bins_dev, double *dl_dq_dev, double *dl_dtheta_dev);
+
 /* Forward-state snapshots (checkpoints, resume).  A snapshot is the plan's whole field and
    CPML state -- both time levels of E and H and every psi array -- as a DEVICE byte image of
    chf_plan_state_bytes bytes owned by the caller.  save copies it out (stream-ordered) and

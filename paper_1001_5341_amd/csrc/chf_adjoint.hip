@@ -66,8 +66,13 @@ __global__ void __launch_bounds__(64) k_adj_sample(Dev d, const double *g, int n
   }
 }
 
-__global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq) {
-  __shared__ double part[256];
+// With dth: also the cotangents of the source's non-linear parameters,
+//   dL/dsigma_r  += -Cb v Q(z_s) sum dW_r/dsigma_r W_z Eb_z,
+//   dL/dz_entry  += -Cb v [Q'(z_s) sum W_r W_z Eb_z + Q(z_s) sum W_r dW_z/dz_s Eb_z]
+// (z_s moves one for one with z_entry; Q' is the slope of the hat interpolation, W_z' that of the
+// window-normalised Gaussian with the window held fixed), Q from the profile q.
+__global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, const double *q, double *dth) {
+  __shared__ double part[256], part_r[256], part_z[256];
   const double tt = (n + 0.5) * d.dt;
   if (!d.src_on || tt < d.t_entry) return;
   const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
@@ -75,14 +80,17 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq) {
   const int klo = (int)ceil((zs - half) / d.dz - 0.5);
   const int khi = (int)floor((zs + half) / d.dz - 0.5);
   const int m = min(khi - klo + 1, kMaxWz);
-  double norm = 0.0;
+  const double sz2 = d.sigma_z * d.sigma_z;
+  double norm = 0.0, dnorm = 0.0;
   for (int s = 0; s < m; s++) {
     const double dd = (klo + s + 0.5) * d.dz - zs;
-    norm += exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) * d.dz;
+    const double e = exp(-0.5 * dd * dd / sz2);
+    norm += e * d.dz;
+    dnorm += e * dd / sz2 * d.dz;
   }
   const float *Ebz = (const float *)d.e[0][2];
-  double acc = 0.0;
   const int npatch = d.src_ni * d.src_nj;
+  double acc = 0.0, acc_r = 0.0, acc_z = 0.0;
   for (int t = threadIdx.x; t < npatch * m; t += blockDim.x) {
     const int s = t / npatch, c = t % npatch;
     const int k = klo + s;
@@ -91,13 +99,25 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq) {
     if (wr == 0.0) continue;
     const int i = d.src_i0 + c % d.src_ni, j = d.src_j0 + c / d.src_ni;
     const double dd = (k + 0.5) * d.dz - zs;
-    const double wz = exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) / norm;
-    acc += wr * wz * (double)Ebz[cidx(d, i, j, k)];
+    const double e = exp(-0.5 * dd * dd / sz2);
+    const double wz = e / norm;
+    const double eb = (double)Ebz[cidx(d, i, j, k)];
+    acc += wr * wz * eb;
+    if (dth) {
+      acc_r += d.dwr[c] * wz * eb;
+      acc_z += wr * (e * dd / sz2 / norm - wz * dnorm / norm) * eb;
+    }
   }
   part[threadIdx.x] = acc;
+  part_r[threadIdx.x] = acc_r;
+  part_z[threadIdx.x] = acc_z;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if ((int)threadIdx.x < w) {
+      part[threadIdx.x] += part[threadIdx.x + w];
+      part_r[threadIdx.x] += part_r[threadIdx.x + w];
+      part_z[threadIdx.x] += part_z[threadIdx.x + w];
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -108,6 +128,15 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq) {
     const double base = -d.a_cb_src * d.v_src * part[0];
     if (b0 >= 0 && b0 < d.n_bins) dq[b0] += base * (1.0 - tfr);
     if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) dq[b0 + 1] += base * tfr;
+    if (dth) {
+      const double *qb = q ? q : d.q_bins;
+      const double q0 = b0 >= 0 && b0 < d.n_bins ? qb[b0] : 0.0;
+      const double q1 = b0 + 1 >= 0 && b0 + 1 < d.n_bins ? qb[b0 + 1] : 0.0;
+      const double Q = (1.0 - tfr) * q0 + tfr * q1, dQ = (q1 - q0) / d.dz_bin;
+      const double g = -d.a_cb_src * d.v_src;
+      dth[0] += g * Q * part_r[0];
+      dth[1] += g * (dQ * part[0] + Q * part_z[0]);
+    }
   }
 }
 
@@ -236,18 +265,18 @@ __global__ void __launch_bounds__(256) k_adj_egather(Dev d) {
 
 }  // namespace
 
-hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s) {
-  const int n = std::max(p.dev.n_bins, 1);
-  hipLaunchKernelGGL(k_adj_zero_q, dim3((n + 255) / 256), dim3(256), 0, s, dl_dq, p.dev.n_bins);
+hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, int n_out) {
+  const int n = n_out >= 0 ? n_out : p.dev.n_bins;
+  hipLaunchKernelGGL(k_adj_zero_q, dim3((std::max(n, 1) + 255) / 256), dim3(256), 0, s, dl_dq, n);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step, const double *dl_dw,
-                               double *dl_dq, hipStream_t s) {
+                               double *dl_dq, hipStream_t s, const double *q_dev, double *dl_dtheta) {
   (void)parity;
   const int T = p.grid.n_steps;
   if (d.n_obs > 0) hipLaunchKernelGGL(k_adj_sample, dim3(1), dim3(64), 0, s, d, dl_dw, step, T);
-  if (d.src_on) hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(256), 0, s, d, step, dl_dq);
+  if (d.src_on) hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(256), 0, s, d, step, dl_dq, q_dev, dl_dtheta);
   dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, (d.nz + kAdjZ - 1) / kAdjZ);
   hipLaunchKernelGGL(k_adj_e, grid, dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_adj_hgather, grid, dim3(256), 0, s, d);

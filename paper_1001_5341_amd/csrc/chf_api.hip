@@ -306,21 +306,34 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     D.src_nj = j1 - j0 + 1;
     p->wr.assign((size_t)D.src_ni * D.src_nj, 0.0);
     double norm = 0.0;
+    // second half: d W / d sigma_r (the disc's support held fixed), for the source-parameter
+    // gradients of the adjoint
+    const size_t npatch = (size_t)D.src_ni * D.src_nj;
+    p->wr.assign(2 * npatch, 0.0);
+    double dnorm = 0.0;
+    const double s2 = src->sigma_r * src->sigma_r;
     for (int j = j0; j <= j1; j++)
       for (int i = i0; i <= i1; i++) {
         const double ddx = i * G.dx - src->x_axis, ddy = j * G.dy - src->y_axis;
         const double r2 = ddx * ddx + ddy * ddy;
         if (r2 <= rc * rc) {
-          const double w = std::exp(-0.5 * r2 / (src->sigma_r * src->sigma_r));
+          const double w = std::exp(-0.5 * r2 / s2);
+          const double dw = w * r2 / (s2 * src->sigma_r);
           p->wr[(size_t)(j - j0) * D.src_ni + (i - i0)] = w;
+          p->wr[npatch + (size_t)(j - j0) * D.src_ni + (i - i0)] = dw;
           norm += w * G.dx * G.dy;
+          dnorm += dw * G.dx * G.dy;
         }
       }
     if (norm <= 0.0) {
       delete p;
       return fail(CHF_EDOMAIN, "source disc misses the grid");
     }
-    for (double &w : p->wr) w /= norm;
+    for (size_t c = 0; c < npatch; c++) {
+      const double wn = p->wr[c] / norm;
+      p->wr[npatch + c] = p->wr[npatch + c] / norm - wn * dnorm / norm;
+      p->wr[c] = wn;
+    }
   }
 
   // observers: base node and fractional offsets per component and axis
@@ -480,6 +493,7 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
     A.adh = tf + p->off_tabf[u][9];
   }
   D.wr = (const double *)(ws + p->off_wr);
+  D.dwr = D.wr + (D.src_on ? (size_t)D.src_ni * D.src_nj : 0);
   D.q_bins = (const double *)(ws + p->off_q);
   D.obs_idx = (const int *)(ws + p->off_oidx);
   D.obs_t = (const double *)(ws + p->off_ot);
@@ -736,6 +750,21 @@ chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, doubl
   chf_status st = chf_adjoint_begin(p, stream, dl_dq_dev);
   if (st != CHF_OK) return st;
   return chf_adjoint_steps(p, stream, dl_dw_dev, dl_dq_dev, 0, p->grid.n_steps);
+}
+
+chf_status chf_adjoint_source_params(chf_plan *p, void *stream, const double *dl_dw_dev, const double *q_bins_dev,
+                                     double *dl_dq_dev, double *dl_dtheta_dev) {
+  if (!p || !dl_dq_dev || !dl_dtheta_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
+  if (!p->dev.src_on) return fail(CHF_EINVAL, "the plan has no source");
+  chf_status st = chf_adjoint_begin(p, stream, dl_dq_dev);
+  if (st != CHF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = chf::launch_adjoint_init(*p, dl_dtheta_dev, s, 2);
+  for (int n = p->grid.n_steps - 1; n >= 0 && e == hipSuccess; n--)
+    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, s, q_bins_dev, dl_dtheta_dev);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  p->adj_next = 0;
+  return CHF_OK;
 }
 
 chf_status chf_plan_state_bytes(const chf_plan *p, uint64_t *bytes) {

@@ -51,6 +51,7 @@ struct Dev {
   double cb_src;             // scale_e * Cb: E increment per unit current density
   const double *q_bins;      // device, the plan's profile
   const double *wr;          // device [src_nj][src_ni] radial weights
+  const double *dwr;         // device [src_nj][src_ni] their derivative with respect to sigma_r
   // observers
   int n_obs;
   const int *obs_idx;        // [n_obs][3 comps][3] base node of the trilinear stencil
@@ -147,8 +148,9 @@ hipError_t launch_zero(const chf_plan &p, hipStream_t s);
 hipError_t launch_get_field(const chf_plan &p, int parity, int comp, float *out, hipStream_t s);
 hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float *in, hipStream_t s);
 hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step,
-                               const double *dl_dw, double *dl_dq, hipStream_t s);
-hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s);
+                               const double *dl_dw, double *dl_dq, hipStream_t s,
+                               const double *q_dev = nullptr, double *dl_dtheta = nullptr);
+hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, int n = -1);
 hipError_t launch_batch_step(const chf_batch &b, int parity, int step, hipStream_t s);
 void set_error(const std::string &msg);
 }  // namespace chf

@@ -153,6 +153,20 @@ class Plan:
                                     ct.c_void_p(out.data_ptr())), "chf_adjoint")
         return out
 
+    def adjoint_source_params(self, dl_dw: torch.Tensor, q_bins: Optional[torch.Tensor] = None, stream=None):
+        """(dL/dq [n_bins], dL/dtheta [2] = (dL/dsigma_r, dL/dz_entry)) for dL/dw of the plan's full
+        run (chf_adjoint_source_params)."""
+        assert dl_dw.dtype == torch.float64 and dl_dw.shape == (self.n_obs, 3, self.n_steps)
+        dl_dw = dl_dw.contiguous()
+        dq = torch.zeros(len(self.w.q_bins), dtype=torch.float64, device=self.device)
+        dth = torch.zeros(2, dtype=torch.float64, device=self.device)
+        qp = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
+        N.check(N.lib().chf_adjoint_source_params(self._h, _stream_handle(stream), ct.c_void_p(dl_dw.data_ptr()),
+                                                  qp, ct.c_void_p(dq.data_ptr()), ct.c_void_p(dth.data_ptr())),
+                "chf_adjoint_source_params")
+        self.sync(stream)
+        return dq, dth
+
     def adjoint_begin(self, dl_dq: torch.Tensor, stream=None):
         N.check(N.lib().chf_adjoint_begin(self._h, _stream_handle(stream), ct.c_void_p(dl_dq.data_ptr())),
                 "chf_adjoint_begin")

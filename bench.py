@@ -73,14 +73,16 @@ def traffic_path(workload: str, storage: str) -> str:
     return os.path.join(ROOT, "profiles", f"traffic_{kern}_{workload}_{storage}.json")
 
 
-def measured_traffic(workload: str, storage: str):
+def measured_traffic(workload: str, storage: str, tile=None):
     """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and (when given) the same tile shape; else None."""
     path = traffic_path(workload, storage)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_digest") != kernel_digest_for(workload):
+        return None
+    if tile is not None and rec.get("tile") != list(tile):
         return None
     return rec.get("bytes_per_launch")
 
@@ -92,7 +94,7 @@ def _dispatches(path: str, counter: str):
                 yield r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, command: str):
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, command: str, tile=None):
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the fused sweep, each scaled by what the
     same counter reads for the 256 MiB calibration copy (read 256 MiB, write 256 MiB)."""
     out = {}
@@ -112,7 +114,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
                      "bytes_per_launch": float(np.mean(fused)) * 1024.0 * factor}
     kdesc = ("axisymmetric two-step launch (k_rz_step2)" if is_rz(workload) else "fused interior sweep (chf::k_fused)")
     rec = {"workload": workload, "storage": storage, "kernel": kdesc,
-           "kernel_digest": kernel_digest_for(workload), "command": command,
+           "kernel_digest": kernel_digest_for(workload), "command": command, "tile": tile,
            "fetch": out["fetch"], "write": out["write"],
            "bytes_per_launch": out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]}
     path = traffic_path(workload, storage)
@@ -313,11 +315,19 @@ def rz_main(args):
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    info, wall, ev_s, ms, launches, got = rz_measure(w, args.steps, args.warmup, args.vx, args.waves,
-                                                     args.zchunk, args.steps_per_launch)
+    shape, tuned = (args.vx, args.waves, args.zchunk, args.steps_per_launch), False
+    if not (args.no_tune or any(shape)):
+        from paper_1001_5341_amd import autotune
+
+        t = autotune.tune_rz(w)
+        shape, tuned = tuple(t["shape"]), True
+        log(f"rz: tuned shape (vx, waves, z_chunk, steps/launch) = {shape} "
+            f"({'cached' if t['cached'] else 'measured'}, {t['ms_per_step']:.4f} ms/step)")
+    info, wall, ev_s, ms, launches, got = rz_measure(w, args.steps, args.warmup, *shape)
     log(f"rz: {args.steps} timed runs, wall {wall:.3f} s, step kernel {ms / launches * 1e3:.1f} us/launch")
     roof = rz_roofline(w, ms, launches, info["steps_per_launch"])
-    roof["traffic"] = measured_traffic(args.workload, "fp32") if not args.time_steps else None
+    tile = [info["vx"], info["waves_per_block"], info["z_chunk"], info["steps_per_launch"]]
+    roof["traffic"] = measured_traffic(args.workload, "fp32", tile) if not args.time_steps else None
     rec = {
         "metric": "Yee Mcell-updates/s and % HBM roofline of the axisymmetric (r, z) scheme, FP32",
         "value": round(w.nr * w.nz * w.n_steps * args.steps / wall / 1e6, 1),
@@ -329,7 +339,8 @@ def rz_main(args):
         "config": {"workload": w.name, "grid_rz": [w.nr, w.nz], "yee_steps_per_run": w.n_steps,
                    "boundary": w.bc, "observers": w.n_obs,
                    "tile": {"vx": info["vx"], "waves_per_block": info["waves_per_block"],
-                            "z_chunk": info["z_chunk"], "steps_per_launch": info["steps_per_launch"]},
+                            "z_chunk": info["z_chunk"], "steps_per_launch": info["steps_per_launch"],
+                            "autotuned": tuned},
                    "parallelism": "single GPU"},
         "roofline": roof,
         "waveforms_finite": bool(np.isfinite(got).all()),
@@ -414,8 +425,10 @@ def main():
     args = ap.parse_args()
 
     if args.summarize_pmc:
+        tile = ([args.vx, args.waves, args.zchunk, args.steps_per_launch] if is_rz(args.workload)
+                else [args.waves, args.zchunk])
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.storage,
-                      args.pmc_command)
+                      args.pmc_command, tile)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
@@ -446,7 +459,8 @@ def main():
     cells = w.nx * w.ny * w.nz
     updates = cells * w.n_steps * args.steps
     roof = roofline(info, fused_ms, launches)
-    roof["traffic"] = measured_traffic(args.workload, args.storage) if not args.time_steps else None
+    roof["traffic"] = (measured_traffic(args.workload, args.storage, [info["waves_per_block"], info["z_chunk"]])
+                       if not args.time_steps else None)
     # whole Yee step (all kernels) against the whole-grid algorithmic bytes, for context
     step_s = ev_s / (args.steps * w.n_steps)
     roof["whole_step"] = {"bytes_per_cell": round(info["bytes_per_cell_update"], 3),

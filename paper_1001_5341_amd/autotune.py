@@ -1,4 +1,4 @@
-"""Tile-shape autotuner for the fused sweep, with a JSON cache.
+"""Tile-shape autotuners (the 3-D fused sweep; the (r, z) step kernels), with a JSON cache.
 
 For one workload shape it times every candidate (waves per workgroup x z chunk) over a short
 run of the real step (interior and boundary sweeps, source, gather) and keeps the fastest.
@@ -126,3 +126,76 @@ def tune_batch(workloads: Iterable, storage: str = "fp32", **kw) -> list:
     res = [tune(w, storage, **kw) for w in workloads]
     waves = max({r["waves"] for r in res}, key=lambda v: sum(r["waves"] == v for r in res))
     return [{"waves": waves, "z_chunk": r["z_chunk"]} for r in res]
+
+
+# ------------------------------------------------------------------ axisymmetric (r, z) scheme
+# (vx, waves per workgroup, z chunk, Yee steps per launch)
+RZ_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (
+    (4, 1, 32, 2), (4, 1, 64, 2), (4, 2, 32, 2), (4, 2, 64, 2), (4, 4, 32, 2), (4, 4, 64, 2),
+    (8, 1, 64, 2), (8, 2, 32, 2), (4, 4, 64, 1), (4, 1, 64, 1))
+
+
+def rz_shape_key(w, device=None) -> str:
+    arch = torch.cuda.get_device_properties(device or torch.cuda.current_device()).gcnArchName.split(":")[0]
+    return f"{arch}/rz/{w.bc}/{w.nr}x{w.nz}"
+
+
+def tune_rz(w, steps: int = 64, cache_path: Optional[str] = None,
+            candidates: Optional[Sequence[Tuple[int, int, int, int]]] = None, use_cache: bool = True,
+            device=None) -> dict:
+    """Fastest (vx, waves, z_chunk, steps_per_launch) for an (r, z) lattice; every candidate must
+    reproduce the first one's waveforms and final fields bit for bit."""
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    path = cache_path or default_cache_path()
+    key = rz_shape_key(w, device)
+    cands = [tuple(c) for c in (candidates or RZ_CANDIDATES)]
+    if use_cache:
+        hit = _load(path).get(key)
+        if hit and tuple(hit["shape"]) in cands:
+            return dict(hit, cached=True)
+    steps = max(2, min(steps, w.n_steps))
+    wt = w.replace(n_steps=steps)
+    trials, ref = [], None
+    for vx, waves, zc, spl in cands:
+        try:
+            plan = solver.RZPlan(wt, vx=vx, waves=waves, zchunk=zc, steps_per_launch=spl, device=device)
+        except N.ChfError as exc:
+            trials.append({"shape": [vx, waves, zc, spl], "error": exc.status})
+            continue
+        try:
+            out = plan.new_waveforms()
+            stream = torch.cuda.current_stream(device)
+            plan.reset(stream)
+            plan.forward(steps, out, 0, stream=stream)  # warm-up
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            out.zero_()
+            plan.reset(stream)
+            ev0.record(stream)
+            plan.forward(steps, out, 0, stream=stream)
+            ev1.record(stream)
+            plan.sync(stream)
+            ms = ev0.elapsed_time(ev1) / steps
+            got = (out.cpu(), torch.stack([plan.get_field(c) for c in range(3)]).cpu())
+        finally:
+            plan.close()
+        if ref is None:
+            ref = got
+        elif not (torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])):
+            raise RuntimeError(f"(r, z) shape {(vx, waves, zc, spl)} changes the results")
+        trials.append({"shape": [vx, waves, zc, spl], "ms_per_step": ms, "bitwise_equal": True})
+    timed = [t for t in trials if "ms_per_step" in t]
+    if not timed:
+        raise RuntimeError(f"no valid (r, z) shape for {key}")
+    best = min(timed, key=lambda t: t["ms_per_step"])
+    rec = {"shape": best["shape"], "ms_per_step": best["ms_per_step"], "steps": steps, "trials": trials}
+    table = _load(path)
+    table[key] = rec
+    _store(path, table)
+    return dict(rec, cached=False)
+
+
+def tuned_rz_plan(w, **kw) -> "solver.RZPlan":
+    t = tune_rz(w, **kw)
+    vx, waves, zc, spl = t["shape"]
+    return solver.RZPlan(w, vx=vx, waves=waves, zchunk=zc, steps_per_launch=spl, device=kw.get("device"))

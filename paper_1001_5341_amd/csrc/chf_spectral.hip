@@ -3,9 +3,9 @@
 //
 // Both transforms are sums S(w) = sum_b x_b exp(i w (x0 + b h)) over uniformly spaced samples
 // with one "frequency" w per thread.  A workgroup stages the samples through LDS in chunks
-// (coalesced loads, then broadcast reads), and each thread advances its phase factor by the
-// rotation exp(i w h), re-anchored with an exact sincos every kAnchor samples so the rounding
-// of the recurrence stays near 1e-14 relative.
+// (coalesced loads, then broadcast reads), and each thread advances four interleaved phase
+// factors by the rotation exp(4 i w h), re-anchored with an exact sincos every kAnchor samples
+// so the rounding of the recurrence stays near 1e-14 relative.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,33 +29,54 @@ chf_status fail(chf_status s, const std::string &m) {
 }
 
 // Block-wide: every thread of the block must call it (it synchronises); `active` threads
-// accumulate sum_b x[b] exp(i w (x0 + b h)) for b < n into (re, im).
+// accumulate sum_b x[b] exp(i w (x0 + b h)) for b < n into (re, im).  Each thread runs four
+// independent phase chains over the samples b = 4c + r (r = 0..3), rotated by exp(4 i w h), so the
+// recurrence's latency overlaps; every kAnchor samples chain 0 is re-anchored with an exact
+// sincos and chains 1-3 follow from it by fixed rotations.
 __device__ void accumulate(const double *x, int n, double x0, double h, double w, bool active, double &re,
                            double &im) {
   __shared__ double sx[kChunk];
-  double sr = 0.0, cr = 1.0;
-  if (active) sincos(w * h, &sr, &cr);
+  // rotations by w h, 2 w h, 3 w h (chain offsets) and 4 w h (chain step)
+  double rs[4] = {0.0, 0.0, 0.0, 0.0}, rc[4] = {1.0, 1.0, 1.0, 1.0};
+  if (active) {
+#pragma unroll
+    for (int r = 1; r < 4; r++) sincos(r * w * h, &rs[r], &rc[r]);
+    sincos(4.0 * w * h, &rs[0], &rc[0]);
+  }
+  const double s4 = rs[0], c4 = rc[0];
+  double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
   for (int base = 0; base < n; base += kChunk) {
     const int m = min(kChunk, n - base);
     __syncthreads();
-    for (int t = threadIdx.x; t < m; t += blockDim.x) sx[t] = x[base + t];
+    for (int t = threadIdx.x; t < kChunk; t += blockDim.x) sx[t] = t < m ? x[base + t] : 0.0;
     __syncthreads();
     if (active) {
       for (int a = 0; a < m; a += kAnchor) {
-        double s, c;
-        sincos(w * (x0 + (base + a) * h), &s, &c);
+        double c[4], s[4];
+        sincos(w * (x0 + (base + a) * h), &s[0], &c[0]);
+#pragma unroll
+        for (int r = 1; r < 4; r++) {
+          c[r] = c[0] * rc[r] - s[0] * rs[r];
+          s[r] = fma(s[0], rc[r], c[0] * rs[r]);
+        }
         const int e = min(a + kAnchor, m);
-        for (int b = a; b < e; b++) {
-          const double v = sx[b];
-          re = fma(v, c, re);
-          im = fma(v, s, im);
-          const double c2 = c * cr - s * sr;
-          s = fma(s, cr, c * sr);
-          c = c2;
+#pragma unroll 4
+        for (int b = a; b < e; b += 4) {  // samples past m are zero in LDS
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const double v = sx[b + r];
+            ar[r] = fma(v, c[r], ar[r]);
+            ai[r] = fma(v, s[r], ai[r]);
+            const double c2 = c[r] * c4 - s[r] * s4;
+            s[r] = fma(s[r], c4, c[r] * s4);
+            c[r] = c2;
+          }
         }
       }
     }
   }
+  re += (ar[0] + ar[1]) + (ar[2] + ar[3]);
+  im += (ai[0] + ai[1]) + (ai[2] + ai[3]);
 }
 
 __global__ void __launch_bounds__(kThreads) k_spectrum(const double *w, int n_t, int ld, double dt, double t0,

@@ -29,3 +29,27 @@ def test_autotune_verifies_caches_and_matches_oracle(gpu, tmp_path):
     ref = oracle.run(w)
     err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
     assert np.all(err <= 1e-5), err
+
+
+def test_rz_autotune_verifies_and_caches(tmp_path):
+    """The (r, z) tuner times every shape, requires identical bits from all of them, caches the
+    winner, and the tuned plan matches the oracle."""
+    import numpy as np
+
+    from oracle import rz_oracle
+    from paper_1001_5341_amd import autotune, workloads as W
+
+    w = W.rz_small(nr=200, nz=300, n_steps=400, n_obs=4)
+    cache = str(tmp_path / "tune.json")
+    cands = [(4, 1, 64, 2), (8, 2, 32, 2), (4, 4, 16, 1), (2, 2, 8, 1)]
+    t = autotune.tune_rz(w, steps=40, cache_path=cache, candidates=cands)
+    assert not t["cached"] and all(x.get("bitwise_equal") for x in t["trials"])
+    assert autotune.tune_rz(w, steps=40, cache_path=cache, candidates=cands)["cached"]
+    plan = autotune.tuned_rz_plan(w, cache_path=cache, candidates=cands)
+    try:
+        got = plan.run().cpu().numpy()
+    finally:
+        plan.close()
+    ref = rz_oracle.run(w)
+    assert np.abs(ref).max() > 0
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5

@@ -423,6 +423,8 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--pmc-command", default="", help="command recorded in the counter summary")
     args = ap.parse_args()
+    # tile shapes measured on MI355X ship with the package; missing shapes are tuned and added
+    os.environ.setdefault("CHFDTD_TUNE_CACHE", os.path.join(ROOT, "paper_1001_5341_amd", "tune_cache_gfx950.json"))
 
     if args.summarize_pmc:
         tile = ([args.vx, args.waves, args.zchunk, args.steps_per_launch] if is_rz(args.workload)

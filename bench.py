@@ -259,14 +259,15 @@ def rz_cpu_baseline(w, n_steps: int = 4):
                       f"{n_steps} steps, {dt:.1f} s"}
 
 
-def rz_measure(w, n_runs: int, warmup: int, vx=0, waves=0, zchunk=0, spl=0):
+def rz_measure(w, n_runs: int, warmup: int, vx=0, waves=0, zchunk=0, spl=0, storage="fp32", dynamic=False):
     """n_runs full runs through chf_rz_forward_timed; returns (info, wall s, event s,
     summed step-kernel ms, launches, waveforms)."""
     import torch
 
     from paper_1001_5341_amd import solver
 
-    plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zchunk, steps_per_launch=spl, device=torch.device("cuda:0"))
+    plan = solver.RZPlan(w, vx=vx, waves=waves, zchunk=zchunk, steps_per_launch=spl, storage=storage,
+                         dynamic_scaling=dynamic, device=torch.device("cuda:0"))
     info = plan.info()
     out = plan.new_waveforms()
     for i in range(warmup):
@@ -345,6 +346,22 @@ def rz_main(args):
         "roofline": roof,
         "waveforms_finite": bool(np.isfinite(got).all()),
     }
+    if not args.time_steps and not args.no_variants:
+        variants = {}
+        for st, dyn in (("bf16", False), ("fp16", False), ("fp16", True)):
+            name = st + ("-dynamic" if dyn else "")
+            log(f"rz storage variant {name}")
+            vinfo, vwall, _, vms, vl, vgot = rz_measure(w, 1, 0, *shape, storage=st, dynamic=dyn)
+            vroof = rz_roofline(w, vms, vl, vinfo["steps_per_launch"])
+            alg = w.nr * (w.nz - 1) * vinfo["bytes_per_cell_update"]
+            variants[name] = {
+                "value": round(w.nr * w.nz * w.n_steps / vwall / 1e6, 1), "unit": "Mcell-updates/s",
+                "launch_avg_us": vroof["launch_avg_us"], "bytes_per_node": vinfo["bytes_per_cell_update"],
+                "roofline_frac": round(alg / (vroof["launch_avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "scale_e": vinfo["scale_e"], "scale_h": vinfo["scale_h"],
+                "rel_l2_vs_fp32_run": float(np.linalg.norm(vgot - got) / np.linalg.norm(got)),
+                "finite": bool(np.isfinite(vgot).all())}
+        rec["storage_variants"] = variants
     if not args.time_steps:
         log("spectral post-processing of the run's waveforms")
         rec["spectral"] = spectral_measure(w, got)

@@ -67,10 +67,20 @@ typedef struct {
    consecutive radial nodes (vx = 1, 2, 4 or 8) of z_chunk rows (>= 1); 0 picks the defaults
    (vx 4, 4 waves, 32 rows).  steps_per_launch: 1, or 2 to advance two Yee steps per pass over
    the fields (temporal blocking; needs vx 4 or 8; an odd remainder takes a one-step pass);
-   0 = 2 when vx >= 4, else 1.  No choice changes a result bit.  nan_watch: check waveforms for
-   non-finite values every step (reported by chf_rz_sync). */
+   0 = 2 when vx >= 4, else 1.  None of these changes a result bit (with fixed scales).
+   storage: CHF_FP32, CHF_BF16 or CHF_FP16 field storage (arithmetic FP32, round to nearest
+   even on store; 16-bit types hold scale * value).  scale_e, scale_h: power-of-two storage
+   scales of E and H (0 = automatic: H at the power of two nearest the wave impedance times the
+   E scale; FP16 puts the Coulomb field of the largest bin charge at one radial width near 2^14).
+   dynamic_scaling (FP16 only): every launch instead picks the largest power-of-two scales that
+   keep a bound on the magnitudes it writes (twice the previous level's maxima, plus the growth
+   one step can add through the curl terms and the source) below 2^14, so fields that grow or
+   decay by orders of magnitude keep FP16 precision; the scales then depend on steps_per_launch.
+   nan_watch: check waveforms for non-finite values every step (reported by chf_rz_sync). */
 typedef struct {
   int32_t bc, vx, waves_per_block, z_chunk, nan_watch, steps_per_launch;
+  int32_t storage, dynamic_scaling;
+  double scale_e, scale_h;
 } chf_rz_exec;
 
 typedef struct chf_rz_plan chf_rz_plan;
@@ -85,8 +95,8 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
 
 void chf_rz_plan_destroy(chf_rz_plan *plan);
 
-/* Bytes of device workspace: E_r, E_z, H_phi in two time levels ([nz][pitch] FP32 each) and
-   the small tables. */
+/* Bytes of device workspace: E_r, E_z, H_phi in two time levels ([nz][pitch] of the storage
+   type each) and the small tables. */
 chf_status chf_rz_workspace_bytes(const chf_rz_plan *plan, uint64_t *bytes);
 
 /* Bind caller-owned DEVICE memory (>= the reported size, 256-byte aligned), upload the tables
@@ -122,9 +132,11 @@ chf_status chf_rz_get_field(chf_rz_plan *plan, void *stream, int32_t comp, float
 chf_status chf_rz_set_field(chf_rz_plan *plan, void *stream, int32_t comp, const float *in_dev);
 
 typedef struct {
-  int32_t vx, waves_per_block, z_chunk, pitch, n_blocks, n_src, steps_per_launch, pad0;
+  int32_t vx, waves_per_block, z_chunk, pitch, n_blocks, n_src, steps_per_launch, storage;
+  int32_t dynamic_scaling, pad0;
   uint64_t field_bytes, workspace_bytes;
   double bytes_per_cell_update; /* algorithmic HBM bytes per node of one pass (one launch) */
+  double scale_e, scale_h;      /* fixed storage scales (the initial ones with dynamic scaling) */
 } chf_rz_info;
 chf_status chf_rz_get_info(const chf_rz_plan *plan, chf_rz_info *info);
 

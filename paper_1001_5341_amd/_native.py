@@ -95,15 +95,18 @@ class RZObservers(ct.Structure):
 
 class RZExec(ct.Structure):
     _fields_ = [("bc", ct.c_int32), ("vx", ct.c_int32), ("waves_per_block", ct.c_int32),
-                ("z_chunk", ct.c_int32), ("nan_watch", ct.c_int32), ("steps_per_launch", ct.c_int32)]
+                ("z_chunk", ct.c_int32), ("nan_watch", ct.c_int32), ("steps_per_launch", ct.c_int32),
+                ("storage", ct.c_int32), ("dynamic_scaling", ct.c_int32), ("scale_e", ct.c_double),
+                ("scale_h", ct.c_double)]
 
 
 class RZInfo(ct.Structure):
     _fields_ = [("vx", ct.c_int32), ("waves_per_block", ct.c_int32), ("z_chunk", ct.c_int32),
                 ("pitch", ct.c_int32), ("n_blocks", ct.c_int32), ("n_src", ct.c_int32),
-                ("steps_per_launch", ct.c_int32), ("pad0", ct.c_int32),
+                ("steps_per_launch", ct.c_int32), ("storage", ct.c_int32),
+                ("dynamic_scaling", ct.c_int32), ("pad0", ct.c_int32),
                 ("field_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
-                ("bytes_per_cell_update", ct.c_double)]
+                ("bytes_per_cell_update", ct.c_double), ("scale_e", ct.c_double), ("scale_h", ct.c_double)]
 
 
 class FarFieldParams(ct.Structure):

@@ -26,11 +26,15 @@
 // is thus one kernel launch.
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/chfdtd_rz.h"
@@ -52,7 +56,15 @@ struct RDev {
   int nr, nz, pitch, zchunk, nrb, n_blocks, n_gblocks, wv;
   int nrb2, n_waves2, n_blocks2;  // two-step launches: overlapped waves of 62*VX stored nodes
   float ca, db_dr, db_dz, cb_dz;
-  float *f[2][3];          // [level][E_r, E_z, H_phi]
+  void *f[2][3];           // [level][E_r, E_z, H_phi], element type = the storage type
+  // 16-bit storage keeps scale * physical value (FP32 stores physical values): fixed scales, or
+  // (dyn) scales chosen by every launch from the maxima of the level it reads
+  float s_e, s_h;
+  int dyn;
+  float *lvl_scale;        // [2 levels][2] (s_e, s_h) of the values a level slot holds
+  unsigned *maxes;         // [3][2] max |E|, max |H| (FP32 bits) of a level, by launch index mod 3
+  float ge, gh, target;    // per-step growth bounds (E from H, H from E); largest stored value aimed at
+  double src_bound;        // Cb v max W_r e^{dz^2/8 sigma_z^2} / dz (source increment per unit charge)
   const float *cp, *cm;    // [pitch]
   // source
   int src_on, n_bins, n_src;
@@ -110,6 +122,10 @@ struct chf_rz_plan {
   char *ws = nullptr;
   RDev dev{};
   int parity = 0, n_done = 0;
+  int li = 0;                 // launches since the reset (dynamic-scale slots)
+  int storage = CHF_FP32, elem = 4;
+  double scale_e = 1.0, scale_h = 1.0;
+  uint64_t off_scale = 0;
   hipGraphExec_t graph = nullptr;
   const void *graph_w = nullptr, *graph_q = nullptr;
 };
@@ -143,6 +159,137 @@ __device__ __forceinline__ void st(float *p, const float (&o)[N], bool on) {
   *reinterpret_cast<F<N> *>(p) = x;
 }
 
+// Field storage: FP32 holds physical values; 16-bit types hold scale * value, rounded to
+// nearest even on the store.
+template <typename T>
+__device__ __forceinline__ float to_f(T x) { return static_cast<float>(x); }
+template <typename T>
+__device__ __forceinline__ T from_f(float x) { return static_cast<T>(x); }
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) V {
+  T v[N];
+};
+
+template <typename T>
+constexpr bool kF32 = std::is_same<T, float>::value;
+
+template <typename T, int N>
+__device__ __forceinline__ void ldf(const T *p, float (&o)[N], bool on, float inv) {
+  if (on) {
+    const V<T, N> x = *reinterpret_cast<const V<T, N> *>(p);
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = kF32<T> ? to_f<T>(x.v[v]) : to_f<T>(x.v[v]) * inv;
+  } else {
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = 0.f;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ float lds(const T *p, float inv) {
+  return kF32<T> ? to_f<T>(*p) : to_f<T>(*p) * inv;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void stf(T *p, const float (&o)[N], bool on, float s) {
+  if (!on) return;
+  V<T, N> x;
+#pragma unroll
+  for (int v = 0; v < N; v++) x.v[v] = from_f<T>(kF32<T> ? o[v] : o[v] * s);
+  *reinterpret_cast<V<T, N> *>(p) = x;
+}
+
+// the value a store with scale s followed by a load returns
+template <typename T, int N>
+__device__ __forceinline__ void as_stored(float (&o)[N], float s, float inv) {
+  if constexpr (!kF32<T>) {
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = to_f<T>(from_f<T>(o[v] * s)) * inv;
+  }
+}
+
+// Scales of one launch: inverse scales of the level read, scales of the level written.
+struct Sc {
+  float ei, hi, eo, ho;
+};
+
+__device__ __forceinline__ float pow2_floor(float x) { return exp2f(floorf(log2f(x))); }
+
+// Bound on the source's E_z increment over `n` steps from `step`, for the dynamic scale bound:
+// Cb v |Q(z_s)| max W_r max W_z, where max W_z <= e^{dz^2 / 8 sigma_z^2} / dz because the
+// normalising window always holds a row within dz/2 of z_s (src_bound = Cb v max W_r times that).
+__device__ float source_peak(const RDev &d, int step, int n, const double *q) {
+  if (!d.src_on || d.n_src <= 0) return 0.f;
+  double peak = 0.0;
+  const double *qb = q ? q : d.q_bins;
+  for (int t = 0; t < n; t++) {
+    const double tt = (step + t + 0.5) * d.dt;
+    if (tt < d.t_entry) continue;
+    const double u = (d.z_entry + d.v_src * (tt - d.t_entry) - d.z_bin0) / d.dz_bin;
+    const double fl = floor(u);
+    const int b0 = (int)fl;
+    const double fr = u - fl;
+    double qz = 0.0;
+    if (b0 >= 0 && b0 < d.n_bins) qz += (1.0 - fr) * qb[b0];
+    if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) qz += fr * qb[b0 + 1];
+    peak = fmax(peak, fabs(qz));
+  }
+  return (float)(peak * d.src_bound);
+}
+
+// Launch li (reading level par, advancing n steps): static scales, or (dyn) the scales of the
+// level read from lvl_scale and, for the level written, the largest power of two keeping the
+// bound B on its magnitudes below `target`: B_E = 2 max|E| + n ge max|H| + 2 n (source peak),
+// B_H = 2 max|H| + n gh B_E (maxima of the level read, slot li mod 3).  Every wave computes the
+// same values.
+__device__ __forceinline__ Sc launch_scales(const RDev &d, int par, int li, int step, int n, const double *q,
+                                           int lane) {
+  if (!d.dyn) return Sc{1.f / d.s_e, 1.f / d.s_h, d.s_e, d.s_h};
+  const float se_in = d.lvl_scale[2 * par], sh_in = d.lvl_scale[2 * par + 1];
+  const unsigned *mx = d.maxes + 2 * (li % 3);
+  const float me = __uint_as_float(mx[0]), mh = __uint_as_float(mx[1]);
+  const float pk = source_peak(d, step, n, q);
+  const float be = 2.f * me + n * d.ge * mh + 2.f * n * pk;
+  const float bh = 2.f * mh + n * d.gh * be;
+  const float cap = 1.0e30f;
+  const float se = be > 0.f ? fminf(pow2_floor(d.target / be), cap) : 1.f;
+  const float sh = bh > 0.f ? fminf(pow2_floor(d.target / bh), cap) : 1.f;
+  return Sc{1.f / se_in, 1.f / sh_in, se, sh};
+}
+
+// dyn bookkeeping at the start of launch li (one thread of the grid): publish the written level's
+// scales and clear the maxima slot the next launch but one will fill.
+__device__ __forceinline__ void publish_scales(const RDev &d, int par, int li, const Sc &sc) {
+  d.lvl_scale[2 * (par ^ 1)] = sc.eo;
+  d.lvl_scale[2 * (par ^ 1) + 1] = sc.ho;
+  d.maxes[2 * ((li + 2) % 3)] = 0u;
+  d.maxes[2 * ((li + 2) % 3) + 1] = 0u;
+}
+
+// wave maximum of two values, then at most one atomic per value and wave into the slot of the
+// level written
+__device__ __forceinline__ void record_max(const RDev &d, int li, float me, float mh, int lane) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) {
+    me = fmaxf(me, __shfl_xor(me, k));
+    mh = fmaxf(mh, __shfl_xor(mh, k));
+  }
+  if (lane == 0) {  // the atomic only where it raises the maximum: thousands of waves share the words
+    unsigned *mx = d.maxes + 2 * ((li + 1) % 3);
+    const unsigned ue = __float_as_uint(me), uh = __float_as_uint(mh);
+    if (ue > *(volatile unsigned *)mx) atomicMax(mx, ue);
+    if (uh > *(volatile unsigned *)(mx + 1)) atomicMax(mx + 1, uh);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ float amax(const float (&a)[N], float m) {
+#pragma unroll
+  for (int v = 0; v < N; v++) m = fmaxf(m, fabsf(a[v]));
+  return m;
+}
+
 // H' = H - db/dz dEr + db/dr dEz (the order every kernel and tile shape uses)
 __device__ __forceinline__ float h_node(float h, float d_er, float d_ez, const RDev &d) {
   return fmaf(d.db_dr, d_ez, fmaf(-d.db_dz, d_er, h));
@@ -151,8 +298,9 @@ __device__ __forceinline__ float h_node(float h, float d_er, float d_ez, const R
 // Observer sampling of level `par` into waveform column `column`: eight observers per wave,
 // lane = 8*observer + 4*component + corner; each lane forms weight * E in FP64 and two
 // butterflies sum the corners.
+template <typename T>
 __device__ __forceinline__ void gather_wave(const RDev &d, int par, double *w, int column, int ld, int o0,
-                                            int lane) {
+                                            int lane, float inv_e) {
   const int o = o0 + (lane >> 3);
   const int comp = (lane >> 2) & 1, a = lane & 1, b = (lane >> 1) & 1;
   double val = 0.0;
@@ -161,7 +309,7 @@ __device__ __forceinline__ void gather_wave(const RDev &d, int par, double *w, i
     const double *tf = d.obs_t + (o * 2 + comp) * 2;
     const double wgt = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]);
     const long long node = (long long)(ix[1] + b) * d.pitch + ix[0] + a;
-    val = wgt * (double)d.f[par][comp][node];
+    val = wgt * (double)lds<T>((const T *)d.f[par][comp] + node, inv_e);
   }
   val += __shfl_xor(val, 1);
   val += __shfl_xor(val, 2);
@@ -174,9 +322,10 @@ __device__ __forceinline__ void gather_wave(const RDev &d, int par, double *w, i
 // The work a launch does for its predecessor: sample the level it starts from into column gcol,
 // and sum the stencil samples a two-step launch took of its intermediate level (buffer sb) into
 // column scol, corners added in the order the gather uses.
+template <typename T>
 __device__ __forceinline__ void pending_wave(const RDev &d, int par, double *w, int ld, int gcol, int scol, int sb,
-                                             int o0, int lane) {
-  if (gcol >= 0) gather_wave(d, par, w, gcol, ld, o0, lane);
+                                             int o0, int lane, float inv_e) {
+  if (gcol >= 0) gather_wave<T>(d, par, w, gcol, ld, o0, lane, inv_e);
   if (scol >= 0) {
     const int o = o0 + (lane >> 1), comp = lane & 1;
     if (lane < 16 && o < d.n_obs) {
@@ -264,16 +413,18 @@ __device__ __forceinline__ void right_of(const float (&a)[VX], float (&r)[VX]) {
 // moving source is subtracted from E_z by the lanes that own its nodes, and the Mur value of E_z
 // on the r wall by the lane that owns the wall (the host adds k_rz_mur_r when the wall is the
 // first node of a wave).
-template <int VX>
+template <typename T, int VX>
 __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, const double *q, double *w,
-                                                 int gcol, int scol, int sb, int ldw) {
+                                                 int gcol, int scol, int sb, int ldw, int li) {
   const int n_all = d.n_blocks + d.n_gblocks;
   const int per = (n_all + 7) >> 3;  // hardware block b runs on XCD b % 8
   const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (logical >= n_all) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const Sc sc = launch_scales(d, par, li, step, 1, q, lane);
+  if (d.dyn && blockIdx.x == 0 && threadIdx.x == 0) publish_scales(d, par, li, sc);
   if (logical >= d.n_blocks) {
-    pending_wave(d, par, w, ldw, gcol, scol, sb, ((logical - d.n_blocks) * d.wv + wv) * 8, lane);
+    pending_wave<T>(d, par, w, ldw, gcol, scol, sb, ((logical - d.n_blocks) * d.wv + wv) * 8, lane, sc.ei);
     return;
   }
   const int rb = logical % d.nrb, zc = logical / d.nrb;
@@ -284,8 +435,9 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
   const int nr = d.nr, nz = d.nz;
   const int k0 = zc * d.zchunk, k1 = min(k0 + d.zchunk, nz - 1);
   const long long P = d.pitch;
-  const float *Er = d.f[par][0], *Ez = d.f[par][1], *Hp = d.f[par][2];
-  float *Ero = d.f[par ^ 1][0], *Ezo = d.f[par ^ 1][1], *Hpo = d.f[par ^ 1][2];
+  const T *Er = (const T *)d.f[par][0], *Ez = (const T *)d.f[par][1], *Hp = (const T *)d.f[par][2];
+  T *Ero = (T *)d.f[par ^ 1][0], *Ezo = (T *)d.f[par ^ 1][1], *Hpo = (T *)d.f[par ^ 1][2];
+  float mx_e = 0.f, mx_h = 0.f;  // magnitudes written (dyn)
   const bool halo_l = lane == 0 && c0 > 0;          // lane 0 recomputes H(c0-1)
   const bool halo_r = lane == 63 && c0 + VX < nr;   // lane 63 reads E_z(c0+VX)
 
@@ -305,31 +457,31 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
   if (k0 > 0) {
     const int kb = k0 - 1;
     float erb[VX], ezb[VX], hb[VX];
-    ld<VX>(Er + kb * P + c0, erb, on);
-    ld<VX>(Er + k0 * P + c0, er_k, on);
-    ld<VX>(Ez + kb * P + c0, ezb, on);
-    ld<VX>(Hp + kb * P + c0, hb, on);
+    ldf<T, VX>(Er + kb * P + c0, erb, on, sc.ei);
+    ldf<T, VX>(Er + k0 * P + c0, er_k, on, sc.ei);
+    ldf<T, VX>(Ez + kb * P + c0, ezb, on, sc.ei);
+    ldf<T, VX>(Hp + kb * P + c0, hb, on, sc.hi);
     float ezr = __shfl_down(ezb[0], 1);
-    if (lane == 63) ezr = halo_r ? Ez[kb * P + c0 + VX] : 0.f;
+    if (lane == 63) ezr = halo_r ? lds<T>(Ez + kb * P + c0 + VX, sc.ei) : 0.f;
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       const float e1 = v + 1 < VX ? ezb[v + 1] : ezr;
       hn_b[v] = live[v] ? h_node(hb[v], er_k[v] - erb[v], e1 - ezb[v], d) : hb[v];
     }
   } else {
-    ld<VX>(Er + c0, er_k, on);
+    ldf<T, VX>(Er + c0, er_k, on, sc.ei);
 #pragma unroll
     for (int v = 0; v < VX; v++) hn_b[v] = 0.f;
   }
-  if (halo_l) erl_k = Er[k0 * P + c0 - 1];
+  if (halo_l) erl_k = lds<T>(Er + k0 * P + c0 - 1, sc.ei);
 
   for (int k = k0; k < k1; k++) {  // k <= nz-2
     float er1[VX], ez[VX], h[VX];
-    ld<VX>(Er + (k + 1) * P + c0, er1, on);
-    ld<VX>(Ez + k * P + c0, ez, on);
-    ld<VX>(Hp + k * P + c0, h, on);
+    ldf<T, VX>(Er + (k + 1) * P + c0, er1, on, sc.ei);
+    ldf<T, VX>(Ez + k * P + c0, ez, on, sc.ei);
+    ldf<T, VX>(Hp + k * P + c0, h, on, sc.hi);
     float ezr = __shfl_down(ez[0], 1);
-    if (lane == 63) ezr = halo_r ? Ez[k * P + c0 + VX] : 0.f;
+    if (lane == 63) ezr = halo_r ? lds<T>(Ez + k * P + c0 + VX, sc.ei) : 0.f;
     float hn[VX];
 #pragma unroll
     for (int v = 0; v < VX; v++) {
@@ -342,7 +494,7 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
       hl = 0.f;
       if (halo_l) {
         const long long c = k * P + c0 - 1;
-        const float h_l = Hp[c], ez_l = Ez[c], er1_l = Er[c + P];
+        const float h_l = lds<T>(Hp + c, sc.hi), ez_l = lds<T>(Ez + c, sc.ei), er1_l = lds<T>(Er + c + P, sc.ei);
         hl = h_node(h_l, er1_l - erl_k, ez[0] - ez_l, d);
         erl_k = er1_l;
       }
@@ -357,23 +509,29 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
     }
     sub_source<VX>(d, S, k, c0, ezo);
     if (wall_wave) mur_r<VX>(d, vw, wall_here, ezo, ez);
-    st<VX>(Hpo + k * P + c0, hn, on);
-    if (k >= 1) st<VX>(Ero + k * P + c0, ero, on);
-    st<VX>(Ezo + k * P + c0, ezo, on);
+    stf<T, VX>(Hpo + k * P + c0, hn, on, sc.ho);
+    if (k >= 1) stf<T, VX>(Ero + k * P + c0, ero, on, sc.eo);
+    stf<T, VX>(Ezo + k * P + c0, ezo, on, sc.eo);
+    if (d.dyn) {
+      mx_h = amax<VX>(hn, mx_h);
+      mx_e = amax<VX>(ezo, amax<VX>(ero, mx_e));
+    }
     if (k == 1) {  // z = 0 wall from row 1
       float w0v[VX];
-      ld<VX>(Er + c0, w0v, on);
+      ldf<T, VX>(Er + c0, w0v, on, sc.ei);
 #pragma unroll
       for (int v = 0; v < VX; v++)
         if (d.mur && live[v]) w0v[v] = fmaf(d.mur_kz, ero[v] - w0v[v], er_k[v]);
-      st<VX>(Ero + c0, w0v, on);
+      stf<T, VX>(Ero + c0, w0v, on, sc.eo);
+      if (d.dyn) mx_e = amax<VX>(w0v, mx_e);
     }
     if (k == nz - 2) {  // z = z_max wall from row nz-2
       float w1v[VX];
 #pragma unroll
       for (int v = 0; v < VX; v++)
         w1v[v] = d.mur && live[v] ? fmaf(d.mur_kz, ero[v] - er1[v], er_k[v]) : er1[v];
-      st<VX>(Ero + (k + 1) * P + c0, w1v, on);
+      stf<T, VX>(Ero + (k + 1) * P + c0, w1v, on, sc.eo);
+      if (d.dyn) mx_e = amax<VX>(w1v, mx_e);
     }
 #pragma unroll
     for (int v = 0; v < VX; v++) {
@@ -381,6 +539,7 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
       hn_b[v] = hn[v];
     }
   }
+  if (d.dyn) record_max(d, li, mx_e, mx_h, lane);
 }
 
 // Two steps in one launch (temporal blocking).  Waves overlap: wave g covers the 64*VX nodes from
@@ -390,16 +549,20 @@ __global__ void __launch_bounds__(512) k_rz_step(RDev d, int par, int step, cons
 // intermediate level never reaches HBM: its observer-stencil values are written, weighted, to
 // the sample buffer sb (summed by the next launch).  Per node and step the arithmetic is that of
 // k_rz_step, so the two kernels give the same bits.
-template <int VX>
+template <typename T, int VX>
 __global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, const double *q, double *w,
-                                                  int gcol, int scol, int sb_in, int sb_out, int ldw) {
+                                                  int gcol, int scol, int sb_in, int sb_out, int ldw, int li) {
   const int n_all = d.n_blocks2 + d.n_gblocks;
   const int per = (n_all + 7) >> 3;
   const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (logical >= n_all) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // both steps store with the written level's scales; the intermediate level is rounded as a
+  // store and load with them would round it
+  const Sc sc = launch_scales(d, par, li, step, 2, q, lane);
+  if (d.dyn && blockIdx.x == 0 && threadIdx.x == 0) publish_scales(d, par, li, sc);
   if (logical >= d.n_blocks2) {
-    pending_wave(d, par, w, ldw, gcol, scol, sb_in, ((logical - d.n_blocks2) * d.wv + wv) * 8, lane);
+    pending_wave<T>(d, par, w, ldw, gcol, scol, sb_in, ((logical - d.n_blocks2) * d.wv + wv) * 8, lane, sc.ei);
     return;
   }
   const int rb = logical % d.nrb2, zc = logical / d.nrb2;
@@ -413,8 +576,10 @@ __global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, con
   const int k0 = zc * d.zchunk, k1 = min(k0 + d.zchunk, nz - 1);  // stage-2 rows [k0, k1)
   const int m0 = max(0, k0 - 2);
   const long long P = d.pitch;
-  const float *Er = d.f[par][0], *Ez = d.f[par][1], *Hp = d.f[par][2];
-  float *Ero = d.f[par ^ 1][0], *Ezo = d.f[par ^ 1][1], *Hpo = d.f[par ^ 1][2];
+  const T *Er = (const T *)d.f[par][0], *Ez = (const T *)d.f[par][1], *Hp = (const T *)d.f[par][2];
+  T *Ero = (T *)d.f[par ^ 1][0], *Ezo = (T *)d.f[par ^ 1][1], *Hpo = (T *)d.f[par ^ 1][2];
+  const float mi_e = 1.f / sc.eo, mi_h = 1.f / sc.ho;  // intermediate level: stored with the out scales
+  float mx_e = 0.f, mx_h = 0.f;
 
   float cp[VX], cm[VX];
   ld<VX>(d.cp + c0, cp, on);
@@ -430,15 +595,19 @@ __global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, con
   double *samp = d.samp + (long long)sb_out * 8 * d.n_obs;
 
   float er_in[VX];                     // E_r^n(m)
-  float er1_b[VX], ez1_b[VX], h1_b[VX];  // stage 1 of row m-1
+  float er1_b[VX], ez1_b[VX], h1_b[VX];  // stage 1 of row m-1 (as stored)
+  float h1u_b[VX];                     // stage-1 H of row m-1 before rounding (stage 1's own E_r)
   float h2_b[VX];                      // stage 2 H of row j-1
-  ld<VX>(Er + m0 * P + c0, er_in, on);
+  float er1w0[VX];                     // stage-1 E_r of the z = 0 wall row (chunks from row 0 or 1)
+  ldf<T, VX>(Er + m0 * P + c0, er_in, on, sc.ei);
 #pragma unroll
   for (int v = 0; v < VX; v++) {
     er1_b[v] = 0.f;
     ez1_b[v] = 0.f;
     h1_b[v] = 0.f;
+    h1u_b[v] = 0.f;
     h2_b[v] = 0.f;
+    er1w0[v] = 0.f;
   }
 
   for (int m = m0; m <= k1; m++) {
@@ -446,37 +615,51 @@ __global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, con
     float er1[VX], ez1[VX], h1[VX], er1n[VX];
     if (m <= nz - 2) {
       float ez[VX], h[VX], e1[VX];
-      ld<VX>(Er + (m + 1) * P + c0, er1n, on);
-      ld<VX>(Ez + m * P + c0, ez, on);
-      ld<VX>(Hp + m * P + c0, h, on);
+      ldf<T, VX>(Er + (m + 1) * P + c0, er1n, on, sc.ei);
+      ldf<T, VX>(Ez + m * P + c0, ez, on, sc.ei);
+      ldf<T, VX>(Hp + m * P + c0, h, on, sc.hi);
       right_of<VX>(ez, e1);
 #pragma unroll
       for (int v = 0; v < VX; v++) h1[v] = live[v] ? h_node(h[v], er1n[v] - er_in[v], e1[v] - ez[v], d) : h[v];
       const float hl = __shfl_up(h1[VX - 1], 1);
 #pragma unroll
       for (int v = 0; v < VX; v++) {
-        er1[v] = live[v] && m >= 1 ? fmaf(-d.cb_dz, h1[v] - h1_b[v], d.ca * er_in[v]) : er_in[v];
+        er1[v] = live[v] && m >= 1 ? fmaf(-d.cb_dz, h1[v] - h1u_b[v], d.ca * er_in[v]) : er_in[v];
         const float hm = v > 0 ? h1[v - 1] : hl;
         ez1[v] = live[v] ? fmaf(-cm[v], hm, fmaf(cp[v], h1[v], d.ca * ez[v])) : ez[v];
       }
       sub_source<VX>(d, S1, m, c0, ez1);
       if (wall_wave) mur_r<VX>(d, vw, wall_here, ez1, ez);
-    } else {  // m == nz-1: only the E_r wall row, from row nz-2
-      float ein_b[VX];
-      ld<VX>(Er + (nz - 2) * P + c0, ein_b, on);
+      if (m == nz - 2) {  // stage-1 z = z_max wall row from the new row nz-2, kept in er1n
+#pragma unroll
+        for (int v = 0; v < VX; v++)
+          er1n[v] = d.mur && live[v] ? fmaf(d.mur_kz, er1[v] - er1n[v], er_in[v]) : er1n[v];
+      }
+    } else {  // m == nz-1: only the E_r wall row, formed with row nz-2
 #pragma unroll
       for (int v = 0; v < VX; v++) {
-        er1[v] = d.mur && live[v] ? fmaf(d.mur_kz, er1_b[v] - er_in[v], ein_b[v]) : er_in[v];
+        er1[v] = er_in[v];
         ez1[v] = 0.f;
         h1[v] = 0.f;
         er1n[v] = 0.f;
       }
     }
-    if (m == 1 && m0 == 0) {  // stage-1 z = 0 wall from row 1 (er1_b holds E_r^n(0) copied)
+    if (m == 1 && m0 == 0) {  // stage-1 z = 0 wall from the new row 1 (er1_b holds E_r^n(0))
 #pragma unroll
       for (int v = 0; v < VX; v++)
         if (d.mur && live[v]) er1_b[v] = fmaf(d.mur_kz, er1[v] - er1_b[v], er_in[v]);
+      as_stored<T, VX>(er1_b, sc.eo, mi_e);
+#pragma unroll
+      for (int v = 0; v < VX; v++) er1w0[v] = er1_b[v];
     }
+    // stage-1 row m as the next step would read it from a stored level (its own E_r update above
+    // used H unrounded, as a one-step launch does within its step)
+    float h1u[VX];
+#pragma unroll
+    for (int v = 0; v < VX; v++) h1u[v] = h1[v];
+    as_stored<T, VX>(er1, sc.eo, mi_e);
+    as_stored<T, VX>(ez1, sc.eo, mi_e);
+    as_stored<T, VX>(h1, sc.ho, mi_h);
     // ---- stage 2 (step n+1 -> n+2), row j = m-1
     const int j = m - 1;
     if (j >= max(0, k0 - 1)) {
@@ -495,25 +678,27 @@ __global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, con
         }
         sub_source<VX>(d, S2, j, c0, ez2);
         if (wall_wave) mur_r<VX>(d, vw, wall_here, ez2, ez1_b);
-        st<VX>(Hpo + j * P + c0, h2, outl);
-        if (j >= 1) st<VX>(Ero + j * P + c0, er2, outl);
-        st<VX>(Ezo + j * P + c0, ez2, outl);
-        if (j == 1) {  // stage-2 z = 0 wall: E_r^{n+1}(0) again from the input level
-          float ein0[VX], ein1[VX], wv0[VX];
-          ld<VX>(Er + c0, ein0, on);
-          ld<VX>(Er + P + c0, ein1, on);
+        stf<T, VX>(Hpo + j * P + c0, h2, outl, sc.ho);
+        if (j >= 1) stf<T, VX>(Ero + j * P + c0, er2, outl, sc.eo);
+        stf<T, VX>(Ezo + j * P + c0, ez2, outl, sc.eo);
+        if (d.dyn && outl) {
+          mx_h = amax<VX>(h2, mx_h);
+          mx_e = amax<VX>(ez2, amax<VX>(er2, mx_e));
+        }
+        if (j == 1) {  // stage-2 z = 0 wall, with the stage-1 wall row kept since row 1
+          float wv0[VX];
 #pragma unroll
-          for (int v = 0; v < VX; v++) {
-            const float e10 = d.mur && live[v] ? fmaf(d.mur_kz, er1_b[v] - ein0[v], ein1[v]) : ein0[v];
-            wv0[v] = d.mur && live[v] ? fmaf(d.mur_kz, er2[v] - e10, er1_b[v]) : e10;
-          }
-          st<VX>(Ero + c0, wv0, outl);
+          for (int v = 0; v < VX; v++)
+            wv0[v] = d.mur && live[v] ? fmaf(d.mur_kz, er2[v] - er1w0[v], er1_b[v]) : er1w0[v];
+          stf<T, VX>(Ero + c0, wv0, outl, sc.eo);
+          if (d.dyn && outl) mx_e = amax<VX>(wv0, mx_e);
         }
         if (j == nz - 2) {  // stage-2 z = z_max wall
           float wv1[VX];
 #pragma unroll
           for (int v = 0; v < VX; v++) wv1[v] = d.mur && live[v] ? fmaf(d.mur_kz, er2[v] - er1[v], er1_b[v]) : er1[v];
-          st<VX>(Ero + (j + 1) * P + c0, wv1, outl);
+          stf<T, VX>(Ero + (j + 1) * P + c0, wv1, outl, sc.eo);
+          if (d.dyn && outl) mx_e = amax<VX>(wv1, mx_e);
         }
         // observer stencil nodes of the intermediate level on row j (and on row nz-1 with it)
         for (int pass = 0; pass < (j == nz - 2 ? 2 : 1); pass++) {
@@ -544,24 +729,65 @@ __global__ void __launch_bounds__(512) k_rz_step2(RDev d, int par, int step, con
       er1_b[v] = er1[v];
       ez1_b[v] = ez1[v];
       h1_b[v] = h1[v];
+      h1u_b[v] = h1u[v];
     }
   }
+  if (d.dyn) record_max(d, li, mx_e, mx_h, lane);
 }
 
 // Mur value of E_z on the r wall (rows 0..nz-2) for single-step tilings whose wall node starts a
 // wave.
-__global__ void k_rz_mur_r(RDev d, int par) {
+template <typename T>
+__global__ void k_rz_mur_r(RDev d, int par, int li) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.nz - 1) return;
   const long long c0 = k * (long long)d.pitch + d.nr - 1, c1 = c0 - 1;
-  const float *Ein = d.f[par][1];
-  float *Eout = d.f[par ^ 1][1];
-  Eout[c0] = fmaf(d.mur_kr, Eout[c1] - Ein[c0], Ein[c1]);
+  const T *Ein = (const T *)d.f[par][1];
+  T *Eout = (T *)d.f[par ^ 1][1];
+  const float si = d.dyn ? 1.f / d.lvl_scale[2 * par] : 1.f / d.s_e;
+  const float so = d.dyn ? d.lvl_scale[2 * (par ^ 1)] : d.s_e;
+  const float e = fmaf(d.mur_kr, lds<T>(Eout + c1, 1.f / so) - lds<T>(Ein + c0, si), lds<T>(Ein + c1, si));
+  Eout[c0] = from_f<T>(kF32<T> ? e : e * so);
+  if (d.dyn) atomicMax(d.maxes + 2 * ((li + 1) % 3), __float_as_uint(fabsf(e)));
 }
 
 // The last launch's pending work, after the last step of a call.
+template <typename T>
 __global__ void __launch_bounds__(64) k_rz_finish(RDev d, int par, double *w, int gcol, int scol, int sb, int ld) {
-  pending_wave(d, par, w, ld, gcol, scol, sb, blockIdx.x * 8, threadIdx.x);
+  const float inv_e = d.dyn ? 1.f / d.lvl_scale[2 * par] : 1.f / d.s_e;
+  pending_wave<T>(d, par, w, ld, gcol, scol, sb, blockIdx.x * 8, threadIdx.x, inv_e);
+}
+
+// Largest |E| and |H| of a level into maxes slot `slot` (dyn, after fields were set directly).
+template <typename T>
+__global__ void k_rz_levelmax(RDev d, int par, int slot) {
+  const long long n = (long long)d.nz * d.pitch;
+  const float ie = d.dyn ? 1.f / d.lvl_scale[2 * par] : 1.f, ih = d.dyn ? 1.f / d.lvl_scale[2 * par + 1] : 1.f;
+  float me = 0.f, mh = 0.f;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    me = fmaxf(me, fmaxf(fabsf(lds<T>((const T *)d.f[par][0] + t, ie)), fabsf(lds<T>((const T *)d.f[par][1] + t, ie))));
+    mh = fmaxf(mh, fabsf(lds<T>((const T *)d.f[par][2] + t, ih)));
+  }
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) {
+    me = fmaxf(me, __shfl_xor(me, k));
+    mh = fmaxf(mh, __shfl_xor(mh, k));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(d.maxes + 2 * slot, __float_as_uint(me));
+    atomicMax(d.maxes + 2 * slot + 1, __float_as_uint(mh));
+  }
+}
+
+// Initial scales and maxima (reset): level slots scaled by 1 until a launch sets them.
+__global__ void k_rz_init_scales(RDev d) {
+  const int t = threadIdx.x;
+  if (t < 4) d.lvl_scale[t] = 1.f;
+  if (t < 6) d.maxes[t] = 0u;
+}
+
+__global__ void k_rz_clear_slot(RDev d, int slot) {
+  if (threadIdx.x < 2) d.maxes[2 * slot + threadIdx.x] = 0u;
 }
 
 __global__ void k_rz_zero(uint4 *p, long long n) {
@@ -569,13 +795,18 @@ __global__ void k_rz_zero(uint4 *p, long long n) {
     p[t] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-__global__ void k_rz_copy(const float *src, float *dst, int nr, int nz, int pitch, int to_dense) {
+// Dense FP32 [nz][nr] physical values <-> a stored component of level `par`.
+template <typename T>
+__global__ void k_rz_copy(RDev d, int par, int comp, const float *src, float *dst, int to_dense) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= (long long)nr * nz) return;
+  const int nr = d.nr;
+  if (t >= (long long)nr * d.nz) return;
   const int i = (int)(t % nr);
   const long long k = t / nr;
-  if (to_dense) dst[t] = src[k * pitch + i];
-  else dst[k * pitch + i] = src[t];
+  T *f = (T *)d.f[par][comp];
+  const float s = d.dyn ? d.lvl_scale[2 * par + (comp == 2)] : (comp == 2 ? d.s_h : d.s_e);
+  if (to_dense) dst[t] = lds<T>(f + k * d.pitch + i, 1.f / s);
+  else f[k * d.pitch + i] = from_f<T>(kF32<T> ? src[t] : src[t] * s);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -586,10 +817,11 @@ struct Pending {
 };
 
 // One launch: `two` steps (k_rz_step2) or one (k_rz_step, plus the r-wall Mur kernel in the
-// wave-start tiling).  Updates `pend` to what this launch leaves.
-hipError_t launch_rz(const chf_rz_plan &p, const RDev &d, int par, int step, bool two, const double *q, double *w,
-                     int col, int ld, Pending &pend, int &samp_par, hipStream_t s, hipEvent_t ev_a = nullptr,
-                     hipEvent_t ev_b = nullptr) {
+// wave-start tiling), launch index li since the reset.  Updates `pend` to what this launch leaves.
+template <typename T>
+hipError_t launch_rz_t(const chf_rz_plan &p, const RDev &d, int par, int step, bool two, const double *q,
+                       double *w, int col, int ld, Pending &pend, int &samp_par, int li, hipStream_t s,
+                       hipEvent_t ev_a, hipEvent_t ev_b) {
   hipError_t e = hipSuccess;
   if (ev_a) e = hipEventRecord(ev_a, s);
   if (e != hipSuccess) return e;
@@ -598,8 +830,8 @@ hipError_t launch_rz(const chf_rz_plan &p, const RDev &d, int par, int step, boo
   if (two) {
     const int sb_out = samp_par ^ 1;
     const dim3 grid(8 * ((p.n_blocks2 + d.n_gblocks + 7) / 8));
-    if (p.vx == 4) k_rz_step2<4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, sb_out, ld);
-    else k_rz_step2<8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, sb_out, ld);
+    if (p.vx == 4) k_rz_step2<T, 4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, sb_out, ld, li);
+    else k_rz_step2<T, 8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, sb_out, ld, li);
     samp_par = sb_out;
     pend.scol = col;
     pend.sb = sb_out;
@@ -607,10 +839,10 @@ hipError_t launch_rz(const chf_rz_plan &p, const RDev &d, int par, int step, boo
   } else {
     const dim3 grid(8 * ((p.n_blocks + d.n_gblocks + 7) / 8));
     switch (p.vx) {
-      case 1: k_rz_step<1><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
-      case 2: k_rz_step<2><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
-      case 4: k_rz_step<4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
-      default: k_rz_step<8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld); break;
+      case 1: k_rz_step<T, 1><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld, li); break;
+      case 2: k_rz_step<T, 2><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld, li); break;
+      case 4: k_rz_step<T, 4><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld, li); break;
+      default: k_rz_step<T, 8><<<grid, block, 0, s>>>(d, par, step, q, w, gcol, scol, pend.sb, ld, li); break;
     }
     pend.scol = -1;
     pend.gcol = col;
@@ -619,15 +851,31 @@ hipError_t launch_rz(const chf_rz_plan &p, const RDev &d, int par, int step, boo
   if (ev_b) e = hipEventRecord(ev_b, s);
   if (e != hipSuccess) return e;
   if (!two && d.mur && p.mur_r_kernel) {
-    k_rz_mur_r<<<(d.nz - 1 + 255) / 256, 256, 0, s>>>(d, par);
+    k_rz_mur_r<T><<<(d.nz - 1 + 255) / 256, 256, 0, s>>>(d, par, li);
     e = hipGetLastError();
   }
   return e;
 }
 
-hipError_t launch_rz_finish(const RDev &d, int par, double *w, const Pending &pend, int ld, hipStream_t s) {
+hipError_t launch_rz(const chf_rz_plan &p, const RDev &d, int par, int step, bool two, const double *q, double *w,
+                     int col, int ld, Pending &pend, int &samp_par, int li, hipStream_t s, hipEvent_t ev_a = nullptr,
+                     hipEvent_t ev_b = nullptr) {
+  switch (p.storage) {
+    case CHF_BF16: return launch_rz_t<__hip_bfloat16>(p, d, par, step, two, q, w, col, ld, pend, samp_par, li, s, ev_a, ev_b);
+    case CHF_FP16: return launch_rz_t<__half>(p, d, par, step, two, q, w, col, ld, pend, samp_par, li, s, ev_a, ev_b);
+    default: return launch_rz_t<float>(p, d, par, step, two, q, w, col, ld, pend, samp_par, li, s, ev_a, ev_b);
+  }
+}
+
+hipError_t launch_rz_finish(const chf_rz_plan &p, const RDev &d, int par, double *w, const Pending &pend, int ld,
+                            hipStream_t s) {
   if (d.n_obs <= 0 || !w || (pend.gcol < 0 && pend.scol < 0)) return hipSuccess;
-  k_rz_finish<<<(d.n_obs + 7) / 8, 64, 0, s>>>(d, par, w, pend.gcol, pend.scol, pend.sb, ld);
+  const dim3 grid((d.n_obs + 7) / 8);
+  switch (p.storage) {
+    case CHF_BF16: k_rz_finish<__hip_bfloat16><<<grid, 64, 0, s>>>(d, par, w, pend.gcol, pend.scol, pend.sb, ld); break;
+    case CHF_FP16: k_rz_finish<__half><<<grid, 64, 0, s>>>(d, par, w, pend.gcol, pend.scol, pend.sb, ld); break;
+    default: k_rz_finish<float><<<grid, 64, 0, s>>>(d, par, w, pend.gcol, pend.scol, pend.sb, ld); break;
+  }
   return hipGetLastError();
 }
 
@@ -638,6 +886,23 @@ hipError_t launch_rz_zero(const chf_rz_plan &p, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_rz_zero<<<1, 64, 0, s>>>((uint4 *)(p.ws + p.off_nan), 16);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_rz_init_scales<<<1, 64, 0, s>>>(p.dev);
+  return hipGetLastError();
+}
+
+// Maxima of the current level into the slot the next launch reads (dynamic scaling, after the
+// fields were set directly).
+hipError_t launch_rz_levelmax(const chf_rz_plan &p, hipStream_t s) {
+  const int slot = p.li % 3;
+  k_rz_clear_slot<<<1, 64, 0, s>>>(p.dev, slot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (p.storage) {
+    case CHF_BF16: k_rz_levelmax<__hip_bfloat16><<<1024, 256, 0, s>>>(p.dev, p.parity, slot); break;
+    case CHF_FP16: k_rz_levelmax<__half><<<1024, 256, 0, s>>>(p.dev, p.parity, slot); break;
+    default: k_rz_levelmax<float><<<1024, 256, 0, s>>>(p.dev, p.parity, slot); break;
+  }
   return hipGetLastError();
 }
 
@@ -667,6 +932,11 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   if (wv != 1 && wv != 2 && wv != 4 && wv != 8) return fail(CHF_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
   if (zchunk < 1) return fail(CHF_EINVAL, "z_chunk must be >= 1");
   const int spl = ex->steps_per_launch ? ex->steps_per_launch : (vx >= 4 ? 2 : 1);
+  if (ex->storage != CHF_FP32 && ex->storage != CHF_BF16 && ex->storage != CHF_FP16)
+    return fail(CHF_EINVAL, "unknown storage type");
+  if (ex->dynamic_scaling && ex->storage != CHF_FP16)
+    return fail(CHF_EINVAL, "dynamic scaling is for FP16 storage");
+  if (!(ex->scale_e >= 0) || !(ex->scale_h >= 0)) return fail(CHF_EINVAL, "negative storage scale");
   if (spl != 1 && spl != 2) return fail(CHF_EINVAL, "steps_per_launch must be 1 or 2");
   if (spl == 2 && vx < 4) return fail(CHF_EINVAL, "two steps per launch need vx 4 or 8");
   const bool src_on = src->n_bins > 0;
@@ -803,7 +1073,9 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   }
 
   // workspace layout: 6 field arrays first (zeroed together), then the tables
-  const uint64_t fbytes = align256(elems * sizeof(float));
+  p->storage = ex->storage;
+  p->elem = ex->storage == CHF_FP32 ? 4 : 2;
+  const uint64_t fbytes = align256(elems * (uint64_t)p->elem);
   uint64_t off = 0;
   for (int l = 0; l < 2; l++)
     for (int c = 0; c < 3; c++) {
@@ -825,6 +1097,8 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   off = align256(off + p->ot.size() * sizeof(double));
   p->off_nan = off;
   off = align256(off + 256);
+  p->off_scale = off;  // level scales [2][2] floats, then maxima [3][2] uints
+  off = align256(off + 64);
   p->off_rowptr = off;
   off = align256(off + p->row_ptr.size() * sizeof(int));
   p->off_ent = off;
@@ -866,6 +1140,35 @@ chf_status chf_rz_plan_create(const chf_rz_grid *grid, const chf_medium *medium,
   D.dt = g.dt;
   D.cb = p->cb;
   D.mur = ex->bc == CHF_BC_MUR1;
+  // storage scales: stored = scale * physical.  H is kept at the power of two nearest the wave
+  // impedance times the E scale; FP16 puts the Coulomb field of the largest bin charge at one
+  // radial width near 2^14 (static), or rescales every launch (dynamic).
+  {
+    const double eta = std::sqrt(mu / eps);
+    const double pow2_eta = std::ldexp(1.0, (int)std::lround(std::log2(eta)));
+    double se = 1.0;
+    if (ex->storage == CHF_FP16 && src_on) {
+      double qmax = 0.0;
+      for (double qv : p->q_bins) qmax = std::max(qmax, std::fabs(qv));
+      const double e_est = qmax / (4.0 * kPi * eps * src->sigma_r * src->sigma_r);
+      if (e_est > 0) se = std::ldexp(1.0, (int)std::floor(std::log2(16384.0 / e_est)));
+    }
+    if (ex->scale_e > 0) se = ex->scale_e;
+    const double sh = ex->scale_h > 0 ? ex->scale_h : se * pow2_eta;
+    p->scale_e = ex->storage == CHF_FP32 ? 1.0 : se;
+    p->scale_h = ex->storage == CHF_FP32 ? 1.0 : sh;
+    D.s_e = (float)p->scale_e;
+    D.s_h = (float)p->scale_h;
+    D.dyn = ex->dynamic_scaling ? 1 : 0;
+    double gmax = 2.0 * p->cb / g.dz;
+    for (int i = 0; i <= g.nr - 2; i++) gmax = std::max(gmax, (double)p->cp[i] + (double)p->cm[i]);
+    D.ge = (float)gmax;
+    D.gh = (float)(2.0 * (p->db / g.dr + p->db / g.dz));
+    D.target = 16384.f;
+    D.src_bound = src_on ? p->cb * src->beta * kC0 * p->wr[0] *
+                               std::exp(g.dz * g.dz / (8.0 * src->sigma_z * src->sigma_z)) / g.dz
+                         : 0.0;
+  }
   D.mur_kr = (float)((v * g.dt - g.dr) / (v * g.dt + g.dr));
   D.mur_kz = (float)((v * g.dt - g.dz) / (v * g.dt + g.dz));
   D.n_obs = obs->n_obs;
@@ -892,6 +1195,7 @@ chf_status chf_rz_reset(chf_rz_plan *p, void *stream) {
   if (e != hipSuccess) return hip_fail(e, "reset");
   p->parity = 0;
   p->n_done = 0;
+  p->li = 0;
   return CHF_OK;
 }
 
@@ -903,8 +1207,6 @@ chf_status chf_rz_bind_workspace(chf_rz_plan *p, void *dev_ptr, uint64_t bytes, 
   char *ws = (char *)dev_ptr;
   p->ws = ws;
   RDev &D = p->dev;
-  for (int l = 0; l < 2; l++)
-    for (int c = 0; c < 3; c++) D.f[l][c] = (float *)(ws + p->off_f[l][c]);
   D.cp = (const float *)(ws + p->off_cp);
   D.cm = (const float *)(ws + p->off_cm);
   D.wr = (const double *)(ws + p->off_wr);
@@ -916,6 +1218,10 @@ chf_status chf_rz_bind_workspace(chf_rz_plan *p, void *dev_ptr, uint64_t bytes, 
   D.ent = (const int2 *)(ws + p->off_ent);
   D.ent_w = (const double *)(ws + p->off_entw);
   D.samp = (double *)(ws + p->off_samp);
+  D.lvl_scale = (float *)(ws + p->off_scale);
+  D.maxes = (unsigned *)(ws + p->off_scale + 16);
+  for (int l = 0; l < 2; l++)
+    for (int c = 0; c < 3; c++) D.f[l][c] = ws + p->off_f[l][c];
   struct Up {
     uint64_t off;
     const void *src;
@@ -955,15 +1261,16 @@ static chf_status rz_forward(chf_rz_plan *p, void *stream, const double *q, doub
   Pending pend;  // each launch samples its predecessor's results
   for (int t = 0, li = 0; t < n_steps; li++) {
     const bool two = p->spl == 2 && t + 1 < n_steps;
-    hipError_t e = launch_rz(*p, d, p->parity, p->n_done, two, q, w, first_column + t, ld, pend, p->samp_par, s,
-                             ev ? (*ev)[2 * li] : nullptr, ev ? (*ev)[2 * li + 1] : nullptr);
+    hipError_t e = launch_rz(*p, d, p->parity, p->n_done, two, q, w, first_column + t, ld, pend, p->samp_par,
+                             p->li, s, ev ? (*ev)[2 * li] : nullptr, ev ? (*ev)[2 * li + 1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "step launch");
+    p->li++;
     p->parity ^= 1;
     p->n_done += two ? 2 : 1;
     t += two ? 2 : 1;
     if (n_launches) *n_launches = li + 1;
   }
-  hipError_t e = launch_rz_finish(d, p->parity, w, pend, ld, s);
+  hipError_t e = launch_rz_finish(*p, d, p->parity, w, pend, ld, s);
   if (e != hipSuccess) return hip_fail(e, "gather launch");
   return CHF_OK;
 }
@@ -1020,15 +1327,16 @@ chf_status chf_rz_forward_graph(chf_rz_plan *p, void *stream, const double *q, d
     RDev d = p->dev;
     if (!p->ex.nan_watch) d.nan_flag = nullptr;
     hipError_t le = launch_rz_zero(*p, cs);
-    int par = 0, sp = p->samp_par;
+    int par = 0, sp = p->samp_par, li = 0;
     Pending pend;
     for (int t = 0; t < T && le == hipSuccess;) {
       const bool two = p->spl == 2 && t + 1 < T;
-      le = launch_rz(*p, d, par, t, two, q, w, t, T, pend, sp, cs);
+      le = launch_rz(*p, d, par, t, two, q, w, t, T, pend, sp, li, cs);
       par ^= 1;
+      li++;
       t += two ? 2 : 1;
     }
-    if (le == hipSuccess) le = launch_rz_finish(d, par, w, pend, T, cs);
+    if (le == hipSuccess) le = launch_rz_finish(*p, d, par, w, pend, T, cs);
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(cs, &gr);
     (void)hipStreamDestroy(cs);
@@ -1051,6 +1359,7 @@ chf_status chf_rz_forward_graph(chf_rz_plan *p, void *stream, const double *q, d
   const int launches = p->spl == 2 ? T / 2 + (T & 1) : T;
   p->parity = launches & 1;
   p->n_done = T;
+  p->li = launches;
   return CHF_OK;
 }
 
@@ -1073,12 +1382,17 @@ static chf_status rz_copy(chf_rz_plan *p, void *stream, int comp, const float *s
   if (!p || comp < 0 || comp > 2 || !(to_dense ? (const void *)dst : (const void *)src))
     return fail(CHF_EINVAL, "bad argument");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
-  float *f = p->dev.f[p->parity][comp];
   const long long n = (long long)p->g.nr * p->g.nz;
   if ((n + 255) / 256 > 0x7fffffffLL) return fail(CHF_EUNSUPPORTED, "field too large to copy in one launch");
-  k_rz_copy<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(to_dense ? f : src, to_dense ? dst : f,
-                                                                         p->g.nr, p->g.nz, p->pitch, to_dense);
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  switch (p->storage) {
+    case CHF_BF16: k_rz_copy<__hip_bfloat16><<<g, 256, 0, s>>>(p->dev, p->parity, comp, src, dst, to_dense); break;
+    case CHF_FP16: k_rz_copy<__half><<<g, 256, 0, s>>>(p->dev, p->parity, comp, src, dst, to_dense); break;
+    default: k_rz_copy<float><<<g, 256, 0, s>>>(p->dev, p->parity, comp, src, dst, to_dense); break;
+  }
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !to_dense && p->dev.dyn) e = launch_rz_levelmax(*p, s);
   return e == hipSuccess ? CHF_OK : hip_fail(e, "field copy");
 }
 
@@ -1099,10 +1413,14 @@ chf_status chf_rz_get_info(const chf_rz_plan *p, chf_rz_info *info) {
   info->n_blocks = p->n_blocks;
   info->n_src = p->n_src;
   info->steps_per_launch = p->spl;
+  info->storage = p->storage;
+  info->dynamic_scaling = p->dev.dyn;
   info->pad0 = 0;
+  info->scale_e = p->scale_e;
+  info->scale_h = p->scale_h;
   info->field_bytes = p->field_bytes;
   info->workspace_bytes = p->ws_bytes;
-  info->bytes_per_cell_update = 6.0 * sizeof(float);  // read E_r, E_z, H; write all three
+  info->bytes_per_cell_update = 6.0 * p->elem;  // read E_r, E_z, H; write all three
   return CHF_OK;
 }
 

@@ -331,7 +331,8 @@ def waveforms(q_bins: torch.Tensor, plan: "Plan", checkpoint_every: Optional[int
 
 
 # ---------------------------------------------------------------- axisymmetric (r, z) solver
-def rz_descriptors(w, vx=0, waves=0, zchunk=0, nan_watch=False, q_bins=None, steps_per_launch=0):
+def rz_descriptors(w, vx=0, waves=0, zchunk=0, nan_watch=False, q_bins=None, steps_per_launch=0,
+                   storage="fp32", dynamic_scaling=False, scale_e=0.0, scale_h=0.0):
     """C descriptor structs for an RZWorkload.  Returns (structs, keepalive)."""
     q = np.ascontiguousarray(w.q_bins if q_bins is None else q_bins, dtype=np.float64)
     obs = np.ascontiguousarray(w.obs_rz, dtype=np.float64).reshape(-1, 2)
@@ -340,7 +341,8 @@ def rz_descriptors(w, vx=0, waves=0, zchunk=0, nan_watch=False, q_bins=None, ste
     s = N.RZSource(w.z_entry, w.t_entry, w.beta, w.sigma_r, w.sigma_z, w.cut_sigmas,
                    len(q) if w.src_on else 0, 0, w.z_bin0, w.dz_bin, _dp(q))
     o = N.RZObservers(obs.shape[0], 0, _dp(obs))
-    e = N.RZExec(N.BC[w.bc], vx, waves, zchunk, 1 if nan_watch else 0, steps_per_launch)
+    e = N.RZExec(N.BC[w.bc], vx, waves, zchunk, 1 if nan_watch else 0, steps_per_launch, N.STORAGE[storage],
+                 1 if dynamic_scaling else 0, scale_e, scale_h)
     return (g, m, s, o, e), (q, obs)
 
 
@@ -361,11 +363,14 @@ class RZPlan:
     """
 
     def __init__(self, w, vx: int = 0, waves: int = 0, zchunk: int = 0, nan_watch: bool = False,
-                 steps_per_launch: int = 0, device=None):
+                 steps_per_launch: int = 0, storage: str = "fp32", dynamic_scaling: bool = False,
+                 scale_e: float = 0.0, scale_h: float = 0.0, device=None):
         self.w = w
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self._h = create_rz_plan_handle(w, vx=vx, waves=waves, zchunk=zchunk, nan_watch=nan_watch,
-                                        steps_per_launch=steps_per_launch)
+                                        steps_per_launch=steps_per_launch, storage=storage,
+                                        dynamic_scaling=dynamic_scaling, scale_e=scale_e, scale_h=scale_h)
+        self.storage = storage
         L = N.lib()
         nbytes = ct.c_uint64()
         N.check(L.chf_rz_workspace_bytes(self._h, ct.byref(nbytes)), "chf_rz_workspace_bytes")

@@ -233,3 +233,55 @@ def test_wall_at_wave_start_and_source_at_wall(nr, vx, sigma_r):
             assert rel_l2(plan.get_field(comp).cpu().numpy(), want) <= TOL, comp
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp16", 2e-2), ("bf16", 1e-1)])
+def test_16bit_storage_against_oracle(small_mur, storage, tol):
+    """FP32 arithmetic on FP16 / BF16 fields (fixed power-of-two scales), against the FP64 oracle."""
+    w = small_mur
+    ref = oracle_run(w)[0]
+    plan = solver.RZPlan(w, storage=storage)
+    try:
+        got = plan.run().cpu().numpy()
+        info = plan.info()
+    finally:
+        plan.close()
+    err = rel_l2(got, ref)
+    print(f"{storage}: rel L2 {err:.3e}, scales {info['scale_e']} {info['scale_h']}", flush=True)
+    assert np.isfinite(got).all() and err <= tol
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_16bit_one_and_two_steps_per_launch_bitwise(small_mur, storage):
+    """With fixed scales the two-step kernel rounds its intermediate level exactly as a store and
+    load would, so one and two steps per launch give the same bits."""
+    w = small_mur.replace(n_steps=301)
+    outs = []
+    for spl, waves, zc in ((1, 4, 32), (2, 2, 9)):
+        plan = solver.RZPlan(w, storage=storage, steps_per_launch=spl, waves=waves, zchunk=zc)
+        try:
+            outs.append((plan.run().cpu(), torch.stack([plan.get_field(c) for c in range(3)]).cpu()))
+        finally:
+            plan.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+def test_fp16_dynamic_scaling(small_mur):
+    """Per-launch scales chosen from the previous level's maxima: within the FP16 tolerance of the
+    oracle from the automatic start, and still there when the fixed scale would be far too small
+    (a 2^-32 fixed scale flushes the fields to zero in FP16)."""
+    w = small_mur
+    ref = oracle_run(w)[0]
+    res = {}
+    for name, kw in (("dynamic", dict(dynamic_scaling=True)), ("dynamic-2", dict(dynamic_scaling=True, steps_per_launch=1)),
+                     ("static-tiny", dict(scale_e=2.0 ** -32, scale_h=2.0 ** -24))):
+        plan = solver.RZPlan(w, storage="fp16", **kw)
+        try:
+            got = plan.run().cpu().numpy()
+        finally:
+            plan.close()
+        res[name] = rel_l2(got, ref) if np.isfinite(got).all() else float("inf")
+    print(res, flush=True)
+    assert res["dynamic"] <= 2e-2 and res["dynamic-2"] <= 2e-2
+    assert res["static-tiny"] > 0.5

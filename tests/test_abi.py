@@ -181,3 +181,34 @@ def test_rz_radial_stability_constant():
         C = np.diag((i + 0.5) / a) - np.diag(((i - 0.5) / a)[1:], k=-1)
         lam = np.max(np.linalg.eigvals(-C @ D).real)
         assert 4.0 < lam < 4.85
+
+
+def test_rz_storage_and_scaling_validation():
+    w = W.rz_small()
+    assert _rz_status(w, storage="bf16") == "CHF_OK"
+    assert _rz_status(w, storage="fp16", dynamic_scaling=True) == "CHF_OK"
+    assert _rz_status(w, storage="bf16", dynamic_scaling=True) == "CHF_EINVAL"
+    assert _rz_status(w, dynamic_scaling=True) == "CHF_EINVAL"           # FP32 needs no scales
+    assert _rz_status(w, storage="fp16", scale_e=-1.0) == "CHF_EINVAL"
+    assert _rz_status(w, vx=2, steps_per_launch=2) == "CHF_EINVAL"       # two steps need vx >= 4
+    assert _rz_status(w, vx=2, steps_per_launch=1) == "CHF_OK"
+
+
+def test_rz_plan_info_reports_storage_and_scales():
+    """Automatic scales: BF16 keeps E unscaled and H at the power of two nearest the wave
+    impedance of ice (about 212 ohm -> 256); FP16 scales E by a power of two as well."""
+    import ctypes as ct
+
+    w = W.rz_small()
+    for storage, exp_bytes in (("fp32", 24.0), ("bf16", 12.0), ("fp16", 12.0)):
+        h = solver.create_rz_plan_handle(w, storage=storage)
+        try:
+            info = N.RZInfo()
+            N.check(N.lib().chf_rz_get_info(h, ct.byref(info)), "info")
+        finally:
+            N.lib().chf_rz_plan_destroy(h)
+        assert info.bytes_per_cell_update == exp_bytes
+        if storage == "bf16":
+            assert info.scale_e == 1.0 and info.scale_h == 256.0
+        if storage == "fp16":
+            assert np.log2(info.scale_e) == int(np.log2(info.scale_e)) and info.scale_h == 256.0 * info.scale_e

@@ -62,6 +62,7 @@ struct orc_state {
   double *psi_e[3][3], *psi_h[3][3]; /* [field component][derivative axis] */
   double *wr;                        /* radial weights on the Ez (i,j) lattice */
   double ca, cb, db, v_med, v_src;
+  double *ca_map[3], *cb_map[3];     /* per-E-node coefficients of a permittivity map, or NULL */
   int32_t n;
 };
 
@@ -317,7 +318,7 @@ orc_state *orc_create(const orc_cfg *cfg) {
 void orc_destroy(orc_state *s) {
   if (!s) return;
   for (int f = 0; f < 6; f++) free(s->f[f]);
-  for (int f = 0; f < 3; f++) free(s->eold[f]);
+  for (int f = 0; f < 3; f++) { free(s->eold[f]); free(s->ca_map[f]); free(s->cb_map[f]); }
   for (int f = 0; f < 3; f++)
     for (int u = 0; u < 3; u++) { free(s->psi_e[f][u]); free(s->psi_h[f][u]); }
   for (int u = 0; u < 3; u++) pml_axis_free(&s->ax[u]);
@@ -327,6 +328,32 @@ void orc_destroy(orc_state *s) {
 
 double *orc_field(orc_state *s, int comp) { return (comp >= 0 && comp < 6) ? s->f[comp] : NULL; }
 int32_t orc_step_index(const orc_state *s) { return s->n; }
+
+/* A heterogeneous medium: Ampere's law with conductivity keeps its form node by node, so each E
+   node takes Ca and Cb from the relative permittivity of its own position.  The CPML grading and
+   the Mur coefficients keep the configuration's uniform eps_r (they belong to the absorber). */
+int orc_set_eps_map(orc_state *s, const double *eps_r_map) {
+  for (int f = 0; f < 3; f++) {
+    free(s->ca_map[f]);
+    free(s->cb_map[f]);
+    s->ca_map[f] = s->cb_map[f] = NULL;
+  }
+  if (!eps_r_map) return 0;
+  for (size_t t = 0; t < 3 * s->ncell; t++)
+    if (!(eps_r_map[t] > 0)) { set_err("bad permittivity map"); return -1; }
+  for (int f = 0; f < 3; f++) {
+    s->ca_map[f] = malloc(sizeof(double) * s->ncell);
+    s->cb_map[f] = malloc(sizeof(double) * s->ncell);
+    if (!s->ca_map[f] || !s->cb_map[f]) { set_err("out of memory"); orc_set_eps_map(s, NULL); return -1; }
+    for (size_t t = 0; t < s->ncell; t++) {
+      double eps = eps0() * eps_r_map[f * s->ncell + t];
+      double loss = s->c.sigma * s->c.dt / (2.0 * eps);
+      s->ca_map[f][t] = (1.0 - loss) / (1.0 + loss);
+      s->cb_map[f][t] = (s->c.dt / eps) / (1.0 + loss);
+    }
+  }
+  return 0;
+}
 
 /* ------------------------------------------------------------ updates */
 #define EX(i, j, k) s->f[0][IDX(s, i, j, k)]
@@ -436,7 +463,9 @@ void orc_update_e(orc_state *s) {
         double dhy_dz = (HY(i, j, k) - HY(i, j, k - 1)) / dz;
         double ty = pml_term(s, s->psi_e[0][1], 1, j, 0, i, j, k, dhz_dy);
         double tz = pml_term(s, s->psi_e[0][2], 2, k, 0, i, j, k, dhy_dz);
-        EX(i, j, k) = ca * EX(i, j, k) + cb * (ty - tz);
+        size_t id = IDX(s, i, j, k);
+        double a = s->ca_map[0] ? s->ca_map[0][id] : ca, b = s->cb_map[0] ? s->cb_map[0][id] : cb;
+        EX(i, j, k) = a * EX(i, j, k) + b * (ty - tz);
       }
   /* Ey(i, j+1/2, k) */
 #pragma omp parallel for schedule(static)
@@ -447,7 +476,9 @@ void orc_update_e(orc_state *s) {
         double dhz_dx = (HZ(i, j, k) - HZ(i - 1, j, k)) / dx;
         double tz = pml_term(s, s->psi_e[1][2], 2, k, 0, i, j, k, dhx_dz);
         double tx = pml_term(s, s->psi_e[1][0], 0, i, 0, i, j, k, dhz_dx);
-        EY(i, j, k) = ca * EY(i, j, k) + cb * (tz - tx);
+        size_t id = IDX(s, i, j, k);
+        double a = s->ca_map[1] ? s->ca_map[1][id] : ca, b = s->cb_map[1] ? s->cb_map[1][id] : cb;
+        EY(i, j, k) = a * EY(i, j, k) + b * (tz - tx);
       }
   /* Ez(i, j, k+1/2), with the shower current J_z = v Q(z_s) W_r(i,j) W_z(k) */
   double wz[64], vq = 0.0;
@@ -467,7 +498,9 @@ void orc_update_e(orc_state *s) {
         double ty = pml_term(s, s->psi_e[2][1], 1, j, 0, i, j, k, dhx_dy);
         double j_src = 0.0;
         if (k >= klo && k < klo + m) j_src = vq * s->wr[(size_t)j * nx + i] * wz[k - klo];
-        EZ(i, j, k) = ca * EZ(i, j, k) + cb * (tx - ty - j_src);
+        size_t id = IDX(s, i, j, k);
+        double a = s->ca_map[2] ? s->ca_map[2][id] : ca, b = s->cb_map[2] ? s->cb_map[2][id] : cb;
+        EZ(i, j, k) = a * EZ(i, j, k) + b * (tx - ty - j_src);
       }
   if (s->c.bc == ORC_BC_MUR1) mur_faces(s);
   s->n += 1;
@@ -507,9 +540,12 @@ void orc_step(orc_state *s, double *w) {
   if (w) orc_sample(s, w);
 }
 
-int orc_run(const orc_cfg *cfg, double *waveforms) {
+int orc_run(const orc_cfg *cfg, double *waveforms) { return orc_run_eps(cfg, NULL, waveforms); }
+
+int orc_run_eps(const orc_cfg *cfg, const double *eps_r_map, double *waveforms) {
   orc_state *s = orc_create(cfg);
   if (!s) return -1;
+  if (orc_set_eps_map(s, eps_r_map)) { orc_destroy(s); return -1; }
   int no = cfg->n_obs, T = cfg->n_steps;
   double *w = malloc(sizeof(double) * (no > 0 ? 3 * no : 1));
   if (!w) { orc_destroy(s); return -1; }

@@ -74,8 +74,15 @@ void orc_step(orc_state *s, double *w);
 /* J_z at half step n+1/2 on the whole Ez lattice (nx*ny*nz, zero elsewhere). */
 void orc_source_current(const orc_state *s, int32_t n, double *jz);
 
+/* Relative permittivity per E node, eps_r_map [3][nz][ny][nx] (component-major, each
+   component on its own staggered lattice), replacing the uniform eps_r in the E update only;
+   NULL restores the uniform medium.  0 on success, -1 on a non-positive entry. */
+int orc_set_eps_map(orc_state *s, const double *eps_r_map);
+
 /* Full forward run from zero fields: waveforms [n_obs][3][n_steps]. */
 int orc_run(const orc_cfg *cfg, double *waveforms);
+/* The same with a permittivity map (NULL = uniform). */
+int orc_run_eps(const orc_cfg *cfg, const double *eps_r_map, double *waveforms);
 /* Discrete-adjoint gradient of L with respect to the profile bins, given
    dL/dw [n_obs][3][n_steps]; PEC and CPML boundaries only. */
 int orc_adjoint(const orc_cfg *cfg, const double *dl_dw, double *dl_dq);

@@ -180,6 +180,24 @@ chf_status chf_adjoint_begin(chf_plan *plan, void *stream, double *dl_dq_dev);
 chf_status chf_adjoint_steps(chf_plan *plan, void *stream, const double *dl_dw_dev, double *dl_dq_dev,
                              int32_t t_lo, int32_t t_hi);
 
+/* chf_adjoint_steps that also accumulates the cotangent of the permittivity at every E node: the
+   sensitivity of L to a relative-permittivity map eps_r(x), evaluated at the plan's uniform
+   medium (Ampere's law with conductivity of the Numerical Method section, with eps per node).
+   Each node's Ca and Cb depend on its eps_r only, and dE^{n+1}/deps_r =
+   -(E^{n+1} - E^n)/(eps_r (1 + sigma dt/(2 eps))) whatever the curl, CPML and source terms were
+   (the CPML grading is held fixed), so step n adds -Eb^{n+1} (E^{n+1} - E^n)/(eps_r (1 + ...))
+   with Eb^{n+1} the adjoint state at that point of the reverse step.  This needs the forward E
+   levels in reverse order, which a checkpointed schedule recomputes segment by segment.
+   e_levels_dev: DEVICE FP32 [t_hi - t_lo + 1][3][nz][ny][nx], level m = E^{t_lo + m} of the
+   forward run (components Ex, Ey, Ez, each dense as chf_plan_get_field writes it; E^t is the
+   field after t steps).  dl_deps_dev: DEVICE FP64 [3][nz][ny][nx], dL/deps_r per node,
+   ACCUMULATED (zero it before the first call); nodes tangential to a wall get nothing.  Same
+   step-range rules, storage (FP32) and boundaries (PEC, CPML) as chf_adjoint_steps; dL/dq is
+   accumulated as there, bit for bit.  For the uniform medium with PEC walls, dL/deps_r of the
+   plan is the sum of the map. */
+chf_status chf_adjoint_steps_eps(chf_plan *plan, void *stream, const double *dl_dw_dev, double *dl_dq_dev,
+                                 int32_t t_lo, int32_t t_hi, const float *e_levels_dev, double *dl_deps_dev);
+
 /* Gradients with respect to the source's non-linear parameters (the radial width sigma_r and the
    trajectory offset z_entry of the Simulation Setup section's moving charge snapshot), with the
    profile gradient, from one reverse sweep: J_z enters the E update linearly, so

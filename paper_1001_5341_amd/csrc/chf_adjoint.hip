@@ -140,6 +140,37 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, co
   }
 }
 
+// Permittivity cotangent of step n at every E node.  With eps = eps0 eps_r(node) in Ampere's law
+// with conductivity, Ca and Cb of the node move with eps_r so that
+//   dE^{n+1}/deps_r = -(E^{n+1} - E^n) / (eps_r (1 + l)),   l = sigma dt / (2 eps),
+// whatever the curl, psi and source terms were (they do not depend on eps_r; the absorber's
+// grading is held fixed).  Eb, at this point of the reverse step, is the full cotangent of
+// E^{n+1}, so g += -coef Eb (E^{n+1} - E^n) with coef = 1/(eps_r (1 + l)).  e0/e1 hold E^n and
+// E^{n+1} as dense [3][nz][ny][nx] FP32; g is FP64 in the same layout.  Only nodes the Yee
+// update advances (not tangential to a wall) collect a value.
+__global__ void __launch_bounds__(256) k_adj_eps(Dev d, const float *e0, const float *e1, double *g, double coef) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= d.nx || j >= d.ny) return;
+  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, d.nz);
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const long long N = (long long)nx * ny * nz;
+  for (int k = k0; k < k1; k++) {
+    const long long c = cidx(d, i, j, k);
+    const long long dn = ((long long)k * ny + j) * nx + i;
+    const bool up[3] = {i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2,
+                        i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2,
+                        i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2};
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+      if (!up[u]) continue;
+      const long long t = u * N + dn;
+      const double eb = (double)((const float *)d.e[0][u])[c];
+      g[t] -= coef * eb * ((double)e1[t] - (double)e0[t]);
+    }
+  }
+}
+
 // E update transpose: per-term cotangents into S[0..5] = (Ex-y, Ex-z, Ey-z, Ey-x, Ez-x, Ez-y)
 __global__ void __launch_bounds__(256) k_adj_e(Dev d) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -272,12 +303,14 @@ hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, 
 }
 
 hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step, const double *dl_dw,
-                               double *dl_dq, hipStream_t s, const double *q_dev, double *dl_dtheta) {
+                               double *dl_dq, hipStream_t s, const double *q_dev, double *dl_dtheta,
+                               const EpsTerm *eps) {
   (void)parity;
   const int T = p.grid.n_steps;
   if (d.n_obs > 0) hipLaunchKernelGGL(k_adj_sample, dim3(1), dim3(64), 0, s, d, dl_dw, step, T);
   if (d.src_on) hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(256), 0, s, d, step, dl_dq, q_dev, dl_dtheta);
   dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, (d.nz + kAdjZ - 1) / kAdjZ);
+  if (eps) hipLaunchKernelGGL(k_adj_eps, grid, dim3(256), 0, s, d, eps->e0, eps->e1, eps->g, eps->coef);
   hipLaunchKernelGGL(k_adj_e, grid, dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_adj_hgather, grid, dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_adj_h, grid, dim3(256), 0, s, d);

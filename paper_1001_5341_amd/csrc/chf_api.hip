@@ -745,6 +745,29 @@ chf_status chf_adjoint_steps(chf_plan *p, void *stream, const double *dl_dw_dev,
   return CHF_OK;
 }
 
+chf_status chf_adjoint_steps_eps(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev,
+                                 int32_t t_lo, int32_t t_hi, const float *e_levels_dev, double *dl_deps_dev) {
+  if (!p || !dl_dq_dev || !e_levels_dev || !dl_deps_dev || (p->dev.n_obs > 0 && !dl_dw_dev))
+    return fail(CHF_EINVAL, "NULL argument");
+  if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
+  if (t_lo < 0 || t_lo > t_hi || t_hi > p->grid.n_steps) return fail(CHF_EINVAL, "bad step range");
+  if (p->adj_next < 0 || t_hi != p->adj_next)
+    return fail(CHF_ESTATE, "adjoint steps must continue where the previous call stopped");
+  const long long level = 3LL * p->grid.nx * p->grid.ny * p->grid.nz;
+  const double eps = kEps0 * p->med.eps_r;
+  const double loss = p->med.sigma * p->grid.dt / (2.0 * eps);
+  const double coef = 1.0 / (p->med.eps_r * (1.0 + loss));
+  hipError_t e = hipSuccess;
+  for (int n = t_hi - 1; n >= t_lo && e == hipSuccess; n--) {
+    const chf::EpsTerm term{e_levels_dev + (long long)(n - t_lo) * level,
+                            e_levels_dev + (long long)(n + 1 - t_lo) * level, dl_deps_dev, coef};
+    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, (hipStream_t)stream, nullptr, nullptr, &term);
+  }
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  p->adj_next = t_lo;
+  return CHF_OK;
+}
+
 chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev) {
   if (!p || !dl_dq_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
   chf_status st = chf_adjoint_begin(p, stream, dl_dq_dev);

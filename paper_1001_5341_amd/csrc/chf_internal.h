@@ -147,9 +147,16 @@ hipError_t launch_step(const chf_plan &p, const Dev &d, int parity, int step, co
 hipError_t launch_zero(const chf_plan &p, hipStream_t s);
 hipError_t launch_get_field(const chf_plan &p, int parity, int comp, float *out, hipStream_t s);
 hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float *in, hipStream_t s);
+// forward E levels of one step and the permittivity cotangent they feed (adjoint of eps_r)
+struct EpsTerm {
+  const float *e0, *e1;  // E^n, E^{n+1}: dense [3][nz][ny][nx] FP32
+  double *g;             // dL/deps_r per E node, same layout, FP64, accumulated
+  double coef;           // 1/(eps_r (1 + sigma dt / (2 eps)))
+};
 hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step,
                                const double *dl_dw, double *dl_dq, hipStream_t s,
-                               const double *q_dev = nullptr, double *dl_dtheta = nullptr);
+                               const double *q_dev = nullptr, double *dl_dtheta = nullptr,
+                               const EpsTerm *eps = nullptr);
 hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, int n = -1);
 hipError_t launch_batch_step(const chf_batch &b, int parity, int step, hipStream_t s);
 void set_error(const std::string &msg);

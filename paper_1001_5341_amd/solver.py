@@ -175,6 +175,21 @@ class Plan:
         N.check(N.lib().chf_adjoint_steps(self._h, _stream_handle(stream), ct.c_void_p(dl_dw.data_ptr()),
                                           ct.c_void_p(dl_dq.data_ptr()), t_lo, t_hi), "chf_adjoint_steps")
 
+    def adjoint_steps_eps(self, dl_dw: torch.Tensor, dl_dq: torch.Tensor, t_lo: int, t_hi: int,
+                          e_levels: torch.Tensor, dl_deps: torch.Tensor, stream=None):
+        """adjoint_steps that also accumulates dL/deps_r per E node into dl_deps ([3, nz, ny, nx]
+        FP64) from the forward levels e_levels ([t_hi - t_lo + 1, 3, nz, ny, nx] FP32, level m =
+        E after t_lo + m steps)."""
+        w = self.w
+        assert e_levels.dtype == torch.float32 and e_levels.is_contiguous()
+        assert tuple(e_levels.shape) == (t_hi - t_lo + 1, 3, w.nz, w.ny, w.nx)
+        assert dl_deps.dtype == torch.float64 and dl_deps.is_contiguous()
+        assert tuple(dl_deps.shape) == (3, w.nz, w.ny, w.nx)
+        N.check(N.lib().chf_adjoint_steps_eps(self._h, _stream_handle(stream), ct.c_void_p(dl_dw.data_ptr()),
+                                              ct.c_void_p(dl_dq.data_ptr()), t_lo, t_hi,
+                                              ct.c_void_p(e_levels.data_ptr()), ct.c_void_p(dl_deps.data_ptr())),
+                "chf_adjoint_steps_eps")
+
     # -- snapshots of the whole field + CPML state
     def state_bytes(self) -> int:
         n = ct.c_uint64()
@@ -194,8 +209,13 @@ class Plan:
                 "chf_plan_load_state")
 
     # -- field access (physical units, [nz, ny, nx] FP32)
-    def get_field(self, comp: int, stream=None) -> torch.Tensor:
-        out = torch.empty((self.w.nz, self.w.ny, self.w.nx), dtype=torch.float32, device=self.device)
+    def get_field(self, comp: int, stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Component 0..5 = Ex, Ey, Ez, Hx, Hy, Hz of the current level as [nz, ny, nx] FP32
+        (physical units), into `out` when given (contiguous FP32 of that shape)."""
+        if out is None:
+            out = torch.empty((self.w.nz, self.w.ny, self.w.nx), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (self.w.nz, self.w.ny, self.w.nx)
         N.check(N.lib().chf_plan_get_field(self._h, _stream_handle(stream), comp,
                                            ct.c_void_p(out.data_ptr())), "chf_plan_get_field")
         return out
@@ -295,6 +315,51 @@ def checkpointed_adjoint(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int]
             plan.adjoint_steps(dl_dw, dq, t0, t1, stream)
         plan.sync(stream)
         return dq
+    finally:
+        fwd.close()
+
+
+def eps_sensitivity(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int] = None,
+                    q_bins: Optional[torch.Tensor] = None, stream=None):
+    """dL/deps_r at every E node (the gradient with respect to a relative-permittivity map,
+    evaluated at the plan's uniform medium) and dL/dq, for L = <dl_dw, w>.
+
+    The permittivity is a non-linear parameter: its cotangent at step n reads the forward
+    levels E^n and E^{n+1}, which come back in reverse order by checkpointed recomputation.
+    A forward run on a second workspace keeps a snapshot every `every` steps (default
+    ceil(sqrt(T))); the reverse sweep takes the segments last to first, restores a segment's
+    snapshot, recomputes its steps one by one keeping the E levels (every + 1 levels of
+    3 nx ny nz FP32 values), and runs that segment's transposed steps with the permittivity
+    term.  Returns (dl_deps [3, nz, ny, nx] FP64, dl_dq [n_bins] FP64); for a uniform medium
+    with PEC walls, dL/deps_r of the plan is dl_deps.sum()."""
+    w = plan.w
+    T = plan.n_steps
+    K = max(1, min(T, every or math.ceil(math.sqrt(T))))
+    n_seg = (T + K - 1) // K
+    fwd = Plan(w, storage=plan.storage, device=plan.device)
+    try:
+        nbytes = fwd.state_bytes()
+        snaps = torch.empty((n_seg, nbytes), dtype=torch.uint8, device=plan.device)
+        fwd.reset(stream)
+        for s_ in range(n_seg):
+            fwd.save_state(snaps[s_], stream)
+            fwd.forward(min(K, T - s_ * K), None, 0, q_bins, stream)
+        dl_dw = dl_dw.to(torch.float64).contiguous()
+        dq = torch.zeros(len(w.q_bins), dtype=torch.float64, device=plan.device)
+        g = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float64, device=plan.device)
+        levels = torch.empty((K + 1, 3, w.nz, w.ny, w.nx), dtype=torch.float32, device=plan.device)
+        plan.adjoint_begin(dq, stream)
+        for s_ in reversed(range(n_seg)):
+            t0, t1 = s_ * K, min((s_ + 1) * K, T)
+            fwd.load_state(snaps[s_], t0, stream)
+            for m in range(t1 - t0 + 1):
+                if m:
+                    fwd.forward(1, None, 0, q_bins, stream)
+                for c in range(3):
+                    fwd.get_field(c, stream, out=levels[m, c])
+            plan.adjoint_steps_eps(dl_dw, dq, t0, t1, levels[: t1 - t0 + 1], g, stream)
+        plan.sync(stream)
+        return g, dq
     finally:
         fwd.close()
 

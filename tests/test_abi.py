@@ -139,6 +139,10 @@ def test_snapshot_size_and_adjoint_state_checks():
         assert N.STATUS[N.lib().chf_plan_save_state(h, None, ct.c_void_p(1), ct.byref(step))] == "CHF_ESTATE"
         assert N.STATUS[N.lib().chf_adjoint_steps(h, None, ct.c_void_p(1), ct.c_void_p(1), 0, 5)] == "CHF_ESTATE"
         assert N.STATUS[N.lib().chf_plan_load_state(h, None, None, 0)] == "CHF_EINVAL"
+        one = ct.c_void_p(1)
+        assert N.STATUS[N.lib().chf_adjoint_steps_eps(h, None, one, one, 0, 5, None, one)] == "CHF_EINVAL"
+        assert N.STATUS[N.lib().chf_adjoint_steps_eps(h, None, one, one, 0, 5, one, None)] == "CHF_EINVAL"
+        assert N.STATUS[N.lib().chf_adjoint_steps_eps(h, None, one, one, 0, 5, one, one)] == "CHF_ESTATE"
     finally:
         N.lib().chf_plan_destroy(h)
 

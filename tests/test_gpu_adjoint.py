@@ -151,3 +151,61 @@ def test_source_parameter_gradients_match_oracle_differences(gpu, bc):
     assert np.all(np.abs(dth - fd) <= 2e-4 * np.abs(fd)), (dth, fd)
     ref = oracle.adjoint(w, g)
     assert np.linalg.norm(dq.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-4
+
+
+def _eps_nodes(gmap, rng, n_top=5, n_rand=5):
+    """The largest entries of the map and a few random ones that are not negligible."""
+    flat = np.abs(gmap).ravel()
+    top = np.argsort(flat)[-n_top:]
+    cand = np.flatnonzero(flat > 1e-2 * flat.max())
+    rand = rng.choice(cand, size=min(n_rand, cand.size), replace=False)
+    idx = np.unique(np.concatenate([top, rand]))
+    return [tuple(int(v) for v in np.unravel_index(t, gmap.shape)) for t in idx]
+
+
+@pytest.mark.parametrize("bc", ["cpml", "pec"])
+def test_eps_sensitivity_matches_oracle_differences(gpu, bc):
+    """dL/deps_r per E node (the permittivity-map gradient at the uniform medium) from the
+    checkpointed reverse sweep, against central differences of the FP64 oracle with one node's
+    permittivity moved; with PEC walls the map's sum against the difference quotient of the
+    uniform eps_r; dL/dq of the same sweep bitwise that of the plain adjoint."""
+    w = W.small_shower(seed=8, nx=40, ny=36, nz=64, n_steps=120, n_obs=4, bc=bc, npml=6)
+    banner(f"permittivity sensitivity {bc}")
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal((w.n_obs, 3, w.n_steps))
+    plan = solver.Plan(w)
+    gt = torch.from_numpy(g).to(gpu)
+    gmap, dq = solver.eps_sensitivity(plan, gt, every=37)
+    gmap = gmap.cpu().numpy()
+    ref_dq = plan.adjoint(gt)
+    plan.sync()
+    assert torch.equal(dq, ref_dq)
+    plan.close()
+    # nodes tangential to a wall collect nothing
+    assert np.all(gmap[0][:, 0, :] == 0) and np.all(gmap[2][:, :, 0] == 0) and np.all(gmap[1][0] == 0)
+    nodes = _eps_nodes(gmap, rng)
+    fd = oracle.eps_sensitivity(w, g, nodes, rel_step=1e-6)
+    got = np.array([gmap[n] for n in nodes])
+    err = np.abs(got - fd)
+    print("nodes", nodes, "\nkernel", got, "\noracle", fd, "\nrel err", err / np.abs(fd))
+    assert np.all(err <= 5e-5 * np.abs(fd) + 2e-6 * np.abs(gmap).max()), (got, fd)
+    if bc == "pec":
+        h = 1e-6 * w.eps_r
+        lp = float((g * oracle.run(w.replace(eps_r=w.eps_r + h))).sum())
+        lm = float((g * oracle.run(w.replace(eps_r=w.eps_r - h))).sum())
+        tot = (lp - lm) / (2 * h)
+        print("sum of the map", gmap.sum(), "oracle d/deps_r", tot)
+        assert abs(gmap.sum() - tot) <= 2e-5 * abs(tot), (gmap.sum(), tot)
+
+
+def test_eps_sensitivity_independent_of_segment_length(gpu):
+    """One segment, a ragged split and one step per segment give the same map bit for bit: the
+    recomputed levels and the reverse steps do not depend on the checkpoint schedule."""
+    w = W.small_shower(seed=9, nx=36, ny=32, nz=56, n_steps=90, n_obs=3, bc="cpml", npml=5)
+    banner("permittivity sensitivity schedules")
+    g = torch.from_numpy(np.random.default_rng(7).standard_normal((w.n_obs, 3, w.n_steps))).to(gpu)
+    plan = solver.Plan(w)
+    maps = [solver.eps_sensitivity(plan, g, every=e)[0] for e in (w.n_steps, 29, 1)]
+    plan.close()
+    assert torch.count_nonzero(maps[0]) > 1000
+    assert torch.equal(maps[0], maps[1]) and torch.equal(maps[0], maps[2])

@@ -209,15 +209,21 @@ def roofline(info, fused_ms: float, launches: int):
 
 
 def tile_shape(w, storage: str, args):
-    """(waves, z_chunk): given on the command line, else from the autotuner (cached by shape)."""
+    """(waves, z_chunk, kernel): given on the command line, else from the autotuner (cached by
+    shape; an explicit --kernel keeps its sweep kind with the tuned waves and z chunk)."""
     if args.waves or args.zchunk or args.kernel == "split" or args.no_tune:
-        return args.waves, args.zchunk, False
+        return args.waves, args.zchunk, args.kernel, False
     from paper_1001_5341_amd import autotune
 
     t = autotune.tune(w, storage)
-    log(f"{storage}: tuned tile waves={t['waves']} z_chunk={t['z_chunk']} "
+    kernel = t["kernel"] if args.kernel == "auto" else args.kernel
+    log(f"{storage}: tuned tile waves={t['waves']} z_chunk={t['z_chunk']} kernel={t['kernel']} "
         f"({'cached' if t['cached'] else 'measured'}, {t['ms_per_step']:.3f} ms/step)")
-    return t["waves"], t["z_chunk"], True
+    return t["waves"], t["z_chunk"], kernel, True
+
+
+def kernel_name(info) -> str:
+    return "fused_prefetch" if info["kernel"] == 3 else "fused"
 
 
 def run_variant(w, storage: str, args, n_runs: int, warmup: int):
@@ -225,8 +231,8 @@ def run_variant(w, storage: str, args, n_runs: int, warmup: int):
 
     from paper_1001_5341_amd import solver
 
-    waves, zchunk, tuned = tile_shape(w, storage, args)
-    plan = solver.Plan(w, storage=storage, kernel=args.kernel, rows=args.rows, waves=waves,
+    waves, zchunk, kernel, tuned = tile_shape(w, storage, args)
+    plan = solver.Plan(w, storage=storage, kernel=kernel, rows=args.rows, waves=waves,
                        zchunk=zchunk, device=torch.device("cuda:0"))
     info = plan.info()
     out = plan.new_waveforms()
@@ -425,7 +431,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single-shower")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "split"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused_prefetch", "split"])
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
@@ -445,7 +451,7 @@ def main():
 
     if args.summarize_pmc:
         tile = ([args.vx, args.waves, args.zchunk, args.steps_per_launch] if is_rz(args.workload)
-                else [args.waves, args.zchunk])
+                else [args.waves, args.zchunk, args.kernel if args.kernel == "fused_prefetch" else "fused"])
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.storage,
                       args.pmc_command, tile)
         return
@@ -478,7 +484,8 @@ def main():
     cells = w.nx * w.ny * w.nz
     updates = cells * w.n_steps * args.steps
     roof = roofline(info, fused_ms, launches)
-    roof["traffic"] = (measured_traffic(args.workload, args.storage, [info["waves_per_block"], info["z_chunk"]])
+    roof["traffic"] = (measured_traffic(args.workload, args.storage,
+                                        [info["waves_per_block"], info["z_chunk"], kernel_name(info)])
                        if not args.time_steps else None)
     # whole Yee step (all kernels) against the whole-grid algorithmic bytes, for context
     step_s = ev_s / (args.steps * w.n_steps)
@@ -500,7 +507,8 @@ def main():
         "data": "synthetic (seeded Greisen-like shower profile and observers; no datasets)",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "yee_steps_per_run": w.n_steps,
                    "boundary": f"{w.bc}{w.npml}", "observers": w.n_obs, "storage": args.storage,
-                   "kernel": {1: "split H/E sweeps", 2: "fused sweep (interior + boundary tiles)"}[info["kernel"]],
+                   "kernel": {1: "split H/E sweeps", 2: "fused sweep (interior + boundary tiles)",
+                              3: "fused sweep, interior tiles loading a plane ahead (+ boundary tiles)"}[info["kernel"]],
                    "tile": {"vx": info["vx"], "waves_per_block": info["waves_per_block"],
                             "z_chunk": info["z_chunk"], "autotuned": info["tuned"]},
                    "parallelism": "single GPU"},

@@ -63,7 +63,13 @@ typedef enum {
 /* Field storage (arithmetic is FP32 in every case; BF16 and FP16 round to nearest even). */
 typedef enum { CHF_FP32 = 0, CHF_BF16 = 1, CHF_FP16 = 2 } chf_storage;
 typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
-typedef enum { CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2 } chf_kernel;
+/* CHF_KERNEL_FUSED_PREFETCH: the fused sweep whose interior tiles issue each plane's row loads one
+   plane ahead (the loads of plane k+1 are in flight while plane k is computed), at the price of
+   more registers per wave (3 waves per SIMD instead of 4); rows of at most 256 nodes and
+   waves_per_block 4, 7 or 8.  Boundary tiles and batches use the plain fused sweep.  Same bits. */
+typedef enum {
+  CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2, CHF_KERNEL_FUSED_PREFETCH = 3
+} chf_kernel;
 
 /* Lattice: node counts (>= 3 each; the fused sweep needs nx <= 512), spacings in metres,
    time step in seconds, number of steps. */

@@ -17,7 +17,7 @@ STATUS = {0: "CHF_OK", -1: "CHF_EINVAL", -2: "CHF_ECFL", -3: "CHF_EDOMAIN", -4: 
           -5: "CHF_EHIP", -6: "CHF_ENAN", -7: "CHF_EUNSUPPORTED", -8: "CHF_ESTATE"}
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 BC = {"pec": 0, "mur1": 1, "cpml": 2}
-KERNEL = {"auto": 0, "split": 1, "fused": 2}
+KERNEL = {"auto": 0, "split": 1, "fused": 2, "fused_prefetch": 3}
 
 EXPORTED = [
     "chf_plan_create", "chf_plan_destroy", "chf_plan_workspace_bytes", "chf_plan_bind_workspace",

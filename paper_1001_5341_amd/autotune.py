@@ -1,7 +1,8 @@
 """Tile-shape autotuners (the 3-D fused sweep; the (r, z) step kernels), with a JSON cache.
 
-For one workload shape it times every candidate (waves per workgroup x z chunk) over a short
-run of the real step (interior and boundary sweeps, source, gather) and keeps the fastest.
+For one workload shape it times every candidate (waves per workgroup x z chunk x sweep kind:
+the plain fused sweep, or the one whose interior tiles issue their loads a plane ahead) over a
+short run of the real step (interior and boundary sweeps, source, gather) and keeps the fastest.
 Every candidate must reproduce the first candidate's observer waveforms bit for bit: the
 per-node arithmetic is the same in every tile shape, so a difference means a bug and the
 tuner raises instead of picking it.
@@ -20,7 +21,15 @@ import torch
 from . import _native as N
 from . import solver
 
-CANDIDATES: Tuple[Tuple[int, int], ...] = tuple((w, z) for w in (4, 7, 8, 15) for z in (8, 12, 16, 24, 32))
+# (waves per workgroup, z chunk, kernel)
+CANDIDATES: Tuple[Tuple[int, int, str], ...] = (
+    tuple((w, z, "fused") for w in (4, 7, 8, 15) for z in (8, 12, 16, 24, 32))
+    + tuple((w, z, "fused_prefetch") for w in (7, 8) for z in (8, 12, 16, 24, 32)))
+
+
+def _cand(c) -> Tuple[int, int, str]:
+    c = tuple(c)
+    return c if len(c) == 3 else (c[0], c[1], "fused")
 
 
 def default_cache_path() -> str:
@@ -50,8 +59,8 @@ def _store(path: str, table: dict) -> None:
     os.replace(tmp, path)
 
 
-def _time_candidate(w, storage: str, waves: int, zchunk: int, steps: int, device):
-    plan = solver.Plan(w.replace(n_steps=steps), storage=storage, kernel="fused", waves=waves,
+def _time_candidate(w, storage: str, waves: int, zchunk: int, steps: int, device, kernel: str = "fused"):
+    plan = solver.Plan(w.replace(n_steps=steps), storage=storage, kernel=kernel, waves=waves,
                        zchunk=zchunk, device=device)
     try:
         out = plan.new_waveforms()
@@ -69,7 +78,7 @@ def _time_candidate(w, storage: str, waves: int, zchunk: int, steps: int, device
         plan.sync(stream)
         ms = ev0.elapsed_time(ev1) / steps
         if not torch.equal(out, ref):
-            raise RuntimeError(f"tile shape waves={waves} z_chunk={zchunk}: run-to-run waveforms differ")
+            raise RuntimeError(f"tile shape waves={waves} z_chunk={zchunk} {kernel}: run-to-run waveforms differ")
         return ms, out.cpu(), plan.info()
     finally:
         plan.close()
@@ -78,35 +87,36 @@ def _time_candidate(w, storage: str, waves: int, zchunk: int, steps: int, device
 def tune(w, storage: str = "fp32", steps: int = 48, cache_path: Optional[str] = None,
          candidates: Optional[Sequence[Tuple[int, int]]] = None, use_cache: bool = True,
          device=None) -> dict:
-    """Best (waves_per_block, z_chunk) for this workload shape; cached by shape_key()."""
+    """Best (waves_per_block, z_chunk, kernel) for this workload shape; cached by shape_key().
+    A cache entry without a kernel is the plain fused sweep."""
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     path = cache_path or default_cache_path()
     key = shape_key(w, storage, device)
-    cands = list(candidates or CANDIDATES)
+    cands = [_cand(c) for c in (candidates or CANDIDATES)]
     if use_cache:
         hit = _load(path).get(key)
-        if hit and (hit["waves"], hit["z_chunk"]) in [tuple(c) for c in cands]:
-            return dict(hit, cached=True)
+        if hit and (hit["waves"], hit["z_chunk"], hit.get("kernel", "fused")) in cands:
+            return dict(hit, kernel=hit.get("kernel", "fused"), cached=True)
     steps = max(2, min(steps, w.n_steps))
     trials, ref = [], None
-    for waves, zchunk in cands:
+    for waves, zchunk, kernel in cands:
         try:
-            ms, wave, info = _time_candidate(w, storage, waves, zchunk, steps, device)
+            ms, wave, info = _time_candidate(w, storage, waves, zchunk, steps, device, kernel)
         except N.ChfError as exc:  # shape not valid for this grid (e.g. 8 waves on wide rows)
-            trials.append({"waves": waves, "z_chunk": zchunk, "error": exc.status})
+            trials.append({"waves": waves, "z_chunk": zchunk, "kernel": kernel, "error": exc.status})
             continue
         if ref is None:
             ref = wave
         elif not torch.equal(wave, ref):
-            raise RuntimeError(f"tile shape waves={waves} z_chunk={zchunk} changes the waveforms")
-        trials.append({"waves": waves, "z_chunk": zchunk, "ms_per_step": ms,
+            raise RuntimeError(f"tile shape waves={waves} z_chunk={zchunk} {kernel} changes the waveforms")
+        trials.append({"waves": waves, "z_chunk": zchunk, "kernel": kernel, "ms_per_step": ms,
                        "vx": info["vx"], "bitwise_equal": True})
     timed = [t for t in trials if "ms_per_step" in t]
     if not timed:
         raise RuntimeError(f"no valid tile shape for {key}")
     best = min(timed, key=lambda t: t["ms_per_step"])
-    rec = {"waves": best["waves"], "z_chunk": best["z_chunk"], "ms_per_step": best["ms_per_step"],
-           "steps": steps, "trials": trials}
+    rec = {"waves": best["waves"], "z_chunk": best["z_chunk"], "kernel": best["kernel"],
+           "ms_per_step": best["ms_per_step"], "steps": steps, "trials": trials}
     table = _load(path)
     table[key] = rec
     _store(path, table)
@@ -116,7 +126,7 @@ def tune(w, storage: str = "fp32", steps: int = 48, cache_path: Optional[str] = 
 def tuned_plan(w, storage: str = "fp32", **kw) -> "solver.Plan":
     """A Plan whose fused-sweep tile shape comes from tune()."""
     t = tune(w, storage, **kw)
-    return solver.Plan(w, storage=storage, kernel="fused", waves=t["waves"], zchunk=t["z_chunk"],
+    return solver.Plan(w, storage=storage, kernel=t["kernel"], waves=t["waves"], zchunk=t["z_chunk"],
                        device=kw.get("device"))
 
 

@@ -109,7 +109,7 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       return fail(CHF_EINVAL, "bad CPML grading");
   }
   if (ex->storage < CHF_FP32 || ex->storage > CHF_FP16) return fail(CHF_EINVAL, "bad storage");
-  if (ex->kernel < CHF_KERNEL_AUTO || ex->kernel > CHF_KERNEL_FUSED) return fail(CHF_EINVAL, "bad kernel");
+  if (ex->kernel < CHF_KERNEL_AUTO || ex->kernel > CHF_KERNEL_FUSED_PREFETCH) return fail(CHF_EINVAL, "bad kernel");
   if (obs->n_obs < 0 || obs->n_obs > chf::kMaxObsPerPlan || (obs->n_obs > 0 && !obs->xyz))
     return fail(CHF_EINVAL, "bad observer list");
   if (src->n_bins < 0 || (src->n_bins > 0 && !src->q_bins)) return fail(CHF_EINVAL, "bad profile");
@@ -133,6 +133,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   // kernel and fused-sweep shape
   int kernel = ex->kernel == CHF_KERNEL_AUTO ? (G.nx <= 64 * chf::kMaxVX ? CHF_KERNEL_FUSED : CHF_KERNEL_SPLIT)
                                              : ex->kernel;
+  const bool prefetch = kernel == CHF_KERNEL_FUSED_PREFETCH;
+  if (prefetch) kernel = CHF_KERNEL_FUSED;
   if (kernel == CHF_KERNEL_FUSED && G.nx > 64 * chf::kMaxVX) {
     delete p;
     return fail(CHF_EUNSUPPORTED, "fused sweep needs nx <= 512");
@@ -149,6 +151,11 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       !(fs.waves == 4 || fs.waves == 7 || fs.waves == 8 || fs.waves == 15)) {
     delete p;
     return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 7, 8 or 15");
+  }
+  fs.prefetch = prefetch ? 1 : 0;
+  if (prefetch && (fs.vx > 4 || fs.waves > 8)) {
+    delete p;
+    return fail(CHF_EINVAL, "the prefetching fused sweep takes rows of at most 256 nodes and waves_per_block 4, 7 or 8");
   }
   if (kernel == CHF_KERNEL_FUSED && fs.vx > 4 && fs.waves != 4 && fs.waves != 7) {
     delete p;
@@ -681,7 +688,7 @@ chf_status chf_plan_set_field(chf_plan *p, void *stream, int32_t comp, const flo
 
 chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
   if (!p || !info) return fail(CHF_EINVAL, "NULL argument");
-  info->kernel = p->kernel;
+  info->kernel = p->fs.prefetch ? CHF_KERNEL_FUSED_PREFETCH : p->kernel;
   info->storage = p->storage;
   info->vx = p->fs.vx;
   info->rows_per_wave = p->fs.rows;

@@ -74,6 +74,7 @@ struct FusedShape {
   // other tiles are listed in two tables: clear of walls (layer) and touching a wall (slow)
   int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_layer, layer_blocks, n_slow, slow_blocks;
   int n_slow_y;  // leading entries of the tile table whose planes lie in [zc_lo, zc_hi) chunks
+  int prefetch;  // interior tiles issue each plane's loads one plane ahead
 };
 
 }  // namespace chf

@@ -57,6 +57,24 @@ __device__ __forceinline__ void ld_at(const T *base, unsigned boff, float (&o)[N
   ld_row<T, N>(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff), o, on);
 }
 
+// Raw storage values of a row (no conversion), zero where the lane holds no node; `unpack`
+// converts them when they are used, so loads issued ahead hold half the registers in BF16/FP16.
+template <typename T, int N>
+__device__ __forceinline__ void ld_raw(const T *base, unsigned boff, Vec<T, N> &x, bool on) {
+  if (on) {
+    x = *reinterpret_cast<const Vec<T, N> *>(reinterpret_cast<const char *>(base) + boff);
+  } else {
+#pragma unroll
+    for (int v = 0; v < N; v++) x.v[v] = from_f<T>(0.f);
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void unpack(const Vec<T, N> &x, float (&o)[N]) {
+#pragma unroll
+  for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
+}
+
 // The value a store of x followed by a load returns: the fused sweep feeds H to the E update
 // exactly as stored, as the split sweeps (which reload it) do.
 template <typename T, int N>
@@ -165,7 +183,7 @@ __device__ __forceinline__ int xcd_logical() {
 // per-lane fix-ups).  G = 1: boundary tiles whose planes lie in the interior z range (y walls
 // and y layers: masks and terms uniform per row).  G = 2: any tile, adding the z walls and the
 // z layers (uniform per plane).
-template <typename T, int VX, int W, int G>
+template <typename T, int VX, int W, int G, bool PREFETCH = false>
 __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zchunk, int par) {
   // Wave r of the workgroup owns row j = j0 - 1 + r: r = 1..W are the tile's rows, r = 0 is
   // the row below the tile, whose H the E update of row j0 needs (it computes H only and
@@ -290,6 +308,32 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     for (int v = 0; v < VX; v++) hxp[v] = hyp[v] = 0.f;
   }
 
+  // Interior tiles (G = 0) can issue each plane's row loads one plane ahead: the raw values of
+  // E(k+2), H(k+1) and the x-slab psi of plane k+1 are in flight while plane k is computed.
+  constexpr bool PF = G == 0 && PREFETCH;
+  Vec<T, VX> rE0, rE1, rE2, rH0, rH1, rH2, rT0, rT2;
+  float rq0 = 0.f, rq1 = 0.f, rq2 = 0.f, rq3 = 0.f;
+  if constexpr (PF) {
+    const long long pn = (long long)min(k0 + 1, nz - 1) * plane, pk = (long long)k0 * plane;
+    ld_raw<T, VX>(Ei0 + pn, o0, rE0, on);
+    ld_raw<T, VX>(Ei1 + pn, o0, rE1, on);
+    ld_raw<T, VX>(Ei2 + pn, o0, rE2, on);
+    ld_raw<T, VX>(Hi0 + pk, o0, rH0, on);
+    ld_raw<T, VX>(Hi1 + pk, o0, rH1, on);
+    ld_raw<T, VX>(Hi2 + pk, o0, rH2, on);
+    ld_raw<T, VX>(Ei0 + pn, op, rT0, on && top_ld);
+    ld_raw<T, VX>(Ei2 + pn, op, rT2, on && top_ld);
+    if (lane < np2 && act) {
+      const long long prow0 = ((long long)k0 * ny + jc) * np2;
+      rq0 = phi0[prow0 + lane];
+      rq1 = phi1[prow0 + lane];
+      if (own) {
+        rq2 = pe0[prow0 + lane];
+        rq3 = pe1[prow0 + lane];
+      }
+    }
+  }
+
   for (int k = k0; k < k1; k++) {
     const int kp = min(k + 1, nz - 1);
     const long long pk = k * plane, pn = kp * plane;
@@ -311,22 +355,56 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     // loads: E(k+1) and H^{n-1/2}(k) of the own row, Ex, Ez(k+1) of the row above the tile
     // (top wave), the own row's x-slab psi (one value per lane) and y/z-slab psi rows
     float nxc[VX], nyc[VX], nzc[VX], hx0[VX], hy0[VX], hz0[VX];
-    ld_at<T, VX>(Ei0 + pn, o0, nxc, on);
-    ld_at<T, VX>(Ei1 + pn, o0, nyc, on);
-    ld_at<T, VX>(Ei2 + pn, o0, nzc, on);
-    ld_at<T, VX>(Hi0 + pk, o0, hx0, on);
-    ld_at<T, VX>(Hi1 + pk, o0, hy0, on);
-    ld_at<T, VX>(Hi2 + pk, o0, hz0, on);
-    ld_at<T, VX>(Ei0 + pn, op, etx, on && top_ld);
-    ld_at<T, VX>(Ei2 + pn, op, etz, on && top_ld);
     const long long prow = ((long long)k * ny + jc) * np2;
     float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-    if (lane < np2 && act) {
-      q0 = phi0[prow + lane];
-      q1 = phi1[prow + lane];
-      if (own) {
-        q2 = pe0[prow + lane];
-        q3 = pe1[prow + lane];
+    if constexpr (PF) {
+      unpack<T, VX>(rE0, nxc);
+      unpack<T, VX>(rE1, nyc);
+      unpack<T, VX>(rE2, nzc);
+      unpack<T, VX>(rH0, hx0);
+      unpack<T, VX>(rH1, hy0);
+      unpack<T, VX>(rH2, hz0);
+      unpack<T, VX>(rT0, etx);
+      unpack<T, VX>(rT2, etz);
+      q0 = rq0;
+      q1 = rq1;
+      q2 = rq2;
+      q3 = rq3;
+      // the next plane's loads (clamped to the last plane; values past k1 - 1 are not used)
+      const long long pa = (long long)min(k + 2, nz - 1) * plane;
+      ld_raw<T, VX>(Ei0 + pa, o0, rE0, on);
+      ld_raw<T, VX>(Ei1 + pa, o0, rE1, on);
+      ld_raw<T, VX>(Ei2 + pa, o0, rE2, on);
+      ld_raw<T, VX>(Hi0 + pn, o0, rH0, on);
+      ld_raw<T, VX>(Hi1 + pn, o0, rH1, on);
+      ld_raw<T, VX>(Hi2 + pn, o0, rH2, on);
+      ld_raw<T, VX>(Ei0 + pa, op, rT0, on && top_ld);
+      ld_raw<T, VX>(Ei2 + pa, op, rT2, on && top_ld);
+      if (lane < np2 && act) {
+        const long long prn = ((long long)kp * ny + jc) * np2;
+        rq0 = phi0[prn + lane];
+        rq1 = phi1[prn + lane];
+        if (own) {
+          rq2 = pe0[prn + lane];
+          rq3 = pe1[prn + lane];
+        }
+      }
+    } else {
+      ld_at<T, VX>(Ei0 + pn, o0, nxc, on);
+      ld_at<T, VX>(Ei1 + pn, o0, nyc, on);
+      ld_at<T, VX>(Ei2 + pn, o0, nzc, on);
+      ld_at<T, VX>(Hi0 + pk, o0, hx0, on);
+      ld_at<T, VX>(Hi1 + pk, o0, hy0, on);
+      ld_at<T, VX>(Hi2 + pk, o0, hz0, on);
+      ld_at<T, VX>(Ei0 + pn, op, etx, on && top_ld);
+      ld_at<T, VX>(Ei2 + pn, op, etz, on && top_ld);
+      if (lane < np2 && act) {
+        q0 = phi0[prow + lane];
+        q1 = phi1[prow + lane];
+        if (own) {
+          q2 = pe0[prow + lane];
+          q3 = pe1[prow + lane];
+        }
       }
     }
     const float chz = d.ax[2].ch[k], cez = d.ax[2].ce[k];
@@ -579,12 +657,12 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     }
   }
 }
-template <typename T, int VX, int W>
+template <typename T, int VX, int W, bool PF>
 __global__ void __launch_bounds__(64 * (W + 1)) k_fused(Dev d, FusedShape fs, int par) {
   const int logical = xcd_logical();
   if (logical >= fs.n_fast) return;
   const int fw = fs.ty_hi - fs.ty_lo;
-  fused_body<T, VX, W, 0>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+  fused_body<T, VX, W, 0, PF>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
 }
 // Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep: G = 1
 // over the table's first n_slow_y entries (interior z range), G = 2 over the rest.
@@ -946,8 +1024,13 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
                            p.fs, d.slow_tiles + 2 * ny_, nr, par);
     } else
       return hipErrorInvalidValue;
+  } else if (p.fs.prefetch) {
+    if constexpr (VX <= 4 && W <= 8)
+      hipLaunchKernelGGL((k_fused<T, VX, W, true>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
+    else
+      return hipErrorInvalidValue;
   } else
-    hipLaunchKernelGGL((k_fused<T, VX, W>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
+    hipLaunchKernelGGL((k_fused<T, VX, W, false>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
   return hipGetLastError();
 }
 

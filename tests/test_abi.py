@@ -86,6 +86,25 @@ def test_fused_sweep_width_limit():
     assert _status(big) == "CHF_OK"  # auto picks the split sweeps
 
 
+def test_prefetching_sweep_limits():
+    """The prefetching sweep holds more registers per wave (3 waves per SIMD): at most 9 waves
+    per workgroup and 4 nodes per lane; the plan reports it as its kernel."""
+    w = W.small_shower()
+    assert _status(w, kernel="fused_prefetch", waves=7) == "CHF_OK"
+    assert _status(w, kernel="fused_prefetch", waves=8) == "CHF_OK"
+    assert _status(w, kernel="fused_prefetch", waves=15) == "CHF_EINVAL"
+    wide = w.replace(nx=300, x_axis=0.5 * 299 * w.dx, obs_xyz=w.obs_xyz + [0.5 * (299 - w.nx + 1) * w.dx, 0, 0])
+    assert _status(wide, kernel="fused", waves=7) == "CHF_OK"
+    assert _status(wide, kernel="fused_prefetch", waves=7) == "CHF_EINVAL"
+    h = solver.create_plan_handle(w, kernel="fused_prefetch", waves=8, zchunk=16)
+    try:
+        info = N.PlanInfo()
+        assert N.lib().chf_plan_get_info(h, ct.byref(info)) == 0
+        assert (info.kernel, info.waves_per_block, info.z_chunk) == (3, 8, 16)
+    finally:
+        N.lib().chf_plan_destroy(h)
+
+
 def test_null_pointers_rejected():
     L = N.lib()
     h = ct.c_void_p()

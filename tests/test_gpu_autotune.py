@@ -9,7 +9,8 @@ from paper_1001_5341_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-CANDS = [(4, 8), (8, 16), (4, 150), (8, 5)]
+CANDS = [(4, 8, "fused"), (8, 16, "fused"), (4, 150, "fused"), (8, 5, "fused"),
+         (8, 16, "fused_prefetch"), (7, 9, "fused_prefetch")]
 
 
 def test_autotune_verifies_caches_and_matches_oracle(gpu, tmp_path):
@@ -20,9 +21,10 @@ def test_autotune_verifies_caches_and_matches_oracle(gpu, tmp_path):
     assert not first["cached"]
     timed = [t for t in first["trials"] if "ms_per_step" in t]
     assert len(timed) == len(CANDS) and all(t["bitwise_equal"] for t in timed)
-    assert (first["waves"], first["z_chunk"]) in CANDS
+    best = (first["waves"], first["z_chunk"], first["kernel"])
+    assert best in CANDS
     again = autotune.tune(w, "fp32", steps=40, cache_path=path, candidates=CANDS)
-    assert again["cached"] and (again["waves"], again["z_chunk"]) == (first["waves"], first["z_chunk"])
+    assert again["cached"] and (again["waves"], again["z_chunk"], again["kernel"]) == best
     plan = autotune.tuned_plan(w, "fp32", cache_path=path, candidates=CANDS)
     got = plan.run().cpu().numpy()
     plan.close()

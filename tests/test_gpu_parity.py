@@ -84,6 +84,29 @@ def test_tile_shape_invariance_bitwise(gpu, shower, waves, zchunk):
     assert np.array_equal(got, base)
 
 
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+def test_prefetching_sweep_bitwise(gpu, storage):
+    """The sweep whose interior tiles load a plane ahead gives the plain fused sweep's bits:
+    waveforms and all six final fields, for one to four nodes per lane, z chunks of one plane,
+    a ragged chunk and one chunk over the whole height."""
+    for nx, waves, zchunk in ((40, 7, 12), (72, 8, 1), (100, 4, 16), (200, 8, 150), (200, 7, 11)):
+        w = W.small_shower(seed=17, nx=nx, ny=44, nz=150, n_steps=120, n_obs=4)
+        banner(f"prefetch {storage} nx={nx} waves={waves} zchunk={zchunk}")
+        res = []
+        for kernel in ("fused", "fused_prefetch"):
+            plan = solver.Plan(w, storage=storage, kernel=kernel, waves=waves, zchunk=zchunk)
+            info = plan.info()
+            assert info["kernel"] == (3 if kernel == "fused_prefetch" else 2)
+            out = plan.run().cpu().numpy()
+            fields = [plan.get_field(c).cpu().numpy() for c in range(6)]
+            plan.close()
+            res.append((out, fields))
+        assert np.abs(res[0][0]).max() > 0
+        assert np.array_equal(res[0][0], res[1][0]), (nx, waves, zchunk)
+        for c in range(6):
+            assert np.array_equal(res[0][1][c], res[1][1][c]), (nx, waves, zchunk, c)
+
+
 def test_graph_replay_matches_eager(gpu, shower):
     w, _ = shower
     banner("graph replay")

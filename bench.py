@@ -410,6 +410,110 @@ def spectral_measure(w, waves, n_freq: int = 1024, reps: int = 5):
             "finite": bool(torch.isfinite(mag).all() and torch.isfinite(ff).all())}
 
 
+# HBM bytes per node of one reverse step (FP32, interior): the transposed E update reads and
+# writes Eb and writes six per-term cotangents (48 B), the H gather reads them and updates Hb
+# (48 B), the transposed H update reads Hb and writes six cotangents (36 B), the E gather reads
+# them and updates Eb (48 B)
+ADJ_BYTES_PER_CELL = 180.0
+
+
+def adjoint_summary():
+    """Differentiation configuration (128x128x1024 CPML-10, 3000 steps, 16 observers, 128 profile
+    bins, L = |w(q) - w(q*)|^2): forward run, one-sweep discrete adjoint, and the checkpointed
+    gradient (forward with snapshots every 55 steps, then segment-wise recomputation and reverse
+    steps), each timed once after a warm-up."""
+    import torch
+
+    from paper_1001_5341_amd import autotune, solver
+    from paper_1001_5341_amd import workloads as W
+
+    w, q_target = W.adjoint_problem()
+    dev = torch.device("cuda:0")
+    plan = autotune.tuned_plan(w, "fp32", device=dev)
+    try:
+        target = plan.run(q_bins=torch.from_numpy(q_target).to(dev))
+        g = (2.0 * (plan.run() - target)).contiguous()
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            return out, time.perf_counter() - t0
+
+        _, t_fwd = timed(lambda: plan.run())
+        dq, t_adj = timed(lambda: plan.adjoint(g))
+        dq_ck, t_ck = timed(lambda: solver.checkpointed_adjoint(plan, g, every=55, verify=False))
+        same = bool(torch.equal(dq, dq_ck))
+        finite = bool(torch.isfinite(dq).all())
+        # permittivity map gradient: the same schedule, forward E levels kept per segment (run once)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gmap, dq_eps = solver.eps_sensitivity(plan, g, every=55)
+        torch.cuda.synchronize()
+        t_eps = time.perf_counter() - t0
+        same_eps = bool(torch.equal(dq, dq_eps))
+        del gmap
+    finally:
+        plan.close()
+    cells = w.nx * w.ny * w.nz
+    rate = cells * w.n_steps / t_adj
+    return {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "yee_steps": w.n_steps, "observers": w.n_obs,
+            "bins": len(w.q_bins), "forward_ms": round(t_fwd * 1e3, 1), "adjoint_ms": round(t_adj * 1e3, 1),
+            "checkpointed_gradient_ms": round(t_ck * 1e3, 1), "checkpoint_every": 55,
+            "adjoint_value": round(rate / 1e6, 1), "unit": "Mcell-updates/s (reverse steps)",
+            "adjoint_bytes_per_cell": ADJ_BYTES_PER_CELL,
+            "adjoint_achieved_gbs": round(rate * ADJ_BYTES_PER_CELL / 1e9, 1),
+            "adjoint_frac": round(rate * ADJ_BYTES_PER_CELL / 1e9 / HBM_PEAK_GBS, 4),
+            "checkpointed_equals_one_sweep": same, "gradient_finite": finite,
+            "eps_sensitivity_ms": round(t_eps * 1e3, 1), "eps_sensitivity_dq_equals_one_sweep": same_eps}
+
+
+# the batched sweep has no prefetching variant: its members are tuned over the plain fused sweep
+BATCH_CANDIDATES = tuple((wv, z, "fused") for wv in (7, 8) for z in (8, 12, 16, 24))
+
+
+def batch_summary():
+    """Batched configuration: 32 showers of uneven grids (96^3 ... 256x256x1024, CPML-10, 16
+    observers each, 2000 steps) advanced together in one hipGraph per run (chf_batch_run), with
+    autotuned tile shapes (one waves_per_block for all members, z chunk per member).  One warm-up
+    run (it also captures the graph), then one timed run."""
+    import torch
+
+    from paper_1001_5341_amd import autotune, solver
+    from paper_1001_5341_amd import workloads as W
+
+    ws = W.batch_showers()
+    shapes = autotune.tune_batch(ws, "fp32", candidates=BATCH_CANDIDATES, steps=24)
+    plans = [solver.Plan(w, kernel="fused", waves=s_["waves"], zchunk=s_["z_chunk"], device=torch.device("cuda:0"))
+             for w, s_ in zip(ws, shapes)]
+    batch = solver.Batch(plans)
+    try:
+        outs = [p.new_waveforms() for p in plans]
+        batch.run(outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.run(outs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        finite = all(bool(torch.isfinite(o).all()) for o in outs)
+        alg = sum(p.info()["bytes_per_cell_update"] * w.n_cells for p, w in zip(plans, ws))
+    finally:
+        batch.close()
+        for p in plans:
+            p.close()
+    T = ws[0].n_steps
+    cells = sum(w.n_cells for w in ws)
+    return {"workload": f"batch-{len(ws)}-showers", "members": len(ws), "yee_steps": T,
+            "cells_total": int(cells), "value": round(cells * T / wall / 1e6, 1), "unit": "Mcell-updates/s",
+            "ms_per_run": round(wall * 1e3, 1), "waves_per_block": shapes[0]["waves"],
+            "z_chunks": sorted({s_["z_chunk"] for s_ in shapes}),
+            "whole_step_bytes_per_cell": round(alg / cells, 3),
+            "achieved_gbs": round(alg * T / wall / 1e9, 1),
+            "frac": round(alg * T / wall / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
+
+
 def rz_summary(n: int = 8192, n_steps: int = 2048):
     """Short measurement of the axisymmetric path for the default line."""
     from paper_1001_5341_amd import workloads as W
@@ -536,6 +640,10 @@ def main():
     if not args.no_variants and not args.time_steps:
         log("axisymmetric (r, z) summary")
         rec["axisymmetric"] = rz_summary()
+        log("adjoint and checkpointed gradient on the differentiation configuration")
+        rec["adjoint"] = adjoint_summary()
+        log("batch of 32 showers")
+        rec["batch"] = batch_summary()
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a CPU sample")
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -155,6 +155,16 @@ def cpu_baseline(w, n_steps: int = 600):
             "sample_1core": f"same sub-grid, {one.n_steps} steps on one thread, {dt1:.1f} s"}
 
 
+def waveform_error(got: np.ndarray, ref: np.ndarray) -> dict:
+    """Relative L2 per observer (3 components x all steps), max and median, and the largest
+    peak-amplitude error."""
+    err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
+    pk_ref = np.abs(ref).max(axis=(1, 2))
+    pk = np.abs(np.abs(got).max(axis=(1, 2)) - pk_ref) / pk_ref
+    return {"rel_l2_max": float(err.max()), "rel_l2_median": float(np.median(err)),
+            "peak_amp_err_max": float(pk.max())}
+
+
 def golden_error(key: str, w, got: np.ndarray):
     """Relative L2 (per observer, 3 components x all steps) and peak-amplitude error against
     the FP64 oracle's stored waveforms, when they exist for this exact workload."""
@@ -166,12 +176,7 @@ def golden_error(key: str, w, got: np.ndarray):
     z = np.load(gold)
     if str(z["digest"]) != workload_digest(w):
         return None
-    ref = z["waveforms"].astype(np.float64)
-    err = np.sqrt(((got - ref) ** 2).sum(axis=(1, 2)) / (ref ** 2).sum(axis=(1, 2)))
-    pk_ref = np.abs(ref).max(axis=(1, 2))
-    pk = np.abs(np.abs(got).max(axis=(1, 2)) - pk_ref) / pk_ref
-    return {"rel_l2_max": float(err.max()), "rel_l2_median": float(np.median(err)),
-            "peak_amp_err_max": float(pk.max())}
+    return waveform_error(got, z["waveforms"].astype(np.float64))
 
 
 def timed_runs(plan, out, n_runs: int):
@@ -635,9 +640,13 @@ def main():
             e = golden_error(args.workload, w, vgot)
             if e is not None:
                 v["accuracy_vs_fp64_oracle"] = e
+            elif args.storage == "fp32":
+                # no stored oracle result for this grid (the precision grid is beyond the host
+                # oracle): distance from the FP32-storage run of the same build instead
+                v["accuracy_vs_fp32_run"] = waveform_error(vgot, got)
             variants[st] = v
         rec["storage_variants"] = variants
-    if not args.no_variants and not args.time_steps:
+    if not args.no_variants and not args.time_steps and args.workload == "single-shower":
         log("axisymmetric (r, z) summary")
         rec["axisymmetric"] = rz_summary()
         log("adjoint and checkpointed gradient on the differentiation configuration")

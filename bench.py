@@ -415,11 +415,10 @@ def spectral_measure(w, waves, n_freq: int = 1024, reps: int = 5):
             "finite": bool(torch.isfinite(mag).all() and torch.isfinite(ff).all())}
 
 
-# HBM bytes per node of one reverse step (FP32, interior): the transposed E update reads and
-# writes Eb and writes six per-term cotangents (48 B), the H gather reads them and updates Hb
-# (48 B), the transposed H update reads Hb and writes six cotangents (36 B), the E gather reads
-# them and updates Eb (48 B)
-ADJ_BYTES_PER_CELL = 180.0
+# HBM bytes per node of one reverse step (FP32, outside the CPML slabs): sweep A reads Eb and Hb
+# and writes Hb' (36 B), sweep B reads Hb' and Eb and writes Eb' (36 B); the neighbour terms are
+# recomputed or exchanged on chip
+ADJ_BYTES_PER_CELL = 72.0
 
 
 def adjoint_summary():

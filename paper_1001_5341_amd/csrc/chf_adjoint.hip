@@ -8,9 +8,13 @@
 //                    psib_tot = psib + tb, s = (tb/kappa + a psib_tot)/delta, psib <- b psib_tot,
 //                    else s = tb/delta; then Eb <- ca Eb.  Hb gathers s(p) - s(p + e_u).
 //   H update^T       same with tb = -+Db Hb; Eb gathers s(p - e_u) - s(p).
-// Gathers replace the scatter of the textbook transpose, so every value is written by one
-// thread and the result is deterministic.  The forward workspace is reused: level-0 E/H hold
-// Eb/Hb, level-1 E/H hold the six per-term cotangents s, the psi slabs hold psib.
+// Each per-term cotangent s is a pure function of the old adjoint state and the old psib, so
+// the step runs as two stencil sweeps that read one level and write the other, recomputing the
+// few neighbour terms they need instead of storing them: sweep A writes Hb' = Hb + (gather of
+// the E terms); sweep B writes Eb' = (ca) Eb + (gather of the H terms of Hb').  The psib of the
+// E terms and of the H terms are double-buffered the same way (the node that owns a term
+// writes its new psib).  Every value is written by one thread: deterministic, and the same
+// arithmetic, in the same order, as a scatter-free gather of stored terms.
 #include <hip/hip_runtime.h>
 
 #include "chf_internal.h"
@@ -31,29 +35,15 @@ __device__ __forceinline__ long long pidx(const Dev &d, int u, int i, int j, int
   return ((long long)s * d.ny + j) * d.pitch + i;
 }
 
-// cotangent of one stretched derivative divided by delta, updating psib in place
-__device__ __forceinline__ float adj_term(const Dev &d, float *psib, int u, int pos, int slot, bool half,
-                                          int i, int j, int k, float tb) {
-  const AxisTab &A = d.ax[u];
-  const float ik = half ? A.ikh[pos] : A.ike[pos];
-  if (slot < 0) return tb * ik;
-  const float a = half ? A.adh[pos] : A.ade[pos];
-  const float b = half ? A.bh[pos] : A.be[pos];
-  const long long id = pidx(d, u, i, j, k, slot);
-  const float tot = psib[id] + tb;
-  psib[id] = b * tot;
-  return fmaf(a, tot, tb * ik);
-}
-
 __global__ void k_adj_zero_q(double *q, int n) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) q[t] = 0.0;
 }
 
-__global__ void __launch_bounds__(64) k_adj_sample(Dev d, const double *g, int n, int T) {
+__global__ void __launch_bounds__(64) k_adj_sample(Dev d, const double *g, int n, int T, int cur) {
   const int lane = threadIdx.x;
   const int comp = lane >> 3, corner = lane & 7;
   if (comp >= 3) return;
-  float *Eb = (float *)d.e[0][comp];
+  float *Eb = (float *)d.e[cur][comp];
   for (int o = 0; o < d.n_obs; o++) {
     const int *ix = d.obs_idx + (o * 3 + comp) * 3;
     const double *tf = d.obs_t + (o * 3 + comp) * 3;
@@ -71,7 +61,7 @@ __global__ void __launch_bounds__(64) k_adj_sample(Dev d, const double *g, int n
 //   dL/dz_entry  += -Cb v [Q'(z_s) sum W_r W_z Eb_z + Q(z_s) sum W_r dW_z/dz_s Eb_z]
 // (z_s moves one for one with z_entry; Q' is the slope of the hat interpolation, W_z' that of the
 // window-normalised Gaussian with the window held fixed), Q from the profile q.
-__global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, const double *q, double *dth) {
+__global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, const double *q, double *dth, int cur) {
   __shared__ double part[256], part_r[256], part_z[256];
   const double tt = (n + 0.5) * d.dt;
   if (!d.src_on || tt < d.t_entry) return;
@@ -88,7 +78,7 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, co
     norm += e * d.dz;
     dnorm += e * dd / sz2 * d.dz;
   }
-  const float *Ebz = (const float *)d.e[0][2];
+  const float *Ebz = (const float *)d.e[cur][2];
   const int npatch = d.src_ni * d.src_nj;
   double acc = 0.0, acc_r = 0.0, acc_z = 0.0;
   for (int t = threadIdx.x; t < npatch * m; t += blockDim.x) {
@@ -148,7 +138,8 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, co
 // E^{n+1}, so g += -coef Eb (E^{n+1} - E^n) with coef = 1/(eps_r (1 + l)).  e0/e1 hold E^n and
 // E^{n+1} as dense [3][nz][ny][nx] FP32; g is FP64 in the same layout.  Only nodes the Yee
 // update advances (not tangential to a wall) collect a value.
-__global__ void __launch_bounds__(256) k_adj_eps(Dev d, const float *e0, const float *e1, double *g, double coef) {
+__global__ void __launch_bounds__(256) k_adj_eps(Dev d, const float *e0, const float *e1, double *g, double coef,
+                                                 int cur) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= d.nx || j >= d.ny) return;
@@ -165,133 +156,242 @@ __global__ void __launch_bounds__(256) k_adj_eps(Dev d, const float *e0, const f
     for (int u = 0; u < 3; u++) {
       if (!up[u]) continue;
       const long long t = u * N + dn;
-      const double eb = (double)((const float *)d.e[0][u])[c];
+      const double eb = (double)((const float *)d.e[cur][u])[c];
       g[t] -= coef * eb * ((double)e1[t] - (double)e0[t]);
     }
   }
 }
 
-// E update transpose: per-term cotangents into S[0..5] = (Ex-y, Ex-z, Ey-z, Ey-x, Ez-x, Ez-y)
-__global__ void __launch_bounds__(256) k_adj_e(Dev d) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= d.nx || j >= d.ny) return;
-  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, d.nz);
+// Coefficients of one stretched derivative at one axis position: 1/(delta kappa), and inside a
+// layer the psi slot with a/delta and b.
+struct TP {
+  float ik, a, b;
+  int slot;
+};
+
+__device__ __forceinline__ TP tparam(const AxisTab &A, bool pml, int pos, bool half) {
+  TP t;
+  t.ik = half ? A.ikh[pos] : A.ike[pos];
+  t.slot = pml ? (half ? A.sh[pos] : A.se[pos]) : -1;
+  t.a = t.slot >= 0 ? (half ? A.adh[pos] : A.ade[pos]) : 0.f;
+  t.b = t.slot >= 0 ? (half ? A.bh[pos] : A.be[pos]) : 0.f;
+  return t;
+}
+
+// Cotangent term of one stretched derivative divided by delta given tb, from the old psib; the
+// new psib goes to *pn (inside a layer).  Same arithmetic as the transposed CPML recursion
+// applied in place: psib_tot = psib + tb, s = tb/(delta kappa) + (a/delta) psib_tot,
+// psib <- b psib_tot.
+__device__ __forceinline__ float tval(float tb, const TP &q, const float *psib, long long id, float *pn) {
+  if (q.slot < 0) return tb * q.ik;
+  const float tot = psib[id] + tb;
+  *pn = q.b * tot;
+  return fmaf(q.a, tot, tb * q.ik);
+}
+
+// psi arrays of one set as [u * 2 + t]: (Ey-x, Ez-x, Ex-y, Ez-y, Ex-z, Ey-z) for the E terms and
+// (Hy-x, Hz-x, Hx-y, Hz-y, Hx-z, Hy-z) for the H terms
+struct PsiSet {
+  float *p[6];
+};
+
+// One term: zero where the node is not updated; the owner stores the new psib.
+__device__ __forceinline__ float term(const Dev &d, bool upd, float tb, const TP &q, const float *pr, float *pw, int u,
+                                      int i, int j, int k) {
+  if (!upd) return 0.f;
+  const long long id = q.slot >= 0 ? pidx(d, u, i, j, k, q.slot) : 0;
+  float pn = 0.f;
+  const float v = tval(tb, q, pr, id, &pn);
+  if (pw && q.slot >= 0) pw[id] = pn;
+  return v;
+}
+
+// Sweep A: Hb' (level cur ^ 1) = Hb (level cur) + sum of s(p) - s(p + e_u) over the E terms
+// that read H(p); the E-term psib move from set `er` to set `ew`.  A workgroup is 64 x nodes by
+// 4 y rows marching a z chunk downwards: s(p + e_z) is the previous plane's own term, s(p + e_x)
+// the next lane's, s(p + e_y) the next row's through LDS; the last lane, the last row and the
+// top plane of the chunk compute their neighbour's term directly (without storing its psib).
+__global__ void __launch_bounds__(256) k_adj_ha(Dev d, int cur, PsiSet er, PsiSet ew) {
+  __shared__ float sy0[2][4][64], sy5[2][4][64];
+  const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  float *Eb[3] = {(float *)d.e[0][0], (float *)d.e[0][1], (float *)d.e[0][2]};
-  float *S[6] = {(float *)d.e[1][0], (float *)d.e[1][1], (float *)d.e[1][2],
-                 (float *)d.h[1][0], (float *)d.h[1][1], (float *)d.h[1][2]};
+  const int i = blockIdx.x * 64 + lane, j = blockIdx.y * 4 + r;
+  const bool on = i < nx && j < ny;
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, nz);
   const bool pml = d.np2 > 0;
-  const int sx = pml ? d.ax[0].se[i] : -1, sy = pml ? d.ax[1].se[j] : -1;
-  for (int k = k0; k < k1; k++) {
-    const int sz = pml ? d.ax[2].se[k] : -1;
-    const long long c = cidx(d, i, j, k);
-    const bool ux = i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-    const bool uy = i >= 1 && i <= nx - 2 && j <= ny - 2 && k >= 1 && k <= nz - 2;
-    const bool uz = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k <= nz - 2;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
-    if (ux) {
-      const float tb = d.a_cb * Eb[0][c];
-      s0 = adj_term(d, d.psi_e[1][0], 1, j, sy, false, i, j, k, tb);
-      s1 = adj_term(d, d.psi_e[2][0], 2, k, sz, false, i, j, k, -tb);
-      Eb[0][c] = d.a_ca * Eb[0][c];
+  const bool xp = i + 1 < nx, yp = j + 1 < ny;
+  const int ip = min(i + 1, nx - 1), jp = min(j + 1, ny - 1);
+  const TP x0 = tparam(d.ax[0], pml, ic, false), x1 = tparam(d.ax[0], pml, ip, false);
+  const TP y0 = tparam(d.ax[1], pml, jc, false), y1 = tparam(d.ax[1], pml, jp, false);
+  // update masks split by axis: Ex (i <= nx-2, 1 <= j <= ny-2, 1 <= k <= nz-2),
+  // Ey (1 <= i <= nx-2, j <= ny-2, 1 <= k <= nz-2), Ez (1 <= i <= nx-2, 1 <= j <= ny-2, k <= nz-2)
+  const bool ix = on && i <= nx - 2, iyz = on && i >= 1 && i <= nx - 2;
+  const bool iyz1 = xp && ip >= 1 && ip <= nx - 2 && j < ny;
+  const bool jxz = j >= 1 && j <= ny - 2, jy = j <= ny - 2;
+  const bool jxz1 = yp && jp >= 1 && jp <= ny - 2;
+  const float *E0 = (const float *)d.e[cur][0], *E1 = (const float *)d.e[cur][1], *E2 = (const float *)d.e[cur][2];
+  const float *H0 = (const float *)d.h[cur][0], *H1 = (const float *)d.h[cur][1], *H2 = (const float *)d.h[cur][2];
+  float *O0 = (float *)d.h[cur ^ 1][0], *O1 = (float *)d.h[cur ^ 1][1], *O2 = (float *)d.h[cur ^ 1][2];
+  const float cb = d.a_cb;
+  float s1n = 0.f, s2n = 0.f;  // terms Ex-z, Ey-z of the node above (p + e_z)
+  for (int k = k1 - 1; k >= k0; k--) {
+    const bool kxy = k >= 1 && k <= nz - 2, kz = k <= nz - 2;
+    const TP zk = tparam(d.ax[2], pml, k, false);
+    const long long c = cidx(d, ic, jc, k);
+    const float bx = cb * (on ? E0[c] : 0.f), by = cb * (on ? E1[c] : 0.f), bz = cb * (on ? E2[c] : 0.f);
+    const bool ux = ix && jxz && kxy, uy = iyz && jy && kxy, uz = iyz && jxz && kz;
+    const float s0 = term(d, ux, bx, y0, er.p[2], ew.p[2], 1, ic, jc, k);
+    const float s1 = term(d, ux, -bx, zk, er.p[4], ew.p[4], 2, ic, jc, k);
+    const float s2 = term(d, uy, by, zk, er.p[5], ew.p[5], 2, ic, jc, k);
+    const float s3 = term(d, uy, -by, x0, er.p[0], ew.p[0], 0, ic, jc, k);
+    const float s4 = term(d, uz, bz, x0, er.p[1], ew.p[1], 0, ic, jc, k);
+    const float s5 = term(d, uz, -bz, y0, er.p[3], ew.p[3], 1, ic, jc, k);
+    // z neighbour: carried, or computed at the top plane of the chunk
+    if (k == k1 - 1) {
+      s1n = s2n = 0.f;
+      if (k + 1 < nz && on) {
+        const int ku = k + 1;
+        const bool kxyu = ku >= 1 && ku <= nz - 2;
+        const TP zu = tparam(d.ax[2], pml, ku, false);
+        const long long cu = cidx(d, ic, jc, ku);
+        s1n = term(d, ix && jxz && kxyu, -cb * E0[cu], zu, er.p[4], nullptr, 2, ic, jc, ku);
+        s2n = term(d, iyz && jy && kxyu, cb * E1[cu], zu, er.p[5], nullptr, 2, ic, jc, ku);
+      }
     }
-    if (uy) {
-      const float tb = d.a_cb * Eb[1][c];
-      s2 = adj_term(d, d.psi_e[2][1], 2, k, sz, false, i, j, k, tb);
-      s3 = adj_term(d, d.psi_e[0][0], 0, i, sx, false, i, j, k, -tb);
-      Eb[1][c] = d.a_ca * Eb[1][c];
+    // x neighbour: the next lane's own terms; the last lane computes them
+    float s3x = __shfl_down(s3, 1), s4x = __shfl_down(s4, 1);
+    if (lane == 63) {
+      s3x = s4x = 0.f;
+      if (xp && j < ny) {
+        const long long cx = cidx(d, ip, jc, k);
+        s3x = term(d, iyz1 && jy && kxy, -cb * E1[cx], x1, er.p[0], nullptr, 0, ip, jc, k);
+        s4x = term(d, iyz1 && jxz && kz, cb * E2[cx], x1, er.p[1], nullptr, 0, ip, jc, k);
+      }
     }
-    if (uz) {
-      const float tb = d.a_cb * Eb[2][c];
-      s4 = adj_term(d, d.psi_e[0][1], 0, i, sx, false, i, j, k, tb);
-      s5 = adj_term(d, d.psi_e[1][1], 1, j, sy, false, i, j, k, -tb);
-      Eb[2][c] = d.a_ca * Eb[2][c];
+    // y neighbour: the next row's own terms through LDS; the last row computes them
+    const int buf = k & 1;
+    sy0[buf][r][lane] = s0;
+    sy5[buf][r][lane] = s5;
+    __syncthreads();
+    float s0y, s5y;
+    if (r < 3) {
+      s0y = sy0[buf][r + 1][lane];
+      s5y = sy5[buf][r + 1][lane];
+    } else {
+      s0y = s5y = 0.f;
+      if (yp && i < nx) {
+        const long long cy = cidx(d, ic, jp, k);
+        s0y = term(d, ix && jxz1 && kxy, cb * E0[cy], y1, er.p[2], nullptr, 1, ic, jp, k);
+        s5y = term(d, iyz && jxz1 && kz, -cb * E2[cy], y1, er.p[3], nullptr, 1, ic, jp, k);
+      }
     }
-    S[0][c] = s0; S[1][c] = s1; S[2][c] = s2; S[3][c] = s3; S[4][c] = s4; S[5][c] = s5;
+    if (on) {
+      O0[c] = H0[c] + ((s2 - s2n) + (s5 - s5y));
+      O1[c] = H1[c] + ((s1 - s1n) + (s4 - s4x));
+      O2[c] = H2[c] + ((s0 - s0y) + (s3 - s3x));
+    }
+    s1n = s1;
+    s2n = s2;
   }
 }
 
-// Hb(p) += s(p) - s(p + e_u) over the E terms that read H(p)
-__global__ void __launch_bounds__(256) k_adj_hgather(Dev d) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= d.nx || j >= d.ny) return;
-  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, d.nz);
-  const float *S[6] = {(const float *)d.e[1][0], (const float *)d.e[1][1], (const float *)d.e[1][2],
-                       (const float *)d.h[1][0], (const float *)d.h[1][1], (const float *)d.h[1][2]};
-  float *Hb[3] = {(float *)d.h[0][0], (float *)d.h[0][1], (float *)d.h[0][2]};
-  for (int k = k0; k < k1; k++) {
-    const long long c = cidx(d, i, j, k);
-    const bool xp = i + 1 < d.nx, yp = j + 1 < d.ny, zp = k + 1 < d.nz;
-    const long long cx = c + 1, cy = c + d.pitch, cz = c + d.plane;
-    const float hx = (S[2][c] - (zp ? S[2][cz] : 0.f)) + (S[5][c] - (yp ? S[5][cy] : 0.f));
-    const float hy = (S[1][c] - (zp ? S[1][cz] : 0.f)) + (S[4][c] - (xp ? S[4][cx] : 0.f));
-    const float hz = (S[0][c] - (yp ? S[0][cy] : 0.f)) + (S[3][c] - (xp ? S[3][cx] : 0.f));
-    Hb[0][c] += hx;
-    Hb[1][c] += hy;
-    Hb[2][c] += hz;
-  }
-}
-
-// H update transpose: per-term cotangents into S[0..5] = (Hx-y, Hx-z, Hy-z, Hy-x, Hz-x, Hz-y)
-__global__ void __launch_bounds__(256) k_adj_h(Dev d) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= d.nx || j >= d.ny) return;
-  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, d.nz);
+// Sweep B: Eb' (level cur ^ 1) = (ca) Eb (level cur) + sum of s(p - e_u) - s(p) over the H terms
+// of Hb' (level cur ^ 1) that read E(p); the H-term psib move from set `hr` to set `hw`.  Same
+// workgroup shape, marching upwards: s(p - e_z) is the previous plane's own term, s(p - e_x) the
+// previous lane's, s(p - e_y) the previous row's; the first lane, the first row and the bottom
+// plane of the chunk compute their neighbour's term directly.
+__global__ void __launch_bounds__(256) k_adj_eb(Dev d, int cur, PsiSet hr, PsiSet hw) {
+  __shared__ float sy0[2][4][64], sy5[2][4][64];
+  const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const float *Hb[3] = {(const float *)d.h[0][0], (const float *)d.h[0][1], (const float *)d.h[0][2]};
-  float *S[6] = {(float *)d.e[1][0], (float *)d.e[1][1], (float *)d.e[1][2],
-                 (float *)d.h[1][0], (float *)d.h[1][1], (float *)d.h[1][2]};
+  const int i = blockIdx.x * 64 + lane, j = blockIdx.y * 4 + r;
+  const bool on = i < nx && j < ny;
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, nz);
   const bool pml = d.np2 > 0;
-  const int sx = pml ? d.ax[0].sh[i] : -1, sy = pml ? d.ax[1].sh[j] : -1;
+  const bool xm = i >= 1 && i <= nx, ym = j >= 1 && j <= ny;
+  const int im = max(min(i, nx) - 1, 0), jm = max(min(j, ny) - 1, 0);
+  const TP x0 = tparam(d.ax[0], pml, ic, true), x1 = tparam(d.ax[0], pml, im, true);
+  const TP y0 = tparam(d.ax[1], pml, jc, true), y1 = tparam(d.ax[1], pml, jm, true);
+  // H masks: Hx (j <= ny-2, k <= nz-2), Hy (i <= nx-2, k <= nz-2), Hz (i <= nx-2, j <= ny-2)
+  const bool ih = on && i <= nx - 2, jh = j <= ny - 2;
+  const bool ih1 = xm && im <= nx - 2 && j < ny, jh1 = ym && jm <= ny - 2;
+  // E masks of the own node
+  const bool ex_i = i <= nx - 2, eyz_i = i >= 1 && i <= nx - 2;
+  const bool exz_j = j >= 1 && j <= ny - 2, ey_j = j <= ny - 2;
+  const float *E0 = (const float *)d.e[cur][0], *E1 = (const float *)d.e[cur][1], *E2 = (const float *)d.e[cur][2];
+  const float *H0 = (const float *)d.h[cur ^ 1][0], *H1 = (const float *)d.h[cur ^ 1][1],
+              *H2 = (const float *)d.h[cur ^ 1][2];
+  float *O0 = (float *)d.e[cur ^ 1][0], *O1 = (float *)d.e[cur ^ 1][1], *O2 = (float *)d.e[cur ^ 1][2];
+  const float db = d.a_db, ca = d.a_ca;
+  float t1p = 0.f, t2p = 0.f;  // terms Hx-z, Hy-z of the node below (p - e_z)
   for (int k = k0; k < k1; k++) {
-    const int sz = pml ? d.ax[2].sh[k] : -1;
-    const long long c = cidx(d, i, j, k);
-    const bool ux = j <= ny - 2 && k <= nz - 2;
-    const bool uy = i <= nx - 2 && k <= nz - 2;
-    const bool uz = i <= nx - 2 && j <= ny - 2;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
-    if (ux) {
-      const float tb = -d.a_db * Hb[0][c];
-      s0 = adj_term(d, d.psi_h[0][1][0], 1, j, sy, true, i, j, k, tb);
-      s1 = adj_term(d, d.psi_h[0][2][0], 2, k, sz, true, i, j, k, -tb);
+    const bool kh = k <= nz - 2;
+    const TP zk = tparam(d.ax[2], pml, k, true);
+    const long long c = cidx(d, ic, jc, k);
+    const float hx = on ? H0[c] : 0.f, hy = on ? H1[c] : 0.f, hz = on ? H2[c] : 0.f;
+    const float ax = -db * hx, ay = -db * hy, az = -db * hz;
+    const bool ux = on && jh && kh, uy = ih && kh, uz = ih && jh;
+    const float t0 = term(d, ux, ax, y0, hr.p[2], hw.p[2], 1, ic, jc, k);
+    const float t1 = term(d, ux, -ax, zk, hr.p[4], hw.p[4], 2, ic, jc, k);
+    const float t2 = term(d, uy, ay, zk, hr.p[5], hw.p[5], 2, ic, jc, k);
+    const float t3 = term(d, uy, -ay, x0, hr.p[0], hw.p[0], 0, ic, jc, k);
+    const float t4 = term(d, uz, az, x0, hr.p[1], hw.p[1], 0, ic, jc, k);
+    const float t5 = term(d, uz, -az, y0, hr.p[3], hw.p[3], 1, ic, jc, k);
+    if (k == k0) {
+      t1p = t2p = 0.f;
+      if (k >= 1 && on) {
+        const int kd = k - 1;
+        const TP zd = tparam(d.ax[2], pml, kd, true);
+        const long long cd = cidx(d, ic, jc, kd);
+        t1p = term(d, jh, db * H0[cd], zd, hr.p[4], nullptr, 2, ic, jc, kd);
+        t2p = term(d, ih, -db * H1[cd], zd, hr.p[5], nullptr, 2, ic, jc, kd);
+      }
     }
-    if (uy) {
-      const float tb = -d.a_db * Hb[1][c];
-      s2 = adj_term(d, d.psi_h[0][2][1], 2, k, sz, true, i, j, k, tb);
-      s3 = adj_term(d, d.psi_h[0][0][0], 0, i, sx, true, i, j, k, -tb);
+    float t3x = __shfl_up(t3, 1), t4x = __shfl_up(t4, 1);
+    if (lane == 0) {
+      t3x = t4x = 0.f;
+      if (xm && j < ny) {
+        const long long cx = cidx(d, im, jc, k);
+        t3x = term(d, ih1 && kh, db * H1[cx], x1, hr.p[0], nullptr, 0, im, jc, k);
+        t4x = term(d, ih1 && jh, -db * H2[cx], x1, hr.p[1], nullptr, 0, im, jc, k);
+      }
     }
-    if (uz) {
-      const float tb = -d.a_db * Hb[2][c];
-      s4 = adj_term(d, d.psi_h[0][0][1], 0, i, sx, true, i, j, k, tb);
-      s5 = adj_term(d, d.psi_h[0][1][1], 1, j, sy, true, i, j, k, -tb);
+    const int buf = k & 1;
+    sy0[buf][r][lane] = t0;
+    sy5[buf][r][lane] = t5;
+    __syncthreads();
+    float t0y, t5y;
+    if (r > 0) {
+      t0y = sy0[buf][r - 1][lane];
+      t5y = sy5[buf][r - 1][lane];
+    } else {
+      t0y = t5y = 0.f;
+      if (ym && i < nx) {
+        const long long cy = cidx(d, ic, jm, k);
+        t0y = term(d, jh1 && kh, -db * H0[cy], y1, hr.p[2], nullptr, 1, ic, jm, k);
+        t5y = term(d, ih && jh1, db * H2[cy], y1, hr.p[3], nullptr, 1, ic, jm, k);
+      }
     }
-    S[0][c] = s0; S[1][c] = s1; S[2][c] = s2; S[3][c] = s3; S[4][c] = s4; S[5][c] = s5;
+    if (on) {
+      const bool kxy = k >= 1 && k <= nz - 2;
+      const float ex = (t2p - t2) + (t5y - t5);
+      const float ey = (t1p - t1) + (t4x - t4);
+      const float ez = (t0y - t0) + (t3x - t3);
+      const float e0 = E0[c], e1 = E1[c], e2 = E2[c];
+      O0[c] = ((ex_i && exz_j && kxy) ? ca * e0 : e0) + ex;
+      O1[c] = ((eyz_i && ey_j && kxy) ? ca * e1 : e1) + ey;
+      O2[c] = ((eyz_i && exz_j && kh) ? ca * e2 : e2) + ez;
+    }
+    t1p = t1;
+    t2p = t2;
   }
 }
 
-// Eb(p) += s(p - e_u) - s(p) over the H terms that read E(p)
-__global__ void __launch_bounds__(256) k_adj_egather(Dev d) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= d.nx || j >= d.ny) return;
-  const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, d.nz);
-  const float *S[6] = {(const float *)d.e[1][0], (const float *)d.e[1][1], (const float *)d.e[1][2],
-                       (const float *)d.h[1][0], (const float *)d.h[1][1], (const float *)d.h[1][2]};
-  float *Eb[3] = {(float *)d.e[0][0], (float *)d.e[0][1], (float *)d.e[0][2]};
-  for (int k = k0; k < k1; k++) {
-    const long long c = cidx(d, i, j, k);
-    const bool xm = i >= 1, ym = j >= 1, zm = k >= 1;
-    const long long cx = c - 1, cy = c - d.pitch, cz = c - d.plane;
-    const float ex = ((zm ? S[2][cz] : 0.f) - S[2][c]) + ((ym ? S[5][cy] : 0.f) - S[5][c]);
-    const float ey = ((zm ? S[1][cz] : 0.f) - S[1][c]) + ((xm ? S[4][cx] : 0.f) - S[4][c]);
-    const float ez = ((ym ? S[0][cy] : 0.f) - S[0][c]) + ((xm ? S[3][cx] : 0.f) - S[3][c]);
-    Eb[0][c] += ex;
-    Eb[1][c] += ey;
-    Eb[2][c] += ez;
-  }
+__global__ void k_adj_zero_f(float *p, long long n) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    p[t] = 0.f;
 }
 
 }  // namespace
@@ -302,19 +402,35 @@ hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, 
   return hipGetLastError();
 }
 
+hipError_t launch_adjoint_clear(const chf_plan &p, hipStream_t s) {
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++)
+      if (p.psi_len[u] > 0 && p.dev.np2 > 0)
+        hipLaunchKernelGGL(k_adj_zero_f, dim3(1024), dim3(256), 0, s, p.dev.psi_eb[u][t], (long long)p.psi_len[u]);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int step, const double *dl_dw,
                                double *dl_dq, hipStream_t s, const double *q_dev, double *dl_dtheta,
                                const EpsTerm *eps) {
-  (void)parity;
   const int T = p.grid.n_steps;
-  if (d.n_obs > 0) hipLaunchKernelGGL(k_adj_sample, dim3(1), dim3(64), 0, s, d, dl_dw, step, T);
-  if (d.src_on) hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(256), 0, s, d, step, dl_dq, q_dev, dl_dtheta);
+  const int cur = parity & 1;
+  if (d.n_obs > 0) hipLaunchKernelGGL(k_adj_sample, dim3(1), dim3(64), 0, s, d, dl_dw, step, T, cur);
+  if (d.src_on) hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(256), 0, s, d, step, dl_dq, q_dev, dl_dtheta, cur);
   dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, (d.nz + kAdjZ - 1) / kAdjZ);
-  if (eps) hipLaunchKernelGGL(k_adj_eps, grid, dim3(256), 0, s, d, eps->e0, eps->e1, eps->g, eps->coef);
-  hipLaunchKernelGGL(k_adj_e, grid, dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_adj_hgather, grid, dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_adj_h, grid, dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_adj_egather, grid, dim3(256), 0, s, d);
+  if (eps) hipLaunchKernelGGL(k_adj_eps, grid, dim3(256), 0, s, d, eps->e0, eps->e1, eps->g, eps->coef, cur);
+  // psib of the E terms alternate between the forward's psi_e slabs and the adjoint's second
+  // set; those of the H terms between the two psi_h levels
+  PsiSet e0, e1, h0, h1;
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) {
+      e0.p[u * 2 + t] = d.psi_e[u][t];
+      e1.p[u * 2 + t] = d.psi_eb[u][t];
+      h0.p[u * 2 + t] = d.psi_h[0][u][t];
+      h1.p[u * 2 + t] = d.psi_h[1][u][t];
+    }
+  hipLaunchKernelGGL(k_adj_ha, grid, dim3(256), 0, s, d, cur, cur ? e1 : e0, cur ? e0 : e1);
+  hipLaunchKernelGGL(k_adj_eb, grid, dim3(256), 0, s, d, cur, cur ? h1 : h0, cur ? h0 : h1);
   return hipGetLastError();
 }
 

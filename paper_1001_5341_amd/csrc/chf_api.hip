@@ -407,6 +407,11 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   off += align256(std::max<size_t>(p->slow_tiles.size(), 1) * sizeof(int));
   p->off_ltiles = off;
   off += align256(std::max<size_t>(p->layer_tiles.size(), 1) * sizeof(int));
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) {
+      p->off_psi_eb[u][t] = off;
+      off += align256(p->psi_len[u] * 4);
+    }
   p->ws_bytes = off;
 
   // kernel parameter block (device pointers are filled at bind time)
@@ -481,6 +486,7 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
       D.psi_e[u][t] = (float *)(ws + p->off_psi_e[u][t]);
       D.psi_h[0][u][t] = (float *)(ws + p->off_psi_h[0][u][t]);
       D.psi_h[1][u][t] = (float *)(ws + p->off_psi_h[1][u][t]);
+      D.psi_eb[u][t] = (float *)(ws + p->off_psi_eb[u][t]);
     }
   const float *tf = (const float *)(ws + p->off_tf);
   const int *ti = (const int *)(ws + p->off_ti);
@@ -729,6 +735,7 @@ chf_status chf_adjoint_begin(chf_plan *p, void *stream, double *dl_dq_dev) {
   hipStream_t s = (hipStream_t)stream;
   // the workspace now holds the adjoint state: zero fields and psi
   hipError_t e = chf::launch_zero(*p, s);
+  if (e == hipSuccess) e = chf::launch_adjoint_clear(*p, s);
   if (e == hipSuccess) e = chf::launch_adjoint_init(*p, dl_dq_dev, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint start");
   p->parity = 0;
@@ -745,8 +752,10 @@ chf_status chf_adjoint_steps(chf_plan *p, void *stream, const double *dl_dw_dev,
   if (p->adj_next < 0 || t_hi != p->adj_next)
     return fail(CHF_ESTATE, "adjoint steps must continue where the previous call stopped");
   hipError_t e = hipSuccess;
-  for (int n = t_hi - 1; n >= t_lo && e == hipSuccess; n--)
-    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, (hipStream_t)stream);
+  for (int n = t_hi - 1; n >= t_lo && e == hipSuccess; n--) {
+    e = chf::launch_adjoint_step(*p, p->dev, p->parity, n, dl_dw_dev, dl_dq_dev, (hipStream_t)stream);
+    p->parity ^= 1;
+  }
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   p->adj_next = t_lo;
   return CHF_OK;
@@ -768,7 +777,9 @@ chf_status chf_adjoint_steps_eps(chf_plan *p, void *stream, const double *dl_dw_
   for (int n = t_hi - 1; n >= t_lo && e == hipSuccess; n--) {
     const chf::EpsTerm term{e_levels_dev + (long long)(n - t_lo) * level,
                             e_levels_dev + (long long)(n + 1 - t_lo) * level, dl_deps_dev, coef};
-    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, (hipStream_t)stream, nullptr, nullptr, &term);
+    e = chf::launch_adjoint_step(*p, p->dev, p->parity, n, dl_dw_dev, dl_dq_dev, (hipStream_t)stream, nullptr, nullptr,
+                                 &term);
+    p->parity ^= 1;
   }
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   p->adj_next = t_lo;
@@ -790,8 +801,10 @@ chf_status chf_adjoint_source_params(chf_plan *p, void *stream, const double *dl
   if (st != CHF_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = chf::launch_adjoint_init(*p, dl_dtheta_dev, s, 2);
-  for (int n = p->grid.n_steps - 1; n >= 0 && e == hipSuccess; n--)
-    e = chf::launch_adjoint_step(*p, p->dev, 0, n, dl_dw_dev, dl_dq_dev, s, q_bins_dev, dl_dtheta_dev);
+  for (int n = p->grid.n_steps - 1; n >= 0 && e == hipSuccess; n--) {
+    e = chf::launch_adjoint_step(*p, p->dev, p->parity, n, dl_dw_dev, dl_dq_dev, s, q_bins_dev, dl_dtheta_dev);
+    p->parity ^= 1;
+  }
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   p->adj_next = 0;
   return CHF_OK;

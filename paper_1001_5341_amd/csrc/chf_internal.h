@@ -42,6 +42,7 @@ struct Dev {
   // 2 (z) -> (Ex,Ey) / (Hx,Hy).  psi_h is kept in two time levels (halo recompute).
   float *psi_e[3][2];
   float *psi_h[2][3][2];
+  float *psi_eb[3][2];       // second set of the E-term psi cotangents (adjoint only)
   AxisTab ax[3];
   // storage scales: stored = scale * physical
   float se, sh;
@@ -101,6 +102,7 @@ struct chf_plan {
   // workspace layout (byte offsets)
   uint64_t off_e[2][3], off_h[2][3], off_psi_e[3][2], off_psi_h[2][3][2];
   uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, off_tiles, off_ltiles, ws_bytes;
+  uint64_t off_psi_eb[3][2];   // after the snapshot region: not part of the forward state
   std::vector<int> slow_tiles, layer_tiles;
   uint64_t field_bytes, psi_bytes, psi_len[3];
   char *ws = nullptr;
@@ -159,6 +161,7 @@ hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int 
                                const double *q_dev = nullptr, double *dl_dtheta = nullptr,
                                const EpsTerm *eps = nullptr);
 hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, int n = -1);
+hipError_t launch_adjoint_clear(const chf_plan &p, hipStream_t s);
 hipError_t launch_batch_step(const chf_batch &b, int parity, int step, hipStream_t s);
 void set_error(const std::string &msg);
 }  // namespace chf

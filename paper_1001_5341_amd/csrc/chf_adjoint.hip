@@ -23,7 +23,7 @@ namespace chf {
 
 namespace {
 
-constexpr int kAdjZ = 16;
+constexpr int kAdjZ = 8;
 
 __device__ __forceinline__ long long cidx(const Dev &d, int i, int j, int k) {
   return (long long)k * d.plane + (long long)j * d.pitch + i;

@@ -178,56 +178,52 @@ __device__ __forceinline__ TP tparam(const AxisTab &A, bool pml, int pos, bool h
   return t;
 }
 
-// Cotangent term of one stretched derivative divided by delta given tb, from the old psib; the
-// new psib goes to *pn (inside a layer).  Same arithmetic as the transposed CPML recursion
-// applied in place: psib_tot = psib + tb, s = tb/(delta kappa) + (a/delta) psib_tot,
-// psib <- b psib_tot.
-__device__ __forceinline__ float tval(float tb, const TP &q, const float *psib, long long id, float *pn) {
-  if (q.slot < 0) return tb * q.ik;
-  const float tot = psib[id] + tb;
-  *pn = q.b * tot;
-  return fmaf(q.a, tot, tb * q.ik);
-}
-
 // psi arrays of one set as [u * 2 + t]: (Ey-x, Ez-x, Ex-y, Ez-y, Ex-z, Ey-z) for the E terms and
 // (Hy-x, Hz-x, Hx-y, Hz-y, Hx-z, Hy-z) for the H terms
 struct PsiSet {
   float *p[6];
 };
 
-// One term: zero where the node is not updated; the owner stores the new psib.
-__device__ __forceinline__ float term(const Dev &d, bool upd, float tb, const TP &q, const float *pr, float *pw, int u,
-                                      int i, int j, int k) {
+// One cotangent term of a stretched derivative divided by delta, given tb and the old psib
+// loaded beforehand: zero where the node is not updated.  Inside a layer psib_tot = psib + tb,
+// s = tb/(delta kappa) + (a/delta) psib_tot, and the owner (pw non-null) stores the new psib
+// b psib_tot: the transposed CPML recursion.
+__device__ __forceinline__ float term(bool upd, float tb, const TP &q, float psib, float *pw, long long id) {
   if (!upd) return 0.f;
-  const long long id = q.slot >= 0 ? pidx(d, u, i, j, k, q.slot) : 0;
-  float pn = 0.f;
-  const float v = tval(tb, q, pr, id, &pn);
-  if (pw && q.slot >= 0) pw[id] = pn;
-  return v;
+  if (q.slot < 0) return tb * q.ik;
+  const float tot = psib + tb;
+  if (pw) pw[id] = q.b * tot;
+  return fmaf(q.a, tot, tb * q.ik);
+}
+
+// psib slot index of a term (slot clamped to 0 outside a layer, so that the address is valid
+// and the load can be issued with the others; its value is then not used)
+__device__ __forceinline__ long long pslot(const Dev &d, int u, int i, int j, int k, const TP &q) {
+  return pidx(d, u, i, j, k, q.slot > 0 ? q.slot : 0);
 }
 
 // Sweep A: Hb' (level cur ^ 1) = Hb (level cur) + sum of s(p) - s(p + e_u) over the E terms
 // that read H(p); the E-term psib move from set `er` to set `ew`.  A workgroup is 64 x nodes by
-// 4 y rows marching a z chunk downwards: s(p + e_z) is the previous plane's own term, s(p + e_x)
-// the next lane's, s(p + e_y) the next row's through LDS; the last lane, the last row and the
-// top plane of the chunk compute their neighbour's term directly (without storing its psib).
+// 4 y rows marching a z chunk downwards; s(p + e_z) is the previous plane's own term, and each
+// node evaluates the terms of its x and y neighbours itself (without storing their psib).
+// Every load of a plane (own values, the neighbours' values and all psib) is issued before any
+// of them is used, so a plane costs one memory round trip.
 __global__ void __launch_bounds__(256) k_adj_ha(Dev d, int cur, PsiSet er, PsiSet ew) {
-  __shared__ float sy0[2][4][64], sy5[2][4][64];
   const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int i = blockIdx.x * 64 + lane, j = blockIdx.y * 4 + r;
   const bool on = i < nx && j < ny;
-  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  if (!on) return;
   const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, nz);
   const bool pml = d.np2 > 0;
   const bool xp = i + 1 < nx, yp = j + 1 < ny;
   const int ip = min(i + 1, nx - 1), jp = min(j + 1, ny - 1);
-  const TP x0 = tparam(d.ax[0], pml, ic, false), x1 = tparam(d.ax[0], pml, ip, false);
-  const TP y0 = tparam(d.ax[1], pml, jc, false), y1 = tparam(d.ax[1], pml, jp, false);
+  const TP x0 = tparam(d.ax[0], pml, i, false), x1 = tparam(d.ax[0], pml, ip, false);
+  const TP y0 = tparam(d.ax[1], pml, j, false), y1 = tparam(d.ax[1], pml, jp, false);
   // update masks split by axis: Ex (i <= nx-2, 1 <= j <= ny-2, 1 <= k <= nz-2),
   // Ey (1 <= i <= nx-2, j <= ny-2, 1 <= k <= nz-2), Ez (1 <= i <= nx-2, 1 <= j <= ny-2, k <= nz-2)
-  const bool ix = on && i <= nx - 2, iyz = on && i >= 1 && i <= nx - 2;
-  const bool iyz1 = xp && ip >= 1 && ip <= nx - 2 && j < ny;
+  const bool ix = i <= nx - 2, iyz = i >= 1 && i <= nx - 2;
+  const bool iyz1 = xp && ip >= 1 && ip <= nx - 2;
   const bool jxz = j >= 1 && j <= ny - 2, jy = j <= ny - 2;
   const bool jxz1 = yp && jp >= 1 && jp <= ny - 2;
   const float *E0 = (const float *)d.e[cur][0], *E1 = (const float *)d.e[cur][1], *E2 = (const float *)d.e[cur][2];
@@ -235,62 +231,55 @@ __global__ void __launch_bounds__(256) k_adj_ha(Dev d, int cur, PsiSet er, PsiSe
   float *O0 = (float *)d.h[cur ^ 1][0], *O1 = (float *)d.h[cur ^ 1][1], *O2 = (float *)d.h[cur ^ 1][2];
   const float cb = d.a_cb;
   float s1n = 0.f, s2n = 0.f;  // terms Ex-z, Ey-z of the node above (p + e_z)
+  if (k1 < nz) {
+    const int ku = k1;
+    const bool kxyu = ku >= 1 && ku <= nz - 2;
+    const TP zu = tparam(d.ax[2], pml, ku, false);
+    const long long cu = cidx(d, i, j, ku);
+    const long long iz = pslot(d, 2, i, j, ku, zu);
+    const float pa = pml ? er.p[4][iz] : 0.f, pb = pml ? er.p[5][iz] : 0.f;
+    s1n = term(ix && jxz && kxyu, -cb * E0[cu], zu, pa, nullptr, 0);
+    s2n = term(iyz && jy && kxyu, cb * E1[cu], zu, pb, nullptr, 0);
+  }
   for (int k = k1 - 1; k >= k0; k--) {
     const bool kxy = k >= 1 && k <= nz - 2, kz = k <= nz - 2;
     const TP zk = tparam(d.ax[2], pml, k, false);
-    const long long c = cidx(d, ic, jc, k);
-    const float bx = cb * (on ? E0[c] : 0.f), by = cb * (on ? E1[c] : 0.f), bz = cb * (on ? E2[c] : 0.f);
+    const long long c = cidx(d, i, j, k), cx = cidx(d, ip, j, k), cy = cidx(d, i, jp, k);
+    // loads
+    const float e0 = E0[c], e1 = E1[c], e2 = E2[c];
+    const float h0 = H0[c], h1 = H1[c], h2 = H2[c];
+    const float e1x = E1[cx], e2x = E2[cx], e0y = E0[cy], e2y = E2[cy];
+    const long long iy0 = pslot(d, 1, i, j, k, y0), iz0 = pslot(d, 2, i, j, k, zk), ix0 = pslot(d, 0, i, j, k, x0);
+    const long long ix1 = pslot(d, 0, ip, j, k, x1), iy1 = pslot(d, 1, i, jp, k, y1);
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+    if (pml) {
+      p0 = er.p[2][iy0];  // Ex-y
+      p1 = er.p[4][iz0];  // Ex-z
+      p2 = er.p[5][iz0];  // Ey-z
+      p3 = er.p[0][ix0];  // Ey-x
+      p4 = er.p[1][ix0];  // Ez-x
+      p5 = er.p[3][iy0];  // Ez-y
+      q0 = er.p[0][ix1];  // Ey-x of p + e_x
+      q1 = er.p[1][ix1];  // Ez-x of p + e_x
+      q2 = er.p[2][iy1];  // Ex-y of p + e_y
+      q3 = er.p[3][iy1];  // Ez-y of p + e_y
+    }
+    // terms
+    const float bx = cb * e0, by = cb * e1, bz = cb * e2;
     const bool ux = ix && jxz && kxy, uy = iyz && jy && kxy, uz = iyz && jxz && kz;
-    const float s0 = term(d, ux, bx, y0, er.p[2], ew.p[2], 1, ic, jc, k);
-    const float s1 = term(d, ux, -bx, zk, er.p[4], ew.p[4], 2, ic, jc, k);
-    const float s2 = term(d, uy, by, zk, er.p[5], ew.p[5], 2, ic, jc, k);
-    const float s3 = term(d, uy, -by, x0, er.p[0], ew.p[0], 0, ic, jc, k);
-    const float s4 = term(d, uz, bz, x0, er.p[1], ew.p[1], 0, ic, jc, k);
-    const float s5 = term(d, uz, -bz, y0, er.p[3], ew.p[3], 1, ic, jc, k);
-    // z neighbour: carried, or computed at the top plane of the chunk
-    if (k == k1 - 1) {
-      s1n = s2n = 0.f;
-      if (k + 1 < nz && on) {
-        const int ku = k + 1;
-        const bool kxyu = ku >= 1 && ku <= nz - 2;
-        const TP zu = tparam(d.ax[2], pml, ku, false);
-        const long long cu = cidx(d, ic, jc, ku);
-        s1n = term(d, ix && jxz && kxyu, -cb * E0[cu], zu, er.p[4], nullptr, 2, ic, jc, ku);
-        s2n = term(d, iyz && jy && kxyu, cb * E1[cu], zu, er.p[5], nullptr, 2, ic, jc, ku);
-      }
-    }
-    // x neighbour: the next lane's own terms; the last lane computes them
-    float s3x = __shfl_down(s3, 1), s4x = __shfl_down(s4, 1);
-    if (lane == 63) {
-      s3x = s4x = 0.f;
-      if (xp && j < ny) {
-        const long long cx = cidx(d, ip, jc, k);
-        s3x = term(d, iyz1 && jy && kxy, -cb * E1[cx], x1, er.p[0], nullptr, 0, ip, jc, k);
-        s4x = term(d, iyz1 && jxz && kz, cb * E2[cx], x1, er.p[1], nullptr, 0, ip, jc, k);
-      }
-    }
-    // y neighbour: the next row's own terms through LDS; the last row computes them
-    const int buf = k & 1;
-    sy0[buf][r][lane] = s0;
-    sy5[buf][r][lane] = s5;
-    __syncthreads();
-    float s0y, s5y;
-    if (r < 3) {
-      s0y = sy0[buf][r + 1][lane];
-      s5y = sy5[buf][r + 1][lane];
-    } else {
-      s0y = s5y = 0.f;
-      if (yp && i < nx) {
-        const long long cy = cidx(d, ic, jp, k);
-        s0y = term(d, ix && jxz1 && kxy, cb * E0[cy], y1, er.p[2], nullptr, 1, ic, jp, k);
-        s5y = term(d, iyz && jxz1 && kz, -cb * E2[cy], y1, er.p[3], nullptr, 1, ic, jp, k);
-      }
-    }
-    if (on) {
-      O0[c] = H0[c] + ((s2 - s2n) + (s5 - s5y));
-      O1[c] = H1[c] + ((s1 - s1n) + (s4 - s4x));
-      O2[c] = H2[c] + ((s0 - s0y) + (s3 - s3x));
-    }
+    const float s0 = term(ux, bx, y0, p0, ew.p[2], iy0);
+    const float s1 = term(ux, -bx, zk, p1, ew.p[4], iz0);
+    const float s2 = term(uy, by, zk, p2, ew.p[5], iz0);
+    const float s3 = term(uy, -by, x0, p3, ew.p[0], ix0);
+    const float s4 = term(uz, bz, x0, p4, ew.p[1], ix0);
+    const float s5 = term(uz, -bz, y0, p5, ew.p[3], iy0);
+    const float s3x = xp ? term(iyz1 && jy && kxy, -cb * e1x, x1, q0, nullptr, 0) : 0.f;
+    const float s4x = xp ? term(iyz1 && jxz && kz, cb * e2x, x1, q1, nullptr, 0) : 0.f;
+    const float s0y = yp ? term(ix && jxz1 && kxy, cb * e0y, y1, q2, nullptr, 0) : 0.f;
+    const float s5y = yp ? term(iyz && jxz1 && kz, -cb * e2y, y1, q3, nullptr, 0) : 0.f;
+    O0[c] = h0 + ((s2 - s2n) + (s5 - s5y));
+    O1[c] = h1 + ((s1 - s1n) + (s4 - s4x));
+    O2[c] = h2 + ((s0 - s0y) + (s3 - s3x));
     s1n = s1;
     s2n = s2;
   }
@@ -298,25 +287,23 @@ __global__ void __launch_bounds__(256) k_adj_ha(Dev d, int cur, PsiSet er, PsiSe
 
 // Sweep B: Eb' (level cur ^ 1) = (ca) Eb (level cur) + sum of s(p - e_u) - s(p) over the H terms
 // of Hb' (level cur ^ 1) that read E(p); the H-term psib move from set `hr` to set `hw`.  Same
-// workgroup shape, marching upwards: s(p - e_z) is the previous plane's own term, s(p - e_x) the
-// previous lane's, s(p - e_y) the previous row's; the first lane, the first row and the bottom
-// plane of the chunk compute their neighbour's term directly.
+// workgroup shape, marching upwards: s(p - e_z) is the previous plane's own term; the x and y
+// neighbours' terms are evaluated in place; all loads of a plane are issued first.
 __global__ void __launch_bounds__(256) k_adj_eb(Dev d, int cur, PsiSet hr, PsiSet hw) {
-  __shared__ float sy0[2][4][64], sy5[2][4][64];
   const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int i = blockIdx.x * 64 + lane, j = blockIdx.y * 4 + r;
   const bool on = i < nx && j < ny;
-  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  if (!on) return;
   const int k0 = blockIdx.z * kAdjZ, k1 = min(k0 + kAdjZ, nz);
   const bool pml = d.np2 > 0;
-  const bool xm = i >= 1 && i <= nx, ym = j >= 1 && j <= ny;
-  const int im = max(min(i, nx) - 1, 0), jm = max(min(j, ny) - 1, 0);
-  const TP x0 = tparam(d.ax[0], pml, ic, true), x1 = tparam(d.ax[0], pml, im, true);
-  const TP y0 = tparam(d.ax[1], pml, jc, true), y1 = tparam(d.ax[1], pml, jm, true);
+  const bool xm = i >= 1, ym = j >= 1;
+  const int im = max(i - 1, 0), jm = max(j - 1, 0);
+  const TP x0 = tparam(d.ax[0], pml, i, true), x1 = tparam(d.ax[0], pml, im, true);
+  const TP y0 = tparam(d.ax[1], pml, j, true), y1 = tparam(d.ax[1], pml, jm, true);
   // H masks: Hx (j <= ny-2, k <= nz-2), Hy (i <= nx-2, k <= nz-2), Hz (i <= nx-2, j <= ny-2)
-  const bool ih = on && i <= nx - 2, jh = j <= ny - 2;
-  const bool ih1 = xm && im <= nx - 2 && j < ny, jh1 = ym && jm <= ny - 2;
+  const bool ih = i <= nx - 2, jh = j <= ny - 2;
+  const bool ih1 = xm && im <= nx - 2, jh1 = ym && jm <= ny - 2;
   // E masks of the own node
   const bool ex_i = i <= nx - 2, eyz_i = i >= 1 && i <= nx - 2;
   const bool exz_j = j >= 1 && j <= ny - 2, ey_j = j <= ny - 2;
@@ -326,64 +313,56 @@ __global__ void __launch_bounds__(256) k_adj_eb(Dev d, int cur, PsiSet hr, PsiSe
   float *O0 = (float *)d.e[cur ^ 1][0], *O1 = (float *)d.e[cur ^ 1][1], *O2 = (float *)d.e[cur ^ 1][2];
   const float db = d.a_db, ca = d.a_ca;
   float t1p = 0.f, t2p = 0.f;  // terms Hx-z, Hy-z of the node below (p - e_z)
+  if (k0 >= 1) {
+    const int kd = k0 - 1;
+    const TP zd = tparam(d.ax[2], pml, kd, true);
+    const long long cd = cidx(d, i, j, kd);
+    const long long iz = pslot(d, 2, i, j, kd, zd);
+    const float pa = pml ? hr.p[4][iz] : 0.f, pb = pml ? hr.p[5][iz] : 0.f;
+    t1p = term(jh, db * H0[cd], zd, pa, nullptr, 0);
+    t2p = term(ih, -db * H1[cd], zd, pb, nullptr, 0);
+  }
   for (int k = k0; k < k1; k++) {
     const bool kh = k <= nz - 2;
     const TP zk = tparam(d.ax[2], pml, k, true);
-    const long long c = cidx(d, ic, jc, k);
-    const float hx = on ? H0[c] : 0.f, hy = on ? H1[c] : 0.f, hz = on ? H2[c] : 0.f;
+    const long long c = cidx(d, i, j, k), cx = cidx(d, im, j, k), cy = cidx(d, i, jm, k);
+    const float hx = H0[c], hy = H1[c], hz = H2[c];
+    const float e0 = E0[c], e1 = E1[c], e2 = E2[c];
+    const float hyx = H1[cx], hzx = H2[cx], hxy = H0[cy], hzy = H2[cy];
+    const long long iy0 = pslot(d, 1, i, j, k, y0), iz0 = pslot(d, 2, i, j, k, zk), ix0 = pslot(d, 0, i, j, k, x0);
+    const long long ix1 = pslot(d, 0, im, j, k, x1), iy1 = pslot(d, 1, i, jm, k, y1);
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+    if (pml) {
+      p0 = hr.p[2][iy0];  // Hx-y
+      p1 = hr.p[4][iz0];  // Hx-z
+      p2 = hr.p[5][iz0];  // Hy-z
+      p3 = hr.p[0][ix0];  // Hy-x
+      p4 = hr.p[1][ix0];  // Hz-x
+      p5 = hr.p[3][iy0];  // Hz-y
+      q0 = hr.p[0][ix1];  // Hy-x of p - e_x
+      q1 = hr.p[1][ix1];  // Hz-x of p - e_x
+      q2 = hr.p[2][iy1];  // Hx-y of p - e_y
+      q3 = hr.p[3][iy1];  // Hz-y of p - e_y
+    }
     const float ax = -db * hx, ay = -db * hy, az = -db * hz;
-    const bool ux = on && jh && kh, uy = ih && kh, uz = ih && jh;
-    const float t0 = term(d, ux, ax, y0, hr.p[2], hw.p[2], 1, ic, jc, k);
-    const float t1 = term(d, ux, -ax, zk, hr.p[4], hw.p[4], 2, ic, jc, k);
-    const float t2 = term(d, uy, ay, zk, hr.p[5], hw.p[5], 2, ic, jc, k);
-    const float t3 = term(d, uy, -ay, x0, hr.p[0], hw.p[0], 0, ic, jc, k);
-    const float t4 = term(d, uz, az, x0, hr.p[1], hw.p[1], 0, ic, jc, k);
-    const float t5 = term(d, uz, -az, y0, hr.p[3], hw.p[3], 1, ic, jc, k);
-    if (k == k0) {
-      t1p = t2p = 0.f;
-      if (k >= 1 && on) {
-        const int kd = k - 1;
-        const TP zd = tparam(d.ax[2], pml, kd, true);
-        const long long cd = cidx(d, ic, jc, kd);
-        t1p = term(d, jh, db * H0[cd], zd, hr.p[4], nullptr, 2, ic, jc, kd);
-        t2p = term(d, ih, -db * H1[cd], zd, hr.p[5], nullptr, 2, ic, jc, kd);
-      }
-    }
-    float t3x = __shfl_up(t3, 1), t4x = __shfl_up(t4, 1);
-    if (lane == 0) {
-      t3x = t4x = 0.f;
-      if (xm && j < ny) {
-        const long long cx = cidx(d, im, jc, k);
-        t3x = term(d, ih1 && kh, db * H1[cx], x1, hr.p[0], nullptr, 0, im, jc, k);
-        t4x = term(d, ih1 && jh, -db * H2[cx], x1, hr.p[1], nullptr, 0, im, jc, k);
-      }
-    }
-    const int buf = k & 1;
-    sy0[buf][r][lane] = t0;
-    sy5[buf][r][lane] = t5;
-    __syncthreads();
-    float t0y, t5y;
-    if (r > 0) {
-      t0y = sy0[buf][r - 1][lane];
-      t5y = sy5[buf][r - 1][lane];
-    } else {
-      t0y = t5y = 0.f;
-      if (ym && i < nx) {
-        const long long cy = cidx(d, ic, jm, k);
-        t0y = term(d, jh1 && kh, -db * H0[cy], y1, hr.p[2], nullptr, 1, ic, jm, k);
-        t5y = term(d, ih && jh1, db * H2[cy], y1, hr.p[3], nullptr, 1, ic, jm, k);
-      }
-    }
-    if (on) {
-      const bool kxy = k >= 1 && k <= nz - 2;
-      const float ex = (t2p - t2) + (t5y - t5);
-      const float ey = (t1p - t1) + (t4x - t4);
-      const float ez = (t0y - t0) + (t3x - t3);
-      const float e0 = E0[c], e1 = E1[c], e2 = E2[c];
-      O0[c] = ((ex_i && exz_j && kxy) ? ca * e0 : e0) + ex;
-      O1[c] = ((eyz_i && ey_j && kxy) ? ca * e1 : e1) + ey;
-      O2[c] = ((eyz_i && exz_j && kh) ? ca * e2 : e2) + ez;
-    }
+    const bool ux = jh && kh, uy = ih && kh, uz = ih && jh;
+    const float t0 = term(ux, ax, y0, p0, hw.p[2], iy0);
+    const float t1 = term(ux, -ax, zk, p1, hw.p[4], iz0);
+    const float t2 = term(uy, ay, zk, p2, hw.p[5], iz0);
+    const float t3 = term(uy, -ay, x0, p3, hw.p[0], ix0);
+    const float t4 = term(uz, az, x0, p4, hw.p[1], ix0);
+    const float t5 = term(uz, -az, y0, p5, hw.p[3], iy0);
+    const float t3x = xm ? term(ih1 && kh, db * hyx, x1, q0, nullptr, 0) : 0.f;
+    const float t4x = xm ? term(ih1 && jh, -db * hzx, x1, q1, nullptr, 0) : 0.f;
+    const float t0y = ym ? term(jh1 && kh, -db * hxy, y1, q2, nullptr, 0) : 0.f;
+    const float t5y = ym ? term(ih && jh1, db * hzy, y1, q3, nullptr, 0) : 0.f;
+    const bool kxy = k >= 1 && k <= nz - 2;
+    const float ex = (t2p - t2) + (t5y - t5);
+    const float ey = (t1p - t1) + (t4x - t4);
+    const float ez = (t0y - t0) + (t3x - t3);
+    O0[c] = ((ex_i && exz_j && kxy) ? ca * e0 : e0) + ex;
+    O1[c] = ((eyz_i && ey_j && kxy) ? ca * e1 : e1) + ey;
+    O2[c] = ((eyz_i && exz_j && kh) ? ca * e2 : e2) + ez;
     t1p = t1;
     t2p = t2;
   }

@@ -39,30 +39,35 @@ __global__ void k_adj_zero_q(double *q, int n) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) q[t] = 0.0;
 }
 
-__global__ void __launch_bounds__(64) k_adj_sample(Dev d, const double *g, int n, int T, int cur) {
-  const int lane = threadIdx.x;
-  const int comp = lane >> 3, corner = lane & 7;
-  if (comp >= 3) return;
+// Transposed sampling: Eb += w g^n at every stencil node, one thread per distinct (component,
+// node) of the plan's table, its contributions added in observer order (each rounded to FP32 as
+// a stored field is), so that stencils sharing a node give the same bits as observers applied
+// one after the other.
+__global__ void __launch_bounds__(256) k_adj_sample(Dev d, const double *g, int n, int T, int cur) {
+  const int key = blockIdx.x * 256 + threadIdx.x;
+  if (key >= d.n_skeys) return;
+  const int comp = d.sk_comp[key];
   float *Eb = (float *)d.e[cur][comp];
-  for (int o = 0; o < d.n_obs; o++) {
-    const int *ix = d.obs_idx + (o * 3 + comp) * 3;
-    const double *tf = d.obs_t + (o * 3 + comp) * 3;
-    const int a = corner & 1, b = (corner >> 1) & 1, c = corner >> 2;
-    const double wgt = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]) * (c ? tf[2] : 1.0 - tf[2]);
-    const double gv = g[((long long)o * 3 + comp) * T + n];
-    const long long node = cidx(d, ix[0] + a, ix[1] + b, ix[2] + c);
-    Eb[node] = (float)((double)Eb[node] + wgt * gv);
-    __threadfence();  // observers one after the other: a later stencil may share a node
-  }
+  const long long node = d.sk_node[key];
+  float v = Eb[node];
+  for (int e = d.sk_ptr[key]; e < d.sk_ptr[key + 1]; e++)
+    v = (float)((double)v + d.se_w[e] * g[((long long)d.se_obs[e] * 3 + comp) * T + n]);
+  Eb[node] = v;
 }
 
-// With dth: also the cotangents of the source's non-linear parameters,
+// Transposed source of step n, dL/dq_b += -Cb v hat_b(z_s) sum W_r W_z Eb_z, as one FP64 workgroup
+// reduction (fixed order, deterministic).  With dth: also the cotangents of the source's
+// non-linear parameters,
 //   dL/dsigma_r  += -Cb v Q(z_s) sum dW_r/dsigma_r W_z Eb_z,
 //   dL/dz_entry  += -Cb v [Q'(z_s) sum W_r W_z Eb_z + Q(z_s) sum W_r dW_z/dz_s Eb_z]
 // (z_s moves one for one with z_entry; Q' is the slope of the hat interpolation, W_z' that of the
 // window-normalised Gaussian with the window held fixed), Q from the profile q.
-__global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, const double *q, double *dth, int cur) {
-  __shared__ double part[256], part_r[256], part_z[256];
+constexpr int kSrcThreads = 1024;
+
+__global__ void __launch_bounds__(kSrcThreads) k_adj_source(Dev d, int n, double *dq, const double *q, double *dth,
+                                                           int cur) {
+  __shared__ double part[kSrcThreads], part_r[kSrcThreads], part_z[kSrcThreads];
+  __shared__ double row_e[kMaxWz], row_d[kMaxWz], sums[2];
   const double tt = (n + 0.5) * d.dt;
   if (!d.src_on || tt < d.t_entry) return;
   const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
@@ -71,30 +76,43 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, co
   const int khi = (int)floor((zs + half) / d.dz - 0.5);
   const int m = min(khi - klo + 1, kMaxWz);
   const double sz2 = d.sigma_z * d.sigma_z;
-  double norm = 0.0, dnorm = 0.0;
-  for (int s = 0; s < m; s++) {
-    const double dd = (klo + s + 0.5) * d.dz - zs;
-    const double e = exp(-0.5 * dd * dd / sz2);
-    norm += e * d.dz;
-    dnorm += e * dd / sz2 * d.dz;
+  // the window's Gaussian per row, then its normalisation summed in row order
+  if ((int)threadIdx.x < m) {
+    const double dd = (klo + (int)threadIdx.x + 0.5) * d.dz - zs;
+    row_e[threadIdx.x] = exp(-0.5 * dd * dd / sz2);
+    row_d[threadIdx.x] = dd;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double norm = 0.0, dnorm = 0.0;
+    for (int s = 0; s < m; s++) {
+      norm += row_e[s] * d.dz;
+      dnorm += row_e[s] * row_d[s] / sz2 * d.dz;
+    }
+    sums[0] = norm;
+    sums[1] = dnorm;
+  }
+  __syncthreads();
+  const double norm = sums[0], dnorm = sums[1];
   const float *Ebz = (const float *)d.e[cur][2];
   const int npatch = d.src_ni * d.src_nj;
   double acc = 0.0, acc_r = 0.0, acc_z = 0.0;
-  for (int t = threadIdx.x; t < npatch * m; t += blockDim.x) {
+#pragma unroll 4
+  for (int t = threadIdx.x; t < npatch * m; t += kSrcThreads) {
     const int s = t / npatch, c = t % npatch;
     const int k = klo + s;
-    if (k < 0 || k > d.nz - 2) continue;
-    const double wr = d.wr[c];
-    if (wr == 0.0) continue;
+    const int kc = min(max(k, 0), d.nz - 2);
     const int i = d.src_i0 + c % d.src_ni, j = d.src_j0 + c / d.src_ni;
-    const double dd = (k + 0.5) * d.dz - zs;
-    const double e = exp(-0.5 * dd * dd / sz2);
+    // every operand loaded before the tests, so the loads of several items are in flight
+    const double wr = d.wr[c];
+    const double eb = (double)Ebz[cidx(d, i, j, kc)];
+    const double dwr = dth ? d.dwr[c] : 0.0;
+    if (k < 0 || k > d.nz - 2 || wr == 0.0) continue;
+    const double e = row_e[s], dd = row_d[s];
     const double wz = e / norm;
-    const double eb = (double)Ebz[cidx(d, i, j, k)];
     acc += wr * wz * eb;
     if (dth) {
-      acc_r += d.dwr[c] * wz * eb;
+      acc_r += dwr * wz * eb;
       acc_z += wr * (e * dd / sz2 / norm - wz * dnorm / norm) * eb;
     }
   }
@@ -102,7 +120,7 @@ __global__ void __launch_bounds__(256) k_adj_source(Dev d, int n, double *dq, co
   part_r[threadIdx.x] = acc_r;
   part_z[threadIdx.x] = acc_z;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kSrcThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       part[threadIdx.x] += part[threadIdx.x + w];
       part_r[threadIdx.x] += part_r[threadIdx.x + w];
@@ -394,8 +412,10 @@ hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int 
                                const EpsTerm *eps) {
   const int T = p.grid.n_steps;
   const int cur = parity & 1;
-  if (d.n_obs > 0) hipLaunchKernelGGL(k_adj_sample, dim3(1), dim3(64), 0, s, d, dl_dw, step, T, cur);
-  if (d.src_on) hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(256), 0, s, d, step, dl_dq, q_dev, dl_dtheta, cur);
+  if (d.n_skeys > 0)
+    hipLaunchKernelGGL(k_adj_sample, dim3((d.n_skeys + 255) / 256), dim3(256), 0, s, d, dl_dw, step, T, cur);
+  if (d.src_on)
+    hipLaunchKernelGGL(k_adj_source, dim3(1), dim3(kSrcThreads), 0, s, d, step, dl_dq, q_dev, dl_dtheta, cur);
   dim3 grid((d.nx + 63) / 64, (d.ny + 3) / 4, (d.nz + kAdjZ - 1) / kAdjZ);
   if (eps) hipLaunchKernelGGL(k_adj_eps, grid, dim3(256), 0, s, d, eps->e0, eps->e1, eps->g, eps->coef, cur);
   // psib of the E terms alternate between the forward's psi_e slabs and the adjoint's second

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -362,6 +363,44 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
 
   // workspace layout
   int pitch = (G.nx + 15) / 16 * 16;
+  {
+    // transposed sampling table: the adjoint adds w g^n into Eb at each stencil node; nodes
+    // shared by several stencils take their contributions in observer order
+    const long long plane_ = (long long)pitch * G.ny;
+    std::map<std::pair<int, long long>, int> key_of;
+    std::vector<std::vector<std::pair<int, double>>> lists;
+    for (int o = 0; o < obs->n_obs; o++)
+      for (int c = 0; c < 3; c++) {
+        const int *ix = &p->obs_idx[(o * 3 + c) * 3];
+        const double *tf = &p->obs_t[(o * 3 + c) * 3];
+        for (int corner = 0; corner < 8; corner++) {
+          const int a = corner & 1, b = (corner >> 1) & 1, cc = corner >> 2;
+          const double w = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]) * (cc ? tf[2] : 1.0 - tf[2]);
+          const long long node = (long long)(ix[2] + cc) * plane_ + (long long)(ix[1] + b) * pitch + (ix[0] + a);
+          auto it = key_of.find({c, node});
+          int key;
+          if (it == key_of.end()) {
+            key = (int)lists.size();
+            key_of[{c, node}] = key;
+            lists.emplace_back();
+            p->sk_comp.push_back(c);
+            p->sk_node.push_back(node);
+          } else {
+            key = it->second;
+          }
+          lists[key].push_back({o, w});
+        }
+      }
+    p->sk_ptr.assign(1, 0);
+    for (const auto &l : lists) {
+      for (const auto &e : l) {
+        p->se_obs.push_back(e.first);
+        p->se_w.push_back(e.second);
+      }
+      p->sk_ptr.push_back((int)p->se_obs.size());
+    }
+    D.n_skeys = (int)lists.size();
+  }
   const uint64_t field = align256((uint64_t)pitch * G.ny * G.nz * p->elem_bytes);
   uint64_t off = 0;
   for (int l = 0; l < 2; l++)
@@ -412,6 +451,16 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       p->off_psi_eb[u][t] = off;
       off += align256(p->psi_len[u] * 4);
     }
+  p->off_sknode = off;
+  off += align256(std::max<size_t>(p->sk_node.size(), 1) * sizeof(long long));
+  p->off_skcomp = off;
+  off += align256(std::max<size_t>(p->sk_comp.size(), 1) * sizeof(int));
+  p->off_skptr = off;
+  off += align256(std::max<size_t>(p->sk_ptr.size(), 1) * sizeof(int));
+  p->off_seobs = off;
+  off += align256(std::max<size_t>(p->se_obs.size(), 1) * sizeof(int));
+  p->off_sew = off;
+  off += align256(std::max<size_t>(p->se_w.size(), 1) * sizeof(double));
   p->ws_bytes = off;
 
   // kernel parameter block (device pointers are filled at bind time)
@@ -510,6 +559,11 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
   D.q_bins = (const double *)(ws + p->off_q);
   D.obs_idx = (const int *)(ws + p->off_oidx);
   D.obs_t = (const double *)(ws + p->off_ot);
+  D.sk_node = (const long long *)(ws + p->off_sknode);
+  D.sk_comp = (const int *)(ws + p->off_skcomp);
+  D.sk_ptr = (const int *)(ws + p->off_skptr);
+  D.se_obs = (const int *)(ws + p->off_seobs);
+  D.se_w = (const double *)(ws + p->off_sew);
   D.nan_flag = (int *)(ws + p->off_nan);
   D.slow_tiles = (const int *)(ws + p->off_tiles);
   D.layer_tiles = (const int *)(ws + p->off_ltiles);
@@ -524,6 +578,11 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
       {p->off_q, p->q_bins.data(), p->q_bins.size() * sizeof(double)},
       {p->off_oidx, p->obs_idx.data(), p->obs_idx.size() * sizeof(int)},
       {p->off_ot, p->obs_t.data(), p->obs_t.size() * sizeof(double)},
+      {p->off_sknode, p->sk_node.data(), p->sk_node.size() * sizeof(long long)},
+      {p->off_skcomp, p->sk_comp.data(), p->sk_comp.size() * sizeof(int)},
+      {p->off_skptr, p->sk_ptr.data(), p->sk_ptr.size() * sizeof(int)},
+      {p->off_seobs, p->se_obs.data(), p->se_obs.size() * sizeof(int)},
+      {p->off_sew, p->se_w.data(), p->se_w.size() * sizeof(double)},
       {p->off_tiles, p->slow_tiles.data(), p->slow_tiles.size() * sizeof(int)},
       {p->off_ltiles, p->layer_tiles.data(), p->layer_tiles.size() * sizeof(int)},
   };

@@ -57,6 +57,12 @@ struct Dev {
   int n_obs;
   const int *obs_idx;        // [n_obs][3 comps][3] base node of the trilinear stencil
   const double *obs_t;       // [n_obs][3 comps][3] fractional offsets
+  // transposed sampling: one key per distinct (component, stencil node), its contributions
+  // (observer, FP64 weight) in observer order
+  int n_skeys;
+  const long long *sk_node;
+  const int *sk_comp, *sk_ptr, *se_obs;
+  const double *se_w;
   double inv_se;             // 1/scale_e for the gather
   int *nan_flag;
   const int *slow_tiles;     // [n_slow][2] (ty, zc) of the tiles taking the general path
@@ -98,11 +104,15 @@ struct chf_plan {
   std::vector<double> wr;      // radial weights
   std::vector<int> obs_idx;
   std::vector<double> obs_t;
+  std::vector<long long> sk_node;
+  std::vector<int> sk_comp, sk_ptr, se_obs;
+  std::vector<double> se_w;
   size_t off_tabf[3][10], off_tabi[3][2];
   // workspace layout (byte offsets)
   uint64_t off_e[2][3], off_h[2][3], off_psi_e[3][2], off_psi_h[2][3][2];
   uint64_t off_tf, off_ti, off_wr, off_q, off_oidx, off_ot, off_nan, off_tiles, off_ltiles, ws_bytes;
   uint64_t off_psi_eb[3][2];   // after the snapshot region: not part of the forward state
+  uint64_t off_sknode, off_skcomp, off_skptr, off_seobs, off_sew;
   std::vector<int> slow_tiles, layer_tiles;
   uint64_t field_bytes, psi_bytes, psi_len[3];
   char *ws = nullptr;

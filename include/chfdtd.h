@@ -216,6 +216,23 @@ chf_status chf_adjoint_steps_eps(chf_plan *plan, void *stream, const double *dl_
 chf_status chf_adjoint_source_params(chf_plan *plan, void *stream, const double *dl_dw_dev,
                                      const double *q_bins_dev, double *dl_dq_dev, double *dl_dtheta_dev);
 
+/* The checkpointed reverse sweep in one call: the schedule of chf_adjoint_begin/steps with
+   recomputation, driven by the library.  `fwd` is a second plan made from the same descriptors
+   with a workspace of its own (the plan's grid, step count, storage and boundary, else
+   CHF_EINVAL); it runs the forward pass from zero fields with q_bins_dev (DEVICE, NULL = its
+   own profile), keeping a snapshot at the start of every `every`-step segment in snapshots_dev
+   (DEVICE, caller-owned, at least ceil(n_steps / every) * chf_plan_state_bytes(fwd) bytes, else
+   CHF_ENOMEM).  Then, segments last to first, it restores the segment's snapshot, recomputes the
+   segment and applies the segment's transposed steps on `plan`.  dl_dw_dev / dl_dq_dev as
+   chf_adjoint (dL/dq is zeroed first and comes out bit for bit as chf_adjoint's).  With
+   dl_deps_dev (DEVICE FP64 [3][nz][ny][nx], accumulated) the recomputation keeps the segment's E
+   levels in e_levels_dev (DEVICE FP32 [every + 1][3][nz][ny][nx], caller-owned) and the reverse
+   steps add the permittivity cotangent as chf_adjoint_steps_eps does; both pointers are NULL or
+   both set.  fwd's field state and plan's are destroyed; PEC and CPML only. */
+chf_status chf_adjoint_checkpointed(chf_plan *plan, chf_plan *fwd, void *stream, const double *q_bins_dev,
+                                    const double *dl_dw_dev, double *dl_dq_dev, int32_t every, void *snapshots_dev,
+                                    uint64_t snapshots_bytes, float *e_levels_dev, double *dl_deps_dev);
+
 /* Forward-state snapshots (checkpoints, resume).  A snapshot is the plan's whole field and
    CPML state -- both time levels of E and H and every psi array -- as a DEVICE byte image of
    chf_plan_state_bytes bytes owned by the caller.  save copies it out (stream-ordered) and

@@ -22,7 +22,7 @@ KERNEL = {"auto": 0, "split": 1, "fused": 2, "fused_prefetch": 3}
 EXPORTED = [
     "chf_plan_create", "chf_plan_destroy", "chf_plan_workspace_bytes", "chf_plan_bind_workspace",
     "chf_plan_reset", "chf_forward", "chf_forward_timed", "chf_forward_graph", "chf_adjoint",
-    "chf_adjoint_begin", "chf_adjoint_steps", "chf_adjoint_steps_eps", "chf_adjoint_source_params", "chf_plan_state_bytes",
+    "chf_adjoint_begin", "chf_adjoint_steps", "chf_adjoint_steps_eps", "chf_adjoint_checkpointed", "chf_adjoint_source_params", "chf_plan_state_bytes",
     "chf_plan_save_state",
     "chf_plan_load_state", "chf_plan_sync",
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
@@ -163,6 +163,8 @@ def lib():
         L.chf_adjoint_steps.argtypes = [vp, vp, vp, vp, ct.c_int32, ct.c_int32]
         L.chf_adjoint_steps_eps.restype = ct.c_int
         L.chf_adjoint_steps_eps.argtypes = [vp, vp, vp, vp, ct.c_int32, ct.c_int32, vp, vp]
+        L.chf_adjoint_checkpointed.restype = ct.c_int
+        L.chf_adjoint_checkpointed.argtypes = [vp, vp, vp, vp, vp, vp, ct.c_int32, vp, ct.c_uint64, vp, vp]
         L.chf_adjoint_source_params.restype = ct.c_int
         L.chf_adjoint_source_params.argtypes = [vp, vp, vp, vp, vp, vp]
         L.chf_plan_state_bytes.restype = ct.c_int

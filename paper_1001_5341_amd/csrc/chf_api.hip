@@ -845,6 +845,56 @@ chf_status chf_adjoint_steps_eps(chf_plan *p, void *stream, const double *dl_dw_
   return CHF_OK;
 }
 
+chf_status chf_adjoint_checkpointed(chf_plan *p, chf_plan *fwd, void *stream, const double *q_bins_dev,
+                                    const double *dl_dw_dev, double *dl_dq_dev, int32_t every, void *snapshots_dev,
+                                    uint64_t snapshots_bytes, float *e_levels_dev, double *dl_deps_dev) {
+  if (!p || !fwd || !dl_dq_dev || !snapshots_dev || (p->dev.n_obs > 0 && !dl_dw_dev))
+    return fail(CHF_EINVAL, "NULL argument");
+  if (p == fwd) return fail(CHF_EINVAL, "the recomputation needs a second plan");
+  if ((dl_deps_dev != nullptr) != (e_levels_dev != nullptr))
+    return fail(CHF_EINVAL, "e_levels_dev and dl_deps_dev go together");
+  if (!p->ws || !fwd->ws) return fail(CHF_ESTATE, "no workspace bound");
+  const chf_grid &a = p->grid, &b = fwd->grid;
+  if (a.nx != b.nx || a.ny != b.ny || a.nz != b.nz || a.n_steps != b.n_steps || p->storage != fwd->storage ||
+      p->bnd.kind != fwd->bnd.kind || p->bnd.npml != fwd->bnd.npml)
+    return fail(CHF_EINVAL, "the recomputing plan must have the plan's grid, steps, storage and boundary");
+  const int T = a.n_steps;
+  if (every < 1) return fail(CHF_EINVAL, "every must be >= 1");
+  const int K = std::min(every, std::max(T, 1));
+  const int n_seg = (T + K - 1) / K;
+  const uint64_t sb = fwd->off_tf;
+  if (snapshots_bytes < sb * (uint64_t)n_seg) return fail(CHF_ENOMEM, "snapshot buffer too small");
+  char *snaps = (char *)snapshots_dev;
+  const long long level = 3LL * a.nx * a.ny * a.nz;
+  // forward run with a snapshot at the start of every segment
+  chf_status st = chf_plan_reset(fwd, stream);
+  int32_t step = 0;
+  for (int g = 0; g < n_seg && st == CHF_OK; g++) {
+    st = chf_plan_save_state(fwd, stream, snaps + sb * g, &step);
+    if (st == CHF_OK) st = chf_forward(fwd, stream, q_bins_dev, nullptr, std::min(K, T - g * K), 0, 0);
+  }
+  if (st == CHF_OK) st = chf_adjoint_begin(p, stream, dl_dq_dev);
+  // segments last to first: restore, recompute (keeping the E levels when the permittivity
+  // gradient is asked for), then the segment's transposed steps
+  for (int g = n_seg - 1; g >= 0 && st == CHF_OK; g--) {
+    const int t0 = g * K, t1 = std::min((g + 1) * K, T);
+    st = chf_plan_load_state(fwd, stream, snaps + sb * g, t0);
+    if (st != CHF_OK) break;
+    if (dl_deps_dev) {
+      for (int m = 0; m <= t1 - t0 && st == CHF_OK; m++) {
+        if (m) st = chf_forward(fwd, stream, q_bins_dev, nullptr, 1, 0, 0);
+        for (int c = 0; c < 3 && st == CHF_OK; c++)
+          st = chf_plan_get_field(fwd, stream, c, e_levels_dev + m * level + c * (level / 3));
+      }
+      if (st == CHF_OK) st = chf_adjoint_steps_eps(p, stream, dl_dw_dev, dl_dq_dev, t0, t1, e_levels_dev, dl_deps_dev);
+    } else {
+      st = chf_forward(fwd, stream, q_bins_dev, nullptr, t1 - t0, 0, 0);
+      if (st == CHF_OK) st = chf_adjoint_steps(p, stream, dl_dw_dev, dl_dq_dev, t0, t1);
+    }
+  }
+  return st;
+}
+
 chf_status chf_adjoint(chf_plan *p, void *stream, const double *dl_dw_dev, double *dl_dq_dev) {
   if (!p || !dl_dq_dev || (p->dev.n_obs > 0 && !dl_dw_dev)) return fail(CHF_EINVAL, "NULL argument");
   chf_status st = chf_adjoint_begin(p, stream, dl_dq_dev);

@@ -283,32 +283,43 @@ def checkpointed_adjoint(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int]
     snapshot every `every` steps (default ceil(sqrt(T))); the reverse sweep then takes the
     segments last to first, restores each segment's snapshot, recomputes its forward steps
     (with the profile q_bins the forward run used, default the plan's)
-    and applies the transposed steps of that segment to the adjoint state.  With verify, every
-    recomputed segment must end on the next snapshot bit for bit (a determinism check).
+    and applies the transposed steps of that segment to the adjoint state.
+
+    verify=False runs the whole schedule in the library (chf_adjoint_checkpointed).  verify=True
+    drives the same schedule from here through the step-range entry points and checks that every
+    recomputed segment ends on the next snapshot bit for bit (a determinism check).
 
     The profile map is linear with zero initial fields, so the transposed steps do not read
     the recomputed forward states: the result is bitwise that of Plan.adjoint.  The schedule
-    is the one gradients with respect to non-linear parameters need."""
+    is the one gradients with respect to non-linear parameters need (eps_sensitivity)."""
     T = plan.n_steps
-    K = max(1, every or math.ceil(math.sqrt(T)))
+    K = max(1, min(T, every or math.ceil(math.sqrt(T))))
     n_seg = (T + K - 1) // K
     fwd = Plan(plan.w, storage=plan.storage, device=plan.device)
     try:
         nbytes = fwd.state_bytes()
         snaps = torch.empty((n_seg, nbytes), dtype=torch.uint8, device=plan.device)
+        dl_dw = dl_dw.to(torch.float64).contiguous()
+        dq = torch.zeros(len(plan.w.q_bins), dtype=torch.float64, device=plan.device)
+        if not verify:
+            q = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
+            N.check(N.lib().chf_adjoint_checkpointed(
+                plan._h, fwd._h, _stream_handle(stream), q, ct.c_void_p(dl_dw.data_ptr()),
+                ct.c_void_p(dq.data_ptr()), K, ct.c_void_p(snaps.data_ptr()), snaps.numel(), ct.c_void_p(),
+                ct.c_void_p()), "chf_adjoint_checkpointed")
+            plan.sync(stream)
+            return dq
         fwd.reset(stream)
         for s_ in range(n_seg):
             fwd.save_state(snaps[s_], stream)
             fwd.forward(min(K, T - s_ * K), None, 0, q_bins, stream)
-        dl_dw = dl_dw.to(torch.float64).contiguous()
-        dq = torch.zeros(len(plan.w.q_bins), dtype=torch.float64, device=plan.device)
-        tail = torch.empty(nbytes, dtype=torch.uint8, device=plan.device) if verify else None
+        tail = torch.empty(nbytes, dtype=torch.uint8, device=plan.device)
         plan.adjoint_begin(dq, stream)
         for s_ in reversed(range(n_seg)):
             t0, t1 = s_ * K, min((s_ + 1) * K, T)
             fwd.load_state(snaps[s_], t0, stream)
             fwd.forward(t1 - t0, None, 0, q_bins, stream)
-            if verify and s_ + 1 < n_seg:
+            if s_ + 1 < n_seg:
                 fwd.save_state(tail, stream)
                 if not torch.equal(tail, snaps[s_ + 1]):
                     raise RuntimeError(f"recomputed segment {s_} does not reproduce its snapshot")
@@ -325,39 +336,29 @@ def eps_sensitivity(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int] = No
     evaluated at the plan's uniform medium) and dL/dq, for L = <dl_dw, w>.
 
     The permittivity is a non-linear parameter: its cotangent at step n reads the forward
-    levels E^n and E^{n+1}, which come back in reverse order by checkpointed recomputation.
-    A forward run on a second workspace keeps a snapshot every `every` steps (default
-    ceil(sqrt(T))); the reverse sweep takes the segments last to first, restores a segment's
-    snapshot, recomputes its steps one by one keeping the E levels (every + 1 levels of
-    3 nx ny nz FP32 values), and runs that segment's transposed steps with the permittivity
-    term.  Returns (dl_deps [3, nz, ny, nx] FP64, dl_dq [n_bins] FP64); for a uniform medium
-    with PEC walls, dL/deps_r of the plan is dl_deps.sum()."""
+    levels E^n and E^{n+1}, which come back in reverse order by checkpointed recomputation
+    (chf_adjoint_checkpointed): a forward run on a second workspace keeps a snapshot every
+    `every` steps (default ceil(sqrt(T))); the reverse sweep takes the segments last to first,
+    restores a segment's snapshot, recomputes its steps one by one keeping the E levels
+    (every + 1 levels of 3 nx ny nz FP32 values), and runs that segment's transposed steps with
+    the permittivity term.  Returns (dl_deps [3, nz, ny, nx] FP64, dl_dq [n_bins] FP64); for a
+    uniform medium with PEC walls, dL/deps_r of the plan is dl_deps.sum()."""
     w = plan.w
     T = plan.n_steps
     K = max(1, min(T, every or math.ceil(math.sqrt(T))))
     n_seg = (T + K - 1) // K
     fwd = Plan(w, storage=plan.storage, device=plan.device)
     try:
-        nbytes = fwd.state_bytes()
-        snaps = torch.empty((n_seg, nbytes), dtype=torch.uint8, device=plan.device)
-        fwd.reset(stream)
-        for s_ in range(n_seg):
-            fwd.save_state(snaps[s_], stream)
-            fwd.forward(min(K, T - s_ * K), None, 0, q_bins, stream)
+        snaps = torch.empty((n_seg, fwd.state_bytes()), dtype=torch.uint8, device=plan.device)
         dl_dw = dl_dw.to(torch.float64).contiguous()
         dq = torch.zeros(len(w.q_bins), dtype=torch.float64, device=plan.device)
         g = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float64, device=plan.device)
         levels = torch.empty((K + 1, 3, w.nz, w.ny, w.nx), dtype=torch.float32, device=plan.device)
-        plan.adjoint_begin(dq, stream)
-        for s_ in reversed(range(n_seg)):
-            t0, t1 = s_ * K, min((s_ + 1) * K, T)
-            fwd.load_state(snaps[s_], t0, stream)
-            for m in range(t1 - t0 + 1):
-                if m:
-                    fwd.forward(1, None, 0, q_bins, stream)
-                for c in range(3):
-                    fwd.get_field(c, stream, out=levels[m, c])
-            plan.adjoint_steps_eps(dl_dw, dq, t0, t1, levels[: t1 - t0 + 1], g, stream)
+        q = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
+        N.check(N.lib().chf_adjoint_checkpointed(
+            plan._h, fwd._h, _stream_handle(stream), q, ct.c_void_p(dl_dw.data_ptr()), ct.c_void_p(dq.data_ptr()),
+            K, ct.c_void_p(snaps.data_ptr()), snaps.numel(), ct.c_void_p(levels.data_ptr()),
+            ct.c_void_p(g.data_ptr())), "chf_adjoint_checkpointed")
         plan.sync(stream)
         return g, dq
     finally:

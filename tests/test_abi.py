@@ -162,6 +162,18 @@ def test_snapshot_size_and_adjoint_state_checks():
         assert N.STATUS[N.lib().chf_adjoint_steps_eps(h, None, one, one, 0, 5, None, one)] == "CHF_EINVAL"
         assert N.STATUS[N.lib().chf_adjoint_steps_eps(h, None, one, one, 0, 5, one, None)] == "CHF_EINVAL"
         assert N.STATUS[N.lib().chf_adjoint_steps_eps(h, None, one, one, 0, 5, one, one)] == "CHF_ESTATE"
+        L = N.lib()
+        h2 = solver.create_plan_handle(W.small_shower())
+        try:
+            def ck(a, b, snaps=one, every=4, lv=None, dg=None):
+                return N.STATUS[L.chf_adjoint_checkpointed(a, b, None, None, one, one, every, snaps, 1 << 40, lv, dg)]
+            assert ck(h, None) == "CHF_EINVAL"
+            assert ck(h, h) == "CHF_EINVAL"            # the recomputation needs a second plan
+            assert ck(h, h2, snaps=None) == "CHF_EINVAL"
+            assert ck(h, h2, lv=one) == "CHF_EINVAL"    # levels without the permittivity output
+            assert ck(h, h2) == "CHF_ESTATE"            # no workspace bound
+        finally:
+            L.chf_plan_destroy(h2)
     finally:
         N.lib().chf_plan_destroy(h)
 

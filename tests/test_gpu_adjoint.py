@@ -106,6 +106,25 @@ def test_checkpointed_adjoint_bitwise_equals_single_sweep(gpu):
     plan.close()
 
 
+def test_library_checkpointed_adjoint_bitwise(gpu):
+    """The schedule run by the library (chf_adjoint_checkpointed) gives the one-sweep adjoint's
+    bits, for a ragged split, one segment and one step per segment, and with a profile other than
+    the plan's as the forward run's."""
+    w = W.small_shower(seed=15, nx=40, ny=36, nz=64, n_steps=110, n_obs=4, npml=6)
+    banner("library checkpointed adjoint")
+    plan = solver.Plan(w)
+    g = torch.from_numpy(np.random.default_rng(4).standard_normal((w.n_obs, 3, w.n_steps))).to(plan.device)
+    ref = plan.adjoint(g)
+    plan.sync()
+    for every in (37, w.n_steps, 1):
+        got = solver.checkpointed_adjoint(plan, g, every=every, verify=False)
+        assert torch.equal(got, ref), every
+    q2 = torch.from_numpy(np.asarray(w.q_bins) * 0.5).to(plan.device)
+    got = solver.checkpointed_adjoint(plan, g, every=23, verify=False, q_bins=q2)
+    assert torch.equal(got, solver.checkpointed_adjoint(plan, g, every=23, verify=True, q_bins=q2))
+    plan.close()
+
+
 def test_state_snapshot_resumes_bitwise(gpu):
     w = W.small_shower(seed=14, n_obs=4)
     print(f"\n[gpu-adjoint] snapshot resume {w.name}", flush=True)

@@ -4,6 +4,9 @@
   radiation terms, retarded time t - r/v): the time-domain form of the Green's-function
   solution the paper starts from (Coherent Cherenkov Pulses section, vector potential
   integral), for a single current element.
+* The superposition of such dipoles for a whole sampled current distribution J_z(x, t) on a
+  set of points: the continuum field of that distribution (static, induction and radiation
+  terms), against which the lattice's propagation of the same source is checked.
 * Fraunhofer spectrum of a line current (the paper's far-field approximation) and the
   closed form of the 1-D far-field formula for a Gaussian profile (Comparison section).
 * Cherenkov cone geometry: cos(theta_c) = 1/(n beta), which is where the paper's phase
@@ -38,6 +41,60 @@ def dipole_e_field(r_vec, t, p, pd, pdd, eps_r: float, mu_r: float = 1.0):
     b = rh * rh[2] - z                # (r^(r^.z) - z)
     E = (np.outer(P, a) / r ** 3 + np.outer(PD, a) / (v * r ** 2) + np.outer(PDD, b) / (v * v * r))
     return E / (4.0 * math.pi * eps)
+
+
+def dipole_superposition(pos, pdot_half, dt: float, obs, t_out, eps_r: float, mu_r: float = 1.0):
+    """E at observers from z-directed point dipoles at `pos` (M, 3) whose moment derivatives
+    dp/dt (= J_z dV, A m) are sampled at the half steps (n + 1/2) dt, n = 0..T-1 (pdot_half (M, T);
+    zero before).  Each dipole's moment at the integer steps is p_n = dt sum_{m<n} pdot_{m+1/2},
+    dp/dt there the mean of the neighbouring half steps, d2p/dt2 their difference over dt; the
+    three are interpolated linearly in time at the retarded time t - r/v and put into the
+    dipole field (near, intermediate and radiation terms).  obs: (n_obs, 3); t_out: times.
+    Returns (n_obs, 3, len(t_out))."""
+    eps = EPS0 * eps_r
+    v = C0 / math.sqrt(eps_r * mu_r)
+    pos = np.asarray(pos, dtype=np.float64)
+    M, T = pdot_half.shape
+    zero = np.zeros((M, 1))
+    p_int = np.concatenate([zero, np.cumsum(pdot_half, axis=1) * dt], axis=1)          # n = 0..T
+    pdp = np.concatenate([zero, pdot_half, zero], axis=1)                              # n -1/2 .. T+1/2
+    pd_int = 0.5 * (pdp[:, :-1] + pdp[:, 1:])
+    pdd_int = (pdp[:, 1:] - pdp[:, :-1]) / dt
+    t_out = np.asarray(t_out, dtype=np.float64)
+    out = np.zeros((len(obs), 3, len(t_out)))
+    for o, ob in enumerate(np.asarray(obs, dtype=np.float64)):
+        rv = ob[None, :] - pos
+        r = np.linalg.norm(rv, axis=1)
+        rh = rv / r[:, None]
+        s = (t_out[None, :] - (r / v)[:, None]) / dt
+        i0 = np.clip(np.floor(s).astype(np.int64), 0, T - 1)
+        f = np.clip(s - i0, 0.0, 1.0)
+        valid = s >= 0
+
+        def at(a):
+            x = np.take_along_axis(a, i0, axis=1) * (1 - f) + np.take_along_axis(a, i0 + 1, axis=1) * f
+            return np.where(valid, x, 0.0)
+
+        P, PD, PDD = at(p_int), at(pd_int), at(pdd_int)
+        for c in range(3):
+            zc = 1.0 if c == 2 else 0.0
+            a_c = 3.0 * rh[:, c] * rh[:, 2] - zc
+            b_c = rh[:, c] * rh[:, 2] - zc
+            E = (P * (a_c / r ** 3)[:, None] + PD * (a_c / (v * r ** 2))[:, None]
+                 + PDD * (b_c / (v * v * r))[:, None])
+            out[o, c] = E.sum(axis=0) / (4.0 * math.pi * eps)
+    return out
+
+
+def lowpass(x, dt: float, fc: float):
+    """Gaussian low-pass exp(-(f/fc)^2) along the last axis, the record extended by its edge
+    values on both sides (so that a static tail does not wrap round)."""
+    n = x.shape[-1]
+    padn = 4 * n
+    xp = np.pad(x, [(0, 0)] * (x.ndim - 1) + [(n, padn - 2 * n)], mode="edge")
+    X = np.fft.rfft(xp, axis=-1)
+    X *= np.exp(-(np.fft.rfftfreq(padn, dt) / fc) ** 2)
+    return np.fft.irfft(X, padn, axis=-1)[..., n:2 * n]
 
 
 def gaussian_dipole(p0: float, t0: float, tau: float):

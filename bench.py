@@ -587,6 +587,8 @@ def main():
                     help="run a 256 MiB device copy first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--pmc-command", default="", help="command recorded in the counter summary")
+    ap.add_argument("--leg", choices=["adjoint", "batch"], default=None,
+                    help="run one extra leg of the default line alone and print its JSON")
     args = ap.parse_args()
     # tile shapes measured on MI355X ship with the package; missing shapes are tuned and added
     os.environ.setdefault("CHFDTD_TUNE_CACHE", os.path.join(ROOT, "paper_1001_5341_amd", "tune_cache_gfx950.json"))
@@ -596,6 +598,12 @@ def main():
                 else [args.waves, args.zchunk, args.kernel if args.kernel == "fused_prefetch" else "fused"])
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.storage,
                       args.pmc_command, tile)
+        return
+    if args.leg:
+        import torch
+
+        torch.cuda.set_device(0)
+        print(json.dumps(adjoint_summary() if args.leg == "adjoint" else batch_summary()), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "

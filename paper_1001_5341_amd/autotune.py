@@ -86,12 +86,12 @@ def _time_candidate(w, storage: str, waves: int, zchunk: int, steps: int, device
 
 def tune(w, storage: str = "fp32", steps: int = 48, cache_path: Optional[str] = None,
          candidates: Optional[Sequence[Tuple[int, int]]] = None, use_cache: bool = True,
-         device=None) -> dict:
+         device=None, key_suffix: str = "") -> dict:
     """Best (waves_per_block, z_chunk, kernel) for this workload shape; cached by shape_key().
     A cache entry without a kernel is the plain fused sweep."""
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     path = cache_path or default_cache_path()
-    key = shape_key(w, storage, device)
+    key = shape_key(w, storage, device) + key_suffix
     cands = [_cand(c) for c in (candidates or CANDIDATES)]
     if use_cache:
         hit = _load(path).get(key)
@@ -132,7 +132,9 @@ def tuned_plan(w, storage: str = "fp32", **kw) -> "solver.Plan":
 
 def tune_batch(workloads: Iterable, storage: str = "fp32", **kw) -> list:
     """Per-member z chunks for a batch (one waves_per_block for all members: the most common
-    best value)."""
+    best value).  Cached under the member shape's key with the suffix "/batch", apart from
+    the plan tunings of the same shape (the batched sweeps offer no prefetching variant)."""
+    kw.setdefault("key_suffix", "/batch")
     res = [tune(w, storage, **kw) for w in workloads]
     waves = max({r["waves"] for r in res}, key=lambda v: sum(r["waves"] == v for r in res))
     return [{"waves": waves, "z_chunk": r["z_chunk"]} for r in res]

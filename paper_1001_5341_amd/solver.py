@@ -63,6 +63,9 @@ class Plan:
         self.w = w
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.storage = storage
+        # execution choices, reused by the second plan of checkpointed recomputations
+        self.exec_kw = dict(kernel=kernel, rows=rows, waves=waves, zchunk=zchunk, scale_e=scale_e,
+                            scale_h=scale_h)
         self._h = create_plan_handle(w, storage=storage, kernel=kernel, rows=rows, waves=waves,
                                      zchunk=zchunk, nan_watch=nan_watch, scale_e=scale_e,
                                      scale_h=scale_h)
@@ -295,7 +298,7 @@ def checkpointed_adjoint(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int]
     T = plan.n_steps
     K = max(1, min(T, every or math.ceil(math.sqrt(T))))
     n_seg = (T + K - 1) // K
-    fwd = Plan(plan.w, storage=plan.storage, device=plan.device)
+    fwd = Plan(plan.w, storage=plan.storage, device=plan.device, **plan.exec_kw)
     try:
         nbytes = fwd.state_bytes()
         snaps = torch.empty((n_seg, nbytes), dtype=torch.uint8, device=plan.device)
@@ -347,7 +350,7 @@ def eps_sensitivity(plan: "Plan", dl_dw: torch.Tensor, every: Optional[int] = No
     T = plan.n_steps
     K = max(1, min(T, every or math.ceil(math.sqrt(T))))
     n_seg = (T + K - 1) // K
-    fwd = Plan(w, storage=plan.storage, device=plan.device)
+    fwd = Plan(w, storage=plan.storage, device=plan.device, **plan.exec_kw)
     try:
         snaps = torch.empty((n_seg, fwd.state_bytes()), dtype=torch.uint8, device=plan.device)
         dl_dw = dl_dw.to(torch.float64).contiguous()

@@ -66,7 +66,8 @@ typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
 /* CHF_KERNEL_FUSED_PREFETCH: the fused sweep whose interior tiles issue each plane's row loads one
    plane ahead (the loads of plane k+1 are in flight while plane k is computed), at the price of
    more registers per wave (3 waves per SIMD instead of 4); rows of at most 256 nodes and
-   waves_per_block 4, 7 or 8.  Boundary tiles and batches use the plain fused sweep.  Same bits. */
+   waves_per_block 4, 7 or 8.  With 4 or 7 the boundary tiles load a plane ahead too; batches use
+   the plain fused sweep.  Same bits. */
 typedef enum {
   CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2, CHF_KERNEL_FUSED_PREFETCH = 3
 } chf_kernel;

@@ -308,9 +308,9 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     for (int v = 0; v < VX; v++) hxp[v] = hyp[v] = 0.f;
   }
 
-  // Interior tiles (G = 0) can issue each plane's row loads one plane ahead: the raw values of
+  // The sweep can issue each plane's row loads one plane ahead: the raw values of
   // E(k+2), H(k+1) and the x-slab psi of plane k+1 are in flight while plane k is computed.
-  constexpr bool PF = G == 0 && PREFETCH;
+  constexpr bool PF = PREFETCH;
   Vec<T, VX> rE0, rE1, rE2, rH0, rH1, rH2, rT0, rT2;
   float rq0 = 0.f, rq1 = 0.f, rq2 = 0.f, rq3 = 0.f;
   if constexpr (PF) {
@@ -354,6 +354,30 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     }
     // loads: E(k+1) and H^{n-1/2}(k) of the own row, Ex, Ez(k+1) of the row above the tile
     // (top wave), the own row's x-slab psi (one value per lane) and y/z-slab psi rows
+    const float chz = d.ax[2].ch[k], cez = d.ax[2].ce[k];
+    // z layer and wall masks of this plane (uniform)
+    const int shz = GZ && np2 > 0 ? d.ax[2].sh[k] : -1, sez = GZ && np2 > 0 ? d.ax[2].se[k] : -1;
+    const bool kh = !GZ || k <= nz - 2;              // Hx, Hy have their z difference
+    const bool ke = !GZ || (k >= 1 && k <= nz - 2);  // Ex, Ey are not tangential to a z wall
+    // y/z slab rows: H terms Hx(y), Hz(y), Hx(z), Hy(z); E terms Ex(y), Ez(y), Ex(z), Ey(z)
+    // (issued before the row loads of the next plane, which the prefetching sweep issues below:
+    // waiting for these then never waits for those)
+    float qhxy[VX], qhzy[VX], qhxz[VX], qhyz[VX], qexy[VX], qezy[VX], qexz[VX], qeyz[VX];
+    long long iyh = 0, iye = 0, izh = 0, ize = 0;
+    if constexpr (GY) {
+      iyh = ((long long)k * np2 + max(shy, 0)) * d.pitch + ib;
+      iye = ((long long)k * np2 + max(sey, 0)) * d.pitch + ib;
+      izh = ((long long)max(shz, 0) * ny + jc) * d.pitch + ib;
+      ize = ((long long)max(sez, 0) * ny + jc) * d.pitch + ib;
+      ld_row<float, VX>(d.psi_h[par][1][0] + iyh, qhxy, on && shy >= 0);
+      ld_row<float, VX>(d.psi_h[par][1][1] + iyh, qhzy, on && shy >= 0);
+      ld_row<float, VX>(d.psi_h[par][2][0] + izh, qhxz, on && shz >= 0);
+      ld_row<float, VX>(d.psi_h[par][2][1] + izh, qhyz, on && shz >= 0);
+      ld_row<float, VX>(d.psi_e[1][0] + iye, qexy, own && on && sey >= 0);
+      ld_row<float, VX>(d.psi_e[1][1] + iye, qezy, own && on && sey >= 0);
+      ld_row<float, VX>(d.psi_e[2][0] + ize, qexz, own && on && sez >= 0);
+      ld_row<float, VX>(d.psi_e[2][1] + ize, qeyz, own && on && sez >= 0);
+    }
     float nxc[VX], nyc[VX], nzc[VX], hx0[VX], hy0[VX], hz0[VX];
     const long long prow = ((long long)k * ny + jc) * np2;
     float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
@@ -406,28 +430,6 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
           q3 = pe1[prow + lane];
         }
       }
-    }
-    const float chz = d.ax[2].ch[k], cez = d.ax[2].ce[k];
-    // z layer and wall masks of this plane (uniform)
-    const int shz = GZ && np2 > 0 ? d.ax[2].sh[k] : -1, sez = GZ && np2 > 0 ? d.ax[2].se[k] : -1;
-    const bool kh = !GZ || k <= nz - 2;              // Hx, Hy have their z difference
-    const bool ke = !GZ || (k >= 1 && k <= nz - 2);  // Ex, Ey are not tangential to a z wall
-    // y/z slab rows: H terms Hx(y), Hz(y), Hx(z), Hy(z); E terms Ex(y), Ez(y), Ex(z), Ey(z)
-    float qhxy[VX], qhzy[VX], qhxz[VX], qhyz[VX], qexy[VX], qezy[VX], qexz[VX], qeyz[VX];
-    long long iyh = 0, iye = 0, izh = 0, ize = 0;
-    if constexpr (GY) {
-      iyh = ((long long)k * np2 + max(shy, 0)) * d.pitch + ib;
-      iye = ((long long)k * np2 + max(sey, 0)) * d.pitch + ib;
-      izh = ((long long)max(shz, 0) * ny + jc) * d.pitch + ib;
-      ize = ((long long)max(sez, 0) * ny + jc) * d.pitch + ib;
-      ld_row<float, VX>(d.psi_h[par][1][0] + iyh, qhxy, on && shy >= 0);
-      ld_row<float, VX>(d.psi_h[par][1][1] + iyh, qhzy, on && shy >= 0);
-      ld_row<float, VX>(d.psi_h[par][2][0] + izh, qhxz, on && shz >= 0);
-      ld_row<float, VX>(d.psi_h[par][2][1] + izh, qhyz, on && shz >= 0);
-      ld_row<float, VX>(d.psi_e[1][0] + iye, qexy, own && on && sey >= 0);
-      ld_row<float, VX>(d.psi_e[1][1] + iye, qezy, own && on && sey >= 0);
-      ld_row<float, VX>(d.psi_e[2][0] + ize, qexz, own && on && sez >= 0);
-      ld_row<float, VX>(d.psi_e[2][1] + ize, qeyz, own && on && sez >= 0);
     }
     __syncthreads();
 
@@ -666,11 +668,11 @@ __global__ void __launch_bounds__(64 * (W + 1)) k_fused(Dev d, FusedShape fs, in
 }
 // Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep: G = 1
 // over the table's first n_slow_y entries (interior z range), G = 2 over the rest.
-template <typename T, int VX, int W, int G>
+template <typename T, int VX, int W, int G, bool PF>
 __global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen(Dev d, FusedShape fs, const int *tiles, int n, int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
-  fused_body<T, VX, W, G>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
+  fused_body<T, VX, W, G, PF>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
 }
 
 // Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
@@ -1016,12 +1018,23 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
   if (general) {
     if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
       const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
-      if (ny_ > 0)
-        hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
-                           p.fs, d.slow_tiles, ny_, par);
-      if (nr > 0)
-        hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
-                           p.fs, d.slow_tiles + 2 * ny_, nr, par);
+      // boundary tiles load a plane ahead as well, with workgroups of at most 8 waves (2 waves per
+      // SIMD hold their registers; 9-wave workgroups would need 3 and spill)
+      if (p.fs.prefetch && W <= 7) {
+        if (ny_ > 0)
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, true>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+                             p.fs, d.slow_tiles, ny_, par);
+        if (nr > 0)
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, true>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+                             p.fs, d.slow_tiles + 2 * ny_, nr, par);
+      } else {
+        if (ny_ > 0)
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, false>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+                             p.fs, d.slow_tiles, ny_, par);
+        if (nr > 0)
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, false>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+                             p.fs, d.slow_tiles + 2 * ny_, nr, par);
+      }
     } else
       return hipErrorInvalidValue;
   } else if (p.fs.prefetch) {

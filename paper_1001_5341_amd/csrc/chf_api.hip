@@ -961,9 +961,11 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) 
       b->storage = p->storage;
       b->waves = p->fs.waves;
       b->n_steps = p->grid.n_steps;
-    } else if (p->storage != b->storage || p->fs.waves != b->waves || p->grid.n_steps != b->n_steps) {
+      b->prefetch = p->fs.prefetch;
+    } else if (p->storage != b->storage || p->fs.waves != b->waves || p->grid.n_steps != b->n_steps ||
+               p->fs.prefetch != b->prefetch) {
       delete b;
-      return fail(CHF_EINVAL, "plans of a batch share storage, waves_per_block and n_steps");
+      return fail(CHF_EINVAL, "plans of a batch share storage, kernel, waves_per_block and n_steps");
     }
     b->plans.push_back(p);
     b->vx = std::max(b->vx, p->fs.vx);

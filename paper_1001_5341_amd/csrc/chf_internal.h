@@ -134,6 +134,7 @@ struct chf_plan {
 struct chf_batch {
   std::vector<chf_plan *> plans;
   int storage = 0, vx = 1, waves = 4, n_steps = 0, max_patch = 0, total_obs = 0;
+  int prefetch = 0;  // the members' sweep kind (all equal): tiles load a plane ahead
   bool any_mur = false;
   std::vector<int> zchunks;   // per plan
   std::vector<int> fast_tab;  // (plan, ty, zc) over the interior rectangles

@@ -676,22 +676,22 @@ __global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen(Dev d, FusedShape fs
 }
 
 // Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
-template <typename T, int VX, int W>
+template <typename T, int VX, int W, bool PF>
 __global__ void __launch_bounds__(64 * (W + 1)) k_fused_batch(const Dev *devs, const int *zchunks, const int *tab,
                                                        int n, int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int pl = tab[3 * logical];
-  fused_body<T, VX, W, 0>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
+  fused_body<T, VX, W, 0, PF>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
 }
 // Batched boundary tiles in the general fused sweep: entries (plan, ty, zc) of one class.
-template <typename T, int VX, int W, int G>
+template <typename T, int VX, int W, int G, bool PF>
 __global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen_batch(const Dev *devs, const int *zchunks, const int *tab,
                                                                  int n, int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int pl = tab[3 * logical];
-  fused_body<T, VX, W, G>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
+  fused_body<T, VX, W, G, PF>(devs[pl], tab[3 * logical + 1], tab[3 * logical + 2], zchunks[pl], par);
 }
 
 // --------------------------------------------------------------- split sweeps
@@ -1159,12 +1159,22 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
   if (general) {
     if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
       const int n1 = (int)(b.gen_tab[0].size() / 3), n2 = (int)(b.gen_tab[1].size() / 3);
-      if (n1 > 0)
-        hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 1>), dim3((n1 + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s,
-                           devs, z, (const int *)(b.ws + b.off_gen[0]), n1, par);
-      if (n2 > 0)
-        hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 2>), dim3((n2 + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s,
-                           devs, z, (const int *)(b.ws + b.off_gen[1]), n2, par);
+      const int *t1 = (const int *)(b.ws + b.off_gen[0]), *t2 = (const int *)(b.ws + b.off_gen[1]);
+      if (b.prefetch && W <= 7) {  // as for single plans: only 8-wave workgroups hold the registers
+        if (n1 > 0)
+          hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 1, true>), dim3((n1 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
+                             s, devs, z, t1, n1, par);
+        if (n2 > 0)
+          hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 2, true>), dim3((n2 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
+                             s, devs, z, t2, n2, par);
+      } else {
+        if (n1 > 0)
+          hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 1, false>), dim3((n1 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
+                             s, devs, z, t1, n1, par);
+        if (n2 > 0)
+          hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 2, false>), dim3((n2 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
+                             s, devs, z, t2, n2, par);
+      }
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -1172,8 +1182,16 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
   const int n = (int)(b.fast_tab.size() / 3);
   if (n == 0) return hipSuccess;
   const int blocks = (n + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_fused_batch<T, VX, W>), dim3(blocks), dim3(64 * (W + 1)), 0, s, devs, z,
-                     (const int *)(b.ws + b.off_fast), n, par);
+  if (b.prefetch) {
+    if constexpr (VX <= 4 && W <= 8)
+      hipLaunchKernelGGL((k_fused_batch<T, VX, W, true>), dim3(blocks), dim3(64 * (W + 1)), 0, s, devs, z,
+                         (const int *)(b.ws + b.off_fast), n, par);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_fused_batch<T, VX, W, false>), dim3(blocks), dim3(64 * (W + 1)), 0, s, devs, z,
+                       (const int *)(b.ws + b.off_fast), n, par);
+  }
   return hipGetLastError();
 }
 

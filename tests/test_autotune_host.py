@@ -1,0 +1,83 @@
+"""Host logic of the tile-shape tuner, without a GPU: the timing of one candidate is replaced by
+a stub, so these tests check the selection, the bitwise guard and the cache rules only."""
+import pytest
+import torch
+
+from paper_1001_5341_amd import _native as N
+from paper_1001_5341_amd import autotune
+from paper_1001_5341_amd import workloads as W
+
+CPU = torch.device("cpu")
+
+
+@pytest.fixture
+def stub(monkeypatch):
+    """Candidate timings from a table; waveforms all equal unless a candidate is marked."""
+    state = {"times": {}, "odd": set(), "calls": [], "invalid": set()}
+
+    def fake(w, storage, waves, zchunk, steps, device, kernel="fused"):
+        key = (waves, zchunk, kernel)
+        state["calls"].append(key)
+        if key in state["invalid"]:
+            raise N.ChfError(-1, "chf_plan_create", "shape not valid for this grid")
+        wave = torch.ones(2, 3, 4) + (1.0 if key in state["odd"] else 0.0)
+        return state["times"].get(key, 5.0), wave, {"vx": 4}
+
+    monkeypatch.setattr(autotune, "_time_candidate", fake)
+    monkeypatch.setattr(autotune, "shape_key", lambda w, storage, device=None: f"test/{storage}/{w.nx}x{w.ny}x{w.nz}")
+    return state
+
+
+def test_fastest_candidate_is_cached_and_reused(stub, tmp_path):
+    w = W.small_shower()
+    path = str(tmp_path / "tune.json")
+    cands = [(7, 8, "fused"), (8, 12, "fused_prefetch"), (4, 16, "fused")]
+    stub["times"] = {(7, 8, "fused"): 2.0, (8, 12, "fused_prefetch"): 1.5, (4, 16, "fused"): 3.0}
+    t = autotune.tune(w, "fp32", cache_path=path, candidates=cands, device=CPU)
+    assert (t["waves"], t["z_chunk"], t["kernel"], t["cached"]) == (8, 12, "fused_prefetch", False)
+    assert len(stub["calls"]) == 3
+    again = autotune.tune(w, "fp32", cache_path=path, candidates=cands, device=CPU)
+    assert again["cached"] and (again["waves"], again["z_chunk"], again["kernel"]) == (8, 12, "fused_prefetch")
+    assert len(stub["calls"]) == 3
+    # a cached shape outside the offered candidates is not used: the shape is tuned again
+    again = autotune.tune(w, "fp32", cache_path=path, candidates=[(7, 8, "fused"), (4, 16, "fused")], device=CPU)
+    assert not again["cached"] and (again["waves"], again["z_chunk"]) == (7, 8)
+    # two-element candidates mean the plain fused sweep
+    t = autotune.tune(w, "fp32", cache_path=path, candidates=[(4, 16)], use_cache=False, device=CPU)
+    assert t["kernel"] == "fused"
+
+
+def test_candidate_changing_the_waveforms_is_an_error(stub, tmp_path):
+    stub["odd"] = {(8, 12, "fused")}
+    with pytest.raises(RuntimeError, match="changes the waveforms"):
+        autotune.tune(W.small_shower(), "fp32", cache_path=str(tmp_path / "t.json"),
+                      candidates=[(7, 8, "fused"), (8, 12, "fused")], device=CPU)
+
+
+def test_invalid_shapes_are_skipped(stub, tmp_path):
+    stub["invalid"] = {(15, 8, "fused")}
+    stub["times"] = {(7, 8, "fused"): 2.0}
+    t = autotune.tune(W.small_shower(), "fp32", cache_path=str(tmp_path / "t.json"),
+                      candidates=[(15, 8, "fused"), (7, 8, "fused")], device=CPU)
+    assert (t["waves"], t["z_chunk"]) == (7, 8)
+    assert {"waves": 15, "z_chunk": 8, "kernel": "fused", "error": "CHF_EINVAL"} in t["trials"]
+    stub["invalid"] = {(15, 8, "fused"), (7, 8, "fused")}
+    with pytest.raises(RuntimeError, match="no valid tile shape"):
+        autotune.tune(W.small_shower(), "fp32", cache_path=str(tmp_path / "t2.json"),
+                      candidates=[(15, 8, "fused"), (7, 8, "fused")], device=CPU)
+
+
+def test_batch_members_cached_apart_with_a_common_row_count(stub, tmp_path):
+    path = str(tmp_path / "tune.json")
+    ws = [W.small_shower(seed=1), W.small_shower(seed=2, nz=160), W.small_shower(seed=3, nz=170)]
+    cands = [(7, 8, "fused"), (7, 12, "fused"), (8, 8, "fused")]
+    stub["times"] = {(8, 8, "fused"): 1.0}
+    plan_t = autotune.tune(ws[0], "fp32", cache_path=path, candidates=cands, device=CPU)
+    assert (plan_t["waves"], plan_t["z_chunk"]) == (8, 8)
+    stub["times"] = {(7, 12, "fused"): 1.0}
+    res = autotune.tune_batch(ws, "fp32", cache_path=path, candidates=cands, device=CPU)
+    assert [r["waves"] for r in res] == [7, 7, 7] and [r["z_chunk"] for r in res] == [12, 12, 12]
+    table = autotune._load(path)
+    assert "test/fp32/72x60x150" in table and "test/fp32/72x60x150/batch" in table
+    # the plan tuning of the shape is untouched by the batch tuning
+    assert (table["test/fp32/72x60x150"]["waves"], table["test/fp32/72x60x150"]["z_chunk"]) == (8, 8)

@@ -487,7 +487,7 @@ def adjoint_summary():
             "accuracy_vs_fp64_oracle": acc}
 
 
-# the batched sweep has no prefetching variant: its members are tuned over the plain fused sweep
+# batch members are tuned over the plain fused sweep of 7 or 8 rows (a short list: 32 members)
 BATCH_CANDIDATES = tuple((wv, z, "fused") for wv in (7, 8) for z in (8, 12, 16, 24))
 
 
@@ -522,7 +522,7 @@ def batch_summary():
 
     ws = W.batch_showers()
     shapes = autotune.tune_batch(ws, "fp32", candidates=BATCH_CANDIDATES, steps=24)
-    plans = [solver.Plan(w, kernel="fused", waves=s_["waves"], zchunk=s_["z_chunk"], device=torch.device("cuda:0"))
+    plans = [solver.Plan(w, kernel=s_["kernel"], waves=s_["waves"], zchunk=s_["z_chunk"], device=torch.device("cuda:0"))
              for w, s_ in zip(ws, shapes)]
     batch = solver.Batch(plans)
     try:

@@ -66,8 +66,8 @@ typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
 /* CHF_KERNEL_FUSED_PREFETCH: the fused sweep whose interior tiles issue each plane's row loads one
    plane ahead (the loads of plane k+1 are in flight while plane k is computed), at the price of
    more registers per wave (3 waves per SIMD instead of 4); rows of at most 256 nodes and
-   waves_per_block 4, 7 or 8.  With 4 or 7 the boundary tiles load a plane ahead too; batches use
-   the plain fused sweep.  Same bits. */
+   waves_per_block 4, 7, 8 or 11 (11 rows: one 12-wave workgroup fills a compute unit).  With 4 or 7
+   the boundary tiles load a plane ahead too.  A batch takes its members' kind.  Same bits. */
 typedef enum {
   CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2, CHF_KERNEL_FUSED_PREFETCH = 3
 } chf_kernel;
@@ -119,7 +119,7 @@ typedef struct {
 /* Execution choices.  storage: field storage type (arithmetic is always FP32; waveforms are
    accumulated in FP64).  scale_e / scale_h: power-of-two storage scales (0 = automatic).
    kernel: split E/H sweeps or the fused single sweep.  waves_per_block is the number of y
-   rows per tile (4, 7, 8 or 15; 4 or 7 for rows wider than 256 nodes; a fused workgroup has
+   rows per tile (4, 7, 8, 11 or 15; 4 or 7 for rows wider than 256 nodes; a fused workgroup has
    one more wave for the row below the tile) and z_chunk the planes per tile (0 = defaults:
    7 rows, 12 planes); rows_per_wave must be 0 or 1.  None of these changes
    a result bit.  nan_watch: check waveforms for non-finite values every step. */

@@ -23,8 +23,8 @@ from . import solver
 
 # (waves per workgroup, z chunk, kernel)
 CANDIDATES: Tuple[Tuple[int, int, str], ...] = (
-    tuple((w, z, "fused") for w in (4, 7, 8, 15) for z in (8, 12, 16, 24, 32))
-    + tuple((w, z, "fused_prefetch") for w in (7, 8) for z in (8, 12, 16, 24, 32)))
+    tuple((w, z, "fused") for w in (4, 7, 8, 11, 15) for z in (8, 12, 16, 24, 32))
+    + tuple((w, z, "fused_prefetch") for w in (7, 8, 11) for z in (8, 12, 16, 24, 32)))
 
 
 def _cand(c) -> Tuple[int, int, str]:
@@ -131,13 +131,14 @@ def tuned_plan(w, storage: str = "fp32", **kw) -> "solver.Plan":
 
 
 def tune_batch(workloads: Iterable, storage: str = "fp32", **kw) -> list:
-    """Per-member z chunks for a batch (one waves_per_block for all members: the most common
-    best value).  Cached under the member shape's key with the suffix "/batch", apart from
-    the plan tunings of the same shape (the batched sweeps offer no prefetching variant)."""
+    """Per-member z chunks for a batch, with one waves_per_block and one sweep kind for all
+    members (a batch holds one of each): the most common best pair.  Cached under the member
+    shape's key with the suffix "/batch", apart from the plan tunings of the same shape."""
     kw.setdefault("key_suffix", "/batch")
     res = [tune(w, storage, **kw) for w in workloads]
-    waves = max({r["waves"] for r in res}, key=lambda v: sum(r["waves"] == v for r in res))
-    return [{"waves": waves, "z_chunk": r["z_chunk"]} for r in res]
+    pairs = [(r["waves"], r["kernel"]) for r in res]
+    waves, kernel = max(sorted(set(pairs)), key=pairs.count)
+    return [{"waves": waves, "z_chunk": r["z_chunk"], "kernel": kernel} for r in res]
 
 
 # ------------------------------------------------------------------ axisymmetric (r, z) scheme

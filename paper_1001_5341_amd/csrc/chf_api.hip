@@ -149,14 +149,14 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 7;
   fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 12;
   if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) ||
-      !(fs.waves == 4 || fs.waves == 7 || fs.waves == 8 || fs.waves == 15)) {
+      !(fs.waves == 4 || fs.waves == 7 || fs.waves == 8 || fs.waves == 11 || fs.waves == 15)) {
     delete p;
-    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 7, 8 or 15");
+    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 7, 8, 11 or 15");
   }
   fs.prefetch = prefetch ? 1 : 0;
-  if (prefetch && (fs.vx > 4 || fs.waves > 8)) {
+  if (prefetch && (fs.vx > 4 || fs.waves > 11)) {
     delete p;
-    return fail(CHF_EINVAL, "the prefetching fused sweep takes rows of at most 256 nodes and waves_per_block 4, 7 or 8");
+    return fail(CHF_EINVAL, "the prefetching fused sweep takes rows of at most 256 nodes and waves_per_block 4, 7, 8 or 11");
   }
   if (kernel == CHF_KERNEL_FUSED && fs.vx > 4 && fs.waves != 4 && fs.waves != 7) {
     delete p;

@@ -14,7 +14,7 @@ namespace chf {
 constexpr int kMaxVX = 8;        // cells per lane along x in the fused sweep (nx <= 64*8)
 constexpr int kMaxFusedLayer = 64;  // 2*npml the fused sweep handles (x-slab psi, one per lane)
 constexpr int kMaxGeneralVX = 4;    // widest rows (64*VX nodes) of the general fused sweep
-constexpr int kMaxGeneralW = 8;     // and most rows per workgroup
+constexpr int kMaxGeneralW = 11;     // and most rows per workgroup
 constexpr int kMaxObsPerPlan = 4096;
 constexpr int kMaxWz = 64;       // longitudinal source support in cells
 

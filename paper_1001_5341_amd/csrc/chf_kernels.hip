@@ -1019,7 +1019,8 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
     if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
       const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
       // boundary tiles load a plane ahead as well, with workgroups of at most 8 waves (2 waves per
-      // SIMD hold their registers; 9-wave workgroups would need 3 and spill)
+      // SIMD hold their registers; 9- and 12-wave workgroups would need 3 and spill); the plain
+      // boundary sweeps of 11-row tiles fit 3 waves per SIMD (the z-wall one with a small spill)
       if (p.fs.prefetch && W <= 7) {
         if (ny_ > 0)
           hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, true>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
@@ -1038,7 +1039,7 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
     } else
       return hipErrorInvalidValue;
   } else if (p.fs.prefetch) {
-    if constexpr (VX <= 4 && W <= 8)
+    if constexpr (VX <= 4 && W <= 11)
       hipLaunchKernelGGL((k_fused<T, VX, W, true>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
     else
       return hipErrorInvalidValue;
@@ -1054,6 +1055,9 @@ static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, boo
     case 7: return fused_launch<T, VX, 7>(p, d, par, general, s);
     case 8:
       if constexpr (VX <= 4) return fused_launch<T, VX, 8>(p, d, par, general, s);
+      return hipErrorInvalidValue;
+    case 11:
+      if constexpr (VX <= 4) return fused_launch<T, VX, 11>(p, d, par, general, s);
       return hipErrorInvalidValue;
     case 15:
       if constexpr (VX <= 4) return fused_launch<T, VX, 15>(p, d, par, general, s);
@@ -1183,7 +1187,7 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
   if (n == 0) return hipSuccess;
   const int blocks = (n + 7) / 8 * 8;
   if (b.prefetch) {
-    if constexpr (VX <= 4 && W <= 8)
+    if constexpr (VX <= 4 && W <= 11)
       hipLaunchKernelGGL((k_fused_batch<T, VX, W, true>), dim3(blocks), dim3(64 * (W + 1)), 0, s, devs, z,
                          (const int *)(b.ws + b.off_fast), n, par);
     else
@@ -1203,6 +1207,9 @@ static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *
     case 7: return batch_fused<T, VX, 7>(b, devs, z, par, general, s);
     case 8:
       if constexpr (VX <= 4) return batch_fused<T, VX, 8>(b, devs, z, par, general, s);
+      return hipErrorInvalidValue;
+    case 11:
+      if constexpr (VX <= 4) return batch_fused<T, VX, 11>(b, devs, z, par, general, s);
       return hipErrorInvalidValue;
     case 15:
       if constexpr (VX <= 4) return batch_fused<T, VX, 15>(b, devs, z, par, general, s);

@@ -87,14 +87,18 @@ def test_fused_sweep_width_limit():
 
 
 def test_prefetching_sweep_limits():
-    """The prefetching sweep holds more registers per wave (3 waves per SIMD): at most 9 waves
+    """The prefetching sweep holds more registers per wave (3 waves per SIMD): at most 12 waves
     per workgroup and 4 nodes per lane; the plan reports it as its kernel."""
     w = W.small_shower()
-    assert _status(w, kernel="fused_prefetch", waves=7) == "CHF_OK"
-    assert _status(w, kernel="fused_prefetch", waves=8) == "CHF_OK"
+    for waves in (4, 7, 8, 11):
+        assert _status(w, kernel="fused_prefetch", waves=waves) == "CHF_OK"
+    assert _status(w, kernel="fused", waves=11) == "CHF_OK"
     assert _status(w, kernel="fused_prefetch", waves=15) == "CHF_EINVAL"
+    for waves in (5, 9, 12, 16):
+        assert _status(w, kernel="fused", waves=waves) == "CHF_EINVAL"
     wide = w.replace(nx=300, x_axis=0.5 * 299 * w.dx, obs_xyz=w.obs_xyz + [0.5 * (299 - w.nx + 1) * w.dx, 0, 0])
     assert _status(wide, kernel="fused", waves=7) == "CHF_OK"
+    assert _status(wide, kernel="fused", waves=11) == "CHF_EINVAL"
     assert _status(wide, kernel="fused_prefetch", waves=7) == "CHF_EINVAL"
     h = solver.create_plan_handle(w, kernel="fused_prefetch", waves=8, zchunk=16)
     try:

@@ -77,7 +77,28 @@ def test_batch_members_cached_apart_with_a_common_row_count(stub, tmp_path):
     stub["times"] = {(7, 12, "fused"): 1.0}
     res = autotune.tune_batch(ws, "fp32", cache_path=path, candidates=cands, device=CPU)
     assert [r["waves"] for r in res] == [7, 7, 7] and [r["z_chunk"] for r in res] == [12, 12, 12]
+    assert [r["kernel"] for r in res] == ["fused"] * 3
     table = autotune._load(path)
     assert "test/fp32/72x60x150" in table and "test/fp32/72x60x150/batch" in table
     # the plan tuning of the shape is untouched by the batch tuning
     assert (table["test/fp32/72x60x150"]["waves"], table["test/fp32/72x60x150"]["z_chunk"]) == (8, 8)
+
+
+def test_batch_takes_one_row_count_and_sweep_kind(stub, tmp_path):
+    """Members tuned to different shapes share the most common (rows, sweep kind) pair and keep
+    their own z chunks."""
+    path = str(tmp_path / "tune.json")
+    ws = [W.small_shower(seed=1, nz=150), W.small_shower(seed=2, nz=160), W.small_shower(seed=3, nz=170)]
+    best = {150: (11, 8, "fused_prefetch"), 160: (11, 16, "fused_prefetch"), 170: (7, 12, "fused")}
+    res = []
+    for w in ws:
+        stub["times"] = {best[w.nz]: 1.0}
+        res += autotune.tune_batch([w], "fp32", cache_path=path,
+                                   candidates=[(7, 12, "fused"), (11, 8, "fused_prefetch"), (11, 16, "fused_prefetch")],
+                                   device=CPU)
+    stub["times"] = {}
+    res = autotune.tune_batch(ws, "fp32", cache_path=path,
+                              candidates=[(7, 12, "fused"), (11, 8, "fused_prefetch"), (11, 16, "fused_prefetch")],
+                              device=CPU)
+    assert [(r["waves"], r["kernel"]) for r in res] == [(11, "fused_prefetch")] * 3
+    assert [r["z_chunk"] for r in res] == [8, 16, 12]

@@ -41,21 +41,25 @@ def test_batch_equals_single_runs(gpu):
 
 
 def test_prefetching_batch_equals_single_runs(gpu):
-    """Members whose tiles load a plane ahead (7-row tiles: the boundary tiles too) give the
-    plain single runs' bits; a batch does not mix the two sweep kinds."""
+    """Members whose tiles load a plane ahead (7-row tiles: the boundary tiles too; 11-row tiles)
+    give the plain single runs' bits; a batch does not mix the two sweep kinds."""
     ws = members()
     singles = []
     for w in ws:
         p = solver.Plan(w, kernel="fused", waves=7)
         singles.append(p.run().cpu().numpy())
         p.close()
-    print("\n[gpu-batch] prefetching batch", flush=True)
-    plans = [solver.Plan(w, kernel="fused_prefetch", waves=7) for w in ws]
-    batch = solver.Batch(plans)
-    outs = [o.cpu().numpy() for o in batch.run()]
-    for a, b in zip(outs, singles):
-        assert np.array_equal(a, b)
-    batch.close()
+    for waves in (11, 7):  # 11 rows: 12-wave workgroups, plain boundary sweeps
+        print(f"\n[gpu-batch] prefetching batch, {waves}-row tiles", flush=True)
+        plans = [solver.Plan(w, kernel="fused_prefetch", waves=waves) for w in ws]
+        batch = solver.Batch(plans)
+        outs = [o.cpu().numpy() for o in batch.run()]
+        for a, b in zip(outs, singles):
+            assert np.array_equal(a, b)
+        batch.close()
+        if waves == 11:
+            for p in plans:
+                p.close()
     plain = solver.Plan(ws[0], kernel="fused", waves=7)
     with pytest.raises(_native.ChfError) as e:
         solver.Batch([plans[1], plain])

@@ -61,7 +61,7 @@ def test_batch_full_size_sampled_members_against_stored_oracle(gpu):
     print(f"\n[gpu-fullsize] batch of {len(ws)}: "
           f"{sum(w.n_cells * w.n_steps for w in ws):.3e} cell-updates", flush=True)
     shapes = autotune.tune_batch(ws, "fp32")
-    plans = [solver.Plan(w, kernel="fused", waves=s["waves"], zchunk=s["z_chunk"]) for w, s in zip(ws, shapes)]
+    plans = [solver.Plan(w, kernel=s["kernel"], waves=s["waves"], zchunk=s["z_chunk"]) for w, s in zip(ws, shapes)]
     batch = solver.Batch(plans)
     outs = batch.run()
     for m in members:

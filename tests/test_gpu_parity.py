@@ -74,7 +74,7 @@ def test_small_shower_cpml_fused_and_split(gpu, shower):
     assert np.array_equal(fused, split)
 
 
-@pytest.mark.parametrize("waves,zchunk", [(4, 7), (8, 32), (4, 16), (8, 150), (8, 1), (7, 12), (15, 9)])
+@pytest.mark.parametrize("waves,zchunk", [(4, 7), (8, 32), (4, 16), (8, 150), (8, 1), (7, 12), (11, 5), (15, 9)])
 def test_tile_shape_invariance_bitwise(gpu, shower, waves, zchunk):
     w, _ = shower
     banner(f"tile shape waves={waves} zchunk={zchunk}")
@@ -89,7 +89,8 @@ def test_prefetching_sweep_bitwise(gpu, storage):
     """The sweep whose interior tiles load a plane ahead gives the plain fused sweep's bits:
     waveforms and all six final fields, for one to four nodes per lane, z chunks of one plane,
     a ragged chunk and one chunk over the whole height."""
-    for nx, waves, zchunk in ((40, 7, 12), (72, 8, 1), (100, 4, 16), (200, 8, 150), (200, 7, 11)):
+    for nx, waves, zchunk in ((40, 7, 12), (72, 8, 1), (100, 4, 16), (200, 8, 150), (200, 7, 11),
+                              (200, 11, 6), (64, 11, 13)):
         w = W.small_shower(seed=17, nx=nx, ny=44, nz=150, n_steps=120, n_obs=4)
         banner(f"prefetch {storage} nx={nx} waves={waves} zchunk={zchunk}")
         res = []

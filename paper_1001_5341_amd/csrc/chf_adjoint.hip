@@ -210,7 +210,7 @@ __device__ __forceinline__ float term(bool upd, float tb, const TP &q, float psi
   if (!upd) return 0.f;
   if (q.slot < 0) return tb * q.ik;
   const float tot = psib + tb;
-  if (pw) pw[id] = q.b * tot;
+  if (pw) __builtin_nontemporal_store(q.b * tot, pw + id);  // the other psib set
   return fmaf(q.a, tot, tb * q.ik);
 }
 
@@ -295,9 +295,10 @@ __global__ void __launch_bounds__(256) k_adj_ha(Dev d, int cur, PsiSet er, PsiSe
     const float s4x = xp ? term(iyz1 && jxz && kz, cb * e2x, x1, q1, nullptr, 0) : 0.f;
     const float s0y = yp ? term(ix && jxz1 && kxy, cb * e0y, y1, q2, nullptr, 0) : 0.f;
     const float s5y = yp ? term(iyz && jxz1 && kz, -cb * e2y, y1, q3, nullptr, 0) : 0.f;
-    O0[c] = h0 + ((s2 - s2n) + (s5 - s5y));
-    O1[c] = h1 + ((s1 - s1n) + (s4 - s4x));
-    O2[c] = h2 + ((s0 - s0y) + (s3 - s3x));
+    // the new level is not read within this sweep: non-temporal stores
+    __builtin_nontemporal_store(h0 + ((s2 - s2n) + (s5 - s5y)), O0 + c);
+    __builtin_nontemporal_store(h1 + ((s1 - s1n) + (s4 - s4x)), O1 + c);
+    __builtin_nontemporal_store(h2 + ((s0 - s0y) + (s3 - s3x)), O2 + c);
     s1n = s1;
     s2n = s2;
   }
@@ -378,9 +379,9 @@ __global__ void __launch_bounds__(256) k_adj_eb(Dev d, int cur, PsiSet hr, PsiSe
     const float ex = (t2p - t2) + (t5y - t5);
     const float ey = (t1p - t1) + (t4x - t4);
     const float ez = (t0y - t0) + (t3x - t3);
-    O0[c] = ((ex_i && exz_j && kxy) ? ca * e0 : e0) + ex;
-    O1[c] = ((eyz_i && ey_j && kxy) ? ca * e1 : e1) + ey;
-    O2[c] = ((eyz_i && exz_j && kh) ? ca * e2 : e2) + ez;
+    __builtin_nontemporal_store(((ex_i && exz_j && kxy) ? ca * e0 : e0) + ex, O0 + c);
+    __builtin_nontemporal_store(((eyz_i && ey_j && kxy) ? ca * e1 : e1) + ey, O1 + c);
+    __builtin_nontemporal_store(((eyz_i && exz_j && kh) ? ca * e2 : e2) + ez, O2 + c);
     t1p = t1;
     t2p = t2;
   }

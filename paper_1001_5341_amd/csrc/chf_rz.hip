@@ -150,13 +150,36 @@ __device__ __forceinline__ void ld(const float *p, float (&o)[N], bool on) {
   }
 }
 
+// Row stores are non-temporal: a launch writes the other time level (and the other Mur
+// memory), which nothing in the same launch reads, so it streams past L2.
+template <int B>
+__device__ __forceinline__ void st_nt(void *p, const void *x) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  if constexpr (B == 16) {
+    u4 b;
+    __builtin_memcpy(&b, x, 16);
+    __builtin_nontemporal_store(b, reinterpret_cast<u4 *>(p));
+  } else if constexpr (B == 8) {
+    u2 b;
+    __builtin_memcpy(&b, x, 8);
+    __builtin_nontemporal_store(b, reinterpret_cast<u2 *>(p));
+  } else if constexpr (B == 4) {
+    unsigned b;
+    __builtin_memcpy(&b, x, 4);
+    __builtin_nontemporal_store(b, reinterpret_cast<unsigned *>(p));
+  } else {
+    __builtin_memcpy(p, x, B);
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void st(float *p, const float (&o)[N], bool on) {
   if (!on) return;
   F<N> x;
 #pragma unroll
   for (int v = 0; v < N; v++) x.v[v] = o[v];
-  *reinterpret_cast<F<N> *>(p) = x;
+  st_nt<sizeof(x)>(p, &x);
 }
 
 // Field storage: FP32 holds physical values; 16-bit types hold scale * value, rounded to
@@ -197,7 +220,7 @@ __device__ __forceinline__ void stf(T *p, const float (&o)[N], bool on, float s)
   V<T, N> x;
 #pragma unroll
   for (int v = 0; v < N; v++) x.v[v] = from_f<T>(kF32<T> ? o[v] : o[v] * s);
-  *reinterpret_cast<V<T, N> *>(p) = x;
+  st_nt<sizeof(x)>(p, &x);
 }
 
 // the value a store with scale s followed by a load returns

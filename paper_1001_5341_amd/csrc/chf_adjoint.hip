@@ -23,7 +23,10 @@ namespace chf {
 
 namespace {
 
-constexpr int kAdjZ = 8;
+// planes per workgroup of the reverse sweeps: each chunk reads one plane beyond it (the carried
+// z term), so longer chunks read less (measured on 128 x 128 x 1024: 8 planes 1.19 s per 3000
+// reverse steps, 16 planes 1.16 s, 32 planes 1.14 s); the result does not depend on it
+constexpr int kAdjZ = 32;
 
 __device__ __forceinline__ long long cidx(const Dev &d, int i, int j, int k) {
   return (long long)k * d.plane + (long long)j * d.pitch + i;

@@ -1007,27 +1007,31 @@ __global__ void k_fill_zero(uint4 *p, long long n16) {
     p[t] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Dense [nz][ny][nx] copies of one component: one wave per (j, k) row at a time (rows dealt
+// round-robin over the waves of the grid), lanes along x, so one division per row.
 template <typename T>
 __global__ void k_get_field(Dev d, const T *src, float *out, float inv_scale) {
-  const long long n = (long long)d.nx * d.ny * d.nz;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t % d.nx);
-    const long long r = t / d.nx;
+  const long long rows = (long long)d.ny * d.nz;
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long r = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < rows; r += nw) {
     const int j = (int)(r % d.ny), k = (int)(r / d.ny);
-    out[t] = to_f(src[(long long)k * d.plane + (long long)j * d.pitch + i]) * inv_scale;
+    const T *sr = src + (long long)k * d.plane + (long long)j * d.pitch;
+    float *o = out + r * d.nx;
+    for (int i = lane; i < d.nx; i += 64) o[i] = to_f(sr[i]) * inv_scale;
   }
 }
 
 template <typename T>
 __global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
-  const long long n = (long long)d.nx * d.ny * d.nz;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t % d.nx);
-    const long long r = t / d.nx;
+  const long long rows = (long long)d.ny * d.nz;
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long r = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < rows; r += nw) {
     const int j = (int)(r % d.ny), k = (int)(r / d.ny);
-    dst[(long long)k * d.plane + (long long)j * d.pitch + i] = from_f<T>(in[t] * scale);
+    T *dr = dst + (long long)k * d.plane + (long long)j * d.pitch;
+    const float *ir = in + r * d.nx;
+    for (int i = lane; i < d.nx; i += 64) dr[i] = from_f<T>(ir[i] * scale);
   }
 }
 
@@ -1321,7 +1325,7 @@ template <typename T>
 static hipError_t get_t(const chf_plan &p, int par, int comp, float *out, hipStream_t s) {
   const T *src = (const T *)(comp < 3 ? p.dev.e[par][comp] : p.dev.h[par][comp - 3]);
   const float inv = (float)(1.0 / (comp < 3 ? p.scale_e : p.scale_h));
-  hipLaunchKernelGGL(k_get_field<T>, dim3(1024), dim3(256), 0, s, p.dev, src, out, inv);
+  hipLaunchKernelGGL(k_get_field<T>, dim3(2048), dim3(256), 0, s, p.dev, src, out, inv);
   return hipGetLastError();
 }
 
@@ -1329,7 +1333,7 @@ template <typename T>
 static hipError_t set_t(const chf_plan &p, int par, int comp, const float *in, hipStream_t s) {
   T *dst = (T *)(comp < 3 ? p.dev.e[par][comp] : p.dev.h[par][comp - 3]);
   const float sc = (float)(comp < 3 ? p.scale_e : p.scale_h);
-  hipLaunchKernelGGL(k_set_field<T>, dim3(1024), dim3(256), 0, s, p.dev, dst, in, sc);
+  hipLaunchKernelGGL(k_set_field<T>, dim3(2048), dim3(256), 0, s, p.dev, dst, in, sc);
   return hipGetLastError();
 }
 

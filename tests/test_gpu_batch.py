@@ -38,6 +38,16 @@ def test_batch_equals_single_runs(gpu):
     batch.close()
     for p in plans:
         p.close()
+    # plain 11-row tiles (12-wave workgroups) in the batched interior and boundary sweeps
+    print("[gpu-batch] batch, 11-row tiles", flush=True)
+    plans = [solver.Plan(w, kernel="fused", waves=11, zchunk=9) for w in ws]
+    batch = solver.Batch(plans)
+    outs = [o.cpu().numpy() for o in batch.run()]
+    for a, b in zip(outs, singles):
+        assert np.array_equal(a, b)
+    batch.close()
+    for p in plans:
+        p.close()
 
 
 def test_prefetching_batch_equals_single_runs(gpu):

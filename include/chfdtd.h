@@ -28,7 +28,8 @@
  *   - All device memory is the caller's: the plan reports how many bytes of workspace it
  *     needs (chf_plan_workspace_bytes) and works inside the buffer bound with
  *     chf_plan_bind_workspace.  Output buffers are the caller's as well.  The library never
- *     allocates or frees device memory.
+ *     allocates or frees device memory; it holds one static array of CHF_SCRATCH_BYTES per GPU
+ *     (reserved when the code object loads) that only chf_forward_scratch uses.
  *   - Calls that take a stream are stream-ordered and return after enqueueing.  Kernel
  *     faults surface as CHF_EHIP and the non-finite watchdog as CHF_ENAN from
  *     chf_plan_sync.  A plan must not be used from two threads at once.
@@ -171,6 +172,24 @@ chf_status chf_forward_timed(chf_plan *plan, void *stream, const double *q_bins_
    (waveform pointer, profile pointer) and replayed on later calls. */
 chf_status chf_forward_graph(chf_plan *plan, void *stream, const double *q_bins_dev,
                              double *waveforms_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): chf_forward_scratch runs the plan's full forward pass
+   from zero fields -- exactly the launches of chf_plan_reset + chf_forward over n_steps, with the
+   boundary sweep in order on `stream` -- inside a static device array of CHF_SCRATCH_BYTES that
+   the library holds on every GPU it runs on until the process ends, instead of a caller-bound
+   workspace.  No device memory is allocated or freed and no stream or event is created; the
+   plan's tables are copied into the array (stream-ordered) at every call.
+   q_bins_dev: DEVICE profile (NULL = plan's); waveforms_dev: DEVICE FP64 [n_obs][3][n_steps]
+   (may be NULL only without observers).  The plan needs no bound workspace; if it has one, that
+   workspace and the plan's step state are left untouched.  Plans whose workspace exceeds
+   CHF_SCRATCH_BYTES (chf_plan_workspace_bytes) get CHF_ENOMEM.  All calls on one GPU share its
+   array, which keeps the last call's contents (the call zeroes fields and CPML state itself):
+   calls that overlap on one GPU (other streams, other threads) race and must be serialised by
+   the caller.  chf_scratch_bytes returns the array's size. */
+#define CHF_SCRATCH_BYTES (64ull << 20)
+chf_status chf_forward_scratch(chf_plan *plan, void *stream, const double *q_bins_dev, double *waveforms_dev);
+uint64_t chf_scratch_bytes(void);
 
 /* Discrete adjoint: given dL/dw (DEVICE FP64 [n_obs][3][n_steps]) returns dL/dq (DEVICE FP64
    [n_bins]) for the plan's full run, by the exact transpose of the forward recurrence run

@@ -27,7 +27,7 @@ EXPORTED = [
     "chf_plan_load_state", "chf_plan_sync",
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
     "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_destroy",
-    "chf_status_str", "chf_last_error", "chf_abi_version",
+    "chf_status_str", "chf_last_error", "chf_abi_version", "chf_forward_scratch", "chf_scratch_bytes",
     "chf_rz_plan_create", "chf_rz_plan_destroy", "chf_rz_workspace_bytes", "chf_rz_bind_workspace",
     "chf_rz_reset", "chf_rz_forward", "chf_rz_forward_timed", "chf_rz_forward_graph", "chf_rz_sync",
     "chf_rz_get_field", "chf_rz_set_field", "chf_rz_get_info",
@@ -155,6 +155,10 @@ def lib():
                                         ct.POINTER(ct.c_double)]
         L.chf_forward_graph.restype = ct.c_int
         L.chf_forward_graph.argtypes = [vp, vp, vp, vp]
+        L.chf_forward_scratch.restype = ct.c_int
+        L.chf_forward_scratch.argtypes = [vp, vp, vp, vp]
+        L.chf_scratch_bytes.restype = ct.c_uint64
+        L.chf_scratch_bytes.argtypes = []
         L.chf_adjoint.restype = ct.c_int
         L.chf_adjoint.argtypes = [vp, vp, vp, vp]
         L.chf_adjoint_begin.restype = ct.c_int

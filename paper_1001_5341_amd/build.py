@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchfdtd.so")
-SOURCES = ["chf_api.hip", "chf_kernels.hip", "chf_adjoint.hip", "chf_rz.hip", "chf_spectral.hip"]
+SOURCES = ["chf_api.hip", "chf_kernels.hip", "chf_adjoint.hip", "chf_rz.hip", "chf_spectral.hip",
+           "chf_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -517,12 +517,12 @@ chf_status chf_plan_workspace_bytes(const chf_plan *plan, uint64_t *bytes) {
   return CHF_OK;
 }
 
-chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, void *stream) {
-  if (!p || !dev_ptr) return fail(CHF_EINVAL, "NULL argument");
-  if (bytes < p->ws_bytes) return fail(CHF_ENOMEM, "workspace smaller than chf_plan_workspace_bytes");
-  if ((uintptr_t)dev_ptr % 256) return fail(CHF_EINVAL, "workspace must be 256-byte aligned");
-  hipStream_t s = (hipStream_t)stream;
-  char *ws = (char *)dev_ptr;
+}  // extern "C"
+
+namespace chf {
+// Points the plan's kernel parameters at the workspace `ws` (>= ws_bytes, 256-byte aligned) and
+// uploads its tables there with stream-ordered copies.  Creates nothing and allocates nothing.
+hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s) {
   p->ws = ws;
   chf::Dev &D = p->dev;
   for (int l = 0; l < 2; l++)
@@ -589,6 +589,21 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
   for (const Up &u : ups) {
     if (!u.n) continue;
     hipError_t e = hipMemcpyAsync(ws + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace chf
+
+extern "C" {
+
+chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, void *stream) {
+  if (!p || !dev_ptr) return fail(CHF_EINVAL, "NULL argument");
+  if (bytes < p->ws_bytes) return fail(CHF_ENOMEM, "workspace smaller than chf_plan_workspace_bytes");
+  if ((uintptr_t)dev_ptr % 256) return fail(CHF_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  {
+    hipError_t e = chf::bind_tables(p, (char *)dev_ptr, s);
     if (e != hipSuccess) return hip_fail(e, "upload of plan tables");
   }
   if (p->graph) {

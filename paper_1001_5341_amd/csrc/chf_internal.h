@@ -175,4 +175,6 @@ hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, 
 hipError_t launch_adjoint_clear(const chf_plan &p, hipStream_t s);
 hipError_t launch_batch_step(const chf_batch &b, int parity, int step, hipStream_t s);
 void set_error(const std::string &msg);
+// plan tables into a workspace (chf_api.hip)
+hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s);
 }  // namespace chf

@@ -145,6 +145,22 @@ class Plan:
             self.sync(stream)
         return out
 
+    def run_scratch(self, q_bins: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                    stream=None, sync: bool = True) -> torch.Tensor:
+        """Full run from zero fields through chf_forward_scratch: inside the library's static
+        device array instead of this plan's workspace (which it leaves untouched)."""
+        out = self.new_waveforms() if out is None else out
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.device == self.device
+        assert tuple(out.shape) == (self.n_obs, 3, self.n_steps)
+        if q_bins is not None:
+            assert q_bins.dtype == torch.float64 and q_bins.numel() == len(self.w.q_bins)
+        qp = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
+        N.check(N.lib().chf_forward_scratch(self._h, _stream_handle(stream), qp, ct.c_void_p(out.data_ptr())),
+                "chf_forward_scratch")
+        if sync:
+            self.sync(stream)
+        return out
+
     def sync(self, stream=None):
         N.check(N.lib().chf_plan_sync(self._h, _stream_handle(stream)), "chf_plan_sync")
 

@@ -12,8 +12,9 @@ CPU = torch.device("cpu")
 
 @pytest.fixture
 def stub(monkeypatch):
-    """Candidate timings from a table; waveforms all equal unless a candidate is marked."""
-    state = {"times": {}, "odd": set(), "calls": [], "invalid": set()}
+    """Candidate timings from a table; waveforms and final-field digests all equal unless a
+    candidate is marked (odd: other waveforms; odd_fields: same waveforms, other final fields)."""
+    state = {"times": {}, "odd": set(), "odd_fields": set(), "calls": [], "invalid": set()}
 
     def fake(w, storage, waves, zchunk, steps, device, kernel="fused"):
         key = (waves, zchunk, kernel)
@@ -21,7 +22,8 @@ def stub(monkeypatch):
         if key in state["invalid"]:
             raise N.ChfError(-1, "chf_plan_create", "shape not valid for this grid")
         wave = torch.ones(2, 3, 4) + (1.0 if key in state["odd"] else 0.0)
-        return state["times"].get(key, 5.0), wave, {"vx": 4}
+        digest = (1, 2, 3, 4, 5, 6 + (1 if key in state["odd_fields"] else 0))
+        return state["times"].get(key, 5.0), (wave, digest), {"vx": 4}
 
     monkeypatch.setattr(autotune, "_time_candidate", fake)
     monkeypatch.setattr(autotune, "shape_key", lambda w, storage, device=None: f"test/{storage}/{w.nx}x{w.ny}x{w.nz}")
@@ -49,9 +51,38 @@ def test_fastest_candidate_is_cached_and_reused(stub, tmp_path):
 
 def test_candidate_changing_the_waveforms_is_an_error(stub, tmp_path):
     stub["odd"] = {(8, 12, "fused")}
-    with pytest.raises(RuntimeError, match="changes the waveforms"):
+    with pytest.raises(RuntimeError, match="changes the results"):
         autotune.tune(W.small_shower(), "fp32", cache_path=str(tmp_path / "t.json"),
                       candidates=[(7, 8, "fused"), (8, 12, "fused")], device=CPU)
+
+
+def test_candidate_changing_only_the_final_fields_is_an_error(stub, tmp_path):
+    # the guard compares every node of the final state, not only the observers' waveforms
+    stub["odd_fields"] = {(8, 12, "fused")}
+    with pytest.raises(RuntimeError, match="changes the results"):
+        autotune.tune(W.small_shower(), "fp32", cache_path=str(tmp_path / "t.json"),
+                      candidates=[(7, 8, "fused"), (8, 12, "fused")], device=CPU)
+
+
+def test_field_digest_sees_a_single_changed_value():
+    # the digest on CPU tensors: one flipped low mantissa bit anywhere changes it
+    class FakePlan:
+        def __init__(self, fields):
+            self.fields = fields
+
+        def get_field(self, c, stream=None):
+            return self.fields[c]
+
+    g = torch.Generator().manual_seed(3)
+    base = [torch.rand((5, 7, 9), generator=g) for _ in range(6)]
+    d0 = autotune.field_digest(FakePlan(base))
+    assert d0 == autotune.field_digest(FakePlan([f.clone() for f in base]))
+    for c, idx in [(0, (0, 0, 0)), (3, (4, 6, 8)), (5, (2, 3, 4))]:
+        alt = [f.clone() for f in base]
+        bits = alt[c].view(torch.int32)
+        bits[idx] ^= 1
+        d1 = autotune.field_digest(FakePlan(alt))
+        assert d1 != d0 and [a != b for a, b in zip(d0, d1)].count(True) == 1
 
 
 def test_invalid_shapes_are_skipped(stub, tmp_path):

@@ -101,8 +101,9 @@ def test_adjoint_full_size_against_stored_oracle(gpu):
 
 def test_precision_grid_full_size_invariants(gpu):
     """512x512x4096 (the precision workload's grid, shower and observers) for 400 steps: the
-    fused sweep with two tile shapes and the split sweeps give identical fields; BF16 and
-    FP16 storage stay within their stated distance of FP32 storage."""
+    fused sweep with two tile shapes and the split sweeps give identical fields; FP16 storage
+    stays within the 1e-2 gate of FP32 storage, and BF16 within its error envelope (1e-1, a
+    regression bound: BF16 misses the gate)."""
     w = W.precision_shower().replace(n_steps=400)
     print(f"\n[gpu-fullsize] {w.name} x {w.n_steps} steps", flush=True)
 

@@ -1,10 +1,13 @@
 """Reduced-precision field storage (FP32 arithmetic, FP64 observer accumulation) against the FP64
 oracle, relative L2 per observer.
 
-Target 1e-2.  FP16 storage with power-of-two per-field scales meets it (~2e-3 here).  BF16
-storage (8-bit mantissa) accumulates rounding noise along the propagation path and lands at
-~1.6e-2 on this workload (stochastic rounding was tried and measured worse, ~2e-2), so it is
-held to the measured envelope 2e-2 rather than to the target."""
+The storage gate is 1e-2.  FP16 storage with power-of-two per-field scales meets it (~2e-3 here)
+and is held to it: that is the parity claim for 16-bit storage.  BF16 storage (8-bit mantissa)
+does not meet it: the rounding noise of every stored update accumulates along the propagation
+path to ~1.6e-2 on this workload (5.9e-2 on the 256x256x2048 shower), and stochastic rounding
+measured worse.  The BF16 test is therefore an error-envelope regression check (bound 2e-2,
+about 1.25x the measured value), not a parity claim; the benchmark reports BF16 with
+gate_met = false."""
 import sys
 
 import numpy as np
@@ -16,7 +19,8 @@ from paper_1001_5341_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp16": 1e-2, "bf16": 2e-2}
+GATE = 1e-2          # the storage gate (FP16 is held to it)
+BF16_ENVELOPE = 2e-2  # BF16: regression bound on its measured error, not the gate
 
 
 def rel_l2(got, ref):
@@ -29,8 +33,7 @@ def shower():
     return w, oracle.run(w)
 
 
-@pytest.mark.parametrize("storage", ["bf16", "fp16"])
-def test_reduced_storage_against_oracle(gpu, shower, storage):
+def _storage_error(shower, storage):
     w, ref = shower
     print(f"\n[gpu-precision] {storage}", flush=True)
     plan = solver.Plan(w, storage=storage)
@@ -43,7 +46,19 @@ def test_reduced_storage_against_oracle(gpu, shower, storage):
           "median", np.median(err), "peak err max", peak.max())
     sys.stdout.flush()
     assert np.all(np.isfinite(got))
-    assert np.all(err <= TOL[storage]), err
+    return err
+
+
+def test_fp16_storage_meets_the_gate(gpu, shower):
+    err = _storage_error(shower, "fp16")
+    assert np.all(err <= GATE), err
+
+
+def test_bf16_storage_error_envelope(gpu, shower):
+    """Regression check of BF16's error (it misses the 1e-2 gate; see the module docstring)."""
+    err = _storage_error(shower, "bf16")
+    assert err.max() > GATE / 10  # the measured error is of the expected size, not accidentally tiny
+    assert np.all(err <= BF16_ENVELOPE), err
 
 
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])

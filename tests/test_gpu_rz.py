@@ -62,8 +62,9 @@ def test_waveforms_and_fields_match_oracle(fixture, request):
         assert np.isfinite(got).all()
         assert np.abs(ref).max() > 0
         assert rel_l2(got, ref) <= TOL
-        for o in range(w.n_obs):
-            assert rel_l2(got[o], ref[o]) <= 10 * TOL
+        per_obs = [rel_l2(got[o], ref[o]) for o in range(w.n_obs)]
+        print("rel L2 per observer", np.array(per_obs), flush=True)
+        assert max(per_obs) <= TOL, per_obs
         for comp, want in ((0, er), (1, ez), (2, hp)):
             f = plan.get_field(comp).cpu().numpy()
             assert rel_l2(f, want) <= TOL, comp
@@ -235,9 +236,12 @@ def test_wall_at_wave_start_and_source_at_wall(nr, vx, sigma_r):
         plan.close()
 
 
-@pytest.mark.parametrize("storage,tol", [("fp16", 2e-2), ("bf16", 1e-1)])
+@pytest.mark.parametrize("storage,tol", [("fp16", 1e-2), ("bf16", 1e-1)])
 def test_16bit_storage_against_oracle(small_mur, storage, tol):
-    """FP32 arithmetic on FP16 / BF16 fields (fixed power-of-two scales), against the FP64 oracle."""
+    """FP32 arithmetic on FP16 / BF16 fields (fixed power-of-two scales), against the FP64 oracle.
+    FP16 is held to the 1e-2 storage gate.  BF16 (8-bit mantissa) does not meet that gate on this
+    path: its bound here is an error-envelope regression check at about five times the measured
+    1.9e-2, not a parity claim."""
     w = small_mur
     ref = oracle_run(w)[0]
     plan = solver.RZPlan(w, storage=storage)

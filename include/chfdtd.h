@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define CHF_ABI_VERSION 1
+#define CHF_ABI_VERSION 2
 
 typedef enum {
   CHF_OK = 0,
@@ -68,9 +68,19 @@ typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
    plane ahead (the loads of plane k+1 are in flight while plane k is computed), at the price of
    more registers per wave (3 waves per SIMD instead of 4); rows of at most 256 nodes and
    waves_per_block 4, 7, 8 or 11 (11 rows: one 12-wave workgroup fills a compute unit).  With 4 or 7
-   the boundary tiles load a plane ahead too.  A batch takes its members' kind.  Same bits. */
+   the boundary tiles load a plane ahead too.  A batch takes its members' kind.  Same bits.
+   CHF_KERNEL_FUSED2: two Yee steps per pass over the fields (temporal blocking of the Numerical
+   Method section's leapfrog): each launch reads E^n, H^{n-1/2} and writes E^{n+2}, H^{n+3/2},
+   keeping E^{n+1}, H^{n+1/2} on chip (its observer samples are taken inside the pass), so a
+   cell-update moves about half the bytes.  waves_per_block is then the rows per interior tile (4,
+   7 or 8; default 8) and z_chunk the planes per tile (default 32); a workgroup also computes two
+   rows below and one above its tile, and tiles near walls and y/z layers take 4 rows.  Rows of at
+   most 256 nodes, PEC and CPML walls (else CHF_EUNSUPPORTED), CPML of at most 16 cells; a step
+   range of odd length ends with one single step of the fused sweep (default tile).  The results
+   equal the one-step sweeps' bit for bit. */
 typedef enum {
-  CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2, CHF_KERNEL_FUSED_PREFETCH = 3
+  CHF_KERNEL_AUTO = 0, CHF_KERNEL_SPLIT = 1, CHF_KERNEL_FUSED = 2, CHF_KERNEL_FUSED_PREFETCH = 3,
+  CHF_KERNEL_FUSED2 = 4
 } chf_kernel;
 
 /* Lattice: node counts (>= 3 each; the fused sweep needs nx <= 512), spacings in metres,
@@ -80,8 +90,10 @@ typedef struct {
   double dx, dy, dz, dt;
 } chf_grid;
 
-/* Uniform medium: relative permittivity and permeability, conductivity in S/m
-   (Ampere's law with sigma E, integrated semi-implicitly). */
+/* Uniform medium (Numerical Method section: the curl equations with permittivity, permeability
+   and the conduction current sigma E in Ampere's law): relative permittivity and permeability,
+   conductivity in S/m, the sigma E term integrated semi-implicitly.  The paper's medium is ice,
+   n = 1.78, lossless. */
 typedef struct {
   double eps_r, mu_r, sigma;
 } chf_medium;
@@ -109,9 +121,10 @@ typedef struct {
   const double *q_bins;
 } chf_source;
 
-/* Detector positions: HOST array xyz[n_obs][3] in metres, copied.  Each component is
-   interpolated trilinearly on its own staggered sub-lattice; the 8-node stencil must lie at
-   least max(1, npml) cells inside every wall. */
+/* Detector positions (Simulation Setup section: detectors at chosen positions record E as the
+   run evolves, so one run gives the pulses of all of them): HOST array xyz[n_obs][3] in metres,
+   copied.  Each component is interpolated trilinearly on its own staggered sub-lattice; the
+   8-node stencil must lie at least max(1, npml) cells inside every wall. */
 typedef struct {
   int32_t n_obs, pad0;
   const double *xyz;
@@ -132,7 +145,9 @@ typedef struct {
 
 typedef struct chf_plan chf_plan;
 
-/* Validate descriptors and build all host-side tables.  Checks: node counts >= 3 and the
+/* Validate descriptors and build all host-side tables for the leapfrog of the Numerical Method
+   section (the discretised curl equations on the staggered lattice, the moving source of the
+   Simulation Setup section, the detector stencils).  Checks: node counts >= 3 and the
    64-bit size of the workspace; dt below the Courant limit dt <= 1/(v sqrt(sum 1/d^2)) with
    v = c0/sqrt(eps_r mu_r) (else CHF_ECFL); observer stencils inside the interior and the
    source axis inside the x-y extent (else CHF_EDOMAIN); supported kernel/storage
@@ -154,7 +169,10 @@ chf_status chf_plan_bind_workspace(chf_plan *plan, void *device_ptr, uint64_t by
 /* Zero the fields and the CPML state (initial condition E^0 = 0, H^{-1/2} = 0). */
 chf_status chf_plan_reset(chf_plan *plan, void *stream);
 
-/* Advance `n_steps` steps from the current state.  q_bins_dev: DEVICE array of n_bins doubles
+/* Advance `n_steps` steps from the current state: per step the H update from the curl of E and
+   the E update from the curl of H minus the source current (the Numerical Method section's
+   leapfrog with central differences in space and time, here on the 3-D lattice), the boundary,
+   and the sampling of E at the detectors.  q_bins_dev: DEVICE array of n_bins doubles
    overriding the plan's profile (NULL = plan's).  waveforms_dev: DEVICE FP64 array
    [n_obs][3][ld_steps]; step s of this call writes column (first_column + s).  A full run from
    zero fields is chf_plan_reset followed by chf_forward(plan, stream, NULL, w, T, 0, T). */
@@ -191,7 +209,9 @@ chf_status chf_forward_graph(chf_plan *plan, void *stream, const double *q_bins_
 chf_status chf_forward_scratch(chf_plan *plan, void *stream, const double *q_bins_dev, double *waveforms_dev);
 uint64_t chf_scratch_bytes(void);
 
-/* Discrete adjoint: given dL/dw (DEVICE FP64 [n_obs][3][n_steps]) returns dL/dq (DEVICE FP64
+/* Discrete adjoint (not in the paper: the reverse-mode derivative of the Numerical Method
+   section's leapfrog with respect to the Simulation Setup section's longitudinal profile bins):
+   given dL/dw (DEVICE FP64 [n_obs][3][n_steps]) returns dL/dq (DEVICE FP64
    [n_bins]) for the plan's full run, by the exact transpose of the forward recurrence run
    backward in time.  PEC and CPML only (CHF_EUNSUPPORTED for Mur).  The forward field state
    is destroyed (the workspace holds the adjoint state). */
@@ -282,6 +302,13 @@ typedef struct {
   double bytes_per_cell_update; /* algorithmic HBM bytes of one cell-update (whole grid) */
   uint64_t fused_cells;         /* nodes covered by one launch of the fused interior sweep */
   double fused_bytes_per_cell;  /* its algorithmic HBM bytes per node (fields + x-layer psi) */
+  int32_t steps_per_launch;     /* Yee steps per interior launch: 1, or 2 (CHF_KERNEL_FUSED2) */
+  int32_t waves_per_row;        /* waves across one row in the two-step sweep (1 or 2) */
+  /* for CHF_KERNEL_FUSED2, fused_cells / fused_bytes_per_cell describe the two-step interior
+     launch: its nodes, and the one-step algorithmic bytes per node of both steps it advances
+     (so bytes / launch time is the single-step-equivalent rate); pass_bytes_per_cell is what
+     the pass itself must move per node (12 values once, x-layer psi once) */
+  double pass_bytes_per_cell;
 } chf_plan_info;
 chf_status chf_plan_get_info(const chf_plan *plan, chf_plan_info *info);
 
@@ -300,6 +327,14 @@ chf_status chf_batch_workspace_bytes(const chf_batch *batch, uint64_t *bytes);
 chf_status chf_batch_bind_workspace(chf_batch *batch, void *device_ptr, uint64_t bytes, void *stream);
 chf_status chf_batch_run(chf_batch *batch, void *stream, double *const *waveforms_dev);
 void chf_batch_destroy(chf_batch *batch);
+
+/* Measurement aid (not part of the solver): copies `bytes` (a multiple of 16) from src_dev to
+   dst_dev (DEVICE, 16-byte aligned, not overlapping) with a streaming kernel -- each lane keeps
+   loads_in_flight (1, 2, 4 or 8) 16-byte loads in flight and writes them with non-temporal
+   stores; `blocks` workgroups of 256 lanes stride over the buffer.  Stream-ordered.  The HBM
+   bandwidth such a copy reaches is the practical ceiling the solver's sweeps are read against. */
+chf_status chf_stream_copy(void *dst_dev, const void *src_dev, uint64_t bytes, int32_t loads_in_flight,
+                           int32_t blocks, void *stream);
 
 const char *chf_status_str(chf_status s);
 const char *chf_last_error(void);

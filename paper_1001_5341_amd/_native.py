@@ -17,7 +17,7 @@ STATUS = {0: "CHF_OK", -1: "CHF_EINVAL", -2: "CHF_ECFL", -3: "CHF_EDOMAIN", -4: 
           -5: "CHF_EHIP", -6: "CHF_ENAN", -7: "CHF_EUNSUPPORTED", -8: "CHF_ESTATE"}
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 BC = {"pec": 0, "mur1": 1, "cpml": 2}
-KERNEL = {"auto": 0, "split": 1, "fused": 2, "fused_prefetch": 3}
+KERNEL = {"auto": 0, "split": 1, "fused": 2, "fused_prefetch": 3, "fused2": 4}
 
 EXPORTED = [
     "chf_plan_create", "chf_plan_destroy", "chf_plan_workspace_bytes", "chf_plan_bind_workspace",
@@ -28,6 +28,7 @@ EXPORTED = [
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
     "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_destroy",
     "chf_status_str", "chf_last_error", "chf_abi_version", "chf_forward_scratch", "chf_scratch_bytes",
+    "chf_stream_copy",
     "chf_rz_plan_create", "chf_rz_plan_destroy", "chf_rz_workspace_bytes", "chf_rz_bind_workspace",
     "chf_rz_reset", "chf_rz_forward", "chf_rz_forward_timed", "chf_rz_forward_graph", "chf_rz_sync",
     "chf_rz_get_field", "chf_rz_set_field", "chf_rz_get_info",
@@ -74,7 +75,8 @@ class PlanInfo(ct.Structure):
                 ("scale_e", ct.c_double), ("scale_h", ct.c_double), ("field_bytes", ct.c_uint64),
                 ("psi_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
                 ("bytes_per_cell_update", ct.c_double), ("fused_cells", ct.c_uint64),
-                ("fused_bytes_per_cell", ct.c_double)]
+                ("fused_bytes_per_cell", ct.c_double), ("steps_per_launch", ct.c_int32),
+                ("waves_per_row", ct.c_int32), ("pass_bytes_per_cell", ct.c_double)]
 
 
 class RZGrid(ct.Structure):
@@ -159,6 +161,8 @@ def lib():
         L.chf_forward_scratch.argtypes = [vp, vp, vp, vp]
         L.chf_scratch_bytes.restype = ct.c_uint64
         L.chf_scratch_bytes.argtypes = []
+        L.chf_stream_copy.restype = ct.c_int
+        L.chf_stream_copy.argtypes = [vp, vp, ct.c_uint64, ct.c_int32, ct.c_int32, vp]
         L.chf_adjoint.restype = ct.c_int
         L.chf_adjoint.argtypes = [vp, vp, vp, vp]
         L.chf_adjoint_begin.restype = ct.c_int

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <cmath>
 #include <cstdio>
@@ -110,7 +111,7 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       return fail(CHF_EINVAL, "bad CPML grading");
   }
   if (ex->storage < CHF_FP32 || ex->storage > CHF_FP16) return fail(CHF_EINVAL, "bad storage");
-  if (ex->kernel < CHF_KERNEL_AUTO || ex->kernel > CHF_KERNEL_FUSED_PREFETCH) return fail(CHF_EINVAL, "bad kernel");
+  if (ex->kernel < CHF_KERNEL_AUTO || ex->kernel > CHF_KERNEL_FUSED2) return fail(CHF_EINVAL, "bad kernel");
   if (obs->n_obs < 0 || obs->n_obs > chf::kMaxObsPerPlan || (obs->n_obs > 0 && !obs->xyz))
     return fail(CHF_EINVAL, "bad observer list");
   if (src->n_bins < 0 || (src->n_bins > 0 && !src->q_bins)) return fail(CHF_EINVAL, "bad profile");
@@ -136,6 +137,10 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
                                              : ex->kernel;
   const bool prefetch = kernel == CHF_KERNEL_FUSED_PREFETCH;
   if (prefetch) kernel = CHF_KERNEL_FUSED;
+  // two steps per pass: waves_per_block and z_chunk shape the two-step tiles; the single steps
+  // of odd step ranges take the fused sweep's default tile
+  const bool two = kernel == CHF_KERNEL_FUSED2;
+  if (two) kernel = CHF_KERNEL_FUSED;
   if (kernel == CHF_KERNEL_FUSED && G.nx > 64 * chf::kMaxVX) {
     delete p;
     return fail(CHF_EUNSUPPORTED, "fused sweep needs nx <= 512");
@@ -146,9 +151,9 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   while (64 * fs.vx < G.nx) fs.vx *= 2;
   fs.rows = 1;
   // defaults: 7 rows (8 waves: two workgroups fill a CU at 4 waves per SIMD), 12 planes
-  fs.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 7;
-  fs.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 12;
-  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) ||
+  fs.waves = ex->waves_per_block > 0 && !two ? ex->waves_per_block : 7;
+  fs.zchunk = ex->z_chunk > 0 && !two ? ex->z_chunk : 12;
+  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1 || (two && ex->rows_per_wave == 2)) ||
       !(fs.waves == 4 || fs.waves == 7 || fs.waves == 8 || fs.waves == 11 || fs.waves == 15)) {
     delete p;
     return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 7, 8, 11 or 15");
@@ -202,6 +207,69 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     }
     fs.n_slow = (int)(p->slow_tiles.size() / 2);
     fs.slow_blocks = (fs.n_slow + 7) / 8 * 8;
+  }
+  chf::Shape2 &f2 = p->fs2;
+  f2 = chf::Shape2{};
+  if (two) {
+    const int nl = bnd->kind == CHF_BC_CPML ? bnd->npml : 0;
+    if (bnd->kind == CHF_BC_MUR1) {
+      delete p;
+      return fail(CHF_EUNSUPPORTED, "the two-step sweep takes PEC or CPML walls");
+    }
+    if (2 * nl > chf::kMaxStep2Layer) {
+      delete p;
+      return fail(CHF_EUNSUPPORTED, "the two-step sweep takes a CPML of at most 16 cells");
+    }
+    f2.on = 1;
+    f2.xs = G.nx > 256 ? 2 : 1;
+    f2.vx = G.nx > 128 ? 4 : (G.nx > 64 ? 2 : 1);
+    f2.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 8;
+    f2.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 32;
+    f2.late = ex->rows_per_wave == 2 ? 1 : 0;
+    if (f2.xs > 1) {
+      delete p;
+      return fail(CHF_EUNSUPPORTED, "the two-step sweep takes rows of at most 256 nodes");
+    }
+    if (!(f2.waves == 4 || f2.waves == 7 || f2.waves == 8)) {
+      delete p;
+      return fail(CHF_EINVAL, "the two-step sweep takes waves_per_block 4, 7 or 8");
+    }
+    const int W = f2.waves, Z = f2.zchunk;
+    f2.nty = (G.ny + W - 1) / W;
+    f2.nzc = (G.nz + Z - 1) / Z;
+    // rectangle: computed rows j0-2 .. j0+W within [fy0, fy1], stage planes k0-2 .. k1 within
+    // [fz0, fz1] (nodes with no wall and no layer term)
+    const int fy0 = std::max(1, nl), fy1 = G.ny - 2 - nl;
+    const int fz0 = std::max(1, nl), fz1 = G.nz - 2 - nl;
+    f2.ty_lo = (fy0 + 2 + W - 1) / W;
+    f2.ty_hi = fy1 - W >= 0 ? (fy1 - W) / W + 1 : 0;
+    f2.zc_lo = (fz0 + 2 + Z - 1) / Z;
+    f2.zc_hi = fz1 - Z >= 0 ? (fz1 - Z) / Z + 1 : 0;
+    f2.ty_hi = std::min(f2.ty_hi, f2.nty);
+    f2.zc_hi = std::min(f2.zc_hi, f2.nzc);
+    if (f2.ty_hi <= f2.ty_lo || f2.zc_hi <= f2.zc_lo) f2.ty_lo = f2.ty_hi = f2.zc_lo = f2.zc_hi = 0;
+    f2.n_fast = (f2.ty_hi - f2.ty_lo) * (f2.zc_hi - f2.zc_lo);
+    f2.fast_blocks = (f2.n_fast + 7) / 8 * 8;
+    // boundary tiles of kStep2BoundaryRows rows: the rows below and above the rectangle in its z
+    // range, then every row of the other chunks
+    const int B = chf::kStep2BoundaryRows;
+    const int ya = f2.ty_lo * W, yb = f2.ty_hi * W;
+    auto cover = [&](int zc, int lo, int hi) {
+      for (int j0 = lo; j0 < hi; j0 += B) {
+        p->tiles2.push_back(j0);
+        p->tiles2.push_back(std::min(j0 + B, hi));
+        p->tiles2.push_back(zc);
+      }
+    };
+    const bool rect = f2.n_fast > 0;
+    for (int zc = f2.zc_lo; zc < f2.zc_hi && rect; zc++) {
+      cover(zc, 0, ya);
+      cover(zc, yb, G.ny);
+    }
+    f2.n_slow_y = (int)(p->tiles2.size() / 3);
+    for (int zc = 0; zc < f2.nzc; zc++)
+      if (!rect || zc < f2.zc_lo || zc >= f2.zc_hi) cover(zc, 0, G.ny);
+    f2.n_slow = (int)(p->tiles2.size() / 3);
   }
 
   // coefficients (FP64)
@@ -401,6 +469,36 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     }
     D.n_skeys = (int)lists.size();
   }
+  if (p->fs2.on && obs->n_obs > 0) {
+    // samples of the intermediate level of a two-step pass: one slot per distinct (component,
+    // node) of the observers' stencils, entries sorted by plane
+    std::map<std::array<int, 4>, int> slot_of;  // (k, j, i, comp) -> slot
+    p->smp_slot.assign((size_t)obs->n_obs * 24, 0);
+    for (int o = 0; o < obs->n_obs; o++)
+      for (int c = 0; c < 3; c++) {
+        const int *ix = &p->obs_idx[(o * 3 + c) * 3];
+        for (int corner = 0; corner < 8; corner++) {
+          const int a = corner & 1, b = (corner >> 1) & 1, cc = corner >> 2;
+          const std::array<int, 4> key{ix[2] + cc, ix[1] + b, ix[0] + a, c};
+          auto it = slot_of.find(key);
+          int slot;
+          if (it == slot_of.end()) {
+            slot = (int)slot_of.size();
+            slot_of[key] = slot;
+          } else {
+            slot = it->second;
+          }
+          p->smp_slot[(o * 3 + c) * 8 + corner] = slot;
+        }
+      }
+    p->n_smp = slot_of.size();
+    p->smp_ptr.assign((size_t)G.nz + 1, 0);
+    for (const auto &kv : slot_of) p->smp_ptr[kv.first[0] + 1]++;
+    for (int k = 0; k < G.nz; k++) p->smp_ptr[k + 1] += p->smp_ptr[k];
+    p->smp_ent.clear();
+    for (const auto &kv : slot_of)  // map order: by plane, then row, node, component
+      p->smp_ent.insert(p->smp_ent.end(), {kv.first[1], kv.first[2], kv.first[3], kv.second});
+  }
   const uint64_t field = align256((uint64_t)pitch * G.ny * G.nz * p->elem_bytes);
   uint64_t off = 0;
   for (int l = 0; l < 2; l++)
@@ -427,6 +525,11 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       off += len;
     }
   }
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) {
+      p->off_psi_e2[u][t] = off;
+      if (p->fs2.on) off += align256(p->psi_len[u] * 4);
+    }
   p->psi_bytes = off - off_psi0;
   p->off_tf = off;
   off += align256(p->tabf.size() * sizeof(float));
@@ -461,6 +564,16 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   off += align256(std::max<size_t>(p->se_obs.size(), 1) * sizeof(int));
   p->off_sew = off;
   off += align256(std::max<size_t>(p->se_w.size(), 1) * sizeof(double));
+  p->off_tiles2 = off;
+  off += align256(std::max<size_t>(p->tiles2.size(), 1) * sizeof(int));
+  p->off_smp_ptr = off;
+  off += align256(std::max<size_t>(p->smp_ptr.size(), 1) * sizeof(int));
+  p->off_smp_ent = off;
+  off += align256(std::max<size_t>(p->smp_ent.size(), 4) * sizeof(int));
+  p->off_smp = off;
+  off += align256(std::max<size_t>(p->n_smp, 1) * sizeof(float));
+  p->off_smp_slot = off;
+  off += align256(std::max<size_t>(p->smp_slot.size(), 1) * sizeof(int));
   p->ws_bytes = off;
 
   // kernel parameter block (device pointers are filled at bind time)
@@ -522,21 +635,78 @@ chf_status chf_plan_workspace_bytes(const chf_plan *plan, uint64_t *bytes) {
 namespace chf {
 // Points the plan's kernel parameters at the workspace `ws` (>= ws_bytes, 256-byte aligned) and
 // uploads its tables there with stream-ordered copies.  Creates nothing and allocates nothing.
-hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s) {
-  p->ws = ws;
-  chf::Dev &D = p->dev;
+// Field and psi pointers in the unexchanged order (level l at its own offsets).
+void canonical_pointers(chf_plan &p) {
+  char *ws = p.ws;
+  chf::Dev &D = p.dev;
   for (int l = 0; l < 2; l++)
     for (int c = 0; c < 3; c++) {
-      D.e[l][c] = ws + p->off_e[l][c];
-      D.h[l][c] = ws + p->off_h[l][c];
+      D.e[l][c] = ws + p.off_e[l][c];
+      D.h[l][c] = ws + p.off_h[l][c];
     }
   for (int u = 0; u < 3; u++)
     for (int t = 0; t < 2; t++) {
-      D.psi_e[u][t] = (float *)(ws + p->off_psi_e[u][t]);
-      D.psi_h[0][u][t] = (float *)(ws + p->off_psi_h[0][u][t]);
-      D.psi_h[1][u][t] = (float *)(ws + p->off_psi_h[1][u][t]);
-      D.psi_eb[u][t] = (float *)(ws + p->off_psi_eb[u][t]);
+      D.psi_e[u][t] = (float *)(ws + p.off_psi_e[u][t]);
+      D.psi_e2[u][t] = (float *)(ws + p.off_psi_e2[u][t]);
+      D.psi_h[0][u][t] = (float *)(ws + p.off_psi_h[0][u][t]);
+      D.psi_h[1][u][t] = (float *)(ws + p.off_psi_h[1][u][t]);
     }
+  p.lev_swap = p.pe_swap = 0;
+}
+
+// After a two-step launch from level `parity` into parity^1: the new state is made level
+// `parity` again by exchanging the two levels (fields, psi_H) and the two psi_E levels.
+void swap_levels(chf_plan &p, Dev &d) {
+  for (int c = 0; c < 3; c++) {
+    std::swap(d.e[0][c], d.e[1][c]);
+    std::swap(d.h[0][c], d.h[1][c]);
+  }
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) {
+      std::swap(d.psi_h[0][u][t], d.psi_h[1][u][t]);
+      std::swap(d.psi_e[u][t], d.psi_e2[u][t]);
+    }
+  if (&d == &p.dev) {
+    p.lev_swap ^= 1;
+    p.pe_swap ^= 1;
+  }
+}
+
+hipError_t advance(chf_plan &p, hipStream_t s, const double *q, double *w, int col0, int ld, int n, hipEvent_t *ev,
+                   int *n_ev) {
+  Dev d = p.dev;
+  if (!p.ex.nan_watch) d.nan_flag = nullptr;
+  int cnt = 0;
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < n && e == hipSuccess;) {
+    if (p.fs2.on && n - t >= 2) {
+      e = launch_step2(p, d, p.parity, p.n_done, q, w, col0 + t, ld, s, ev ? ev[2 * cnt] : nullptr,
+                       ev ? ev[2 * cnt + 1] : nullptr);
+      cnt++;
+      swap_levels(p, d);
+      swap_levels(p, p.dev);
+      p.n_done += 2;
+      t += 2;
+    } else {
+      const bool timed = ev && !p.fs2.on;
+      e = launch_step(p, d, p.parity, p.n_done, q, w, col0 + t, ld, s, timed ? ev[2 * cnt] : nullptr,
+                      timed ? ev[2 * cnt + 1] : nullptr);
+      if (timed) cnt++;
+      p.parity ^= 1;
+      p.n_done++;
+      t++;
+    }
+  }
+  if (n_ev) *n_ev = cnt;
+  return e;
+}
+
+hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s) {
+  p->ws = ws;
+  chf::Dev &D = p->dev;
+  canonical_pointers(*p);
+  for (int u = 0; u < 3; u++)
+    for (int t = 0; t < 2; t++) D.psi_eb[u][t] = (float *)(ws + p->off_psi_eb[u][t]);
   const float *tf = (const float *)(ws + p->off_tf);
   const int *ti = (const int *)(ws + p->off_ti);
   for (int u = 0; u < 3; u++) {
@@ -567,6 +737,10 @@ hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s) {
   D.nan_flag = (int *)(ws + p->off_nan);
   D.slow_tiles = (const int *)(ws + p->off_tiles);
   D.layer_tiles = (const int *)(ws + p->off_ltiles);
+  D.smp_ptr = p->n_smp ? (const int *)(ws + p->off_smp_ptr) : nullptr;
+  D.smp_ent = (const int4 *)(ws + p->off_smp_ent);
+  D.smp = (float *)(ws + p->off_smp);
+  D.smp_slot = (const int *)(ws + p->off_smp_slot);
   struct Up {
     uint64_t off;
     const void *src;
@@ -585,6 +759,10 @@ hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s) {
       {p->off_sew, p->se_w.data(), p->se_w.size() * sizeof(double)},
       {p->off_tiles, p->slow_tiles.data(), p->slow_tiles.size() * sizeof(int)},
       {p->off_ltiles, p->layer_tiles.data(), p->layer_tiles.size() * sizeof(int)},
+      {p->off_tiles2, p->tiles2.data(), p->tiles2.size() * sizeof(int)},
+      {p->off_smp_ptr, p->smp_ptr.data(), p->smp_ptr.size() * sizeof(int)},
+      {p->off_smp_ent, p->smp_ent.data(), p->smp_ent.size() * sizeof(int)},
+      {p->off_smp_slot, p->smp_slot.data(), p->smp_slot.size() * sizeof(int)},
   };
   for (const Up &u : ups) {
     if (!u.n) continue;
@@ -625,6 +803,7 @@ chf_status chf_plan_reset(chf_plan *p, void *stream) {
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
   hipError_t e = chf::launch_zero(*p, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "reset");
+  chf::canonical_pointers(*p);
   p->parity = 0;
   p->n_done = 0;
   p->adj_next = -1;
@@ -639,15 +818,8 @@ chf_status chf_forward(chf_plan *p, void *stream, const double *q_bins_dev, doub
   if (n_steps < 0 || first_column < 0) return fail(CHF_EINVAL, "negative step count or column");
   if (p->dev.n_obs > 0 && w_dev && (ld_steps < first_column + n_steps))
     return fail(CHF_EINVAL, "ld_steps too small for first_column + n_steps");
-  chf::Dev d = p->dev;
-  if (!p->ex.nan_watch) d.nan_flag = nullptr;
-  hipStream_t s = (hipStream_t)stream;
-  for (int t = 0; t < n_steps; t++) {
-    hipError_t e = chf::launch_step(*p, d, p->parity, p->n_done, q_bins_dev, w_dev, first_column + t, ld_steps, s);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
-    p->parity ^= 1;
-    p->n_done++;
-  }
+  hipError_t e = chf::advance(*p, (hipStream_t)stream, q_bins_dev, w_dev, first_column, ld_steps, n_steps);
+  if (e != hipSuccess) return hip_fail(e, "step launch");
   return CHF_OK;
 }
 
@@ -663,18 +835,16 @@ chf_status chf_forward_timed(chf_plan *p, void *stream, const double *q_bins_dev
   std::vector<hipEvent_t> ev(2 * (size_t)n_steps, nullptr);
   hipError_t e = hipSuccess;
   for (size_t t = 0; t < ev.size() && e == hipSuccess; t++) e = hipEventCreate(&ev[t]);
-  chf::Dev d = p->dev;
-  if (!p->ex.nan_watch) d.nan_flag = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  for (int t = 0; t < n_steps && e == hipSuccess; t++) {
-    e = chf::launch_step(*p, d, p->parity, p->n_done, q_bins_dev, w_dev, first_column + t, ld_steps, s,
-                         ev[2 * t], ev[2 * t + 1]);
-    p->parity ^= 1;
-    p->n_done++;
-  }
+  int launches = 0;
+  // with two steps per pass only the two-step launches are timed (an odd range's single step
+  // runs another kernel)
+  if (e == hipSuccess)
+    e = chf::advance(*p, s, q_bins_dev, w_dev, first_column, ld_steps, n_steps, ev.data(), &launches);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   double total = 0.0;
-  for (int t = 0; t < n_steps && e == hipSuccess && p->fs.n_fast > 0; t++) {
+  const bool timed = p->fs2.on ? p->fs2.n_fast > 0 : p->fs.n_fast > 0;
+  for (int t = 0; t < launches && e == hipSuccess && timed; t++) {
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]);
     total += ms;
@@ -705,14 +875,19 @@ chf_status chf_forward_graph(chf_plan *p, void *stream, const double *q_bins_dev
       (void)hipStreamDestroy(cs);
       return hip_fail(e, "begin capture");
     }
-    chf::Dev d = p->dev;
-    if (!p->ex.nan_watch) d.nan_flag = nullptr;
+    // the captured run starts from zero fields with the levels in their unexchanged order
+    const chf::Dev keep = p->dev;
+    const int keep_par = p->parity, keep_done = p->n_done;
+    chf::canonical_pointers(*p);
+    p->parity = 0;
+    p->n_done = 0;
     hipError_t le = chf::launch_zero(*p, cs);
-    int par = 0;
-    for (int t = 0; t < T && le == hipSuccess; t++) {
-      le = chf::launch_step(*p, d, par, t, q_bins_dev, w_dev, t, T, cs);
-      par ^= 1;
-    }
+    if (le == hipSuccess) le = chf::advance(*p, cs, q_bins_dev, w_dev, 0, T, T);
+    p->graph_swap = p->lev_swap;
+    p->dev = keep;
+    p->parity = keep_par;
+    p->n_done = keep_done;
+    p->lev_swap = p->pe_swap = 0;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
@@ -732,6 +907,8 @@ chf_status chf_forward_graph(chf_plan *p, void *stream, const double *q_bins_dev
   }
   hipError_t e = hipGraphLaunch(p->graph, s);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
+  chf::canonical_pointers(*p);
+  if (p->graph_swap) chf::swap_levels(*p, p->dev);
   p->parity = T & 1;
   p->n_done = T;
   return CHF_OK;
@@ -796,8 +973,25 @@ chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
   const uint64_t rows = (uint64_t)std::max(0, (p->fs.ty_hi - p->fs.ty_lo) * p->fs.waves);
   const uint64_t planes = (uint64_t)std::max(0, (p->fs.zc_hi - p->fs.zc_lo) * p->fs.zchunk);
   info->fused_cells = rows * planes * (uint64_t)p->grid.nx;
-  info->fused_bytes_per_cell =
-      12.0 * p->elem_bytes + (p->bnd.npml > 0 ? (2.0 * p->bnd.npml / p->grid.nx) * 4 * 2 * 4.0 : 0.0);
+  const double one_step = 12.0 * p->elem_bytes + (p->bnd.npml > 0 ? (2.0 * p->bnd.npml / p->grid.nx) * 4 * 2 * 4.0 : 0.0);
+  info->fused_bytes_per_cell = one_step;
+  info->pass_bytes_per_cell = one_step;
+  info->steps_per_launch = 1;
+  info->waves_per_row = 1;
+  if (p->fs2.on) {
+    const chf::Shape2 &f2 = p->fs2;
+    info->kernel = CHF_KERNEL_FUSED2;
+    info->steps_per_launch = 2;
+    info->waves_per_row = f2.xs;
+    info->vx = f2.vx;
+    info->waves_per_block = f2.waves;
+    info->z_chunk = f2.zchunk;
+    const uint64_t r2 = (uint64_t)std::max(0, (f2.ty_hi - f2.ty_lo) * f2.waves);
+    const uint64_t z2 = (uint64_t)std::max(0, (f2.zc_hi - f2.zc_lo) * f2.zchunk);
+    info->fused_cells = r2 * z2 * (uint64_t)p->grid.nx;
+    info->fused_bytes_per_cell = 2.0 * one_step;  // both steps at the one-step algorithmic bytes
+    info->pass_bytes_per_cell = one_step;         // the pass reads and writes each value once
+  }
   return CHF_OK;
 }
 
@@ -940,11 +1134,43 @@ chf_status chf_plan_state_bytes(const chf_plan *p, uint64_t *bytes) {
   return CHF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// A snapshot holds the state in the unexchanged order: level l of the fields and psi_H, and the
+// current psi_E, at their own offsets.  Pieces (snapshot offset, workspace offset, bytes) for
+// the plan's present exchange state; a single piece when nothing is exchanged.
+struct Piece {
+  uint64_t snap, ws, n;
+};
+std::vector<Piece> state_pieces(const chf_plan &p) {
+  if (!p.lev_swap && !p.pe_swap) return {{0, 0, p.off_tf}};
+  std::vector<Piece> v;
+  const uint64_t lev = p.off_e[1][0] - p.off_e[0][0];  // one level: six field arrays
+  for (int l = 0; l < 2; l++) v.push_back({p.off_e[l][0], p.off_e[l ^ p.lev_swap][0], lev});
+  for (int u = 0; u < 3; u++) {
+    const uint64_t len = align256(p.psi_len[u] * 4);
+    for (int t = 0; t < 2; t++) {
+      for (int l = 0; l < 2; l++) v.push_back({p.off_psi_h[l][u][t], p.off_psi_h[l ^ p.lev_swap][u][t], len});
+      const uint64_t a = p.off_psi_e[u][t], b = p.off_psi_e2[u][t];
+      v.push_back({a, p.pe_swap ? b : a, len});
+      if (p.fs2.on) v.push_back({b, p.pe_swap ? a : b, len});
+    }
+  }
+  return v;
+}
+}  // namespace
+
+extern "C" {
+
 chf_status chf_plan_save_state(chf_plan *p, void *stream, void *dst_dev, int32_t *step) {
   if (!p || !dst_dev || !step) return fail(CHF_EINVAL, "NULL argument");
   if (!p->ws) return fail(CHF_ESTATE, "no workspace bound");
-  hipError_t e = hipMemcpyAsync(dst_dev, p->ws, p->off_tf, hipMemcpyDeviceToDevice, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "save state");
+  for (const Piece &c : state_pieces(*p)) {
+    hipError_t e = hipMemcpyAsync((char *)dst_dev + c.snap, p->ws + c.ws, c.n, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "save state");
+  }
   *step = p->n_done;
   return CHF_OK;
 }
@@ -955,6 +1181,7 @@ chf_status chf_plan_load_state(chf_plan *p, void *stream, const void *src_dev, i
   if (step < 0) return fail(CHF_EINVAL, "negative step");
   hipError_t e = hipMemcpyAsync(p->ws, src_dev, p->off_tf, hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "load state");
+  chf::canonical_pointers(*p);
   p->n_done = step;
   p->parity = step & 1;
   p->adj_next = -1;

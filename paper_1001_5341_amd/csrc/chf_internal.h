@@ -17,6 +17,8 @@ constexpr int kMaxGeneralVX = 4;    // widest rows (64*VX nodes) of the general 
 constexpr int kMaxGeneralW = 11;     // and most rows per workgroup
 constexpr int kMaxObsPerPlan = 4096;
 constexpr int kMaxWz = 64;       // longitudinal source support in cells
+constexpr int kMaxStep2Layer = 32;  // 2*npml the two-step sweep handles (x-slab psi in LDS)
+constexpr int kStep2BoundaryRows = 4;  // rows per boundary tile of the two-step sweep
 
 // Per-axis coefficient tables, one entry per node index along the axis.  "e" entries belong
 // to the E-update derivative (backward difference, integer position), "h" entries to the
@@ -42,6 +44,7 @@ struct Dev {
   // 2 (z) -> (Ex,Ey) / (Hx,Hy).  psi_h is kept in two time levels (halo recompute).
   float *psi_e[3][2];
   float *psi_h[2][3][2];
+  float *psi_e2[3][2];       // second level of psi_E, written by the two-step sweeps
   float *psi_eb[3][2];       // second set of the E-term psi cotangents (adjoint only)
   AxisTab ax[3];
   // storage scales: stored = scale * physical
@@ -65,6 +68,13 @@ struct Dev {
   const double *se_w;
   double inv_se;             // 1/scale_e for the gather
   int *nan_flag;
+  // samples of the intermediate level of a two-step pass: entries (j, i, comp, slot) of the
+  // observers' distinct stencil nodes sorted by plane (smp_ptr[k] .. smp_ptr[k+1]), the FP32
+  // values (smp[slot]) and the slot of each (observer, comp, corner)
+  const int *smp_ptr;
+  const int4 *smp_ent;
+  float *smp;
+  const int *smp_slot;
   const int *slow_tiles;     // [n_slow][2] (ty, zc) of the tiles taking the general path
   const int *layer_tiles;    // [n_layer][2] (ty, zc) of the wall-free tiles touching a layer
   // Mur
@@ -84,6 +94,17 @@ struct FusedShape {
   int prefetch;  // interior tiles issue each plane's loads one plane ahead
 };
 
+// Two-step sweep shape: W rows per tile (XS waves of 64 VX nodes per row), Z planes per chunk;
+// tiles whose computed rows and planes (two below, one above) lie clear of walls and y/z
+// layers form the rectangle [ty_lo, ty_hi) x [zc_lo, zc_hi); the remaining rows are covered by
+// tiles of kStep2BoundaryRows rows listed in the table as (first row, end of owned rows, chunk),
+// first those in the rectangle's z range (y walls and layers only), then the rest.
+struct Shape2 {
+  int on, vx, xs, waves, zchunk, nty, nzc;
+  int late;  // next iteration's row loads issued after stage-2 H instead of at the iteration start
+  int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_slow, n_slow_y;
+};
+
 }  // namespace chf
 
 struct chf_plan {
@@ -98,6 +119,7 @@ struct chf_plan {
   int storage;
   int elem_bytes;
   chf::FusedShape fs;
+  chf::Shape2 fs2;             // two Yee steps per pass (CHF_KERNEL_FUSED2)
   // host-side tables (uploaded at bind time)
   std::vector<float> tabf;     // all float axis tables
   std::vector<int> tabi;       // all int slot tables
@@ -114,6 +136,14 @@ struct chf_plan {
   uint64_t off_psi_eb[3][2];   // after the snapshot region: not part of the forward state
   uint64_t off_sknode, off_skcomp, off_skptr, off_seobs, off_sew;
   std::vector<int> slow_tiles, layer_tiles;
+  std::vector<int> tiles2;               // boundary tiles of the two-step sweep
+  std::vector<int> smp_ptr, smp_ent, smp_slot;
+  uint64_t off_psi_e2[3][2], off_tiles2, off_smp_ptr, off_smp_ent, off_smp, off_smp_slot;
+  size_t n_smp = 0;
+  // the two field levels (with psi_H) and the two psi_E levels are exchanged relative to their
+  // workspace offsets after every two-step launch, so that level `parity` always holds the
+  // state after n_done steps; snapshots are stored in the unexchanged order
+  int lev_swap = 0, pe_swap = 0;
   uint64_t field_bytes, psi_bytes, psi_len[3];
   char *ws = nullptr;
   chf::Dev dev;
@@ -129,6 +159,7 @@ struct chf_plan {
   hipGraphExec_t graph = nullptr;
   const void *graph_w = nullptr, *graph_q = nullptr;
   int graph_parity = -1;
+  int graph_swap = 0;  // level exchange state at the end of the captured run
 };
 
 struct chf_batch {
@@ -159,6 +190,19 @@ hipError_t launch_step(const chf_plan &p, const Dev &d, int parity, int step, co
                        double *w_dev, int column, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
                        hipEvent_t ev_b = nullptr);
 hipError_t launch_zero(const chf_plan &p, hipStream_t s);
+// two Yee steps (step, step+1) from level `parity` into level parity^1 (chf_step2.hip): the
+// waveform columns `column` (intermediate level) and `column + 1`
+hipError_t launch_step2(const chf_plan &p, const Dev &d, int parity, int step, const double *q_dev,
+                        double *w_dev, int column, int ld, hipStream_t s, hipEvent_t ev_a = nullptr,
+                        hipEvent_t ev_b = nullptr);
+// exchange the level pointers after a two-step launch; canonical pointers from the offsets
+void swap_levels(chf_plan &p, Dev &d);
+void canonical_pointers(chf_plan &p);
+// n steps from the plan's state (chf_api.hip): two-step launches while two or more steps remain
+// on a two-step plan, single steps otherwise; with `ev`, an event pair around every interior
+// launch of the dominant kind, their number in *n_ev
+hipError_t advance(chf_plan &p, hipStream_t s, const double *q, double *w, int col0, int ld, int n,
+                   hipEvent_t *ev = nullptr, int *n_ev = nullptr);
 hipError_t launch_get_field(const chf_plan &p, int parity, int comp, float *out, hipStream_t s);
 hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float *in, hipStream_t s);
 // forward E levels of one step and the permittivity cotangent they feed (adjoint of eps_r)

@@ -23,129 +23,10 @@
 
 #include <type_traits>
 
+#include "chf_cell.h"
 #include "chf_internal.h"
 
 namespace chf {
-
-// ------------------------------------------------------------------ storage
-template <typename T>
-__device__ __forceinline__ float to_f(T x) { return static_cast<float>(x); }
-template <typename T>
-__device__ __forceinline__ T from_f(float x) { return static_cast<T>(x); }  // RNE
-
-template <typename T, int N>
-struct alignas(sizeof(T) * N) Vec {
-  T v[N];
-};
-
-// Lanes whose cells start beyond the last node (`on` false) neither load nor store.
-template <typename T, int N>
-__device__ __forceinline__ void ld_row(const T *p, float (&o)[N], bool on) {
-  if (on) {
-    Vec<T, N> x = *reinterpret_cast<const Vec<T, N> *>(p);
-#pragma unroll
-    for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
-  } else {
-#pragma unroll
-    for (int v = 0; v < N; v++) o[v] = 0.f;
-  }
-}
-
-// Row access at a wave-uniform base plus a 32-bit byte offset (global_load saddr form).
-template <typename T, int N>
-__device__ __forceinline__ void ld_at(const T *base, unsigned boff, float (&o)[N], bool on) {
-  ld_row<T, N>(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff), o, on);
-}
-
-// Raw storage values of a row (no conversion), zero where the lane holds no node; `unpack`
-// converts them when they are used, so loads issued ahead hold half the registers in BF16/FP16.
-template <typename T, int N>
-__device__ __forceinline__ void ld_raw(const T *base, unsigned boff, Vec<T, N> &x, bool on) {
-  if (on) {
-    x = *reinterpret_cast<const Vec<T, N> *>(reinterpret_cast<const char *>(base) + boff);
-  } else {
-#pragma unroll
-    for (int v = 0; v < N; v++) x.v[v] = from_f<T>(0.f);
-  }
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void unpack(const Vec<T, N> &x, float (&o)[N]) {
-#pragma unroll
-  for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
-}
-
-// The value a store of x followed by a load returns: the fused sweep feeds H to the E update
-// exactly as stored, as the split sweeps (which reload it) do.
-template <typename T, int N>
-__device__ __forceinline__ void as_stored(float (&o)[N]) {
-  if constexpr (!std::is_same<T, float>::value) {
-#pragma unroll
-    for (int v = 0; v < N; v++) o[v] = to_f<T>(from_f<T>(o[v]));
-  }
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on);
-
-template <typename T, int N>
-__device__ __forceinline__ void st_at(T *base, unsigned boff, const float (&o)[N], bool on) {
-  st_row<T, N>(reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff), o, on);
-}
-
-// Stores are non-temporal: a sweep writes the other time level, which no workgroup of the same
-// sweep reads, so streaming it past the caches leaves L2 to the rows and planes that neighbouring
-// tiles read twice (measured 3 % faster per step in FP32 and BF16).
-template <typename T, int N>
-__device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on) {
-  if (!on) return;
-  Vec<T, N> x;
-#pragma unroll
-  for (int v = 0; v < N; v++) x.v[v] = from_f<T>(o[v]);
-  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-  if constexpr (sizeof(x) == 16) {
-    u4 b;
-    __builtin_memcpy(&b, &x, 16);
-    __builtin_nontemporal_store(b, reinterpret_cast<u4 *>(p));
-  } else if constexpr (sizeof(x) == 8) {
-    u2 b;
-    __builtin_memcpy(&b, &x, 8);
-    __builtin_nontemporal_store(b, reinterpret_cast<u2 *>(p));
-  } else if constexpr (sizeof(x) == 4) {
-    unsigned b;
-    __builtin_memcpy(&b, &x, 4);
-    __builtin_nontemporal_store(b, reinterpret_cast<unsigned *>(p));
-  } else {
-    *reinterpret_cast<Vec<T, N> *>(p) = x;
-  }
-}
-
-// ------------------------------------------------------------- cell updates
-// Canonical order of one node update: the two central-difference terms (fmaf), then the CPML
-// terms of the node's derivative axes added in the fixed axis order x, y, z, each with its sign
-// folded in (s = +psi or -psi).  Every sweep variant applies exactly this sequence, so the
-// results agree bitwise whichever variant computed a node.
-__device__ __forceinline__ float pml_psi(float psi, float a, float b, float d) {
-  return fmaf(b, psi, a * d);
-}
-
-// h' = h - c1 d1 + c2 d2, then the layer terms
-__device__ __forceinline__ float h_plain(float h, float d1, float c1, float d2, float c2) {
-  return fmaf(c2, d2, fmaf(-c1, d1, h));
-}
-
-// e' = ca e + c1 d1 - c2 d2, then the layer terms
-__device__ __forceinline__ float e_plain(float ca, float e, float d1, float c1, float d2, float c2) {
-  return fmaf(-c2, d2, fmaf(c1, d1, ca * e));
-}
-
-__device__ __forceinline__ float add_layers(float t, bool qx, float sx, bool qy, float sy, bool qz, float sz) {
-  if (qx) t = t + sx;
-  if (qy) t = t + sy;
-  if (qz) t = t + sz;
-  return t;
-}
 
 __device__ __forceinline__ long long psi_index(const Dev &d, int u, int i, int j, int k, int s) {
   if (u == 0) return ((long long)k * d.ny + j) * d.np2 + s;
@@ -191,13 +72,6 @@ __device__ __forceinline__ float psi_e(const Dev &d, float *p, int u, int pos, i
 // values.  k_fused_gen covers the remaining tiles from a table, with the wall masks of every
 // component and the y/z CPML terms (uniform per row and per plane).  Both apply the canonical
 // per-node sequence, as the split sweeps do.
-// Logical tile of this workgroup: consecutive logical tiles on one XCD (the hardware deals
-// workgroups to the 8 XCDs round-robin).
-__device__ __forceinline__ int xcd_logical() {
-  const int b = blockIdx.x;
-  return (b & 7) * (gridDim.x >> 3) + (b >> 3);
-}
-
 // G = 0: the interior rectangle (no wall and no y/z layer in reach; x walls and the x layer are
 // per-lane fix-ups).  G = 1: boundary tiles whose planes lie in the interior z range (y walls
 // and y layers: masks and terms uniform per row).  G = 2: any tile, adding the z walls and the
@@ -866,25 +740,6 @@ __global__ void __launch_bounds__(1024) k_split_batch(const Dev *devs, const int
 // J_z of the moving Gaussian charge snapshot at (n+1/2) dt, subtracted (times scale*Cb)
 // from Ez^{n+1}.  Bookkeeping in FP64: bunch position, Q(z_s) from the hat bins, and the
 // lattice-normalised longitudinal weights.  One thread per (i, j) of the radial patch.
-__device__ __forceinline__ int source_window(const Dev &d, double zs, int *klo) {
-  const double half = d.cut_sigmas * d.sigma_z;
-  const int lo = (int)ceil((zs - half) / d.dz - 0.5);
-  const int hi = (int)floor((zs + half) / d.dz - 0.5);
-  *klo = lo;
-  return min(hi - lo + 1, kMaxWz);
-}
-
-__device__ __forceinline__ double source_q(const Dev &d, const double *q, double zs) {
-  const double u = (zs - d.z_bin0) / d.dz_bin;
-  const double fl = floor(u);
-  const int b0 = (int)fl;
-  const double t = u - fl;
-  double acc = 0.0;
-  if (b0 >= 0 && b0 < d.n_bins) acc += (1.0 - t) * q[b0];
-  if (b0 + 1 >= 0 && b0 + 1 < d.n_bins) acc += t * q[b0 + 1];
-  return acc;
-}
-
 template <typename T>
 __device__ __forceinline__ void source_body(const Dev &d, int out_par, int step, const double *q, int t) {
   if (!d.src_on || t >= d.src_ni * d.src_nj) return;
@@ -961,32 +816,6 @@ __global__ void k_mur(Dev d, int par) {
 }
 
 // ------------------------------------------------------------------- gather
-// One wave per observer: lane = 8*component + corner.  Each lane forms weight * E in FP64,
-// then a butterfly over the 8 corners sums each component; lanes 0, 8, 16 write.
-template <typename T>
-__device__ __forceinline__ void gather_body(const Dev &d, int par, double *w, int column, int ld, int o) {
-  const int lane = threadIdx.x;
-  const int comp = lane >> 3, corner = lane & 7;
-  double val = 0.0;
-  if (comp < 3) {
-    const int *ix = d.obs_idx + (o * 3 + comp) * 3;
-    const double *tf = d.obs_t + (o * 3 + comp) * 3;
-    const int a = corner & 1, b = (corner >> 1) & 1, c = corner >> 2;
-    const double wgt = (a ? tf[0] : 1.0 - tf[0]) * (b ? tf[1] : 1.0 - tf[1]) * (c ? tf[2] : 1.0 - tf[2]);
-    const long long node = (long long)(ix[2] + c) * d.plane + (long long)(ix[1] + b) * d.pitch + ix[0] + a;
-    const T *E = (const T *)d.e[par][comp];
-    val = wgt * (double)to_f(E[node]);
-  }
-  val += __shfl_xor(val, 1);
-  val += __shfl_xor(val, 2);
-  val += __shfl_xor(val, 4);
-  if (comp < 3 && corner == 0) {
-    const double out = val * d.inv_se;
-    w[((long long)o * 3 + comp) * ld + column] = out;
-    if (d.nan_flag && !isfinite(out)) *d.nan_flag = 1;
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(64) k_gather(Dev d, int par, double *w, int column, int ld) {
   gather_body<T>(d, par, w, column, ld, blockIdx.x);

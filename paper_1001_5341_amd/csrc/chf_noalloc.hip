@@ -69,23 +69,21 @@ chf_status chf_forward_scratch(chf_plan *p, void *stream, const double *q_bins_d
   // parameter block by value)
   char *ws0 = p->ws;
   const chf::Dev dev0 = p->dev;
-  const int par0 = p->parity, done0 = p->n_done, adj0 = p->adj_next;
+  const int par0 = p->parity, done0 = p->n_done, adj0 = p->adj_next, ls0 = p->lev_swap, ps0 = p->pe_swap;
   hipStream_t aux0 = p->aux;
   p->aux = nullptr;  // no side stream: the boundary sweep runs in order on `stream`
   e = chf::bind_tables(p, (char *)sp, s);
-  chf::Dev d = p->dev;
-  if (!p->ex.nan_watch) d.nan_flag = nullptr;
   if (e == hipSuccess) e = chf::launch_zero(*p, s);
-  int par = 0;
-  for (int t = 0; t < p->grid.n_steps && e == hipSuccess; t++) {
-    e = chf::launch_step(*p, d, par, t, q_bins_dev, w_dev, t, p->grid.n_steps, s);
-    par ^= 1;
-  }
+  p->parity = 0;
+  p->n_done = 0;
+  if (e == hipSuccess) e = chf::advance(*p, s, q_bins_dev, w_dev, 0, p->grid.n_steps, p->grid.n_steps);
   p->ws = ws0;
   p->dev = dev0;
   p->parity = par0;
   p->n_done = done0;
   p->adj_next = adj0;
+  p->lev_swap = ls0;
+  p->pe_swap = ps0;
   p->aux = aux0;
   if (e != hipSuccess) {
     chf::set_error(std::string("scratch forward: ") + hipGetErrorString(e));

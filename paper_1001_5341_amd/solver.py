@@ -134,6 +134,11 @@ class Plan:
             graph: bool = False, stream=None, sync: bool = True) -> torch.Tensor:
         """Full run from zero fields; returns [n_obs, 3, n_steps] FP64 waveforms."""
         out = self.new_waveforms() if out is None else out
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.device == self.device
+        assert tuple(out.shape) == (self.n_obs, 3, self.n_steps)
+        if q_bins is not None:
+            assert q_bins.dtype == torch.float64 and q_bins.is_contiguous() and q_bins.device == self.device
+            assert q_bins.numel() == len(self.w.q_bins), (q_bins.numel(), len(self.w.q_bins))
         qp = ct.c_void_p(q_bins.data_ptr()) if q_bins is not None else ct.c_void_p()
         if graph:
             N.check(N.lib().chf_forward_graph(self._h, _stream_handle(stream), qp,
@@ -389,26 +394,33 @@ class CherenkovFDTD(torch.autograd.Function):
 
     forward:  w = A q  (the full run from zero fields; FP64 waveforms [n_obs, 3, n_steps])
     backward: dL/dq = A^T dL/dw by the library's discrete adjoint (exact transpose of the
-              forward recurrence run backward in time), either in one reverse sweep or, with
-              checkpoint_every, by checkpointed recomputation (checkpointed_adjoint)."""
+              forward recurrence run backward in time), in one reverse sweep by default.
+              With checkpoint_every it runs the checkpointed schedule instead
+              (checkpointed_adjoint): same bits, but for this linear map the recomputed forward
+              states are not read, so that schedule only costs time here; it is the one the
+              permittivity gradient (eps_sensitivity) needs.
+    The gradient comes back on the input's device and in its dtype."""
 
     @staticmethod
     def forward(ctx, q_bins: torch.Tensor, plan: "Plan", checkpoint_every: Optional[int] = None):
+        if q_bins.numel() != len(plan.w.q_bins):
+            raise ValueError(f"q_bins has {q_bins.numel()} entries, the plan's profile {len(plan.w.q_bins)}")
         ctx.plan = plan
         ctx.every = checkpoint_every
-        q = q_bins.detach().to(device=plan.device, dtype=torch.float64).contiguous()
+        ctx.in_device, ctx.in_dtype, ctx.in_shape = q_bins.device, q_bins.dtype, q_bins.shape
+        q = q_bins.detach().to(device=plan.device, dtype=torch.float64).contiguous().reshape(-1)
         ctx.q = q
         return plan.run(q_bins=q)
 
     @staticmethod
     def backward(ctx, grad_w: torch.Tensor):
-        g = grad_w.to(torch.float64).contiguous()
+        g = grad_w.to(device=ctx.plan.device, dtype=torch.float64).contiguous()
         if ctx.every:
             dq = checkpointed_adjoint(ctx.plan, g, every=ctx.every, q_bins=ctx.q)
         else:
             dq = ctx.plan.adjoint(g)
             ctx.plan.sync()
-        return dq, None, None
+        return dq.reshape(ctx.in_shape).to(device=ctx.in_device, dtype=ctx.in_dtype), None, None
 
 
 def waveforms(q_bins: torch.Tensor, plan: "Plan", checkpoint_every: Optional[int] = None) -> torch.Tensor:

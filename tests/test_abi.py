@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(N.EXPORTED)
-    assert L.chf_abi_version() == 1
+    assert L.chf_abi_version() == 2
 
 
 def _status(w, **kw):

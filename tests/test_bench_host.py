@@ -57,10 +57,16 @@ def test_counter_summary_calibration_and_traffic_lookup(tmp_path, monkeypatch):
 
 
 def test_roofline_figures():
-    r = bench.roofline({"fused_cells": 1_000_000, "fused_bytes_per_cell": 50.0}, fused_ms=10.0, launches=100)
+    r = bench.roofline({"fused_cells": 1_000_000, "fused_bytes_per_cell": 50.0}, fused_ms=10.0, yee_steps=100)
     # 50 MB per launch in 0.1 ms
     assert r["achieved"] == 500.0 and r["launch_avg_us"] == 100.0
     assert r["frac"] == round(500.0 / bench.HBM_PEAK_GBS, 4) and r["bound"] == "hbm"
+    # two Yee steps per launch: 50 launches of 0.2 ms, each counting both steps' one-step bytes
+    # (100 B per node), beside the pass's own 50 B per node
+    r2 = bench.roofline({"fused_cells": 1_000_000, "fused_bytes_per_cell": 100.0, "pass_bytes_per_cell": 50.0,
+                         "steps_per_launch": 2}, fused_ms=10.0, yee_steps=100)
+    assert r2["launches"] == 50 and r2["launch_avg_us"] == 200.0 and r2["achieved"] == 500.0
+    assert r2["temporal_blocking"]["pass_achieved_gbs"] == 250.0
     w = types.SimpleNamespace(nr=1000, nz=1001)
     z = bench.rz_roofline(w, ms=20.0, launches=100, spl=2)
     # 1000 x 1000 marched nodes x 24 B in 0.2 ms; two Yee steps per pass double the effective rate

@@ -1,0 +1,161 @@
+"""Two Yee steps per pass (CHF_KERNEL_FUSED2, temporal blocking) against the one-step sweeps and
+the FP64 oracle, through the C ABI.
+
+The two-step pass computes every node of both steps with the one-step sweeps' operations and
+rounds the carried intermediate level through the storage type, so its waveforms and all six
+final field components must equal the one-step fused sweep's bit for bit: for FP32, BF16 and
+FP16 storage, CPML and PEC walls, every tile shape, odd step counts (ending on a single step),
+graph replays, random initial fields (every node, layer and wall exercised from the first step),
+and snapshots taken in the middle of a two-step run.  FP32 waveforms also stay within 1e-5 of the
+oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1001_5341_amd import solver
+from paper_1001_5341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+def banner(msg):
+    print(f"\n[gpu-step2] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(got, ref):
+    """Relative L2 per observer, over the observers the pulse has reached within the run (an
+    observer that only the lattice's exponentially small precursor reaches has FP64 values far
+    below FP32's range)."""
+    peak = np.abs(ref).max(axis=(1, 2))
+    seen = peak >= 1e-3 * peak.max()
+    assert seen.sum() >= 1
+    num, den = ((got - ref) ** 2).sum(axis=(1, 2))[seen], (ref ** 2).sum(axis=(1, 2))[seen]
+    return np.sqrt(num / den)
+
+
+def run_fields(w, seed_fields=False, **kw):
+    plan = solver.Plan(w, **kw)
+    info = plan.info()
+    out = plan.new_waveforms()
+    plan.reset()
+    if seed_fields:
+        g = torch.Generator(device=plan.device)
+        g.manual_seed(7)
+        for c in range(6):
+            sc = info["scale_e"] if c < 3 else info["scale_h"]
+            v = torch.rand((w.nz, w.ny, w.nx), generator=g, device=plan.device) * 2 - 1
+            plan.set_field(c, v / sc)
+    plan.forward(w.n_steps, out, 0)
+    plan.sync()
+    wave = out.cpu().numpy()
+    fields = [plan.get_field(c).cpu().numpy() for c in range(6)]
+    plan.close()
+    return wave, fields, info
+
+
+def assert_same(a, b, what):
+    wa, fa, _ = a
+    wb, fb, _ = b
+    assert np.array_equal(wa, wb), (what, float(np.abs(wa - wb).max()))
+    for c in range(6):
+        assert np.array_equal(fa[c], fb[c]), (what, c, float(np.abs(fa[c] - fb[c]).max()))
+
+
+CASES = [
+    # (label, workload, two-step tile: waves, z chunk, late loads)
+    ("small cpml 72x60x150", W.small_shower(seed=11), [(8, 32, 0), (7, 16, 2), (4, 5, 0), (8, 150, 2)]),
+    ("vx2 cpml 100x44x140, odd steps", W.small_shower(seed=17, nx=100, ny=44, nz=140, n_steps=121, n_obs=5),
+     [(8, 16, 0), (4, 9, 2)]),
+    ("vx1 cpml 48x52x90", W.small_shower(seed=5, nx=48, ny=52, nz=90, n_steps=80, n_obs=3, npml=6),
+     [(8, 12, 0), (7, 7, 2)]),
+    ("vx4 pec 200x70x96", W.small_shower(seed=9, nx=200, ny=70, nz=96, n_steps=90, n_obs=4, bc="pec"),
+     [(8, 24, 2), (4, 13, 0)]),
+]
+
+
+@pytest.mark.parametrize("label,w,tiles", CASES, ids=[c[0] for c in CASES])
+def test_two_step_equals_one_step_fp32(gpu, label, w, tiles):
+    banner(f"{label}: one-step reference")
+    ref = run_fields(w, kernel="fused")
+    orc = oracle.run(w)
+    assert np.abs(ref[0]).max() > 0
+    for waves, zchunk, late in tiles:
+        banner(f"{label}: two-step waves={waves} zchunk={zchunk} late={late}")
+        got = run_fields(w, kernel="fused2", waves=waves, zchunk=zchunk, rows=late)
+        assert got[2]["kernel"] == 4 and got[2]["steps_per_launch"] == 2
+        assert (got[2]["waves_per_block"], got[2]["z_chunk"]) == (waves, zchunk)
+        assert_same(got, ref, (label, waves, zchunk, late))
+        err = rel_l2(got[0], orc)
+        assert np.all(err <= TOL_FP32), err
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_two_step_equals_one_step_16bit(gpu, storage):
+    w = W.small_shower(seed=11)
+    banner(f"16-bit {storage}")
+    ref = run_fields(w, storage=storage, kernel="fused")
+    for waves, zchunk, late in [(8, 32, 0), (4, 7, 2)]:
+        got = run_fields(w, storage=storage, kernel="fused2", waves=waves, zchunk=zchunk, rows=late)
+        assert_same(got, ref, (storage, waves, zchunk, late))
+
+
+@pytest.mark.parametrize("bc", ["cpml", "pec"])
+def test_two_step_random_fields(gpu, bc):
+    """From pseudo-random initial fields every node takes a non-trivial update from the first
+    step, so tile edges, halos, layers and walls are all compared."""
+    w = W.small_shower(seed=3, nx=120, ny=58, nz=110, n_steps=33, n_obs=4, bc=bc)
+    banner(f"random fields {bc}")
+    ref = run_fields(w, seed_fields=True, kernel="fused")
+    for waves, zchunk, late in [(8, 16, 0), (7, 11, 2), (4, 32, 0)]:
+        got = run_fields(w, seed_fields=True, kernel="fused2", waves=waves, zchunk=zchunk, rows=late)
+        assert_same(got, ref, (bc, waves, zchunk, late))
+
+
+def test_two_step_graph_and_snapshots(gpu):
+    w = W.small_shower(seed=11, n_steps=101)
+    banner("graph replays and mid-run snapshots")
+    ref = run_fields(w, kernel="fused")
+    plan = solver.Plan(w, kernel="fused2", waves=8, zchunk=16)
+    out = plan.new_waveforms()
+    for rep in range(3):
+        out.zero_()
+        plan.run(out=out, graph=True)
+        assert np.array_equal(out.cpu().numpy(), ref[0]), rep
+        for c in range(6):
+            assert np.array_equal(plan.get_field(c).cpu().numpy(), ref[1][c]), (rep, c)
+    # snapshot after an odd number of steps taken as two-step launches plus a single step
+    snap = torch.empty(plan.state_bytes(), dtype=torch.uint8, device=plan.device)
+    plan.reset()
+    out.zero_()
+    plan.forward(37, out, 0)
+    step = plan.save_state(snap)
+    assert step == 37
+    plan.forward(w.n_steps - 37, out, 37)
+    plan.sync()
+    assert np.array_equal(out.cpu().numpy(), ref[0])
+    part = out.clone()
+    plan.load_state(snap, 37)
+    out[:, :, 37:] = 0
+    plan.forward(w.n_steps - 37, out, 37)
+    plan.sync()
+    assert np.array_equal(out.cpu().numpy(), part.cpu().numpy())
+    for c in range(6):
+        assert np.array_equal(plan.get_field(c).cpu().numpy(), ref[1][c]), c
+    plan.close()
+
+
+def test_two_step_scratch_entry_point(gpu):
+    w = W.small_shower(seed=12, nx=40, ny=36, nz=64, n_steps=90, n_obs=3, npml=5)
+    banner("scratch entry point with two steps per pass")
+    ref = run_fields(w, kernel="fused")
+    plan = solver.Plan(w, kernel="fused2", waves=4, zchunk=8)
+    got = plan.run_scratch().cpu().numpy()
+    plan.close()
+    assert np.array_equal(got, ref[0])

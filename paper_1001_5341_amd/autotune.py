@@ -22,10 +22,13 @@ import torch
 from . import _native as N
 from . import solver
 
-# (waves per workgroup, z chunk, kernel)
+# (waves per workgroup, z chunk, kernel); shapes a grid does not take are skipped: the prefetching
+# sweep takes 4 or 5 rows on rows wider than 256 nodes (two waves per row) and 4-11 otherwise,
+# the two-step sweep ("fused2") rows of at most 256 nodes with PEC or CPML walls
 CANDIDATES: Tuple[Tuple[int, int, str], ...] = (
     tuple((w, z, "fused") for w in (4, 7, 8, 11, 15) for z in (8, 12, 16, 24, 32))
-    + tuple((w, z, "fused_prefetch") for w in (7, 8, 11) for z in (8, 12, 16, 24, 32)))
+    + tuple((w, z, "fused_prefetch") for w in (4, 5, 7, 8, 11) for z in (8, 12, 16, 24, 32))
+    + tuple((w, z, "fused2") for w in (7, 8) for z in (16, 24, 32)))
 
 
 def _cand(c) -> Tuple[int, int, str]:

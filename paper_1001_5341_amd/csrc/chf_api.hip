@@ -153,15 +153,29 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   // defaults: 7 rows (8 waves: two workgroups fill a CU at 4 waves per SIMD), 12 planes
   fs.waves = ex->waves_per_block > 0 && !two ? ex->waves_per_block : 7;
   fs.zchunk = ex->z_chunk > 0 && !two ? ex->z_chunk : 12;
-  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1 || (two && ex->rows_per_wave == 2)) ||
-      !(fs.waves == 4 || fs.waves == 7 || fs.waves == 8 || fs.waves == 11 || fs.waves == 15)) {
+  if (!(ex->rows_per_wave == 0 || ex->rows_per_wave == 1) ||
+      !(fs.waves == 4 || fs.waves == 5 || fs.waves == 7 || fs.waves == 8 || fs.waves == 11 || fs.waves == 15)) {
     delete p;
-    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 7, 8, 11 or 15");
+    return fail(CHF_EINVAL, "rows_per_wave must be 0 or 1 and waves_per_block 4, 5, 7, 8, 11 or 15");
   }
   fs.prefetch = prefetch ? 1 : 0;
-  if (prefetch && (fs.vx > 4 || fs.waves > 11)) {
+  fs.xs = 1;
+  if (prefetch && fs.vx > 4) {
+    // rows of 257-512 nodes: two waves of 64 x 4 nodes per row, 4 or 5 rows per tile
+    fs.vx = 4;
+    fs.xs = 2;
+    if (ex->waves_per_block <= 0) fs.waves = 5;
+    if (fs.waves != 4 && fs.waves != 5) {
+      delete p;
+      return fail(CHF_EINVAL, "the prefetching fused sweep over rows wider than 256 nodes takes waves_per_block 4 or 5");
+    }
+  } else if (prefetch && fs.waves > 11) {
     delete p;
-    return fail(CHF_EINVAL, "the prefetching fused sweep takes rows of at most 256 nodes and waves_per_block 4, 7, 8 or 11");
+    return fail(CHF_EINVAL, "the prefetching fused sweep takes waves_per_block 4, 7, 8 or 11");
+  }
+  if (fs.waves == 5 && fs.xs != 2) {
+    delete p;
+    return fail(CHF_EINVAL, "waves_per_block 5 is for the prefetching sweep over rows wider than 256 nodes");
   }
   if (kernel == CHF_KERNEL_FUSED && fs.vx > 4 && fs.waves != 4 && fs.waves != 7) {
     delete p;
@@ -225,7 +239,6 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     f2.vx = G.nx > 128 ? 4 : (G.nx > 64 ? 2 : 1);
     f2.waves = ex->waves_per_block > 0 ? ex->waves_per_block : 8;
     f2.zchunk = ex->z_chunk > 0 ? ex->z_chunk : 32;
-    f2.late = ex->rows_per_wave == 2 ? 1 : 0;
     if (f2.xs > 1) {
       delete p;
       return fail(CHF_EUNSUPPORTED, "the two-step sweep takes rows of at most 256 nodes");
@@ -977,7 +990,7 @@ chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
   info->fused_bytes_per_cell = one_step;
   info->pass_bytes_per_cell = one_step;
   info->steps_per_launch = 1;
-  info->waves_per_row = 1;
+  info->waves_per_row = p->fs.xs;
   if (p->fs2.on) {
     const chf::Shape2 &f2 = p->fs2;
     info->kernel = CHF_KERNEL_FUSED2;

@@ -92,6 +92,7 @@ struct FusedShape {
   int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_layer, layer_blocks, n_slow, slow_blocks;
   int n_slow_y;  // leading entries of the tile table whose planes lie in [zc_lo, zc_hi) chunks
   int prefetch;  // interior tiles issue each plane's loads one plane ahead
+  int xs;        // waves per row: 2 splits rows of 257-512 nodes (prefetching sweep, VX 4)
 };
 
 // Two-step sweep shape: W rows per tile (XS waves of 64 VX nodes per row), Z planes per chunk;
@@ -101,7 +102,6 @@ struct FusedShape {
 // first those in the rectangle's z range (y walls and layers only), then the rest.
 struct Shape2 {
   int on, vx, xs, waves, zchunk, nty, nzc;
-  int late;  // next iteration's row loads issued after stage-2 H instead of at the iteration start
   int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_slow, n_slow_y;
 };
 

@@ -76,7 +76,9 @@ __device__ __forceinline__ float psi_e(const Dev &d, float *p, int u, int pos, i
 // per-lane fix-ups).  G = 1: boundary tiles whose planes lie in the interior z range (y walls
 // and y layers: masks and terms uniform per row).  G = 2: any tile, adding the z walls and the
 // z layers (uniform per plane).
-template <typename T, int VX, int W, int G, bool PREFETCH = false>
+// XS = 2: rows of up to 512 nodes split across two waves of 64 VX nodes each (the x neighbour
+// across the split comes through LDS words published with the row exchange).
+template <typename T, int VX, int W, int G, bool PREFETCH = false, int XS = 1>
 __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zchunk, int par) {
   // Wave r of the workgroup owns row j = j0 - 1 + r: r = 1..W are the tile's rows, r = 0 is
   // the row below the tile, whose H the E update of row j0 needs (it computes H only and
@@ -87,15 +89,19 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   //   for its E update.
   // Two barriers per plane.  Per plane a wave loads only its own row (6 vector loads), so the
   // registers that wait on HBM hold no duplicated data.
-  constexpr int NL = 64 * VX;
+  constexpr int NL = 64 * VX * XS;
   __shared__ float sEx[W + 2][NL], sEz[W + 2][NL], sHx[W][NL], sHz[W][NL];
+  // split rows: (Ey, Ez) of the first node of each wave's segment (E(k) of the own row), and
+  // (Hy, Hz) of its last node (H^{n+1/2}(k)), per row
+  __shared__ float sBE[W + 1][XS][2], sBH[W + 1][XS][2];
   __shared__ float sTab[8][NL];  // per x node: ch, ce, ah, bh, ae, be, x-slab index (H, E)
   // x-slab psi of the own row (H: Hy, Hz terms; E: Ey, Ez terms), staged so that both the
   // loads and the stores of a row's slab are one contiguous value per lane; the node that owns
   // slab index s replaces its value in place
-  __shared__ float sPsi[W + 1][4][kMaxFusedLayer];
+  __shared__ float sPsi[(W + 1) * XS][4][kMaxFusedLayer];
   const int lane = threadIdx.x & 63;
-  const int r = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
+  const int r = wv / XS, xs = wv - r * XS;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const int j0 = ty * W;
   const int j = j0 - 1 + r;
@@ -105,8 +111,19 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   const bool own = r > 0 && act, top = r == W;
   const bool top_ld = top && (!GY || j + 1 < ny);
   const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
-  const int ib = lane * VX;
+  const int ib = xs * 64 * VX + lane * VX;
   const bool on = ib < nx && act;
+  // x-slab psi slots this wave writes back: those whose node lies in its segment
+  bool own_sh = true, own_se = true;
+  if constexpr (XS > 1) {
+    if (lane < d.np2) {
+      const int npml = d.npml;
+      const int nh = lane < npml ? lane : lane - npml + (nx - 1 - npml);
+      const int ne = lane < npml ? lane : lane - npml + (nx - npml);
+      own_sh = nh / (64 * VX) == xs;
+      own_se = ne / (64 * VX) == xs;
+    }
+  }
   const unsigned esz = (unsigned)sizeof(T);
   const unsigned o0 = ((unsigned)jc * (unsigned)d.pitch + (unsigned)ib) * esz;  // own row
   const unsigned op = ((unsigned)min(jc + 1, ny - 1) * (unsigned)d.pitch + (unsigned)ib) * esz;  // row above
@@ -120,7 +137,7 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   float *pho0 = d.psi_h[par ^ 1][0][0], *pho1 = d.psi_h[par ^ 1][0][1];
   float *pe0 = d.psi_e[0][0], *pe1 = d.psi_e[0][1];
 
-  for (int i = threadIdx.x; i < NL; i += 64 * (W + 1)) {
+  for (int i = threadIdx.x; i < NL; i += 64 * (W + 1) * XS) {
     const int ic = min(i, nx - 1);
     const bool lay = np2 > 0 && i < nx;
     sTab[0][i] = d.ax[0].ch[ic];
@@ -171,7 +188,11 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     ld_at<T, VX>(Hi1 + km * plane, o0, hyo, on);
     const float chz = d.ax[2].ch[km];
     const int shz = np2 > 0 ? d.ax[2].sh[km] : -1;
-    const float ezn = __shfl_down(ez_[0], 1);
+    float ezn = __shfl_down(ez_[0], 1);
+    if constexpr (XS > 1) {  // the next segment's first node, read directly
+      if (lane == 63 && xs + 1 < XS && ib + VX < nx)
+        ezn = to_f(*reinterpret_cast<const T *>(reinterpret_cast<const char *>(Ei2 + km * plane) + o0 + VX * esz));
+    }
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       const int i = ib + v;
@@ -236,6 +257,12 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
       for (int v = 0; v < VX; v++) {
         sEx[r][ib + v] = exc[v];
         sEz[r][ib + v] = ezc[v];
+      }
+    }
+    if constexpr (XS > 1) {
+      if (lane == 0) {
+        sBE[r][xs][0] = eyc[0];
+        sBE[r][xs][1] = ezc[0];
       }
     }
     if (top) {
@@ -328,10 +355,10 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
 
     // ---- H^{n+1/2}(k) of the own row
     if (lane < np2) {
-      sPsi[r][0][lane] = q0;
-      sPsi[r][1][lane] = q1;
-      sPsi[r][2][lane] = q2;
-      sPsi[r][3][lane] = q3;
+      sPsi[wv][0][lane] = q0;
+      sPsi[wv][1][lane] = q1;
+      sPsi[wv][2][lane] = q2;
+      sPsi[wv][3][lane] = q3;
     }
     float eux[VX], euz[VX], chx[VX];
 #pragma unroll
@@ -340,7 +367,13 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
       euz[v] = sEz[r + 1][ib + v];
       chx[v] = sTab[0][ib + v];
     }
-    const float eyn = __shfl_down(eyc[0], 1), ezn = __shfl_down(ezc[0], 1);
+    float eyn = __shfl_down(eyc[0], 1), ezn = __shfl_down(ezc[0], 1);
+    if constexpr (XS > 1) {
+      if (lane == 63 && xs + 1 < XS) {
+        eyn = sBE[r][xs + 1][0];
+        ezn = sBE[r][xs + 1][1];
+      }
+    }
     float hx[VX], hy[VX], hz[VX];
 #pragma unroll
     for (int v = 0; v < VX; v++) {
@@ -364,14 +397,14 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
           const float ezx = (v + 1 < VX) ? ezc[v + 1] : ezn;
           const float ah = sTab[2][i], bh = sTab[3][i];
           if (kh) {
-            const float py = pml_psi(sPsi[r][0][sh], ah, bh, ezx - ezc[v]);
+            const float py = pml_psi(sPsi[wv][0][sh], ah, bh, ezx - ezc[v]);
             hy[v] = hy[v] + py;
-            sPsi[r][0][sh] = py;
+            sPsi[wv][0][sh] = py;
           }
           if (jh) {
-            const float pz = pml_psi(sPsi[r][1][sh], ah, bh, eyx - eyc[v]);
+            const float pz = pml_psi(sPsi[wv][1][sh], ah, bh, eyx - eyc[v]);
             hz[v] = hz[v] + -pz;
-            sPsi[r][1][sh] = pz;
+            sPsi[wv][1][sh] = pz;
           }
         }
       }
@@ -423,6 +456,12 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
         sHz[r][ib + v] = hz[v];
       }
     }
+    if constexpr (XS > 1) {
+      if (lane == 63) {
+        sBH[r][xs][0] = hy[VX - 1];
+        sBH[r][xs][1] = hz[VX - 1];
+      }
+    }
     __syncthreads();
 
     if (own) {
@@ -434,7 +473,13 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
         hzm[v] = sHz[r - 1][ib + v];
         cex[v] = sTab[1][ib + v];
       }
-      const float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
+      float hzw0 = __shfl_up(hz[VX - 1], 1), hyw0 = __shfl_up(hy[VX - 1], 1);
+      if constexpr (XS > 1) {
+        if (lane == 0 && xs > 0) {
+          hyw0 = sBH[r][xs - 1][0];
+          hzw0 = sBH[r][xs - 1][1];
+        }
+      }
       float oex[VX], oey[VX], oez[VX];
 #pragma unroll
       for (int v = 0; v < VX; v++) {
@@ -461,14 +506,14 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
             const float hyw = (v > 0) ? hy[v - 1] : hyw0;
             const float ae = sTab[4][i], be = sTab[5][i];
             if (jh && ke) {
-              const float py = pml_psi(sPsi[r][2][se], ae, be, hz[v] - hzw);
+              const float py = pml_psi(sPsi[wv][2][se], ae, be, hz[v] - hzw);
               oey[v] = oey[v] + -py;
-              sPsi[r][2][se] = py;
+              sPsi[wv][2][se] = py;
             }
             if (je && kh) {
-              const float pz = pml_psi(sPsi[r][3][se], ae, be, hy[v] - hyw);
+              const float pz = pml_psi(sPsi[wv][3][se], ae, be, hy[v] - hyw);
               oez[v] = oez[v] + pz;
-              sPsi[r][3][se] = pz;
+              sPsi[wv][3][se] = pz;
             }
           }
         }
@@ -518,10 +563,14 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
       st_at<T, VX>(Eo2 + pk, o0, oez, on);
       // the row's x-slab psi back to memory (slab indices of wall nodes keep their values)
       if (lane < np2) {
-        pho0[prow + lane] = sPsi[r][0][lane];
-        pho1[prow + lane] = sPsi[r][1][lane];
-        pe0[prow + lane] = sPsi[r][2][lane];
-        pe1[prow + lane] = sPsi[r][3][lane];
+        if (own_sh) {
+          pho0[prow + lane] = sPsi[wv][0][lane];
+          pho1[prow + lane] = sPsi[wv][1][lane];
+        }
+        if (own_se) {
+          pe0[prow + lane] = sPsi[wv][2][lane];
+          pe1[prow + lane] = sPsi[wv][3][lane];
+        }
       }
       if constexpr (GY) {
         if (shy >= 0) {
@@ -552,20 +601,21 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
     }
   }
 }
-template <typename T, int VX, int W, bool PF>
-__global__ void __launch_bounds__(64 * (W + 1)) k_fused(Dev d, FusedShape fs, int par) {
+template <typename T, int VX, int W, bool PF, int XS = 1>
+__global__ void __launch_bounds__(64 * (W + 1) * XS) k_fused(Dev d, FusedShape fs, int par) {
   const int logical = xcd_logical();
   if (logical >= fs.n_fast) return;
   const int fw = fs.ty_hi - fs.ty_lo;
-  fused_body<T, VX, W, 0, PF>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+  fused_body<T, VX, W, 0, PF, XS>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
 }
 // Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep: G = 1
 // over the table's first n_slow_y entries (interior z range), G = 2 over the rest.
-template <typename T, int VX, int W, int G, bool PF>
-__global__ void __launch_bounds__(64 * (W + 1)) k_fused_gen(Dev d, FusedShape fs, const int *tiles, int n, int par) {
+template <typename T, int VX, int W, int G, bool PF, int XS = 1>
+__global__ void __launch_bounds__(64 * (W + 1) * XS) k_fused_gen(Dev d, FusedShape fs, const int *tiles, int n,
+                                                                  int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
-  fused_body<T, VX, W, G, PF>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
+  fused_body<T, VX, W, G, PF, XS>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
 }
 
 // Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
@@ -918,9 +968,33 @@ static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, boo
   }
 }
 
+// Rows of up to 512 nodes split across two waves (VX 4): the prefetching interior sweep with 4 or 5
+// rows per tile (10 or 12 waves) and the plain general sweep for the boundary tiles.
+template <typename T, int W>
+static hipError_t split_rows_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+  const dim3 block(64 * (W + 1) * 2);
+  if (general) {
+    const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
+    if (ny_ > 0)
+      hipLaunchKernelGGL((k_fused_gen<T, 4, W, 1, false, 2>), dim3((ny_ + 7) / 8 * 8), block, 0, s, d, p.fs,
+                         d.slow_tiles, ny_, par);
+    if (nr > 0)
+      hipLaunchKernelGGL((k_fused_gen<T, 4, W, 2, false, 2>), dim3((nr + 7) / 8 * 8), block, 0, s, d, p.fs,
+                         d.slow_tiles + 2 * ny_, nr, par);
+  } else {
+    hipLaunchKernelGGL((k_fused<T, 4, W, true, 2>), dim3(p.fs.fast_blocks), block, 0, s, d, p.fs, par);
+  }
+  return hipGetLastError();
+}
+
 // general = false: the interior rectangle; true: the boundary tiles of the tile table
 template <typename T>
 static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+  if (p.fs.xs == 2) {
+    if (p.fs.waves == 4) return split_rows_launch<T, 4>(p, d, par, general, s);
+    if (p.fs.waves == 5) return split_rows_launch<T, 5>(p, d, par, general, s);
+    return hipErrorInvalidValue;
+  }
   switch (p.fs.vx) {
     case 1: return fused_dispatch_w<T, 1>(p, d, par, general, s);
     case 2: return fused_dispatch_w<T, 2>(p, d, par, general, s);
@@ -943,7 +1017,7 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
     // fit its registers, in split H and E sweeps).  Both read only the input
     // level and write disjoint nodes, so the boundary sweep (its H half, when split) runs on
     // the side stream beside the interior one.
-    const bool gen = p.fs.vx <= kMaxGeneralVX && p.fs.waves <= kMaxGeneralW;
+    const bool gen = (p.fs.vx <= kMaxGeneralVX && p.fs.waves <= kMaxGeneralW) || p.fs.xs == 2;
     const bool fork = p.fs.n_fast > 0 && p.fs.n_slow > 0 && p.aux;
     if (fork) {
       e = hipEventRecord(p.ev_fork, s);

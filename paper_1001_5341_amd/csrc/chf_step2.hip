@@ -99,39 +99,28 @@ __device__ __forceinline__ void src_apply(const Dev &d, const SrcLds &S, int st,
   }
 }
 
-template <int VX>
-__device__ __forceinline__ float pick(const float (&a)[VX], int v) {
-  float r = a[0];
-#pragma unroll
-  for (int u = 1; u < VX; u++)
-    if (v == u) r = a[u];
-  return r;
-}
-
-// LATE: the next iteration's row loads are issued after stage-2 H (in flight through stage-2 E
-// and the barriers) instead of at the start of the iteration, which keeps their registers out of
-// the busiest part of the iteration.
-template <typename T, int VX, int W, int XS, int G, bool LATE>
+template <typename T, int VX, int W, int XS, int G>
 __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int zc, int zchunk, int par, int step,
                                            const double *q) {
   constexpr int NR = W + 3;  // computed rows: j0-2 .. j0+W; row NR (j0+W+1) is only loaded
   constexpr int SEG = 64 * VX, NL = SEG * XS;
   constexpr bool GY = G >= 1, GZ = G >= 2;
   constexpr int NP = kMaxStep2Layer;
-  // Row exchange.  sE0: E^n(k) (x, z) of row j0-2+s for s <= W+2, s = NR the row above the top
-  // halo.  sH1: H^{n+1/2}(k) of rows s = 0 .. W+1.  sE1[k & 1]: E^{n+1}(k) of rows s+2, s = 0 .. W.
+  // Row exchange.  sE0: E^n(k) of row j0-2+s for s <= W+2 (read by the row itself and by the row
+  // below), s = NR the row above the top halo.  sH1: H^{n+1/2}(k) of rows s = 0 .. W+1.  sE1[k & 1]: E^{n+1}(k) of rows s+1, s = 0 .. W+1
+  // (read by the row itself one iteration later and by the row below).
   // sH2: H^{n+3/2}(k-1) of rows s+1, s = 0 .. W-1.
-  __shared__ float sE0x[NR + 1][NL], sE0z[NR + 1][NL];
+  __shared__ float sE0x[NR + 1][NL], sE0y[NR + 1][NL], sE0z[NR + 1][NL];
   __shared__ float sH1x[NR - 1][NL], sH1z[NR - 1][NL];
-  __shared__ float sE1x[2][NR - 2][NL], sE1z[2][NR - 2][NL];
+  __shared__ float sE1x[2][NR - 1][NL], sE1y[2][NR - 1][NL], sE1z[2][NR - 1][NL];
   __shared__ float sH2x[NR - 3][NL], sH2z[NR - 3][NL];
   // x tables: ch, ce, ah, bh, ae, be, x-slab slot (H), x-slab slot (E)
   __shared__ float sTab[8][NL];
   // x-slab psi of each wave's row, per plane parity: Hy, Hz terms (slots 0, 1), Ey, Ez terms (2, 3)
   __shared__ float sPsi[(NR + 1) * XS][2][4][NP];
-  // split rows: the x neighbours across a wave boundary -- the first node's (Ey, Ez) of E levels,
-  // the last node's (Hy, Hz) of H levels, per row and wave
-  __shared__ float sBE0[NR + 1][XS][2], sBH1[NR + 1][XS][2], sBE1[2][NR + 1][XS][2], sBH2[NR + 1][XS][2];
+  // split rows: the x neighbours across a wave boundary -- the last node's (Hy, Hz) of H levels,
+  // per row and wave (E levels are whole rows in LDS)
+  __shared__ float sBH1[NR + 1][XS][2], sBH2[NR + 1][XS][2];
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = wv / XS, xs = wv - r * XS;
@@ -375,15 +364,8 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
     as_stored<T, VX>(oez);
   };
 
-  // x neighbours: the next node's value (lane + 1, or the next wave of a split row), the
-  // previous node's value (lane - 1, or the previous wave)
-  auto next_of = [&](float first, const float *bword) -> float {
-    float n = __shfl_down(first, 1);
-    if constexpr (XS > 1) {
-      if (lane == 63 && xs + 1 < XS) n = bword[2 * (xs + 1)];
-    }
-    return n;
-  };
+  // x neighbour of H levels: the previous node's value (lane - 1, or the previous wave of a
+  // split row); E levels sit in LDS as whole rows
   auto prev_of = [&](float last, const float *bword) -> float {
     float p = __shfl_up(last, 1);
     if constexpr (XS > 1) {
@@ -394,8 +376,8 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
 
   // ---------------------------------------------------------------- prologue
   // E^n(k0-2) of the row (and the row above the top halo), published for stage-1 H(k0-2)
-  float e0x[VX], e0y[VX], e0z[VX];
   {
+    float e0x[VX], e0y[VX], e0z[VX];
     const int kb = max(k0 - 2, 0);
     const bool pk = k0 - 2 >= 0;
     ld_at<T, VX>(Ei0 + kb * plane, o0, e0x, on && pk);
@@ -404,13 +386,8 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       sE0x[r][ib + v] = e0x[v];
+      sE0y[r][ib + v] = e0y[v];
       sE0z[r][ib + v] = e0z[v];
-    }
-    if constexpr (XS > 1) {
-      if (lane == 0) {
-        sBE0[r][xs][0] = e0y[0];
-        sBE0[r][xs][1] = e0z[0];
-      }
     }
   }
   // raw loads of the first iteration: E^n(k+1), H^{n-1/2}(k), x-slab psi(k) (the loader wave:
@@ -441,11 +418,11 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
 
   // carried between iterations: stage-1 H and E of the previous plane, stage-2 H two planes back,
   // y/z-slab psi of the previous plane's stage 1
-  float h1x[VX], h1y[VX], h1z[VX], e1x[VX], e1y[VX], e1z[VX], h2x[VX], h2y[VX];
+  float h1x[VX], h1y[VX], h1z[VX], h2x[VX], h2y[VX];
   float c_hxy[VX], c_hzy[VX], c_hxz[VX], c_hyz[VX], c_exy[VX], c_ezy[VX], c_exz[VX], c_eyz[VX];
 #pragma unroll
   for (int v = 0; v < VX; v++) {
-    h1x[v] = h1y[v] = h1z[v] = e1x[v] = e1y[v] = e1z[v] = h2x[v] = h2y[v] = 0.f;
+    h1x[v] = h1y[v] = h1z[v] = h2x[v] = h2y[v] = 0.f;
     c_hxy[v] = c_hzy[v] = c_hxz[v] = c_hyz[v] = c_exy[v] = c_ezy[v] = c_exz[v] = c_eyz[v] = 0.f;
   }
 
@@ -456,10 +433,9 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
     const bool st2H = m >= k0 - 1 && m >= 0;         // stage-2 H(m) is needed (m <= k1 - 1 < nz)
     const bool st2E = m >= k0;                       // stage-2 E(m) is stored
     // this iteration's operands
-    float nxc[VX], nyc[VX], nzc[VX], h0x[VX], h0y[VX], h0z[VX];
+    float nxc[VX], nyc[VX], h0x[VX], h0y[VX], h0z[VX];
     unpack<T, VX>(rE0, nxc);
     unpack<T, VX>(rE1, nyc);
-    unpack<T, VX>(rE2, nzc);
     unpack<T, VX>(rH0, h0x);
     unpack<T, VX>(rH1, h0y);
     unpack<T, VX>(rH2, h0z);
@@ -487,8 +463,6 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
 #pragma unroll
       for (int v = 0; v < VX; v++) qhxy[v] = qhzy[v] = qhxz[v] = qhyz[v] = qexy[v] = qezy[v] = qexz[v] = qeyz[v] = 0.f;
     }
-    // next iteration's row loads, in flight through this one
-    if constexpr (!LATE) issue(k + 1);
     const int pb = k & 1, pm = m & 1;
     if (lane < np2 && !loader) {
       float *p0 = PS(pb, 0), *p1 = PS(pb, 1), *p2 = PS(pb, 2), *p3 = PS(pb, 3);
@@ -501,13 +475,19 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
     // ---- A: stage-1 H(k)
     float hx[VX], hy[VX], hz[VX];
     if (pk && doH1) {
-      float uax[VX], uaz[VX];
+      float uax[VX], uaz[VX], e0x[VX], e0y[VX], e0z[VX];
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         uax[v] = sE0x[r + 1][ib + v];
         uaz[v] = sE0z[r + 1][ib + v];
+        e0x[v] = sE0x[r][ib + v];
+        e0y[v] = sE0y[r][ib + v];
+        e0z[v] = sE0z[r][ib + v];
       }
-      const float eyn = next_of(e0y[0], &sBE0[r][0][0]), ezn = next_of(e0z[0], &sBE0[r][0][1]);
+      // the next node's Ey, Ez: the row is contiguous in LDS across the waves of a split row (the
+      // last node of the row reads a clamped slot; its update does not use it)
+      const int inx = min(ib + VX, NL - 1);
+      const float eyn = sE0y[r][inx], ezn = sE0z[r][inx];
       h_upd(k, h0x, h0y, h0z, e0x, e0y, e0z, nxc, nyc, uax, uaz, eyn, ezn, pb, qhxy, qhzy, qhxz, qhyz, hx, hy, hz);
     } else {
 #pragma unroll
@@ -531,11 +511,14 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
     // ---- B: stage-1 E(k), stage-2 H(m)
     float ox[VX], oy[VX], oz[VX];
     if (doE1 && st1E) {
-      float bx[VX], bz[VX];
+      float bx[VX], bz[VX], e0x[VX], e0y[VX], e0z[VX];
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         bx[v] = sH1x[r - 1][ib + v];
         bz[v] = sH1z[r - 1][ib + v];
+        e0x[v] = sE0x[r][ib + v];
+        e0y[v] = sE0y[r][ib + v];
+        e0z[v] = sE0z[r][ib + v];
       }
       const float hzw0 = prev_of(hz[VX - 1], &sBH1[r][0][1]), hyw0 = prev_of(hy[VX - 1], &sBH1[r][0][0]);
       e_upd(k, e0x, e0y, e0z, hx, hy, hz, h1x, h1y, bx, bz, hzw0, hyw0, pb, qexy, qezy, qexz, qeyz, ox, oy, oz);
@@ -545,9 +528,14 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
         const int e_lo = d.smp_ptr[k], e_hi = d.smp_ptr[k + 1];
         for (int e = e_lo; e < e_hi; e++) {
           const int4 en = d.smp_ent[e];
-          const int li = en.y - ib;
-          if (en.x == j && li >= 0 && li < VX) {
-            const float val = en.z == 0 ? pick<VX>(ox, li) : en.z == 1 ? pick<VX>(oy, li) : pick<VX>(oz, li);
+          if (en.x != j) continue;
+          // static indices only (a selected register array would go to scratch memory)
+#pragma unroll
+          for (int v = 0; v < VX; v++) {
+            if (en.y != ib + v) continue;
+            float val = oz[v];
+            if (en.z == 0) val = ox[v];
+            if (en.z == 1) val = oy[v];
             d.smp[en.w] = val;
           }
         }
@@ -556,28 +544,27 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
 #pragma unroll
       for (int v = 0; v < VX; v++) ox[v] = oy[v] = oz[v] = 0.f;
     }
-    if (r >= 2 && r <= NR - 1) {
+    if (r >= 1 && r <= NR - 1) {
 #pragma unroll
       for (int v = 0; v < VX; v++) {
-        sE1x[pb][r - 2][ib + v] = ox[v];
-        sE1z[pb][r - 2][ib + v] = oz[v];
-      }
-    }
-    if constexpr (XS > 1) {
-      if (lane == 0) {
-        sBE1[pb][r][xs][0] = oy[0];
-        sBE1[pb][r][xs][1] = oz[0];
+        sE1x[pb][r - 1][ib + v] = ox[v];
+        sE1y[pb][r - 1][ib + v] = oy[v];
+        sE1z[pb][r - 1][ib + v] = oz[v];
       }
     }
     float gx[VX], gy[VX], gz[VX];
     if (doH2 && st2H) {
-      float uax[VX], uaz[VX];
+      float uax[VX], uaz[VX], e1x[VX], e1y[VX], e1z[VX];
 #pragma unroll
       for (int v = 0; v < VX; v++) {
-        uax[v] = sE1x[pm][r - 1][ib + v];
-        uaz[v] = sE1z[pm][r - 1][ib + v];
+        uax[v] = sE1x[pm][r][ib + v];
+        uaz[v] = sE1z[pm][r][ib + v];
+        e1x[v] = sE1x[pm][r - 1][ib + v];
+        e1y[v] = sE1y[pm][r - 1][ib + v];
+        e1z[v] = sE1z[pm][r - 1][ib + v];
       }
-      const float eyn = next_of(e1y[0], &sBE1[pm][r][0][0]), ezn = next_of(e1z[0], &sBE1[pm][r][0][1]);
+      const int inx = min(ib + VX, NL - 1);
+      const float eyn = sE1y[pm][r - 1][inx], ezn = sE1z[pm][r - 1][inx];
       h_upd(m, h1x, h1y, h1z, e1x, e1y, e1z, ox, oy, uax, uaz, eyn, ezn, pm, c_hxy, c_hzy, c_hxz, c_hyz, gx, gy, gz);
     } else {
 #pragma unroll
@@ -596,28 +583,33 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
         sBH2[r][xs][1] = gz[VX - 1];
       }
     }
-    // E^n(k+1) of the row for the next iteration's stage-1 H
+    // E^n(k+1) of the row for the next iteration (its own stages and the row below's H); then the
+    // next iteration's row loads, in flight through stage-2 E and the barriers
+    {
+      float t0[VX], t1[VX], t2[VX];
+      unpack<T, VX>(rE0, t0);
+      unpack<T, VX>(rE1, t1);
+      unpack<T, VX>(rE2, t2);
 #pragma unroll
-    for (int v = 0; v < VX; v++) {
-      sE0x[r][ib + v] = nxc[v];
-      sE0z[r][ib + v] = nzc[v];
-    }
-    if constexpr (XS > 1) {
-      if (lane == 0) {
-        sBE0[r][xs][0] = nyc[0];
-        sBE0[r][xs][1] = nzc[0];
+      for (int v = 0; v < VX; v++) {
+        sE0x[r][ib + v] = t0[v];
+        sE0y[r][ib + v] = t1[v];
+        sE0z[r][ib + v] = t2[v];
       }
     }
-    if constexpr (LATE) issue(k + 1);
+    issue(k + 1);
     __syncthreads();
 
     // ---- C: stage-2 E(m), stores
     if (own && st2E) {
-      float bx[VX], bz[VX], fx[VX], fy[VX], fz[VX];
+      float bx[VX], bz[VX], fx[VX], fy[VX], fz[VX], e1x[VX], e1y[VX], e1z[VX];
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         bx[v] = sH2x[r - 2][ib + v];
         bz[v] = sH2z[r - 2][ib + v];
+        e1x[v] = sE1x[pm][r - 1][ib + v];
+        e1y[v] = sE1y[pm][r - 1][ib + v];
+        e1z[v] = sE1z[pm][r - 1][ib + v];
       }
       const float hzw0 = prev_of(gz[VX - 1], &sBH2[r][0][1]), hyw0 = prev_of(gy[VX - 1], &sBH2[r][0][0]);
       e_upd(m, e1x, e1y, e1z, gx, gy, gz, h2x, h2y, bx, bz, hzw0, hyw0, pm, c_exy, c_ezy, c_exz, c_eyz, fx, fy, fz);
@@ -672,12 +664,6 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
       h1x[v] = hx[v];
       h1y[v] = hy[v];
       h1z[v] = hz[v];
-      e1x[v] = ox[v];
-      e1y[v] = oy[v];
-      e1z[v] = oz[v];
-      e0x[v] = nxc[v];
-      e0y[v] = nyc[v];
-      e0z[v] = nzc[v];
       if constexpr (GY) {
         c_hxy[v] = qhxy[v];
         c_hzy[v] = qhzy[v];
@@ -693,25 +679,25 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
 }
 
 // The interior rectangle (no wall and no y/z layer within any computed row or plane).
-template <typename T, int VX, int W, int XS, bool LATE>
+template <typename T, int VX, int W, int XS>
 __global__ void __launch_bounds__(64 * (W + 4) * XS) k_step2(Dev d, Shape2 f2, int par, int step, const double *q) {
   const int logical = xcd_logical();
   if (logical >= f2.n_fast) return;
   const int fw = f2.ty_hi - f2.ty_lo;
   const int j0 = (f2.ty_lo + logical % fw) * W;
-  step2_body<T, VX, W, XS, 0, LATE>(d, j0, j0 + W, f2.zc_lo + logical / fw, f2.zchunk, par, step, q);
+  step2_body<T, VX, W, XS, 0>(d, j0, j0 + W, f2.zc_lo + logical / fw, f2.zchunk, par, step, q);
 }
 
 // Boundary tiles of kStep2BoundaryRows rows from the table (first row, end of the rows the tile
 // owns, chunk): G = 1 over the first n_slow_y entries (y walls and layers), G = 2 over the rest
 // (z walls and layers as well).
-template <typename T, int VX, int XS, int G, bool LATE>
+template <typename T, int VX, int XS, int G>
 __global__ void __launch_bounds__(64 * (kStep2BoundaryRows + 4) * XS)
     k_step2_gen(Dev d, Shape2 f2, const int *tiles, int n, int par, int step, const double *q) {
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int *t = tiles + 3 * logical;
-  step2_body<T, VX, kStep2BoundaryRows, XS, G, LATE>(d, t[0], t[1], t[2], f2.zchunk, par, step, q);
+  step2_body<T, VX, kStep2BoundaryRows, XS, G>(d, t[0], t[1], t[2], f2.zchunk, par, step, q);
 }
 
 template <typename T>
@@ -741,7 +727,7 @@ __global__ void __launch_bounds__(64) k_gather_smp(Dev d, double *w, int column,
   }
 }
 
-template <typename T, int VX, int W, bool LATE>
+template <typename T, int VX, int W>
 static hipError_t step2_launch(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
                                hipStream_t s) {
   const Shape2 &f2 = p.fs2;
@@ -750,23 +736,15 @@ static hipError_t step2_launch(const chf_plan &p, const Dev &d, int par, int ste
     const int *tiles = (const int *)(p.ws + p.off_tiles2);
     const int n1 = f2.n_slow_y, n2 = f2.n_slow - f2.n_slow_y;
     if (n1 > 0)
-      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 1, LATE>), dim3((n1 + 7) / 8 * 8), block, 0, s, d, f2, tiles, n1,
-                         par, step, q);
+      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 1>), dim3((n1 + 7) / 8 * 8), block, 0, s, d, f2, tiles, n1, par, step,
+                         q);
     if (n2 > 0)
-      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 2, LATE>), dim3((n2 + 7) / 8 * 8), block, 0, s, d, f2,
-                         tiles + 3 * n1, n2, par, step, q);
+      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 2>), dim3((n2 + 7) / 8 * 8), block, 0, s, d, f2, tiles + 3 * n1, n2,
+                         par, step, q);
   } else if (f2.n_fast > 0) {
-    hipLaunchKernelGGL((k_step2<T, VX, W, 1, LATE>), dim3(f2.fast_blocks), dim3(64 * (W + 4)), 0, s, d, f2, par, step,
-                       q);
+    hipLaunchKernelGGL((k_step2<T, VX, W, 1>), dim3(f2.fast_blocks), dim3(64 * (W + 4)), 0, s, d, f2, par, step, q);
   }
   return hipGetLastError();
-}
-
-template <typename T, int VX, int W>
-static hipError_t step2_late(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
-                             hipStream_t s) {
-  return p.fs2.late ? step2_launch<T, VX, W, true>(p, d, par, step, q, general, s)
-                    : step2_launch<T, VX, W, false>(p, d, par, step, q, general, s);
 }
 
 template <typename T>
@@ -774,15 +752,15 @@ static hipError_t step2_dispatch(const chf_plan &p, const Dev &d, int par, int s
                                  hipStream_t s) {
   const Shape2 &f2 = p.fs2;
   switch (f2.vx * 100 + f2.waves) {
-    case 104: return step2_late<T, 1, 4>(p, d, par, step, q, general, s);
-    case 107: return step2_late<T, 1, 7>(p, d, par, step, q, general, s);
-    case 108: return step2_late<T, 1, 8>(p, d, par, step, q, general, s);
-    case 204: return step2_late<T, 2, 4>(p, d, par, step, q, general, s);
-    case 207: return step2_late<T, 2, 7>(p, d, par, step, q, general, s);
-    case 208: return step2_late<T, 2, 8>(p, d, par, step, q, general, s);
-    case 404: return step2_late<T, 4, 4>(p, d, par, step, q, general, s);
-    case 407: return step2_late<T, 4, 7>(p, d, par, step, q, general, s);
-    case 408: return step2_late<T, 4, 8>(p, d, par, step, q, general, s);
+    case 104: return step2_launch<T, 1, 4>(p, d, par, step, q, general, s);
+    case 107: return step2_launch<T, 1, 7>(p, d, par, step, q, general, s);
+    case 108: return step2_launch<T, 1, 8>(p, d, par, step, q, general, s);
+    case 204: return step2_launch<T, 2, 4>(p, d, par, step, q, general, s);
+    case 207: return step2_launch<T, 2, 7>(p, d, par, step, q, general, s);
+    case 208: return step2_launch<T, 2, 8>(p, d, par, step, q, general, s);
+    case 404: return step2_launch<T, 4, 4>(p, d, par, step, q, general, s);
+    case 407: return step2_launch<T, 4, 7>(p, d, par, step, q, general, s);
+    case 408: return step2_launch<T, 4, 8>(p, d, par, step, q, general, s);
   }
   return hipErrorInvalidValue;
 }

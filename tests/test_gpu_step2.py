@@ -69,14 +69,14 @@ def assert_same(a, b, what):
 
 
 CASES = [
-    # (label, workload, two-step tile: waves, z chunk, late loads)
-    ("small cpml 72x60x150", W.small_shower(seed=11), [(8, 32, 0), (7, 16, 2), (4, 5, 0), (8, 150, 2)]),
+    # (label, workload, two-step tiles: waves, z chunk)
+    ("small cpml 72x60x150", W.small_shower(seed=11), [(8, 32), (7, 16), (4, 5), (8, 150)]),
     ("vx2 cpml 100x44x140, odd steps", W.small_shower(seed=17, nx=100, ny=44, nz=140, n_steps=121, n_obs=5),
-     [(8, 16, 0), (4, 9, 2)]),
+     [(8, 16), (4, 9)]),
     ("vx1 cpml 48x52x90", W.small_shower(seed=5, nx=48, ny=52, nz=90, n_steps=80, n_obs=3, npml=6),
-     [(8, 12, 0), (7, 7, 2)]),
+     [(8, 12), (7, 7)]),
     ("vx4 pec 200x70x96", W.small_shower(seed=9, nx=200, ny=70, nz=96, n_steps=90, n_obs=4, bc="pec"),
-     [(8, 24, 2), (4, 13, 0)]),
+     [(8, 24), (4, 13)]),
 ]
 
 
@@ -86,12 +86,12 @@ def test_two_step_equals_one_step_fp32(gpu, label, w, tiles):
     ref = run_fields(w, kernel="fused")
     orc = oracle.run(w)
     assert np.abs(ref[0]).max() > 0
-    for waves, zchunk, late in tiles:
-        banner(f"{label}: two-step waves={waves} zchunk={zchunk} late={late}")
-        got = run_fields(w, kernel="fused2", waves=waves, zchunk=zchunk, rows=late)
+    for waves, zchunk in tiles:
+        banner(f"{label}: two-step waves={waves} zchunk={zchunk}")
+        got = run_fields(w, kernel="fused2", waves=waves, zchunk=zchunk)
         assert got[2]["kernel"] == 4 and got[2]["steps_per_launch"] == 2
         assert (got[2]["waves_per_block"], got[2]["z_chunk"]) == (waves, zchunk)
-        assert_same(got, ref, (label, waves, zchunk, late))
+        assert_same(got, ref, (label, waves, zchunk))
         err = rel_l2(got[0], orc)
         assert np.all(err <= TOL_FP32), err
 
@@ -101,9 +101,9 @@ def test_two_step_equals_one_step_16bit(gpu, storage):
     w = W.small_shower(seed=11)
     banner(f"16-bit {storage}")
     ref = run_fields(w, storage=storage, kernel="fused")
-    for waves, zchunk, late in [(8, 32, 0), (4, 7, 2)]:
-        got = run_fields(w, storage=storage, kernel="fused2", waves=waves, zchunk=zchunk, rows=late)
-        assert_same(got, ref, (storage, waves, zchunk, late))
+    for waves, zchunk in [(8, 32), (4, 7)]:
+        got = run_fields(w, storage=storage, kernel="fused2", waves=waves, zchunk=zchunk)
+        assert_same(got, ref, (storage, waves, zchunk))
 
 
 @pytest.mark.parametrize("bc", ["cpml", "pec"])
@@ -113,9 +113,9 @@ def test_two_step_random_fields(gpu, bc):
     w = W.small_shower(seed=3, nx=120, ny=58, nz=110, n_steps=33, n_obs=4, bc=bc)
     banner(f"random fields {bc}")
     ref = run_fields(w, seed_fields=True, kernel="fused")
-    for waves, zchunk, late in [(8, 16, 0), (7, 11, 2), (4, 32, 0)]:
-        got = run_fields(w, seed_fields=True, kernel="fused2", waves=waves, zchunk=zchunk, rows=late)
-        assert_same(got, ref, (bc, waves, zchunk, late))
+    for waves, zchunk in [(8, 16), (7, 11), (4, 32)]:
+        got = run_fields(w, seed_fields=True, kernel="fused2", waves=waves, zchunk=zchunk)
+        assert_same(got, ref, (bc, waves, zchunk))
 
 
 def test_two_step_graph_and_snapshots(gpu):

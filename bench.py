@@ -48,6 +48,7 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20
 FUSED_KERNEL = "chf::k_fused<"
+STEP2_KERNEL = "chf::k_step2<"
 RZ_KERNEL = "k_rz_step2<"
 RZ_BYTES_PER_NODE = 24.0  # read E_r, E_z, H_phi once and write them once (FP32)
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -75,7 +76,8 @@ def is_rz(workload: str) -> bool:
 
 
 def kernel_digest_for(workload: str) -> str:
-    return kernel_source_digest(("chf_rz.hip",) if is_rz(workload) else ("chf_kernels.hip", "chf_internal.h"))
+    return kernel_source_digest(("chf_rz.hip",) if is_rz(workload)
+                                else ("chf_kernels.hip", "chf_step2.hip", "chf_cell.h", "chf_internal.h"))
 
 
 def traffic_path(workload: str, storage: str) -> str:
@@ -108,7 +110,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the fused sweep, each scaled by what the
     same counter reads for the 256 MiB calibration copy (read 256 MiB, write 256 MiB)."""
     out = {}
-    kname = RZ_KERNEL if is_rz(workload) else FUSED_KERNEL
+    kname = RZ_KERNEL if is_rz(workload) else (STEP2_KERNEL if tile and tile[-1] == "fused2" else FUSED_KERNEL)
     for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = list(_dispatches(path, counter))
         copies = [v for k, g, v in rows if "copyBuffer" in k]
@@ -122,7 +124,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
         out[name] = {"copy_probe_kib": copy_kib, "scale": factor, "dispatches": len(fused),
                      "raw_kib_per_launch": float(np.mean(fused)),
                      "bytes_per_launch": float(np.mean(fused)) * 1024.0 * factor}
-    kdesc = ("axisymmetric two-step launch (k_rz_step2)" if is_rz(workload) else "fused interior sweep (chf::k_fused)")
+    kdesc = ("axisymmetric two-step launch (k_rz_step2)" if is_rz(workload)
+             else "two-step interior sweep (chf::k_step2)" if kname == STEP2_KERNEL
+             else "fused interior sweep (chf::k_fused)")
     rec = {"workload": workload, "storage": storage, "kernel": kdesc,
            "kernel_digest": kernel_digest_for(workload), "command": command, "tile": tile,
            "fetch": out["fetch"], "write": out["write"],
@@ -705,7 +709,7 @@ def main():
 
     if args.summarize_pmc:
         tile = ([args.vx, args.waves, args.zchunk, args.steps_per_launch] if is_rz(args.workload)
-                else [args.waves, args.zchunk, args.kernel if args.kernel == "fused_prefetch" else "fused"])
+                else [args.waves, args.zchunk, args.kernel if args.kernel in ("fused_prefetch", "fused2") else "fused"])
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, args.storage,
                       args.pmc_command, tile)
         return

@@ -66,9 +66,12 @@ typedef enum { CHF_FP32 = 0, CHF_BF16 = 1, CHF_FP16 = 2 } chf_storage;
 typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
 /* CHF_KERNEL_FUSED_PREFETCH: the fused sweep whose interior tiles issue each plane's row loads one
    plane ahead (the loads of plane k+1 are in flight while plane k is computed), at the price of
-   more registers per wave (3 waves per SIMD instead of 4); rows of at most 256 nodes and
-   waves_per_block 4, 7, 8 or 11 (11 rows: one 12-wave workgroup fills a compute unit).  With 4 or 7
-   the boundary tiles load a plane ahead too.  A batch takes its members' kind.  Same bits.
+   more registers per wave (3 waves per SIMD instead of 4); waves_per_block 4, 7, 8 or 11 (11
+   rows: one 12-wave workgroup fills a compute unit).  Rows of 257-512 nodes are split across two
+   waves of four nodes per lane, which exchange the x neighbours at their seam through LDS; there
+   waves_per_block is the rows per tile, 4 or 5 (default 5: 12 waves).  With 4 or 7 rows of at
+   most 256 nodes the boundary tiles load a plane ahead too.  A batch takes its members' kind.
+   Same bits.
    CHF_KERNEL_FUSED2: two Yee steps per pass over the fields (temporal blocking of the Numerical
    Method section's leapfrog): each launch reads E^n, H^{n-1/2} and writes E^{n+2}, H^{n+3/2},
    keeping E^{n+1}, H^{n+1/2} on chip (its observer samples are taken inside the pass), so a
@@ -133,8 +136,8 @@ typedef struct {
 /* Execution choices.  storage: field storage type (arithmetic is always FP32; waveforms are
    accumulated in FP64).  scale_e / scale_h: power-of-two storage scales (0 = automatic).
    kernel: split E/H sweeps or the fused single sweep.  waves_per_block is the number of y
-   rows per tile (4, 7, 8, 11 or 15; 4 or 7 for rows wider than 256 nodes; a fused workgroup has
-   one more wave for the row below the tile) and z_chunk the planes per tile (0 = defaults:
+   rows per tile (4, 7, 8, 11 or 15; 4 or 7 for rows wider than 256 nodes, 4 or 5 for the
+   prefetching sweep there; a fused workgroup has one more wave for the row below the tile) and z_chunk the planes per tile (0 = defaults:
    7 rows, 12 planes); rows_per_wave must be 0 or 1.  None of these changes
    a result bit.  nan_watch: check waveforms for non-finite values every step. */
 typedef struct {

@@ -56,6 +56,23 @@ def test_counter_summary_calibration_and_traffic_lookup(tmp_path, monkeypatch):
     assert bench.measured_traffic("single-shower", "fp32", tile) is None
 
 
+def test_counter_summary_of_the_two_step_sweep(tmp_path, monkeypatch):
+    """With the two-step tile the counted dispatches are the two-step interior kernel's, not the
+    one-step sweep's."""
+    step2 = "void chf::k_step2<float, 4, 8, 1>(chf::Dev, chf::Shape2, int, int, double const*)"
+    fused = "void chf::k_fused<float, 4, 8, true>(chf::Dev, chf::FusedShape, int)"
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    _csv(f, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 131072.0), (step2, 3000.0), (fused, 10.0)])
+    _csv(w, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 262144.0), (step2, 700.0), (fused, 10.0)])
+    monkeypatch.setattr(bench, "traffic_path", lambda wl, st: str(tmp_path / f"traffic_{wl}_{st}.json"))
+    tile = [8, 32, "fused2"]
+    bench.summarize_pmc(str(f), str(w), "single-shower", "fp32", "cmd", tile)
+    rec = json.load(open(tmp_path / "traffic_single-shower_fp32.json"))
+    assert "k_step2" in rec["kernel"]
+    assert rec["bytes_per_launch"] == 3000.0 * 1024 * 2.0 + 700.0 * 1024
+    assert bench.measured_traffic("single-shower", "fp32", tile) == rec["bytes_per_launch"]
+
+
 def test_roofline_figures():
     r = bench.roofline({"fused_cells": 1_000_000, "fused_bytes_per_cell": 50.0}, fused_ms=10.0, yee_steps=100)
     # 50 MB per launch in 0.1 ms

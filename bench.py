@@ -313,14 +313,14 @@ def kernel_name(info) -> str:
     return {3: "fused_prefetch", 4: "fused2"}.get(info["kernel"], "fused")
 
 
-def run_variant(w, storage: str, args, n_slices: int, warmup: int):
+def run_variant(w, storage: str, args, n_slices: int, warmup: int, dynamic: bool = False):
     import torch
 
     from paper_1001_5341_amd import solver
 
     waves, zchunk, kernel, tuned = tile_shape(w, storage, args)
     plan = solver.Plan(w, storage=storage, kernel=kernel, rows=args.rows, waves=waves,
-                       zchunk=zchunk, device=torch.device("cuda:0"))
+                       zchunk=zchunk, device=torch.device("cuda:0"), dynamic_scaling=dynamic)
     info = plan.info()
     out = plan.new_waveforms()
     s_len = slice_steps(w)
@@ -654,11 +654,12 @@ def rz_summary(n: int = 8192, n_steps: int = 2048):
             "note": "python bench.py --workload rz-8192 gives the full line"}
 
 
-def storage_variant(w, st: str, args, ref, n_slices: int, ref_label: str):
+def storage_variant(w, st: str, args, ref, n_slices: int, ref_label: str, dynamic: bool = False):
     """One storage variant over n_slices slices (a complete run at the default 25), its speed,
     roofline fraction and its distance from `ref` (the FP64 oracle's stored waveforms when they
-    exist for this workload, else the FP32-storage run of the same build)."""
-    vinfo, vwall, _, vms, vl, vgot = run_variant(w, st, args, n_slices, 1)
+    exist for this workload, else the FP32-storage run of the same build).  `dynamic`: FP16 with
+    the storage scale picked per launch."""
+    vinfo, vwall, _, vms, vl, vgot = run_variant(w, st, args, n_slices, 1, dynamic)
     cells = w.nx * w.ny * w.nz
     v = {"value": round(cells * vl / vwall / 1e6, 1), "unit": "Mcell-updates/s",
          "roofline_frac": roofline(vinfo, vms, vl)["frac"],
@@ -666,6 +667,7 @@ def storage_variant(w, st: str, args, ref, n_slices: int, ref_label: str):
          "fused_bytes_per_cell": round(vinfo["fused_bytes_per_cell"], 3),
          "whole_step_bytes_per_cell": round(vinfo["bytes_per_cell_update"], 3),
          "scale_e": vinfo["scale_e"], "scale_h": vinfo["scale_h"],
+         "dynamic_scaling": bool(vinfo.get("dynamic_scaling", 0)),
          "tile": {"vx": vinfo["vx"], "waves_per_block": vinfo["waves_per_block"], "z_chunk": vinfo["z_chunk"],
                   "kernel": kernel_name(vinfo)}}
     if vgot is not None and ref is not None:
@@ -695,6 +697,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the BF16/FP16 storage runs")
     ap.add_argument("--no-copy-ceiling", action="store_true", help="skip the streaming-copy ceiling probe")
+    ap.add_argument("--dynamic-fp16", action="store_true",
+                    help="also run FP16 storage with the scale picked per launch (storage variant fp16_dynamic)")
     ap.add_argument("--legs", action="store_true",
                     help="also run the (r, z), differentiation and 32-shower batch summaries")
     ap.add_argument("--copy-probe", action="store_true",
@@ -808,6 +812,9 @@ def main():
             ref, label = np.load(gold)["waveforms"].astype(np.float64), "fp64_oracle"
         rec["storage_variants"] = {st: storage_variant(w, st, args, ref, SLICES_PER_RUN, label)
                                    for st in ("bf16", "fp16")}
+        if args.dynamic_fp16:
+            rec["storage_variants"]["fp16_dynamic"] = storage_variant(w, "fp16", args, ref, SLICES_PER_RUN, label,
+                                                                      dynamic=True)
     if args.legs:
         log("axisymmetric (r, z) summary")
         rec["axisymmetric"] = rz_summary()

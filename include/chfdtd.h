@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define CHF_ABI_VERSION 2
+#define CHF_ABI_VERSION 3
 
 typedef enum {
   CHF_OK = 0,
@@ -139,11 +139,24 @@ typedef struct {
    rows per tile (4, 7, 8, 11 or 15; 4 or 7 for rows wider than 256 nodes, 4 or 5 for the
    prefetching sweep there; a fused workgroup has one more wave for the row below the tile) and z_chunk the planes per tile (0 = defaults:
    7 rows, 12 planes); rows_per_wave must be 0 or 1.  None of these changes
-   a result bit.  nan_watch: check waveforms for non-finite values every step. */
+   a result bit.  nan_watch: check waveforms for non-finite values every step.
+   dynamic_scaling (FP16 storage with the fused, prefetching or two-step sweeps, PEC or CPML
+   walls, single plans; else CHF_EUNSUPPORTED): every launch picks the storage scale of the
+   level it writes.  Both fields of a level carry an extra factor 2^e on top of scale_e and
+   scale_h (their ratio fixed, so the coefficient tables hold); the launch reading a level with
+   maxima M_E, M_H (stored units) bounds what its n steps (1 or 2) can reach,
+   B_E = 2 M_E + 2 n (g_E M_H + S), B_H = 2 M_H + 2 n g_H B_E (g_E, g_H the largest per-step gains
+   of the curl terms, S the source's largest E_z increment, the factors 2 covering the CPML
+   terms), and stores the new level with the largest power of two keeping max(B_E, B_H) below
+   2^14.  Scales and maxima live in device memory, so graph capture works; changing by powers of
+   two, they leave every mantissa as a static run with the same scales would.  The one-step
+   sweeps give equal bits among themselves; the two-step sweep picks its scales per launch of
+   two steps. */
 typedef struct {
   int32_t storage, kernel;
   int32_t rows_per_wave, waves_per_block, z_chunk, nan_watch;
   double scale_e, scale_h;
+  int32_t dynamic_scaling, pad0;
 } chf_exec;
 
 typedef struct chf_plan chf_plan;
@@ -277,7 +290,9 @@ chf_status chf_adjoint_checkpointed(chf_plan *plan, chf_plan *fwd, void *stream,
                                     uint64_t snapshots_bytes, float *e_levels_dev, double *dl_deps_dev);
 
 /* Forward-state snapshots (checkpoints, resume).  A snapshot is the plan's whole field and
-   CPML state -- both time levels of E and H and every psi array -- as a DEVICE byte image of
+   CPML state -- both time levels of E and H, every psi array and the 256-byte block of
+   dynamic-scaling words (each level's scale exponent and the field maxima) -- as a DEVICE byte
+   image of
    chf_plan_state_bytes bytes owned by the caller.  save copies it out (stream-ordered) and
    reports the step it belongs to; load copies it back and sets the step (and with it the
    source clock and the current time level).  Restarting from a snapshot reproduces the run
@@ -290,11 +305,14 @@ chf_status chf_plan_load_state(chf_plan *plan, void *stream, const void *src_dev
 chf_status chf_plan_sync(chf_plan *plan, void *stream);
 
 /* Copy one field component (0..5 = Ex,Ey,Ez,Hx,Hy,Hz) of the current time level into a DEVICE
-   FP32 array [nz][ny][nx] (unscaled, physical units). */
+   FP32 array [nz][ny][nx] (unscaled, physical units; under dynamic scaling with the level's
+   present factor). */
 chf_status chf_plan_get_field(chf_plan *plan, void *stream, int32_t comp, float *out_dev);
 
 /* Overwrite one field component of the current time level from a DEVICE FP32 array
-   [nz][ny][nx] (physical units). */
+   [nz][ny][nx] (physical units).  Under dynamic scaling the values are stored with the level's
+   present factor (values beyond the FP16 range at that factor become infinite) and the level's
+   maxima are recomputed. */
 chf_status chf_plan_set_field(chf_plan *plan, void *stream, int32_t comp, const float *in_dev);
 
 /* Introspection: chosen kernel, storage scales, fused-sweep shape, pitch. */
@@ -312,6 +330,7 @@ typedef struct {
      (so bytes / launch time is the single-step-equivalent rate); pass_bytes_per_cell is what
      the pass itself must move per node (12 values once, x-layer psi once) */
   double pass_bytes_per_cell;
+  int32_t dynamic_scaling, pad0; /* 1 when the storage scale is picked per launch */
 } chf_plan_info;
 chf_status chf_plan_get_info(const chf_plan *plan, chf_plan_info *info);
 

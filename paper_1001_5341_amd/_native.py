@@ -65,7 +65,8 @@ class Observers(ct.Structure):
 class Exec(ct.Structure):
     _fields_ = [("storage", ct.c_int32), ("kernel", ct.c_int32), ("rows_per_wave", ct.c_int32),
                 ("waves_per_block", ct.c_int32), ("z_chunk", ct.c_int32), ("nan_watch", ct.c_int32),
-                ("scale_e", ct.c_double), ("scale_h", ct.c_double)]
+                ("scale_e", ct.c_double), ("scale_h", ct.c_double), ("dynamic_scaling", ct.c_int32),
+                ("pad0", ct.c_int32)]
 
 
 class PlanInfo(ct.Structure):
@@ -76,7 +77,8 @@ class PlanInfo(ct.Structure):
                 ("psi_bytes", ct.c_uint64), ("workspace_bytes", ct.c_uint64),
                 ("bytes_per_cell_update", ct.c_double), ("fused_cells", ct.c_uint64),
                 ("fused_bytes_per_cell", ct.c_double), ("steps_per_launch", ct.c_int32),
-                ("waves_per_row", ct.c_int32), ("pass_bytes_per_cell", ct.c_double)]
+                ("waves_per_row", ct.c_int32), ("pass_bytes_per_cell", ct.c_double),
+                ("dynamic_scaling", ct.c_int32), ("pad0", ct.c_int32)]
 
 
 class RZGrid(ct.Structure):

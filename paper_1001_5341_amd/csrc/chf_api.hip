@@ -181,6 +181,16 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     delete p;
     return fail(CHF_EINVAL, "the fused sweep over rows wider than 256 nodes takes waves_per_block 4 or 7");
   }
+  if (ex->dynamic_scaling) {
+    // the fused sweeps (one or two steps) carry the scale; their boundary tiles must take the
+    // general fused sweep (not the split sweeps), and Mur's update reads two levels
+    const bool gen = (fs.vx <= chf::kMaxGeneralVX && fs.waves <= chf::kMaxGeneralW) || fs.xs == 2;
+    if (ex->storage != CHF_FP16 || kernel != CHF_KERNEL_FUSED || !gen || bnd->kind == CHF_BC_MUR1) {
+      delete p;
+      return fail(CHF_EUNSUPPORTED, "dynamic scaling takes FP16 storage, the fused sweeps with tiles of at most 11 "
+                                    "rows of at most 256 nodes (or split rows), and PEC or CPML walls");
+    }
+  }
   if ((int64_t)((G.nx + 15) / 16 * 16) * G.ny >= ((int64_t)1 << 31)) {
     delete p;
     return fail(CHF_EUNSUPPORTED, "one x-y plane must hold fewer than 2^31 nodes");
@@ -544,6 +554,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       if (p->fs2.on) off += align256(p->psi_len[u] * 4);
     }
   p->psi_bytes = off - off_psi0;
+  p->off_dyn = off;  // dynamic scaling words: part of the state (snapshots carry them)
+  off += 256;
   p->off_tf = off;
   off += align256(p->tabf.size() * sizeof(float));
   p->off_ti = off;
@@ -620,6 +632,28 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   D.a_db = (float)p->db;
   D.a_ca = (float)p->ca;
   D.a_cb_src = p->cb;
+  if (ex->dynamic_scaling) {
+    // bound constants of the per-launch scale choice, in stored units at exponent 0: the
+    // largest per-step gain of the curl terms (2 |c| per axis), and the source's largest Ez
+    // increment (the normalised longitudinal weights are at most 1/dz)
+    double ge = 0.0, gh = 0.0;
+    for (int u = 0; u < 3; u++) {
+      double me = 0.0, mh = 0.0;
+      for (int i = 0; i < n3[u]; i++) {
+        me = std::max(me, (double)std::fabs(p->tabf[p->off_tabf[u][0] + i]));
+        mh = std::max(mh, (double)std::fabs(p->tabf[p->off_tabf[u][1] + i]));
+      }
+      ge += 2.0 * me;
+      gh += 2.0 * mh;
+    }
+    double qmax = 0.0, wmax = 0.0;
+    for (double q : p->q_bins) qmax = std::max(qmax, std::fabs(q));
+    for (int t = 0; t < D.src_ni * D.src_nj && t < (int)p->wr.size(); t++) wmax = std::max(wmax, std::fabs(p->wr[t]));
+    D.dyn = 1;
+    D.dyn_ge = (float)ge;
+    D.dyn_gh = (float)gh;
+    D.dyn_src = D.src_on ? (float)(std::fabs(D.cb_src) * D.v_src * qmax * wmax / G.dz) : 0.f;
+  }
   const double vdt = v * G.dt;
   D.mur_kx = (float)((vdt - G.dx) / (vdt + G.dx));
   D.mur_ky = (float)((vdt - G.dy) / (vdt + G.dy));
@@ -664,6 +698,11 @@ void canonical_pointers(chf_plan &p) {
       D.psi_h[0][u][t] = (float *)(ws + p.off_psi_h[0][u][t]);
       D.psi_h[1][u][t] = (float *)(ws + p.off_psi_h[1][u][t]);
     }
+  for (int l = 0; l < 2; l++) {
+    D.dexp[l] = (int *)(ws + p.off_dyn + 16 * l);
+    D.dslot[l] = (int *)(ws + p.off_dyn + 16 * l + 4);
+  }
+  D.dmax = (unsigned *)(ws + p.off_dyn + 32);
   p.lev_swap = p.pe_swap = 0;
 }
 
@@ -679,6 +718,8 @@ void swap_levels(chf_plan &p, Dev &d) {
       std::swap(d.psi_h[0][u][t], d.psi_h[1][u][t]);
       std::swap(d.psi_e[u][t], d.psi_e2[u][t]);
     }
+  std::swap(d.dexp[0], d.dexp[1]);
+  std::swap(d.dslot[0], d.dslot[1]);
   if (&d == &p.dev) {
     p.lev_swap ^= 1;
     p.pe_swap ^= 1;
@@ -991,6 +1032,7 @@ chf_status chf_plan_get_info(const chf_plan *p, chf_plan_info *info) {
   info->pass_bytes_per_cell = one_step;
   info->steps_per_launch = 1;
   info->waves_per_row = p->fs.xs;
+  info->dynamic_scaling = p->dev.dyn;
   if (p->fs2.on) {
     const chf::Shape2 &f2 = p->fs2;
     info->kernel = CHF_KERNEL_FUSED2;
@@ -1170,6 +1212,10 @@ std::vector<Piece> state_pieces(const chf_plan &p) {
       if (p.fs2.on) v.push_back({b, p.pe_swap ? a : b, len});
     }
   }
+  // dynamic scaling words: each level's (exponent, maxima slot) follows its level; the maxima
+  // slots stay
+  for (int l = 0; l < 2; l++) v.push_back({p.off_dyn + 16 * l, p.off_dyn + 16 * (l ^ p.lev_swap), 16});
+  v.push_back({p.off_dyn + 32, p.off_dyn + 32, 224});
   return v;
 }
 }  // namespace
@@ -1211,6 +1257,10 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) 
     if (!p || !p->ws) {
       delete b;
       return fail(p ? CHF_ESTATE : CHF_EINVAL, "every plan must exist and have its workspace bound");
+    }
+    if (p->dev.dyn) {
+      delete b;
+      return fail(CHF_EUNSUPPORTED, "a batch takes plans with static storage scales");
     }
     if (i == 0) {
       b->storage = p->storage;

@@ -106,6 +106,80 @@ __device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on) {
   }
 }
 
+// Scaled stores of dynamically scaled levels: the values times a power of two r (exact), then
+// rounded as st_row rounds.
+template <typename T, int N>
+__device__ __forceinline__ void st_row_s(T *p, const float (&o)[N], bool on, float r) {
+  float t[N];
+#pragma unroll
+  for (int v = 0; v < N; v++) t[v] = o[v] * r;
+  st_row<T, N>(p, t, on);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void st_at_s(T *base, unsigned boff, const float (&o)[N], bool on, float r) {
+  st_row_s<T, N>(reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff), o, on, r);
+}
+
+// ------------------------------------------------------- dynamic FP16 scaling
+constexpr int kDynStep = 24;  // largest exponent change of one launch
+constexpr int kDynExp = 60;   // range of a level's exponent
+
+// Exponent change of the level that a launch of n steps writes, from the maxima of the level
+// `par` it reads: with M_E, M_H those maxima and S the source's largest Ez increment (stored
+// units), B_E = 2 M_E + 2 n (g_E M_H + S) and B_H = 2 M_H + 2 n g_H B_E bound what n steps can
+// reach (the factors 2 cover the CPML terms, which add at most the size of the curl terms
+// again), and the written level takes the largest power of two r with r max(B_E, B_H) < 2^14.
+// Every wave of every kernel of the launch, and the publishing kernel after it, evaluates these
+// expressions on the same words (contraction off), so all agree.
+__device__ __forceinline__ int dyn_shift(const Dev &d, int par, int n) {
+  const int e = *d.dexp[par];
+  const int sl = *d.dslot[par];
+  const float me = __uint_as_float(d.dmax[2 * sl]), mh = __uint_as_float(d.dmax[2 * sl + 1]);
+  const float fn = (float)n;
+  const float src = ldexpf(d.dyn_src, e);
+  const float be = 2.f * me + 2.f * fn * (d.dyn_ge * mh + src);
+  const float bh = 2.f * mh + 2.f * fn * (d.dyn_gh * be);
+  const float b = fmaxf(be, bh);
+  int sh;
+  if (!(b <= 3.0e38f)) {
+    sh = -kDynStep;  // non-finite maxima: scale down as far as one launch may
+  } else if (b <= 0.f) {
+    sh = kDynStep;  // zero fields and no source: scale up
+  } else {
+    int x;
+    (void)frexpf(b, &x);  // b < 2^x, so 2^(14 - x) b < 2^14
+    sh = 14 - x;
+  }
+  sh = min(max(sh, -kDynStep), kDynStep);
+  return min(max(sh, -kDynExp - e), kDynExp - e);
+}
+
+// Loaded values brought to another level's units (a power of two: exact).
+template <int N>
+__device__ __forceinline__ void scale_in(float (&o)[N], float r) {
+#pragma unroll
+  for (int v = 0; v < N; v++) o[v] *= r;
+}
+
+// Largest |value| of the lanes' row (lanes without nodes add nothing).
+template <int N>
+__device__ __forceinline__ float absmax(float m, const float (&o)[N], bool on) {
+  if (on) {
+#pragma unroll
+    for (int v = 0; v < N; v++) m = fmaxf(m, fabsf(o[v]));
+  }
+  return m;
+}
+
+// Raise a maxima word (float bits, values >= 0) to the wave's largest m: one atomic per wave,
+// and only when it would raise the word.  Every lane of the wave takes part.
+__device__ __forceinline__ void dyn_raise(unsigned *w, float m) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0 && m > __uint_as_float(*(volatile unsigned *)w)) atomicMax(w, __float_as_uint(m));
+}
+
 // ------------------------------------------------------------- cell updates
 // Canonical order of one node update: the two central-difference terms (fmaf), then the CPML
 // terms of the node's derivative axes added in the fixed axis order x, y, z, each with its sign
@@ -181,7 +255,7 @@ __device__ __forceinline__ void gather_body(const Dev &d, int par, double *w, in
   val += __shfl_xor(val, 2);
   val += __shfl_xor(val, 4);
   if (comp < 3 && corner == 0) {
-    const double out = val * d.inv_se;
+    const double out = val * (d.dyn ? ldexp(d.inv_se, -*d.dexp[par]) : d.inv_se);
     w[((long long)o * 3 + comp) * ld + column] = out;
     if (d.nan_flag && !isfinite(out)) *d.nan_flag = 1;
   }

@@ -83,6 +83,15 @@ struct Dev {
   // adjoint coefficients (physical units)
   float a_cb, a_db, a_ca;
   double a_cb_src;           // Cb (unscaled)
+  // dynamic FP16 scaling (dyn != 0): per time level the exponent e of its extra storage factor
+  // (stored = 2^e * scale * physical) and the index of the slot holding the level's maxima;
+  // three slots of (max |E|, max |H|) in stored units, as float bits; the per-step gains of the
+  // curl terms and the source's largest Ez increment, in stored units at e = 0
+  int dyn;
+  int *dexp[2];
+  int *dslot[2];
+  unsigned *dmax;
+  float dyn_ge, dyn_gh, dyn_src;
 };
 
 struct FusedShape {
@@ -139,6 +148,9 @@ struct chf_plan {
   std::vector<int> tiles2;               // boundary tiles of the two-step sweep
   std::vector<int> smp_ptr, smp_ent, smp_slot;
   uint64_t off_psi_e2[3][2], off_tiles2, off_smp_ptr, off_smp_ent, off_smp, off_smp_slot;
+  // dynamic scaling words (inside the state region, after psi): per level (exponent, maxima slot)
+  // at off_dyn + 16 l, the three maxima slots at off_dyn + 32
+  uint64_t off_dyn = 0;
   size_t n_smp = 0;
   // the two field levels (with psi_H) and the two psi_E levels are exchanged relative to their
   // workspace offsets after every two-step launch, so that level `parity` always holds the
@@ -203,6 +215,11 @@ void canonical_pointers(chf_plan &p);
 // launch of the dominant kind, their number in *n_ev
 hipError_t advance(chf_plan &p, hipStream_t s, const double *q, double *w, int col0, int ld, int n,
                    hipEvent_t *ev = nullptr, int *n_ev = nullptr);
+// dynamic scaling: after the sweeps of a launch of n steps from level `parity`, publish the
+// written level's exponent and maxima slot and clear the slot the next launch raises; and the
+// maxima of level `parity` recomputed from its fields (after a direct write)
+hipError_t launch_dyn_publish(const Dev &d, int parity, int n, hipStream_t s);
+hipError_t launch_dyn_levelmax(const chf_plan &p, int parity, hipStream_t s);
 hipError_t launch_get_field(const chf_plan &p, int parity, int comp, float *out, hipStream_t s);
 hipError_t launch_set_field(const chf_plan &p, int parity, int comp, const float *in, hipStream_t s);
 // forward E levels of one step and the permittivity cotangent they feed (adjoint of eps_r)

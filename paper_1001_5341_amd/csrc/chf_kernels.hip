@@ -78,7 +78,10 @@ __device__ __forceinline__ float psi_e(const Dev &d, float *p, int u, int pos, i
 // z layers (uniform per plane).
 // XS = 2: rows of up to 512 nodes split across two waves of 64 VX nodes each (the x neighbour
 // across the split comes through LDS words published with the row exchange).
-template <typename T, int VX, int W, int G, bool PREFETCH = false, int XS = 1>
+// DYN: dynamically scaled FP16 levels -- the step is computed in the units of the level read and
+// every value stored (fields and psi) is multiplied by the launch's power of two r on the way
+// out; the wave's largest stored magnitudes raise the written level's maxima.
+template <typename T, int VX, int W, int G, bool PREFETCH = false, int XS = 1, bool DYN = false>
 __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zchunk, int par) {
   // Wave r of the workgroup owns row j = j0 - 1 + r: r = 1..W are the tile's rows, r = 0 is
   // the row below the tile, whose H the E update of row j0 needs (it computes H only and
@@ -136,6 +139,8 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   const float *phi0 = d.psi_h[par][0][0], *phi1 = d.psi_h[par][0][1];
   float *pho0 = d.psi_h[par ^ 1][0][0], *pho1 = d.psi_h[par ^ 1][0][1];
   float *pe0 = d.psi_e[0][0], *pe1 = d.psi_e[0][1];
+  float dyn_r = 1.f, dyn_me = 0.f, dyn_mh = 0.f;
+  if constexpr (DYN) dyn_r = ldexpf(1.f, dyn_shift(d, par, 1));
 
   for (int i = threadIdx.x; i < NL; i += 64 * (W + 1) * XS) {
     const int ic = min(i, nx - 1);
@@ -555,39 +560,50 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
           if (!uz) oez[v] = ezc[v];
         }
       }
-      st_at<T, VX>(Ho0 + pk, o0, hx, on);
-      st_at<T, VX>(Ho1 + pk, o0, hy, on);
-      st_at<T, VX>(Ho2 + pk, o0, hz, on);
-      st_at<T, VX>(Eo0 + pk, o0, oex, on);
-      st_at<T, VX>(Eo1 + pk, o0, oey, on);
-      st_at<T, VX>(Eo2 + pk, o0, oez, on);
+      if constexpr (DYN) {
+        dyn_mh = absmax<VX>(absmax<VX>(absmax<VX>(dyn_mh, hx, on), hy, on), hz, on);
+        dyn_me = absmax<VX>(absmax<VX>(absmax<VX>(dyn_me, oex, on), oey, on), oez, on);
+        st_at_s<T, VX>(Ho0 + pk, o0, hx, on, dyn_r);
+        st_at_s<T, VX>(Ho1 + pk, o0, hy, on, dyn_r);
+        st_at_s<T, VX>(Ho2 + pk, o0, hz, on, dyn_r);
+        st_at_s<T, VX>(Eo0 + pk, o0, oex, on, dyn_r);
+        st_at_s<T, VX>(Eo1 + pk, o0, oey, on, dyn_r);
+        st_at_s<T, VX>(Eo2 + pk, o0, oez, on, dyn_r);
+      } else {
+        st_at<T, VX>(Ho0 + pk, o0, hx, on);
+        st_at<T, VX>(Ho1 + pk, o0, hy, on);
+        st_at<T, VX>(Ho2 + pk, o0, hz, on);
+        st_at<T, VX>(Eo0 + pk, o0, oex, on);
+        st_at<T, VX>(Eo1 + pk, o0, oey, on);
+        st_at<T, VX>(Eo2 + pk, o0, oez, on);
+      }
       // the row's x-slab psi back to memory (slab indices of wall nodes keep their values)
       if (lane < np2) {
         if (own_sh) {
-          pho0[prow + lane] = sPsi[wv][0][lane];
-          pho1[prow + lane] = sPsi[wv][1][lane];
+          pho0[prow + lane] = DYN ? sPsi[wv][0][lane] * dyn_r : sPsi[wv][0][lane];
+          pho1[prow + lane] = DYN ? sPsi[wv][1][lane] * dyn_r : sPsi[wv][1][lane];
         }
         if (own_se) {
-          pe0[prow + lane] = sPsi[wv][2][lane];
-          pe1[prow + lane] = sPsi[wv][3][lane];
+          pe0[prow + lane] = DYN ? sPsi[wv][2][lane] * dyn_r : sPsi[wv][2][lane];
+          pe1[prow + lane] = DYN ? sPsi[wv][3][lane] * dyn_r : sPsi[wv][3][lane];
         }
       }
       if constexpr (GY) {
         if (shy >= 0) {
-          st_row<float, VX>(d.psi_h[par ^ 1][1][0] + iyh, qhxy, on);
-          st_row<float, VX>(d.psi_h[par ^ 1][1][1] + iyh, qhzy, on);
+          st_row_s<float, VX>(d.psi_h[par ^ 1][1][0] + iyh, qhxy, on, dyn_r);
+          st_row_s<float, VX>(d.psi_h[par ^ 1][1][1] + iyh, qhzy, on, dyn_r);
         }
         if (shz >= 0) {
-          st_row<float, VX>(d.psi_h[par ^ 1][2][0] + izh, qhxz, on);
-          st_row<float, VX>(d.psi_h[par ^ 1][2][1] + izh, qhyz, on);
+          st_row_s<float, VX>(d.psi_h[par ^ 1][2][0] + izh, qhxz, on, dyn_r);
+          st_row_s<float, VX>(d.psi_h[par ^ 1][2][1] + izh, qhyz, on, dyn_r);
         }
         if (sey >= 0) {
-          st_row<float, VX>(d.psi_e[1][0] + iye, qexy, on);
-          st_row<float, VX>(d.psi_e[1][1] + iye, qezy, on);
+          st_row_s<float, VX>(d.psi_e[1][0] + iye, qexy, on, dyn_r);
+          st_row_s<float, VX>(d.psi_e[1][1] + iye, qezy, on, dyn_r);
         }
         if (sez >= 0) {
-          st_row<float, VX>(d.psi_e[2][0] + ize, qexz, on);
-          st_row<float, VX>(d.psi_e[2][1] + ize, qeyz, on);
+          st_row_s<float, VX>(d.psi_e[2][0] + ize, qexz, on, dyn_r);
+          st_row_s<float, VX>(d.psi_e[2][1] + ize, qeyz, on, dyn_r);
         }
       }
     }
@@ -600,22 +616,27 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
       ezc[v] = nzc[v];
     }
   }
+  if constexpr (DYN) {
+    unsigned *slot = d.dmax + 2 * ((*d.dslot[par] + 1) % 3);
+    dyn_raise(slot, dyn_me);
+    dyn_raise(slot + 1, dyn_mh);
+  }
 }
-template <typename T, int VX, int W, bool PF, int XS = 1>
+template <typename T, int VX, int W, bool PF, int XS = 1, bool DYN = false>
 __global__ void __launch_bounds__(64 * (W + 1) * XS) k_fused(Dev d, FusedShape fs, int par) {
   const int logical = xcd_logical();
   if (logical >= fs.n_fast) return;
   const int fw = fs.ty_hi - fs.ty_lo;
-  fused_body<T, VX, W, 0, PF, XS>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
+  fused_body<T, VX, W, 0, PF, XS, DYN>(d, fs.ty_lo + logical % fw, fs.zc_lo + logical / fw, fs.zchunk, par);
 }
 // Boundary tiles (walls, y/z layers) from the tile table, in the general fused sweep: G = 1
 // over the table's first n_slow_y entries (interior z range), G = 2 over the rest.
-template <typename T, int VX, int W, int G, bool PF, int XS = 1>
+template <typename T, int VX, int W, int G, bool PF, int XS = 1, bool DYN = false>
 __global__ void __launch_bounds__(64 * (W + 1) * XS) k_fused_gen(Dev d, FusedShape fs, const int *tiles, int n,
                                                                   int par) {
   const int logical = xcd_logical();
   if (logical >= n) return;
-  fused_body<T, VX, W, G, PF, XS>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
+  fused_body<T, VX, W, G, PF, XS, DYN>(d, tiles[2 * logical], tiles[2 * logical + 1], fs.zchunk, par);
 }
 
 // Batched: entries (plan, ty, zc) over the interior rectangles of every plan of a batch.
@@ -790,13 +811,14 @@ __global__ void __launch_bounds__(1024) k_split_batch(const Dev *devs, const int
 // J_z of the moving Gaussian charge snapshot at (n+1/2) dt, subtracted (times scale*Cb)
 // from Ez^{n+1}.  Bookkeeping in FP64: bunch position, Q(z_s) from the hat bins, and the
 // lattice-normalised longitudinal weights.  One thread per (i, j) of the radial patch.
+// Returns the largest |Ez| this thread stored (dynamic scaling raises the level's maxima by it).
 template <typename T>
-__device__ __forceinline__ void source_body(const Dev &d, int out_par, int step, const double *q, int t) {
-  if (!d.src_on || t >= d.src_ni * d.src_nj) return;
+__device__ __forceinline__ float source_body(const Dev &d, int out_par, int step, const double *q, int t) {
+  if (!d.src_on || t >= d.src_ni * d.src_nj) return 0.f;
   const double tt = (step + 0.5) * d.dt;
-  if (tt < d.t_entry) return;
+  if (tt < d.t_entry) return 0.f;
   const double wr = d.wr[t];
-  if (wr == 0.0) return;
+  if (wr == 0.0) return 0.f;
   const int i = d.src_i0 + t % d.src_ni, j = d.src_j0 + t / d.src_ni;
   const double zs = d.z_entry + d.v_src * (tt - d.t_entry);
   const double qz = source_q(d, q, zs);
@@ -808,27 +830,34 @@ __device__ __forceinline__ void source_body(const Dev &d, int out_par, int step,
     norm += exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) * d.dz;
   }
   T *Ez = (T *)d.e[out_par][2];
+  // a dynamically scaled level holds 2^e times the static scale: the increment scales exactly
+  const double cb = d.dyn ? ldexp(d.cb_src, *d.dexp[out_par]) : d.cb_src;
+  float mx = 0.f;
   for (int s = 0; s < m; s++) {
     const int k = klo + s;
     if (k < 0 || k > d.nz - 2) continue;
     const double dd = (klo + s + 0.5) * d.dz - zs;
     const double wz = exp(-0.5 * dd * dd / (d.sigma_z * d.sigma_z)) / norm;
-    const double inc = d.cb_src * d.v_src * qz * wr * wz;
+    const double inc = cb * d.v_src * qz * wr * wz;
     const long long c = (long long)k * d.plane + (long long)j * d.pitch + i;
-    Ez[c] = from_f<T>(to_f(Ez[c]) - (float)inc);
+    const float nv = to_f(Ez[c]) - (float)inc;
+    Ez[c] = from_f<T>(nv);
+    mx = fmaxf(mx, fabsf(nv));
   }
+  return mx;
 }
 
 template <typename T>
 __global__ void k_source(Dev d, int out_par, int step, const double *q) {
-  source_body<T>(d, out_par, step, q, blockIdx.x * blockDim.x + threadIdx.x);
+  const float m = source_body<T>(d, out_par, step, q, blockIdx.x * blockDim.x + threadIdx.x);
+  if (d.dyn) dyn_raise(d.dmax + 2 * *d.dslot[out_par], m);
 }
 
 // Batched: blockIdx.y is the plan; each plan uses its own profile.
 template <typename T>
 __global__ void k_source_batch(const Dev *devs, int out_par, int step) {
   const Dev &d = devs[blockIdx.y];
-  source_body<T>(d, out_par, step, d.q_bins, blockIdx.x * blockDim.x + threadIdx.x);
+  (void)source_body<T>(d, out_par, step, d.q_bins, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // --------------------------------------------------------------------- Mur-1
@@ -889,7 +918,8 @@ __global__ void k_fill_zero(uint4 *p, long long n16) {
 // Dense [nz][ny][nx] copies of one component: one wave per (j, k) row at a time (rows dealt
 // round-robin over the waves of the grid), lanes along x, so one division per row.
 template <typename T>
-__global__ void k_get_field(Dev d, const T *src, float *out, float inv_scale) {
+__global__ void k_get_field(Dev d, const T *src, float *out, float inv_scale, const int *dexp) {
+  if (dexp) inv_scale = ldexpf(inv_scale, -*dexp);
   const long long rows = (long long)d.ny * d.nz;
   const int lane = threadIdx.x & 63;
   const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
@@ -902,7 +932,8 @@ __global__ void k_get_field(Dev d, const T *src, float *out, float inv_scale) {
 }
 
 template <typename T>
-__global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
+__global__ void k_set_field(Dev d, T *dst, const float *in, float scale, const int *dexp) {
+  if (dexp) scale = ldexpf(scale, *dexp);
   const long long rows = (long long)d.ny * d.nz;
   const int lane = threadIdx.x & 63;
   const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
@@ -915,7 +946,7 @@ __global__ void k_set_field(Dev d, T *dst, const float *in, float scale) {
 }
 
 // ------------------------------------------------------------------ launch
-template <typename T, int VX, int W>
+template <typename T, int VX, int W, bool DYN>
 static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   if (general) {
     if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
@@ -925,44 +956,44 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
       // boundary sweeps of 11-row tiles fit 3 waves per SIMD (the z-wall one with a small spill)
       if (p.fs.prefetch && W <= 7) {
         if (ny_ > 0)
-          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, true>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, true, 1, DYN>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles, ny_, par);
         if (nr > 0)
-          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, true>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, true, 1, DYN>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles + 2 * ny_, nr, par);
       } else {
         if (ny_ > 0)
-          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, false>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, false, 1, DYN>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles, ny_, par);
         if (nr > 0)
-          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, false>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
+          hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, false, 1, DYN>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles + 2 * ny_, nr, par);
       }
     } else
       return hipErrorInvalidValue;
   } else if (p.fs.prefetch) {
     if constexpr (VX <= 4 && W <= 11)
-      hipLaunchKernelGGL((k_fused<T, VX, W, true>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
+      hipLaunchKernelGGL((k_fused<T, VX, W, true, 1, DYN>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
     else
       return hipErrorInvalidValue;
   } else
-    hipLaunchKernelGGL((k_fused<T, VX, W, false>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
+    hipLaunchKernelGGL((k_fused<T, VX, W, false, 1, DYN>), dim3(p.fs.fast_blocks), dim3(64 * (W + 1)), 0, s, d, p.fs, par);
   return hipGetLastError();
 }
 
-template <typename T, int VX>
+template <typename T, int VX, bool DYN>
 static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   switch (p.fs.waves) {
-    case 4: return fused_launch<T, VX, 4>(p, d, par, general, s);
-    case 7: return fused_launch<T, VX, 7>(p, d, par, general, s);
+    case 4: return fused_launch<T, VX, 4, DYN>(p, d, par, general, s);
+    case 7: return fused_launch<T, VX, 7, DYN>(p, d, par, general, s);
     case 8:
-      if constexpr (VX <= 4) return fused_launch<T, VX, 8>(p, d, par, general, s);
+      if constexpr (VX <= 4) return fused_launch<T, VX, 8, DYN>(p, d, par, general, s);
       return hipErrorInvalidValue;
     case 11:
-      if constexpr (VX <= 4) return fused_launch<T, VX, 11>(p, d, par, general, s);
+      if constexpr (VX <= 4) return fused_launch<T, VX, 11, DYN>(p, d, par, general, s);
       return hipErrorInvalidValue;
     case 15:
-      if constexpr (VX <= 4) return fused_launch<T, VX, 15>(p, d, par, general, s);
+      if constexpr (VX <= 4) return fused_launch<T, VX, 15, DYN>(p, d, par, general, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -970,38 +1001,50 @@ static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, boo
 
 // Rows of up to 512 nodes split across two waves (VX 4): the prefetching interior sweep with 4 or 5
 // rows per tile (10 or 12 waves) and the plain general sweep for the boundary tiles.
-template <typename T, int W>
+template <typename T, int W, bool DYN>
 static hipError_t split_rows_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   const dim3 block(64 * (W + 1) * 2);
   if (general) {
     const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
     if (ny_ > 0)
-      hipLaunchKernelGGL((k_fused_gen<T, 4, W, 1, false, 2>), dim3((ny_ + 7) / 8 * 8), block, 0, s, d, p.fs,
+      hipLaunchKernelGGL((k_fused_gen<T, 4, W, 1, false, 2, DYN>), dim3((ny_ + 7) / 8 * 8), block, 0, s, d, p.fs,
                          d.slow_tiles, ny_, par);
     if (nr > 0)
-      hipLaunchKernelGGL((k_fused_gen<T, 4, W, 2, false, 2>), dim3((nr + 7) / 8 * 8), block, 0, s, d, p.fs,
+      hipLaunchKernelGGL((k_fused_gen<T, 4, W, 2, false, 2, DYN>), dim3((nr + 7) / 8 * 8), block, 0, s, d, p.fs,
                          d.slow_tiles + 2 * ny_, nr, par);
   } else {
-    hipLaunchKernelGGL((k_fused<T, 4, W, true, 2>), dim3(p.fs.fast_blocks), block, 0, s, d, p.fs, par);
+    hipLaunchKernelGGL((k_fused<T, 4, W, true, 2, DYN>), dim3(p.fs.fast_blocks), block, 0, s, d, p.fs, par);
   }
   return hipGetLastError();
 }
 
 // general = false: the interior rectangle; true: the boundary tiles of the tile table
-template <typename T>
-static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+template <typename T, bool DYN>
+static hipError_t fused_dispatch_t(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
   if (p.fs.xs == 2) {
-    if (p.fs.waves == 4) return split_rows_launch<T, 4>(p, d, par, general, s);
-    if (p.fs.waves == 5) return split_rows_launch<T, 5>(p, d, par, general, s);
+    if (p.fs.waves == 4) return split_rows_launch<T, 4, DYN>(p, d, par, general, s);
+    if (p.fs.waves == 5) return split_rows_launch<T, 5, DYN>(p, d, par, general, s);
     return hipErrorInvalidValue;
   }
   switch (p.fs.vx) {
-    case 1: return fused_dispatch_w<T, 1>(p, d, par, general, s);
-    case 2: return fused_dispatch_w<T, 2>(p, d, par, general, s);
-    case 4: return fused_dispatch_w<T, 4>(p, d, par, general, s);
-    case 8: return fused_dispatch_w<T, 8>(p, d, par, general, s);
+    case 1: return fused_dispatch_w<T, 1, DYN>(p, d, par, general, s);
+    case 2: return fused_dispatch_w<T, 2, DYN>(p, d, par, general, s);
+    case 4: return fused_dispatch_w<T, 4, DYN>(p, d, par, general, s);
+    case 8: return fused_dispatch_w<T, 8, DYN>(p, d, par, general, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Dynamically scaled levels exist for FP16 storage only (plan validation), so only the FP16
+// sweeps are built in that form.
+template <typename T>
+static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+  if constexpr (std::is_same<T, _Float16>::value) {
+    if (d.dyn) return fused_dispatch_t<T, true>(p, d, par, general, s);
+  } else {
+    if (d.dyn) return hipErrorInvalidValue;
+  }
+  return fused_dispatch_t<T, false>(p, d, par, general, s);
 }
 
 template <typename T>
@@ -1058,6 +1101,10 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
+  if (d.dyn) {
+    e = launch_dyn_publish(d, par, 1, s);
+    if (e != hipSuccess) return e;
+  }
   if (d.src_on) {
     const int n = d.src_ni * d.src_nj;
     hipLaunchKernelGGL(k_source<T>, dim3((n + 255) / 256), dim3(256), 0, s, d, par ^ 1, step,
@@ -1215,6 +1262,65 @@ hipError_t launch_batch_step(const chf_batch &b, int par, int step, hipStream_t 
   return hipErrorInvalidValue;
 }
 
+// --------------------------------------------------------- dynamic scaling
+// After the sweeps of a launch of n steps from level par: the written level's exponent (the
+// sweeps' own choice, recomputed from the same words), its maxima slot, and the slot the next
+// launch raises cleared.  One lane.
+__global__ void k_dyn_publish(Dev d, int par, int n) {
+  if (threadIdx.x != 0) return;
+  const int sh = dyn_shift(d, par, n);
+  const int sl = *d.dslot[par];
+  *d.dexp[par ^ 1] = *d.dexp[par] + sh;
+  *d.dslot[par ^ 1] = (sl + 1) % 3;
+  const int nx = (sl + 2) % 3;
+  d.dmax[2 * nx] = 0u;
+  d.dmax[2 * nx + 1] = 0u;
+}
+
+hipError_t launch_dyn_publish(const Dev &d, int par, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_dyn_publish, dim3(1), dim3(64), 0, s, d, par, n);
+  return hipGetLastError();
+}
+
+// The maxima of level par from its stored values: the slot cleared (one lane), then raised by
+// every wave (rows dealt round-robin as in the field copies).
+__global__ void k_dyn_clear(Dev d, int par) {
+  if (threadIdx.x == 0) {
+    const int sl = *d.dslot[par];
+    d.dmax[2 * sl] = 0u;
+    d.dmax[2 * sl + 1] = 0u;
+  }
+}
+
+template <typename T>
+__global__ void k_dyn_levelmax(Dev d, int par) {
+  const long long rows = (long long)d.ny * d.nz;
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+  float me = 0.f, mh = 0.f;
+  for (long long r = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < rows; r += nw) {
+    const int j = (int)(r % d.ny), k = (int)(r / d.ny);
+    const long long o = (long long)k * d.plane + (long long)j * d.pitch;
+    for (int c = 0; c < 3; c++) {
+      const T *e = (const T *)d.e[par][c] + o, *h = (const T *)d.h[par][c] + o;
+      for (int i = lane; i < d.nx; i += 64) {
+        me = fmaxf(me, fabsf(to_f(e[i])));
+        mh = fmaxf(mh, fabsf(to_f(h[i])));
+      }
+    }
+  }
+  unsigned *slot = d.dmax + 2 * *d.dslot[par];
+  dyn_raise(slot, me);
+  dyn_raise(slot + 1, mh);
+}
+
+hipError_t launch_dyn_levelmax(const chf_plan &p, int par, hipStream_t s) {
+  hipLaunchKernelGGL(k_dyn_clear, dim3(1), dim3(64), 0, s, p.dev, par);
+  if (p.storage == CHF_FP16)
+    hipLaunchKernelGGL(k_dyn_levelmax<_Float16>, dim3(1024), dim3(256), 0, s, p.dev, par);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(const chf_plan &p, hipStream_t s) {
   // fields and psi occupy [0, off_tf) of the workspace (16-byte multiples)
   const long long n16 = (long long)(p.off_tf / 16);
@@ -1228,7 +1334,8 @@ template <typename T>
 static hipError_t get_t(const chf_plan &p, int par, int comp, float *out, hipStream_t s) {
   const T *src = (const T *)(comp < 3 ? p.dev.e[par][comp] : p.dev.h[par][comp - 3]);
   const float inv = (float)(1.0 / (comp < 3 ? p.scale_e : p.scale_h));
-  hipLaunchKernelGGL(k_get_field<T>, dim3(2048), dim3(256), 0, s, p.dev, src, out, inv);
+  hipLaunchKernelGGL(k_get_field<T>, dim3(2048), dim3(256), 0, s, p.dev, src, out, inv,
+                     (const int *)(p.dev.dyn ? p.dev.dexp[par] : nullptr));
   return hipGetLastError();
 }
 
@@ -1236,7 +1343,9 @@ template <typename T>
 static hipError_t set_t(const chf_plan &p, int par, int comp, const float *in, hipStream_t s) {
   T *dst = (T *)(comp < 3 ? p.dev.e[par][comp] : p.dev.h[par][comp - 3]);
   const float sc = (float)(comp < 3 ? p.scale_e : p.scale_h);
-  hipLaunchKernelGGL(k_set_field<T>, dim3(2048), dim3(256), 0, s, p.dev, dst, in, sc);
+  hipLaunchKernelGGL(k_set_field<T>, dim3(2048), dim3(256), 0, s, p.dev, dst, in, sc,
+                     (const int *)(p.dev.dyn ? p.dev.dexp[par] : nullptr));
+  if (p.dev.dyn) return launch_dyn_levelmax(p, par, s);
   return hipGetLastError();
 }
 

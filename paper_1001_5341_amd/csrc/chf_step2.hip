@@ -51,7 +51,7 @@ struct SrcLds {
   double wz[2][kMaxWz];
 };
 
-__device__ __forceinline__ void src_prepare(const Dev &d, int step, const double *q, SrcLds &S) {
+__device__ __forceinline__ void src_prepare(const Dev &d, int step, const double *q, SrcLds &S, int dyn_e) {
   const int t = threadIdx.x;
   if (t < 2) {
     S.m[t] = 0;
@@ -74,7 +74,9 @@ __device__ __forceinline__ void src_prepare(const Dev &d, int step, const double
       }
       S.klo[t] = klo;
       S.m[t] = m;
-      S.a[t] = d.cb_src * d.v_src * qz;
+      // dynamic scaling: the pass computes in the units of the level it writes, 2^dyn_e times
+      // the static scale, which scales the increment exactly
+      S.a[t] = (d.dyn ? ldexp(d.cb_src, dyn_e) : d.cb_src) * d.v_src * qz;
     }
   }
 }
@@ -99,7 +101,11 @@ __device__ __forceinline__ void src_apply(const Dev &d, const SrcLds &S, int st,
   }
 }
 
-template <typename T, int VX, int W, int XS, int G>
+// DYN: dynamically scaled FP16 levels -- every value the pass loads (fields and psi) is multiplied
+// by the launch's power of two r, so both stages, the source, the intermediate level's rounding
+// and its samples work in the units of the level written (chosen for both steps); the wave's
+// largest stored magnitudes raise that level's maxima.
+template <typename T, int VX, int W, int XS, int G, bool DYN = false>
 __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int zc, int zchunk, int par, int step,
                                            const double *q) {
   constexpr int NR = W + 3;  // computed rows: j0-2 .. j0+W; row NR (j0+W+1) is only loaded
@@ -133,6 +139,13 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
   const bool doE1 = r >= 1 && act && !loader, doH2 = r >= 1 && r <= W + 1 && act, own = r >= 2 && r <= W + 1 && act && j < jend;
   const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
   const int ib = xs * SEG + lane * VX;
+  float dyn_r = 1.f, dyn_me = 0.f, dyn_mh = 0.f;
+  int dyn_e = 0;  // exponent of the written level
+  if constexpr (DYN) {
+    const int sh = dyn_shift(d, par, 2);
+    dyn_r = ldexpf(1.f, sh);
+    dyn_e = *d.dexp[par] + sh;
+  }
   const bool on = ib < nx && act;
   const unsigned esz = (unsigned)sizeof(T);
   const unsigned o0 = ((unsigned)jc * (unsigned)d.pitch + (unsigned)ib) * esz;
@@ -179,7 +192,7 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
   const bool je = !GY || (j >= 1 && j <= ny - 2);
   // source constants of the two steps (LDS; visible after the prologue's barrier)
   __shared__ SrcLds sSrc;
-  src_prepare(d, step, q, sSrc);
+  src_prepare(d, step, q, sSrc, dyn_e);
   float *psA = &sPsi[wv][0][0][0];  // this wave's x-slab psi, [parity][term][slot]
   auto PS = [&](int par_k, int t) -> float * { return psA + (par_k * 4 + t) * NP; };
 
@@ -383,6 +396,11 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
     ld_at<T, VX>(Ei0 + kb * plane, o0, e0x, on && pk);
     ld_at<T, VX>(Ei1 + kb * plane, o0, e0y, on && pk && !loader);
     ld_at<T, VX>(Ei2 + kb * plane, o0, e0z, on && pk);
+    if constexpr (DYN) {
+      scale_in<VX>(e0x, dyn_r);
+      scale_in<VX>(e0y, dyn_r);
+      scale_in<VX>(e0z, dyn_r);
+    }
 #pragma unroll
     for (int v = 0; v < VX; v++) {
       sE0x[r][ib + v] = e0x[v];
@@ -439,7 +457,18 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
     unpack<T, VX>(rH0, h0x);
     unpack<T, VX>(rH1, h0y);
     unpack<T, VX>(rH2, h0z);
-    const float q0 = rq0, q1 = rq1, q2 = rq2, q3 = rq3;
+    float q0 = rq0, q1 = rq1, q2 = rq2, q3 = rq3;
+    if constexpr (DYN) {
+      scale_in<VX>(nxc, dyn_r);
+      scale_in<VX>(nyc, dyn_r);
+      scale_in<VX>(h0x, dyn_r);
+      scale_in<VX>(h0y, dyn_r);
+      scale_in<VX>(h0z, dyn_r);
+      q0 *= dyn_r;
+      q1 *= dyn_r;
+      q2 *= dyn_r;
+      q3 *= dyn_r;
+    }
     // y/z-slab psi rows of stage 1 at plane k (boundary tiles only)
     float qhxy[VX], qhzy[VX], qhxz[VX], qhyz[VX], qexy[VX], qezy[VX], qexz[VX], qeyz[VX];
     int shz1 = -1, sez1 = -1;
@@ -459,6 +488,16 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
       ld_row<float, VX>(d.psi_e[1][1] + iye, qezy, on && pk && sey >= 0);
       ld_row<float, VX>(d.psi_e[2][0] + ize, qexz, on && pk && sez1 >= 0);
       ld_row<float, VX>(d.psi_e[2][1] + ize, qeyz, on && pk && sez1 >= 0);
+      if constexpr (DYN) {
+        scale_in<VX>(qhxy, dyn_r);
+        scale_in<VX>(qhzy, dyn_r);
+        scale_in<VX>(qhxz, dyn_r);
+        scale_in<VX>(qhyz, dyn_r);
+        scale_in<VX>(qexy, dyn_r);
+        scale_in<VX>(qezy, dyn_r);
+        scale_in<VX>(qexz, dyn_r);
+        scale_in<VX>(qeyz, dyn_r);
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < VX; v++) qhxy[v] = qhzy[v] = qhxz[v] = qhyz[v] = qexy[v] = qezy[v] = qexz[v] = qeyz[v] = 0.f;
@@ -590,6 +629,11 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
       unpack<T, VX>(rE0, t0);
       unpack<T, VX>(rE1, t1);
       unpack<T, VX>(rE2, t2);
+      if constexpr (DYN) {
+        scale_in<VX>(t0, dyn_r);
+        scale_in<VX>(t1, dyn_r);
+        scale_in<VX>(t2, dyn_r);
+      }
 #pragma unroll
       for (int v = 0; v < VX; v++) {
         sE0x[r][ib + v] = t0[v];
@@ -615,6 +659,10 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
       e_upd(m, e1x, e1y, e1z, gx, gy, gz, h2x, h2y, bx, bz, hzw0, hyw0, pm, c_exy, c_ezy, c_exz, c_eyz, fx, fy, fz);
       src_apply<T, VX>(d, sSrc, 1, ib, j, m, fz);
       const long long pmo = (long long)m * plane;
+      if constexpr (DYN) {
+        dyn_mh = absmax<VX>(absmax<VX>(absmax<VX>(dyn_mh, gx, on), gy, on), gz, on);
+        dyn_me = absmax<VX>(absmax<VX>(absmax<VX>(dyn_me, fx, on), fy, on), fz, on);
+      }
       st_at<T, VX>(Ho0 + pmo, o0, gx, on);
       st_at<T, VX>(Ho1 + pmo, o0, gy, on);
       st_at<T, VX>(Ho2 + pmo, o0, gz, on);
@@ -676,28 +724,33 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
       }
     }
   }
+  if constexpr (DYN) {
+    unsigned *slot = d.dmax + 2 * ((*d.dslot[par] + 1) % 3);
+    dyn_raise(slot, dyn_me);
+    dyn_raise(slot + 1, dyn_mh);
+  }
 }
 
 // The interior rectangle (no wall and no y/z layer within any computed row or plane).
-template <typename T, int VX, int W, int XS>
+template <typename T, int VX, int W, int XS, bool DYN = false>
 __global__ void __launch_bounds__(64 * (W + 4) * XS) k_step2(Dev d, Shape2 f2, int par, int step, const double *q) {
   const int logical = xcd_logical();
   if (logical >= f2.n_fast) return;
   const int fw = f2.ty_hi - f2.ty_lo;
   const int j0 = (f2.ty_lo + logical % fw) * W;
-  step2_body<T, VX, W, XS, 0>(d, j0, j0 + W, f2.zc_lo + logical / fw, f2.zchunk, par, step, q);
+  step2_body<T, VX, W, XS, 0, DYN>(d, j0, j0 + W, f2.zc_lo + logical / fw, f2.zchunk, par, step, q);
 }
 
 // Boundary tiles of kStep2BoundaryRows rows from the table (first row, end of the rows the tile
 // owns, chunk): G = 1 over the first n_slow_y entries (y walls and layers), G = 2 over the rest
 // (z walls and layers as well).
-template <typename T, int VX, int XS, int G>
+template <typename T, int VX, int XS, int G, bool DYN = false>
 __global__ void __launch_bounds__(64 * (kStep2BoundaryRows + 4) * XS)
     k_step2_gen(Dev d, Shape2 f2, const int *tiles, int n, int par, int step, const double *q) {
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int *t = tiles + 3 * logical;
-  step2_body<T, VX, kStep2BoundaryRows, XS, G>(d, t[0], t[1], t[2], f2.zchunk, par, step, q);
+  step2_body<T, VX, kStep2BoundaryRows, XS, G, DYN>(d, t[0], t[1], t[2], f2.zchunk, par, step, q);
 }
 
 template <typename T>
@@ -707,7 +760,7 @@ __global__ void __launch_bounds__(64) k_gather_level(Dev d, int par, double *w, 
 
 // Waveform column of the intermediate level from the samples a two-step pass took: the
 // one-step gather's arithmetic (FP64 weight times the stored value, butterfly over the corners).
-__global__ void __launch_bounds__(64) k_gather_smp(Dev d, double *w, int column, int ld) {
+__global__ void __launch_bounds__(64) k_gather_smp(Dev d, int par, double *w, int column, int ld) {
   const int o = blockIdx.x, lane = threadIdx.x;
   const int comp = lane >> 3, corner = lane & 7;
   double val = 0.0;
@@ -721,13 +774,14 @@ __global__ void __launch_bounds__(64) k_gather_smp(Dev d, double *w, int column,
   val += __shfl_xor(val, 2);
   val += __shfl_xor(val, 4);
   if (comp < 3 && corner == 0) {
-    const double out = val * d.inv_se;
+    // samples are in the units of level `par` (dynamic scaling: the level the pass wrote)
+    const double out = val * (d.dyn ? ldexp(d.inv_se, -*d.dexp[par]) : d.inv_se);
     w[((long long)o * 3 + comp) * ld + column] = out;
     if (d.nan_flag && !isfinite(out)) *d.nan_flag = 1;
   }
 }
 
-template <typename T, int VX, int W>
+template <typename T, int VX, int W, bool DYN>
 static hipError_t step2_launch(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
                                hipStream_t s) {
   const Shape2 &f2 = p.fs2;
@@ -736,33 +790,45 @@ static hipError_t step2_launch(const chf_plan &p, const Dev &d, int par, int ste
     const int *tiles = (const int *)(p.ws + p.off_tiles2);
     const int n1 = f2.n_slow_y, n2 = f2.n_slow - f2.n_slow_y;
     if (n1 > 0)
-      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 1>), dim3((n1 + 7) / 8 * 8), block, 0, s, d, f2, tiles, n1, par, step,
+      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 1, DYN>), dim3((n1 + 7) / 8 * 8), block, 0, s, d, f2, tiles, n1, par, step,
                          q);
     if (n2 > 0)
-      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 2>), dim3((n2 + 7) / 8 * 8), block, 0, s, d, f2, tiles + 3 * n1, n2,
+      hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 2, DYN>), dim3((n2 + 7) / 8 * 8), block, 0, s, d, f2, tiles + 3 * n1, n2,
                          par, step, q);
   } else if (f2.n_fast > 0) {
-    hipLaunchKernelGGL((k_step2<T, VX, W, 1>), dim3(f2.fast_blocks), dim3(64 * (W + 4)), 0, s, d, f2, par, step, q);
+    hipLaunchKernelGGL((k_step2<T, VX, W, 1, DYN>), dim3(f2.fast_blocks), dim3(64 * (W + 4)), 0, s, d, f2, par, step, q);
   }
   return hipGetLastError();
 }
 
+template <typename T, bool DYN>
+static hipError_t step2_dispatch_t(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
+                                   hipStream_t s) {
+  const Shape2 &f2 = p.fs2;
+  switch (f2.vx * 100 + f2.waves) {
+    case 104: return step2_launch<T, 1, 4, DYN>(p, d, par, step, q, general, s);
+    case 107: return step2_launch<T, 1, 7, DYN>(p, d, par, step, q, general, s);
+    case 108: return step2_launch<T, 1, 8, DYN>(p, d, par, step, q, general, s);
+    case 204: return step2_launch<T, 2, 4, DYN>(p, d, par, step, q, general, s);
+    case 207: return step2_launch<T, 2, 7, DYN>(p, d, par, step, q, general, s);
+    case 208: return step2_launch<T, 2, 8, DYN>(p, d, par, step, q, general, s);
+    case 404: return step2_launch<T, 4, 4, DYN>(p, d, par, step, q, general, s);
+    case 407: return step2_launch<T, 4, 7, DYN>(p, d, par, step, q, general, s);
+    case 408: return step2_launch<T, 4, 8, DYN>(p, d, par, step, q, general, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// dynamically scaled levels exist for FP16 storage only
 template <typename T>
 static hipError_t step2_dispatch(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
                                  hipStream_t s) {
-  const Shape2 &f2 = p.fs2;
-  switch (f2.vx * 100 + f2.waves) {
-    case 104: return step2_launch<T, 1, 4>(p, d, par, step, q, general, s);
-    case 107: return step2_launch<T, 1, 7>(p, d, par, step, q, general, s);
-    case 108: return step2_launch<T, 1, 8>(p, d, par, step, q, general, s);
-    case 204: return step2_launch<T, 2, 4>(p, d, par, step, q, general, s);
-    case 207: return step2_launch<T, 2, 7>(p, d, par, step, q, general, s);
-    case 208: return step2_launch<T, 2, 8>(p, d, par, step, q, general, s);
-    case 404: return step2_launch<T, 4, 4>(p, d, par, step, q, general, s);
-    case 407: return step2_launch<T, 4, 7>(p, d, par, step, q, general, s);
-    case 408: return step2_launch<T, 4, 8>(p, d, par, step, q, general, s);
+  if constexpr (std::is_same<T, _Float16>::value) {
+    if (d.dyn) return step2_dispatch_t<T, true>(p, d, par, step, q, general, s);
+  } else {
+    if (d.dyn) return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
+  return step2_dispatch_t<T, false>(p, d, par, step, q, general, s);
 }
 
 template <typename T>
@@ -791,8 +857,12 @@ static hipError_t step2_t(const chf_plan &p, const Dev &d, int par, int step, co
     e = fork ? hipStreamWaitEvent(s, p.ev_join, 0) : step2_dispatch<T>(p, d, par, step, qq, true, s);
     if (e != hipSuccess) return e;
   }
+  if (d.dyn) {
+    e = launch_dyn_publish(d, par, 2, s);
+    if (e != hipSuccess) return e;
+  }
   if (d.n_obs > 0 && w) {
-    hipLaunchKernelGGL(k_gather_smp, dim3(d.n_obs), dim3(64), 0, s, d, w, column, ld);
+    hipLaunchKernelGGL(k_gather_smp, dim3(d.n_obs), dim3(64), 0, s, d, par ^ 1, w, column, ld);
     hipLaunchKernelGGL(k_gather_level<T>, dim3(d.n_obs), dim3(64), 0, s, d, par ^ 1, w, column + 1, ld);
   }
   return hipGetLastError();

@@ -20,7 +20,7 @@ def _dp(a: np.ndarray):
 
 
 def descriptors(w, storage="fp32", kernel="auto", rows=0, waves=0, zchunk=0, nan_watch=False,
-                scale_e=0.0, scale_h=0.0, q_bins=None):
+                scale_e=0.0, scale_h=0.0, q_bins=None, dynamic_scaling=False):
     """Build the C descriptor structs for a workload.  Returns (structs, keepalive)."""
     q = np.ascontiguousarray(w.q_bins if q_bins is None else q_bins, dtype=np.float64)
     obs = np.ascontiguousarray(w.obs_xyz, dtype=np.float64).reshape(-1, 3)
@@ -32,7 +32,7 @@ def descriptors(w, storage="fp32", kernel="auto", rows=0, waves=0, zchunk=0, nan
                  w.cut_sigmas, len(q) if w.src_on else 0, 0, w.z_bin0, w.dz_bin, _dp(q))
     o = N.Observers(obs.shape[0], 0, _dp(obs))
     e = N.Exec(N.STORAGE[storage], N.KERNEL[kernel], rows, waves, zchunk, 1 if nan_watch else 0,
-               scale_e, scale_h)
+               scale_e, scale_h, 1 if dynamic_scaling else 0, 0)
     return (g, m, b, s, o, e), (q, obs)
 
 
@@ -59,16 +59,16 @@ class Plan:
 
     def __init__(self, w, storage: str = "fp32", kernel: str = "auto", rows: int = 0, waves: int = 0,
                  zchunk: int = 0, nan_watch: bool = False, scale_e: float = 0.0, scale_h: float = 0.0,
-                 device=None):
+                 device=None, dynamic_scaling: bool = False):
         self.w = w
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.storage = storage
         # execution choices, reused by the second plan of checkpointed recomputations
         self.exec_kw = dict(kernel=kernel, rows=rows, waves=waves, zchunk=zchunk, scale_e=scale_e,
-                            scale_h=scale_h)
+                            scale_h=scale_h, dynamic_scaling=dynamic_scaling)
         self._h = create_plan_handle(w, storage=storage, kernel=kernel, rows=rows, waves=waves,
                                      zchunk=zchunk, nan_watch=nan_watch, scale_e=scale_e,
-                                     scale_h=scale_h)
+                                     scale_h=scale_h, dynamic_scaling=dynamic_scaling)
         L = N.lib()
         nbytes = ct.c_uint64()
         N.check(L.chf_plan_workspace_bytes(self._h, ct.byref(nbytes)), "chf_plan_workspace_bytes")

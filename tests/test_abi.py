@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(N.EXPORTED)
-    assert L.chf_abi_version() == 2
+    assert L.chf_abi_version() == 3
 
 
 def _status(w, **kw):
@@ -156,8 +156,8 @@ def test_snapshot_size_and_adjoint_state_checks():
         assert N.lib().chf_plan_get_info(h, ct.byref(info)) == 0
         n = ct.c_uint64()
         assert N.lib().chf_plan_state_bytes(h, ct.byref(n)) == 0
-        # a snapshot is both field levels plus every psi array
-        assert n.value == info.field_bytes + info.psi_bytes
+        # a snapshot is both field levels, every psi array and the dynamic-scaling words
+        assert n.value == info.field_bytes + info.psi_bytes + 256
         step = ct.c_int32()
         assert N.STATUS[N.lib().chf_plan_save_state(h, None, ct.c_void_p(1), ct.byref(step))] == "CHF_ESTATE"
         assert N.STATUS[N.lib().chf_adjoint_steps(h, None, ct.c_void_p(1), ct.c_void_p(1), 0, 5)] == "CHF_ESTATE"
@@ -189,6 +189,26 @@ def _rz_status(w, **kw):
         return e.status
     N.lib().chf_rz_plan_destroy(h)
     return "CHF_OK"
+
+
+def test_dynamic_scaling_validation():
+    """Per-launch scaling is accepted for FP16 storage with the fused one- and two-step sweeps
+    (PEC or CPML walls) and rejected elsewhere, on the host."""
+    w = W.small_shower()
+    for kernel in ("auto", "fused", "fused_prefetch", "fused2"):
+        assert _status(w, storage="fp16", kernel=kernel, dynamic_scaling=True) == "CHF_OK", kernel
+    assert _status(w.replace(nx=300), storage="fp16", kernel="fused_prefetch", dynamic_scaling=True) == "CHF_OK"
+    assert _status(w.replace(bc="pec", npml=0), storage="fp16", dynamic_scaling=True) == "CHF_OK"
+    assert _status(w, storage="fp32", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
+    assert _status(w, storage="bf16", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
+    assert _status(w, storage="fp16", kernel="split", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
+    assert _status(w, storage="fp16", waves=15, dynamic_scaling=True) == "CHF_EUNSUPPORTED"
+    assert _status(W.gaussian_cube(1), storage="fp16", dynamic_scaling=True) == "CHF_EUNSUPPORTED"  # Mur
+    h = solver.create_plan_handle(w, storage="fp16", dynamic_scaling=True)
+    pi = N.PlanInfo()
+    N.check(N.lib().chf_plan_get_info(h, ct.byref(pi)), "info")
+    N.lib().chf_plan_destroy(h)
+    assert pi.dynamic_scaling == 1
 
 
 def test_rz_plan_validation():

@@ -53,7 +53,8 @@ RZ_KERNEL = "k_rz_step2<"
 RZ_BYTES_PER_NODE = 24.0  # read E_r, E_z, H_phi once and write them once (FP32)
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 DFT_FLOPS_PER_TERM = 10.0  # 2 FMA into the sums + one complex rotation of the phase (4 mul, 2 add)
-DTYPE = {"fp32": "f32", "bf16": "f32 (bf16 storage)", "fp16": "f32 (f16 storage)"}
+DTYPE = {"fp32": "f32", "bf16": "f32 (bf16 storage)", "fp16": "f32 (f16 storage)",
+         "bf16x": "f32 (bf16 + 8-bit extension storage)"}
 SLICES_PER_RUN = 25          # a bench step is one slice of a full run
 STORAGE_GATE = 1e-2          # relative L2 the 16-bit storage runs must meet
 COPY_CEILING_BYTES = 4 << 30  # source size of the streaming-copy ceiling probe
@@ -685,7 +686,7 @@ def main():
                     help=f"timed slices ({SLICES_PER_RUN} slices = one complete run)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed slices before the timed region")
     ap.add_argument("--workload", default="precision")
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16", "bf16x"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused_prefetch", "fused2", "split"])
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
@@ -811,7 +812,7 @@ def main():
         if acc is not None and os.path.exists(gold):
             ref, label = np.load(gold)["waveforms"].astype(np.float64), "fp64_oracle"
         rec["storage_variants"] = {st: storage_variant(w, st, args, ref, SLICES_PER_RUN, label)
-                                   for st in ("bf16", "fp16")}
+                                   for st in ("bf16", "bf16x", "fp16")}
         if args.dynamic_fp16:
             rec["storage_variants"]["fp16_dynamic"] = storage_variant(w, "fp16", args, ref, SLICES_PER_RUN, label,
                                                                       dynamic=True)

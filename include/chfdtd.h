@@ -61,8 +61,12 @@ typedef enum {
   CHF_ESTATE = -8        /* call out of order (e.g. no workspace bound) */
 } chf_status;
 
-/* Field storage (arithmetic is FP32 in every case; BF16 and FP16 round to nearest even). */
-typedef enum { CHF_FP32 = 0, CHF_BF16 = 1, CHF_FP16 = 2 } chf_storage;
+/* Field storage (arithmetic is FP32 in every case; the reduced types round to nearest even).
+   CHF_BF16X: BF16 with an 8-bit mantissa extension -- the 24 leading bits of the FP32 value (8
+   exponent bits, 15 fraction bits) in 3 bytes, 36 B per node against FP32's 48; FP32's exponent
+   range, so no scale is needed (scale_e/scale_h as for BF16).  The 3-D path only (the (r, z)
+   scheme takes the other three). */
+typedef enum { CHF_FP32 = 0, CHF_BF16 = 1, CHF_FP16 = 2, CHF_BF16X = 3 } chf_storage;
 typedef enum { CHF_BC_PEC = 0, CHF_BC_MUR1 = 1, CHF_BC_CPML = 2 } chf_bc;
 /* CHF_KERNEL_FUSED_PREFETCH: the fused sweep whose interior tiles issue each plane's row loads one
    plane ahead (the loads of plane k+1 are in flight while plane k is computed), at the price of

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libchfdtd.so")
 CHF_OK = 0
 STATUS = {0: "CHF_OK", -1: "CHF_EINVAL", -2: "CHF_ECFL", -3: "CHF_EDOMAIN", -4: "CHF_ENOMEM",
           -5: "CHF_EHIP", -6: "CHF_ENAN", -7: "CHF_EUNSUPPORTED", -8: "CHF_ESTATE"}
-STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x": 3}
 BC = {"pec": 0, "mur1": 1, "cpml": 2}
 KERNEL = {"auto": 0, "split": 1, "fused": 2, "fused_prefetch": 3, "fused2": 4}
 

@@ -110,7 +110,7 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     if (!(bnd->poly_m >= 0 && bnd->sigma_scale >= 0 && bnd->kappa_max >= 1 && bnd->alpha_max >= 0))
       return fail(CHF_EINVAL, "bad CPML grading");
   }
-  if (ex->storage < CHF_FP32 || ex->storage > CHF_FP16) return fail(CHF_EINVAL, "bad storage");
+  if (ex->storage < CHF_FP32 || ex->storage > CHF_BF16X) return fail(CHF_EINVAL, "bad storage");
   if (ex->kernel < CHF_KERNEL_AUTO || ex->kernel > CHF_KERNEL_FUSED2) return fail(CHF_EINVAL, "bad kernel");
   if (obs->n_obs < 0 || obs->n_obs > chf::kMaxObsPerPlan || (obs->n_obs > 0 && !obs->xyz))
     return fail(CHF_EINVAL, "bad observer list");
@@ -130,7 +130,7 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   p->obs_xyz.assign(obs->xyz, obs->xyz + 3 * (size_t)obs->n_obs);
   p->src.q_bins = nullptr;
   p->storage = ex->storage;
-  p->elem_bytes = ex->storage == CHF_FP32 ? 4 : 2;
+  p->elem_bytes = ex->storage == CHF_FP32 ? 4 : (ex->storage == CHF_BF16X ? 3 : 2);
 
   // kernel and fused-sweep shape
   int kernel = ex->kernel == CHF_KERNEL_AUTO ? (G.nx <= 64 * chf::kMaxVX ? CHF_KERNEL_FUSED : CHF_KERNEL_SPLIT)

@@ -13,26 +13,97 @@
 namespace chf {
 
 // ------------------------------------------------------------------ storage
+// BF16X: BF16 with an 8-bit mantissa extension -- the 24 leading bits of the FP32 value (sign,
+// 8 exponent bits, 15 fraction bits), rounded to nearest even, in 3 bytes (little endian: the
+// extension byte, then the BF16 half).  FP32's exponent range, so no storage scale.
+struct bf16x {
+  unsigned char b[3];
+};
+
 template <typename T>
 __device__ __forceinline__ float to_f(T x) { return static_cast<float>(x); }
 template <typename T>
 __device__ __forceinline__ T from_f(float x) { return static_cast<T>(x); }  // RNE
 
+template <>
+__device__ __forceinline__ float to_f<bf16x>(bf16x x) {
+  const unsigned u = (unsigned)x.b[0] | ((unsigned)x.b[1] << 8) | ((unsigned)x.b[2] << 16);
+  return __uint_as_float(u << 8);
+}
+__device__ __forceinline__ unsigned bf16x_round(float x);
+template <>
+__device__ __forceinline__ bf16x from_f<bf16x>(float x) {
+  const unsigned r = bf16x_round(x);
+  bf16x o;
+  o.b[0] = (unsigned char)(r >> 8);
+  o.b[1] = (unsigned char)(r >> 16);
+  o.b[2] = (unsigned char)(r >> 24);
+  return o;
+}
+
+// Row vectors: aligned to their size when it is a power of two, else to the largest power of
+// two dividing it.  BF16X rows of a multiple of four values are held as whole dwords (three per
+// four values), so that they live in registers and move with dword loads and stores.
+constexpr unsigned vec_align(unsigned b) { return (b & (b - 1)) == 0 ? b : (b & (~b + 1)); }
+
 template <typename T, int N>
-struct alignas(sizeof(T) * N) Vec {
+constexpr bool kDwordRow = std::is_same<T, bf16x>::value && N % 4 == 0;
+
+template <typename T, int N, bool D = kDwordRow<T, N>>
+struct alignas(vec_align(sizeof(T) * N)) Vec {
   T v[N];
 };
+template <typename T, int N>
+struct alignas(vec_align(sizeof(T) * N)) Vec<T, N, true> {
+  unsigned w[3 * N / 4];
+};
+
+// 24-bit rounding of BF16X on a register: the FP32 bits rounded to nearest even at bit 8 (the low
+// byte is left as it falls).  Integer rounding of the bit pattern carries into the exponent
+// exactly as IEEE rounding does: the largest finite values round to infinity, infinity stays,
+// and a NaN with a fraction bit at or above bit 8 (every NaN that arithmetic produces) stays NaN.
+__device__ __forceinline__ unsigned bf16x_round(float x) {
+  const unsigned u = __float_as_uint(x);
+  return u + 0x7fu + ((u >> 8) & 1u);
+}
+
+// BF16X rows of a multiple of four values are whole dwords: value k of a group of four is the
+// dword starting one byte before it with its low byte cleared (the 24 bits shifted into place).
+template <int N>
+__device__ __forceinline__ void bf16x_decode(const unsigned (&d)[3 * N / 4], float (&o)[N]) {
+#pragma unroll
+  for (int g = 0; g < N / 4; g++) {
+    const unsigned d0 = d[3 * g], d1 = d[3 * g + 1], d2 = d[3 * g + 2];
+    o[4 * g + 0] = __uint_as_float(d0 << 8);
+    o[4 * g + 1] = __uint_as_float(__builtin_amdgcn_alignbyte(d1, d0, 2) & 0xffffff00u);
+    o[4 * g + 2] = __uint_as_float(__builtin_amdgcn_alignbyte(d2, d1, 1) & 0xffffff00u);
+    o[4 * g + 3] = __uint_as_float(d2 & 0xffffff00u);
+  }
+}
 
 // Lanes whose cells start beyond the last node (`on` false) neither load nor store.
 template <typename T, int N>
 __device__ __forceinline__ void ld_row(const T *p, float (&o)[N], bool on) {
-  if (on) {
-    Vec<T, N> x = *reinterpret_cast<const Vec<T, N> *>(p);
+  if constexpr (kDwordRow<T, N>) {
+    if (on) {
+      unsigned d[3 * N / 4];
+      const unsigned *q = reinterpret_cast<const unsigned *>(p);
 #pragma unroll
-    for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
+      for (int t = 0; t < 3 * N / 4; t++) d[t] = q[t];
+      bf16x_decode<N>(d, o);
+    } else {
+#pragma unroll
+      for (int v = 0; v < N; v++) o[v] = 0.f;
+    }
   } else {
+    if (on) {
+      Vec<T, N> x = *reinterpret_cast<const Vec<T, N> *>(p);
 #pragma unroll
-    for (int v = 0; v < N; v++) o[v] = 0.f;
+      for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < N; v++) o[v] = 0.f;
+    }
   }
 }
 
@@ -46,25 +117,43 @@ __device__ __forceinline__ void ld_at(const T *base, unsigned boff, float (&o)[N
 // converts them when they are used, so loads issued ahead hold half the registers in BF16/FP16.
 template <typename T, int N>
 __device__ __forceinline__ void ld_raw(const T *base, unsigned boff, Vec<T, N> &x, bool on) {
-  if (on) {
-    x = *reinterpret_cast<const Vec<T, N> *>(reinterpret_cast<const char *>(base) + boff);
-  } else {
+  if constexpr (kDwordRow<T, N>) {
+    if (on) {
+      const unsigned *q = reinterpret_cast<const unsigned *>(reinterpret_cast<const char *>(base) + boff);
 #pragma unroll
-    for (int v = 0; v < N; v++) x.v[v] = from_f<T>(0.f);
+      for (int t = 0; t < 3 * N / 4; t++) x.w[t] = q[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < 3 * N / 4; t++) x.w[t] = 0u;
+    }
+  } else {
+    if (on) {
+      x = *reinterpret_cast<const Vec<T, N> *>(reinterpret_cast<const char *>(base) + boff);
+    } else {
+#pragma unroll
+      for (int v = 0; v < N; v++) x.v[v] = from_f<T>(0.f);
+    }
   }
 }
 
 template <typename T, int N>
 __device__ __forceinline__ void unpack(const Vec<T, N> &x, float (&o)[N]) {
+  if constexpr (kDwordRow<T, N>) {
+    bf16x_decode<N>(x.w, o);
+  } else {
 #pragma unroll
-  for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
+    for (int v = 0; v < N; v++) o[v] = to_f<T>(x.v[v]);
+  }
 }
 
 // The value a store of x followed by a load returns: the fused sweep feeds H to the E update
 // exactly as stored, as the split sweeps (which reload it) do.
 template <typename T, int N>
 __device__ __forceinline__ void as_stored(float (&o)[N]) {
-  if constexpr (!std::is_same<T, float>::value) {
+  if constexpr (std::is_same<T, bf16x>::value) {
+#pragma unroll
+    for (int v = 0; v < N; v++) o[v] = __uint_as_float(bf16x_round(o[v]) & 0xffffff00u);
+  } else if constexpr (!std::is_same<T, float>::value) {
 #pragma unroll
     for (int v = 0; v < N; v++) o[v] = to_f<T>(from_f<T>(o[v]));
   }
@@ -84,25 +173,41 @@ __device__ __forceinline__ void st_at(T *base, unsigned boff, const float (&o)[N
 template <typename T, int N>
 __device__ __forceinline__ void st_row(T *p, const float (&o)[N], bool on) {
   if (!on) return;
-  Vec<T, N> x;
+  if constexpr (kDwordRow<T, N>) {
+    // four 24-bit values (the top three bytes of each rounded word) packed into three dwords
 #pragma unroll
-  for (int v = 0; v < N; v++) x.v[v] = from_f<T>(o[v]);
-  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-  if constexpr (sizeof(x) == 16) {
-    u4 b;
-    __builtin_memcpy(&b, &x, 16);
-    __builtin_nontemporal_store(b, reinterpret_cast<u4 *>(p));
-  } else if constexpr (sizeof(x) == 8) {
-    u2 b;
-    __builtin_memcpy(&b, &x, 8);
-    __builtin_nontemporal_store(b, reinterpret_cast<u2 *>(p));
-  } else if constexpr (sizeof(x) == 4) {
-    unsigned b;
-    __builtin_memcpy(&b, &x, 4);
-    __builtin_nontemporal_store(b, reinterpret_cast<unsigned *>(p));
+    for (int g = 0; g < N / 4; g++) {
+      const unsigned r0 = bf16x_round(o[4 * g]), r1 = bf16x_round(o[4 * g + 1]);
+      const unsigned r2 = bf16x_round(o[4 * g + 2]), r3 = bf16x_round(o[4 * g + 3]);
+      const unsigned w0 = (r0 >> 8) | (r1 & 0x0000ff00u) << 16;
+      const unsigned w1 = (r1 >> 16) | ((r2 << 8) & 0xffff0000u);
+      const unsigned w2 = (r2 >> 8 >> 16) | (r3 & 0xffffff00u);
+      unsigned *q = reinterpret_cast<unsigned *>(p) + 3 * g;
+      __builtin_nontemporal_store(w0, q);
+      __builtin_nontemporal_store(w1, q + 1);
+      __builtin_nontemporal_store(w2, q + 2);
+    }
   } else {
-    *reinterpret_cast<Vec<T, N> *>(p) = x;
+    Vec<T, N> x;
+#pragma unroll
+    for (int v = 0; v < N; v++) x.v[v] = from_f<T>(o[v]);
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(x) == 16) {
+      u4 b;
+      __builtin_memcpy(&b, &x, 16);
+      __builtin_nontemporal_store(b, reinterpret_cast<u4 *>(p));
+    } else if constexpr (sizeof(x) == 8) {
+      u2 b;
+      __builtin_memcpy(&b, &x, 8);
+      __builtin_nontemporal_store(b, reinterpret_cast<u2 *>(p));
+    } else if constexpr (sizeof(x) == 4) {
+      unsigned b;
+      __builtin_memcpy(&b, &x, 4);
+      __builtin_nontemporal_store(b, reinterpret_cast<unsigned *>(p));
+    } else {
+      *reinterpret_cast<Vec<T, N> *>(p) = x;
+    }
   }
 }
 

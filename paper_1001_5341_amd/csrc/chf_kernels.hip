@@ -1124,6 +1124,7 @@ hipError_t launch_step(const chf_plan &p, const Dev &d, int par, int step, const
   switch (p.storage) {
     case CHF_FP32: return step_t<float>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
     case CHF_BF16: return step_t<__bf16>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
+    case CHF_BF16X: return step_t<bf16x>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
     case CHF_FP16: return step_t<_Float16>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
   }
   return hipErrorInvalidValue;
@@ -1257,6 +1258,7 @@ hipError_t launch_batch_step(const chf_batch &b, int par, int step, hipStream_t 
   switch (b.storage) {
     case CHF_FP32: return batch_step_t<float>(b, par, step, s);
     case CHF_BF16: return batch_step_t<__bf16>(b, par, step, s);
+    case CHF_BF16X: return batch_step_t<bf16x>(b, par, step, s);
     case CHF_FP16: return batch_step_t<_Float16>(b, par, step, s);
   }
   return hipErrorInvalidValue;
@@ -1353,6 +1355,7 @@ hipError_t launch_get_field(const chf_plan &p, int par, int comp, float *out, hi
   switch (p.storage) {
     case CHF_FP32: return get_t<float>(p, par, comp, out, s);
     case CHF_BF16: return get_t<__bf16>(p, par, comp, out, s);
+    case CHF_BF16X: return get_t<bf16x>(p, par, comp, out, s);
     case CHF_FP16: return get_t<_Float16>(p, par, comp, out, s);
   }
   return hipErrorInvalidValue;
@@ -1362,6 +1365,7 @@ hipError_t launch_set_field(const chf_plan &p, int par, int comp, const float *i
   switch (p.storage) {
     case CHF_FP32: return set_t<float>(p, par, comp, in, s);
     case CHF_BF16: return set_t<__bf16>(p, par, comp, in, s);
+    case CHF_BF16X: return set_t<bf16x>(p, par, comp, in, s);
     case CHF_FP16: return set_t<_Float16>(p, par, comp, in, s);
   }
   return hipErrorInvalidValue;

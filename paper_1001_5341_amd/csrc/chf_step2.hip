@@ -873,6 +873,7 @@ hipError_t launch_step2(const chf_plan &p, const Dev &d, int par, int step, cons
   switch (p.storage) {
     case CHF_FP32: return step2_t<float>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
     case CHF_BF16: return step2_t<__bf16>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
+    case CHF_BF16X: return step2_t<bf16x>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
     case CHF_FP16: return step2_t<_Float16>(p, d, par, step, q, w, column, ld, s, ev_a, ev_b);
   }
   return hipErrorInvalidValue;

@@ -44,6 +44,7 @@ def test_valid_plans_accepted():
     assert _status(W.gaussian_cube(1)) == "CHF_OK"
     assert _status(W.small_shower()) == "CHF_OK"
     assert _status(W.small_shower(), storage="bf16") == "CHF_OK"
+    assert _status(W.small_shower(), storage="bf16x") == "CHF_OK"
     assert _status(W.small_shower(), kernel="split") == "CHF_OK"
 
 
@@ -201,6 +202,7 @@ def test_dynamic_scaling_validation():
     assert _status(w.replace(bc="pec", npml=0), storage="fp16", dynamic_scaling=True) == "CHF_OK"
     assert _status(w, storage="fp32", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
     assert _status(w, storage="bf16", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
+    assert _status(w, storage="bf16x", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
     assert _status(w, storage="fp16", kernel="split", dynamic_scaling=True) == "CHF_EUNSUPPORTED"
     assert _status(w, storage="fp16", waves=15, dynamic_scaling=True) == "CHF_EUNSUPPORTED"
     assert _status(W.gaussian_cube(1), storage="fp16", dynamic_scaling=True) == "CHF_EUNSUPPORTED"  # Mur
@@ -271,3 +273,20 @@ def test_rz_plan_info_reports_storage_and_scales():
             assert info.scale_e == 1.0 and info.scale_h == 256.0
         if storage == "fp16":
             assert np.log2(info.scale_e) == int(np.log2(info.scale_e)) and info.scale_h == 256.0 * info.scale_e
+
+
+def test_bf16x_plan_layout():
+    """3 bytes per stored value: the field region is 12 arrays of 3-byte elements, the interior
+    sweep's algorithmic bytes 36 per node plus the x-layer psi; FP32's range, so unit scales as
+    BF16 has."""
+    h = solver.create_plan_handle(W.single_shower(), storage="bf16x")
+    try:
+        info = N.PlanInfo()
+        assert N.lib().chf_plan_get_info(h, ct.byref(info)) == 0
+        assert info.storage == 3 and info.pitch == 256
+        assert info.field_bytes == 12 * 256 * 256 * 2048 * 3
+        assert abs(info.fused_bytes_per_cell - (36 + 32 * 20 / 256)) < 1e-9
+        assert info.scale_e == 1.0
+    finally:
+        N.lib().chf_plan_destroy(h)
+    assert _rz_status(W.rz_small(), storage="bf16x") == "CHF_EINVAL"  # the (r, z) scheme does not take it

@@ -84,7 +84,7 @@ def test_tile_shape_invariance_bitwise(gpu, shower, waves, zchunk):
     assert np.array_equal(got, base)
 
 
-@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16", "bf16x"])
 def test_prefetching_sweep_bitwise(gpu, storage):
     """The sweep whose interior tiles load a plane ahead gives the plain fused sweep's bits:
     waveforms and all six final fields, for one to four nodes per lane, rows of 257-512 nodes

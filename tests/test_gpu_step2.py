@@ -96,7 +96,7 @@ def test_two_step_equals_one_step_fp32(gpu, label, w, tiles):
         assert np.all(err <= TOL_FP32), err
 
 
-@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+@pytest.mark.parametrize("storage", ["bf16", "fp16", "bf16x"])
 def test_two_step_equals_one_step_16bit(gpu, storage):
     w = W.small_shower(seed=11)
     banner(f"16-bit {storage}")

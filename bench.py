@@ -603,7 +603,8 @@ def batch_summary():
     """Batched configuration: 32 showers of uneven grids (96^3 ... 256x256x1024, CPML-10, 16
     observers each, 2000 steps) advanced together in one hipGraph per run (chf_batch_run), with
     autotuned tile shapes (one waves_per_block for all members, z chunk per member).  One warm-up
-    run (it also captures the graph), then one timed run."""
+    run (it also captures the graph), then one timed run; then the same for the persistent
+    cooperative launch (chf_batch_run_persistent), compared bit for bit."""
     import torch
 
     from paper_1001_5341_amd import autotune, solver
@@ -625,6 +626,16 @@ def batch_summary():
         finite = all(bool(torch.isfinite(o).all()) for o in outs)
         alg = sum(p.info()["bytes_per_cell_update"] * w.n_cells for p, w in zip(plans, ws))
         acc = batch_accuracy(ws, outs)
+        # the same run as one persistent cooperative launch (every tile through the general fused
+        # sweep, grid barriers between phases): same bits, timed after one warm-up run
+        pouts = [p.new_waveforms() for p in plans]
+        batch.run(pouts, persistent=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.run(pouts, persistent=True)
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t0
+        same = all(bool(torch.equal(a, b)) for a, b in zip(pouts, outs))
     finally:
         batch.close()
         for p in plans:
@@ -638,7 +649,10 @@ def batch_summary():
             "whole_step_bytes_per_cell": round(alg / cells, 3),
             "achieved_gbs": round(alg * T / wall / 1e9, 1),
             "frac": round(alg * T / wall / 1e9 / HBM_PEAK_GBS, 4), "finite": finite,
-            "accuracy_vs_fp64_oracle": acc}
+            "accuracy_vs_fp64_oracle": acc,
+            "persistent_launch": {"value": round(cells * T / pwall / 1e6, 1), "ms_per_run": round(pwall * 1e3, 1),
+                                  "frac": round(alg * T / pwall / 1e9 / HBM_PEAK_GBS, 4),
+                                  "bitwise_equal_to_graph": same}}
 
 
 def rz_summary(n: int = 8192, n_steps: int = 2048):

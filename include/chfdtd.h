@@ -352,6 +352,18 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out);
 chf_status chf_batch_workspace_bytes(const chf_batch *batch, uint64_t *bytes);
 chf_status chf_batch_bind_workspace(chf_batch *batch, void *device_ptr, uint64_t bytes, void *stream);
 chf_status chf_batch_run(chf_batch *batch, void *stream, double *const *waveforms_dev);
+
+/* The same run as chf_batch_run in ONE persistent cooperative kernel launch (batching of many
+   showers as one launch; the Parallelization with GPU section's host loop over kernels moved onto
+   the device): every workgroup that fits the GPU at once loops over the Yee steps, taking tiles of
+   every member from one combined table (interior and boundary tiles alike, through the general
+   fused sweep), then the workgroups meet at a grid barrier, inject every member's source, meet
+   again and gather the observers.  Same waveforms and fields, bit for bit, as chf_batch_run.
+   FP32 members with PEC or CPML walls whose boundary tiles fit the general fused sweep (rows of at
+   most 256 nodes, at most 11 rows per tile), else CHF_EUNSUPPORTED; a launch the device cannot
+   hold at once fails with CHF_EHIP.  Allocates nothing; the captured graph of chf_batch_run is
+   kept unless the waveform pointers change. */
+chf_status chf_batch_run_persistent(chf_batch *batch, void *stream, double *const *waveforms_dev);
 void chf_batch_destroy(chf_batch *batch);
 
 /* Measurement aid (not part of the solver): copies `bytes` (a multiple of 16) from src_dev to

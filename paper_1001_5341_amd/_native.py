@@ -26,7 +26,8 @@ EXPORTED = [
     "chf_plan_save_state",
     "chf_plan_load_state", "chf_plan_sync",
     "chf_plan_get_field", "chf_plan_set_field", "chf_plan_get_info", "chf_batch_create",
-    "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_destroy",
+    "chf_batch_workspace_bytes", "chf_batch_bind_workspace", "chf_batch_run", "chf_batch_run_persistent",
+    "chf_batch_destroy",
     "chf_status_str", "chf_last_error", "chf_abi_version", "chf_forward_scratch", "chf_scratch_bytes",
     "chf_stream_copy",
     "chf_rz_plan_create", "chf_rz_plan_destroy", "chf_rz_workspace_bytes", "chf_rz_bind_workspace",
@@ -199,6 +200,8 @@ def lib():
         L.chf_batch_bind_workspace.argtypes = [vp, vp, ct.c_uint64, vp]
         L.chf_batch_run.restype = ct.c_int
         L.chf_batch_run.argtypes = [vp, vp, ct.POINTER(vp)]
+        L.chf_batch_run_persistent.restype = ct.c_int
+        L.chf_batch_run_persistent.argtypes = [vp, vp, ct.POINTER(vp)]
         L.chf_batch_destroy.restype = None
         L.chf_batch_destroy.argtypes = [vp]
         L.chf_status_str.restype = ct.c_char_p

@@ -1323,6 +1323,12 @@ chf_status chf_batch_create(int32_t n, chf_plan *const *plans, chf_batch **out) 
     b->off_gen[c] = off;
     off += align256(std::max<size_t>(b->gen_tab[c].size(), 1) * sizeof(int));
   }
+  // the persistent launch's work list: interior tiles, then boundary tiles of both classes
+  b->all_tab = b->fast_tab;
+  b->all_tab.insert(b->all_tab.end(), b->gen_tab[0].begin(), b->gen_tab[0].end());
+  b->all_tab.insert(b->all_tab.end(), b->gen_tab[1].begin(), b->gen_tab[1].end());
+  b->off_all = off;
+  off += align256(std::max<size_t>(b->all_tab.size(), 1) * sizeof(int));
   b->off_obs = off;
   off += align256(std::max<size_t>(b->obs_tab.size(), 1) * sizeof(int));
   b->off_wptr = off;
@@ -1356,6 +1362,7 @@ chf_status chf_batch_bind_workspace(chf_batch *b, void *dev_ptr, uint64_t bytes,
       {b->off_gen[0], b->gen_tab[0].data(), b->gen_tab[0].size() * sizeof(int)},
       {b->off_gen[1], b->gen_tab[1].data(), b->gen_tab[1].size() * sizeof(int)},
       {b->off_obs, b->obs_tab.data(), b->obs_tab.size() * sizeof(int)},
+      {b->off_all, b->all_tab.data(), b->all_tab.size() * sizeof(int)},
   };
   for (const Up &u : ups) {
     if (!u.n) continue;
@@ -1424,6 +1431,40 @@ chf_status chf_batch_run(chf_batch *b, void *stream, double *const *w) {
   }
   hipError_t e = hipGraphLaunch(b->graph, s);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
+  for (chf_plan *p : b->plans) {
+    p->parity = b->n_steps & 1;
+    p->n_done = b->n_steps;
+  }
+  return CHF_OK;
+}
+
+chf_status chf_batch_run_persistent(chf_batch *b, void *stream, double *const *w) {
+  if (!b || !w) return fail(CHF_EINVAL, "NULL argument");
+  if (!b->ws) return fail(CHF_ESTATE, "no batch workspace bound");
+  if (b->storage != CHF_FP32 || !b->gen || b->any_mur)
+    return fail(CHF_EUNSUPPORTED, "the persistent batch launch takes FP32 members with PEC or CPML walls whose "
+                                  "boundary tiles fit the general fused sweep (rows of at most 256 nodes, at most 11 "
+                                  "rows per tile)");
+  hipStream_t s = (hipStream_t)stream;
+  bool same = true;
+  for (size_t i = 0; i < b->plans.size(); i++) same = same && b->wptr[i] == w[i];
+  if (!same) {
+    if (b->graph) {  // the captured per-phase graph holds the old pointers
+      (void)hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    for (size_t i = 0; i < b->plans.size(); i++) b->wptr[i] = w[i];
+    hipError_t e = hipMemcpyAsync(b->ws + b->off_wptr, b->wptr.data(), b->wptr.size() * sizeof(double *),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "upload of waveform pointers");
+  }
+  hipError_t e = hipSuccess;
+  for (chf_plan *p : b->plans)
+    if (e == hipSuccess) e = chf::launch_zero(*p, s);
+  if (e == hipSuccess)
+    e = chf::launch_batch_persistent(*b, (const int *)(b->ws + b->off_all), (int)(b->all_tab.size() / 3), s);
+  if (e != hipSuccess) return hip_fail(e, "persistent batch launch");
   for (chf_plan *p : b->plans) {
     p->parity = b->n_steps & 1;
     p->n_done = b->n_steps;

@@ -343,8 +343,8 @@ __device__ __forceinline__ double source_q(const Dev &d, const double *q, double
 // lane forms weight * E in FP64, then a butterfly over the 8 corners sums each component; lanes
 // 0, 8, 16 write.
 template <typename T>
-__device__ __forceinline__ void gather_body(const Dev &d, int par, double *w, int column, int ld, int o) {
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void gather_body(const Dev &d, int par, double *w, int column, int ld, int o,
+                                            int lane = threadIdx.x) {
   const int comp = lane >> 3, corner = lane & 7;
   double val = 0.0;
   if (comp < 3) {

@@ -188,6 +188,8 @@ struct chf_batch {
   std::vector<int> obs_tab;   // (plan, observer)
   uint64_t off_devs = 0, off_z = 0, off_fast = 0, off_slow = 0, off_obs = 0, off_wptr = 0, ws_bytes = 0;
   uint64_t off_gen[2] = {0, 0};
+  std::vector<int> all_tab;  // (plan, ty, zc) over every tile: the persistent launch's work list
+  uint64_t off_all = 0;
   char *ws = nullptr;
   std::vector<chf::Dev> devs;
   std::vector<double *> wptr;
@@ -235,6 +237,9 @@ hipError_t launch_adjoint_step(const chf_plan &p, const Dev &d, int parity, int 
 hipError_t launch_adjoint_init(const chf_plan &p, double *dl_dq, hipStream_t s, int n = -1);
 hipError_t launch_adjoint_clear(const chf_plan &p, hipStream_t s);
 hipError_t launch_batch_step(const chf_batch &b, int parity, int step, hipStream_t s);
+// the whole batch run in one cooperative launch over the combined tile table `tab` (device,
+// n_tab entries of (plan, ty, zc)); FP32 members with boundary tiles in the general fused sweep
+hipError_t launch_batch_persistent(const chf_batch &b, const int *tab, int n_tab, hipStream_t s);
 void set_error(const std::string &msg);
 // plan tables into a workspace (chf_api.hip)
 hipError_t bind_tables(chf_plan *p, char *ws, hipStream_t s);

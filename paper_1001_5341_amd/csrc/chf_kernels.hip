@@ -18,9 +18,11 @@
 //     Ez = ca*Ez + cex*(Hy[i]-Hy[i-1]) - cey*(Hx[j]-Hx[j-1])
 //   with chu = Db/(du kappa_u) and ceu = Cb/(du kappa_u) folded with the storage scales, and
 //   the CFS-CPML recursion psi <- b psi + a d  (a prescaled the same way).
-#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "chf_cell.h"
@@ -1252,6 +1254,83 @@ static hipError_t batch_step_t(const chf_batch &b, int par, int step, hipStream_
                        (double *const *)(b.ws + b.off_wptr), (const int *)(b.ws + b.off_obs), par ^ 1, step,
                        b.n_steps);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ persistent batch launch
+// The whole batch run in one cooperative launch: every resident workgroup loops over the Yee
+// steps; per step it takes tiles of every member from the combined table (interior and boundary
+// alike, through the general fused sweep, whose per-node arithmetic is the canonical one, so the
+// results equal the per-phase launches bit for bit), then all workgroups meet at a grid barrier,
+// inject the sources of every member, meet again, and gather the observers (one wave each; the
+// gathers read the level the next step only reads, so no barrier follows them).  Every loop is
+// bounded and every workgroup passes every barrier.
+template <int VX, int W>
+__global__ void __launch_bounds__(64 * (W + 1)) k_batch_persistent(const Dev *devs, const int *zchunks, const int *tab,
+                                                                   int n_tab, const int *obs, int n_obs,
+                                                                   double *const *waves, int n_plans, int max_patch,
+                                                                   int n_steps) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63, wave = gt >> 6, n_waves = gs >> 6;
+  for (int step = 0; step < n_steps; step++) {
+    const int par = step & 1;
+    for (int t = blockIdx.x; t < n_tab; t += gridDim.x) {
+      const int *e = tab + 3 * t;
+      fused_body<float, VX, W, 2, false>(devs[e[0]], e[1], e[2], zchunks[e[0]], par);
+      __syncthreads();  // the tile's LDS rows and tables before the next tile overwrites them
+    }
+    grid.sync();
+    for (int u = gt; u < n_plans * max_patch; u += gs) {
+      const Dev &d = devs[u / max_patch];
+      (void)source_body<float>(d, par ^ 1, step, d.q_bins, u % max_patch);
+    }
+    grid.sync();
+    for (int o = wave; o < n_obs; o += n_waves) {
+      const int pl = obs[2 * o];
+      gather_body<float>(devs[pl], par ^ 1, waves[pl], step, n_steps, obs[2 * o + 1], lane);
+    }
+  }
+}
+
+template <int VX, int W>
+static hipError_t persistent_launch(const chf_batch &b, const int *tab, int n_tab, hipStream_t s) {
+  const void *fn = reinterpret_cast<const void *>(&k_batch_persistent<VX, W>);
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * (W + 1), 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  // every workgroup resident at once (the cooperative launch checks it), no more than there are tiles
+  const int grid = std::max(1, std::min(cus * per_cu, n_tab));
+  const Dev *devs = (const Dev *)(b.ws + b.off_devs);
+  const int *z = (const int *)(b.ws + b.off_z);
+  const int *obs = (const int *)(b.ws + b.off_obs);
+  double *const *waves = (double *const *)(b.ws + b.off_wptr);
+  int n_obs = b.total_obs, n_plans = (int)b.plans.size(), max_patch = b.max_patch, n_steps = b.n_steps;
+  void *args[] = {(void *)&devs, (void *)&z, (void *)&tab, (void *)&n_tab, (void *)&obs, (void *)&n_obs,
+                  (void *)&waves, (void *)&n_plans, (void *)&max_patch, (void *)&n_steps};
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(64 * (W + 1)), args, 0, s);
+}
+
+hipError_t launch_batch_persistent(const chf_batch &b, const int *tab, int n_tab, hipStream_t s) {
+  if (b.storage != CHF_FP32) return hipErrorInvalidValue;
+  switch (b.vx * 100 + b.waves) {
+    case 104: return persistent_launch<1, 4>(b, tab, n_tab, s);
+    case 107: return persistent_launch<1, 7>(b, tab, n_tab, s);
+    case 108: return persistent_launch<1, 8>(b, tab, n_tab, s);
+    case 111: return persistent_launch<1, 11>(b, tab, n_tab, s);
+    case 204: return persistent_launch<2, 4>(b, tab, n_tab, s);
+    case 207: return persistent_launch<2, 7>(b, tab, n_tab, s);
+    case 208: return persistent_launch<2, 8>(b, tab, n_tab, s);
+    case 211: return persistent_launch<2, 11>(b, tab, n_tab, s);
+    case 404: return persistent_launch<4, 4>(b, tab, n_tab, s);
+    case 407: return persistent_launch<4, 7>(b, tab, n_tab, s);
+    case 408: return persistent_launch<4, 8>(b, tab, n_tab, s);
+    case 411: return persistent_launch<4, 11>(b, tab, n_tab, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_step(const chf_batch &b, int par, int step, hipStream_t s) {

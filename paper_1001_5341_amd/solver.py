@@ -279,11 +279,14 @@ class Batch:
         N.check(L.chf_batch_bind_workspace(self._h, ct.c_void_p(self.workspace.data_ptr()), int(nbytes.value),
                                            _stream_handle()), "chf_batch_bind_workspace")
 
-    def run(self, outs=None, stream=None, sync=True):
+    def run(self, outs=None, stream=None, sync=True, persistent=False):
+        """The whole batch run from zero fields: one captured graph of per-phase launches, or
+        (persistent=True) one cooperative kernel launch looping over the steps."""
         outs = outs or [p.new_waveforms() for p in self.plans]
         ptrs = (ct.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
         self._ptrs = ptrs
-        N.check(N.lib().chf_batch_run(self._h, _stream_handle(stream), ptrs), "chf_batch_run")
+        fn = "chf_batch_run_persistent" if persistent else "chf_batch_run"
+        N.check(getattr(N.lib(), fn)(self._h, _stream_handle(stream), ptrs), fn)
         if sync:
             for p in self.plans:
                 p.sync(stream)

@@ -97,3 +97,42 @@ def test_batch_rejects_mismatched_steps(gpu):
     with pytest.raises(_native.ChfError) as e:
         solver.Batch([a, b])
     assert e.value.status == "CHF_EINVAL"
+
+
+@pytest.mark.parametrize("waves", [7, 11])
+def test_persistent_batch_equals_graph_batch(gpu, waves):
+    """The whole batch run in one persistent cooperative launch (every tile through the general
+    fused sweep, grid barriers between the phases) gives the per-phase graph's bits: waveforms
+    and all six final fields of every member, twice in a row."""
+    ws = members()[:4]  # the persistent launch takes PEC and CPML members
+    print(f"\n[gpu-batch] persistent, {waves}-row tiles", flush=True)
+    plans = [solver.Plan(w, kernel="fused", waves=waves) for w in ws]
+    batch = solver.Batch(plans)
+    ref = [o.cpu().numpy() for o in batch.run()]
+    ref_f = [[p.get_field(c).cpu().numpy() for c in range(6)] for p in plans]
+    for rep in range(2):
+        got = [o.cpu().numpy() for o in batch.run(persistent=True)]
+        for m, (a, b) in enumerate(zip(got, ref)):
+            assert np.array_equal(a, b), (rep, m)
+        for m, p in enumerate(plans):
+            for c in range(6):
+                assert np.array_equal(p.get_field(c).cpu().numpy(), ref_f[m][c]), (rep, m, c)
+    # the captured graph still replays after the persistent runs
+    again = [o.cpu().numpy() for o in batch.run()]
+    for a, b in zip(again, ref):
+        assert np.array_equal(a, b)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_persistent_batch_rejects_unsupported_members(gpu):
+    ws = members()  # includes a Mur member
+    plans = [solver.Plan(w) for w in ws]
+    batch = solver.Batch(plans)
+    with pytest.raises(_native.ChfError) as e:
+        batch.run(persistent=True)
+    assert e.value.status == "CHF_EUNSUPPORTED"
+    batch.close()
+    for p in plans:
+        p.close()

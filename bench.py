@@ -139,7 +139,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
     print(json.dumps(rec))
 
 
-def cpu_baseline(w, n_steps: int = 600):
+def cpu_baseline(w, n_steps: int = 300):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: a 256x256x256 sub-grid
     (same spacing, medium, CPML and shower source; 8 observers placed inside it) for n_steps."""
     import oracle
@@ -154,7 +154,7 @@ def cpu_baseline(w, n_steps: int = 600):
     rate = sub.n_cells * sub.n_steps / dt / 1e6
     cores = oracle.threads()
     # one thread, as the paper's sequential CPU code ran (a shorter sample of the same grid)
-    one = sub.replace(n_steps=20)
+    one = sub.replace(n_steps=8)
     oracle.set_threads(1)
     try:
         t0 = time.perf_counter()

@@ -195,25 +195,33 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
     delete p;
     return fail(CHF_EUNSUPPORTED, "one x-y plane must hold fewer than 2^31 nodes");
   }
-  fs.nty = (G.ny + fs.waves - 1) / fs.waves;
-  fs.nzc = (G.nz + fs.zchunk - 1) / fs.zchunk;
-  fs.n_tiles = fs.nty * fs.nzc;
-  fs.n_blocks = (fs.n_tiles + 7) / 8 * 8;
   {
     // fast rectangle: every row of the tile and the row below it lie in [fy0, fy1], every plane
     // of the chunk in [fz0, fz1], where [f0, f1] are the nodes with no wall and no layer term
-    // (integer and half positions alike); all other tiles go to the split sweeps
+    // (integer and half positions alike); all other tiles go to the boundary sweeps.  The tile
+    // grid is shifted (tile ty from row ty*W - ysh, chunk zc from plane zc*Z - zsh) so that the
+    // rectangle starts at row fy0 + 1 and plane fz0: the boundary sweeps, which cost more per
+    // node, then cover only the walls and layers and less than one tile or chunk beyond them.
     const int nl = bnd->kind == CHF_BC_CPML ? bnd->npml : 0;
     const int fy0 = std::max(1, nl), fy1 = G.ny - 2 - nl;
     const int fz0 = std::max(1, nl), fz1 = G.nz - 2 - nl;
     const int W = fs.waves, Z = fs.zchunk;
-    fs.ty_lo = (fy0 + 1 + W - 1) / W;          // j0 - 1 >= fy0
-    fs.ty_hi = (fy1 + 1) / W;                  // j0 + W - 1 <= fy1
-    fs.zc_lo = (fz0 + Z - 1) / Z;              // k0 >= fz0
-    fs.zc_hi = (fz1 + 1) / Z;                  // k1 - 1 <= fz1
-    if (kernel != CHF_KERNEL_FUSED || fs.ty_hi <= fs.ty_lo || fs.zc_hi <= fs.zc_lo ||
-        2 * nl > chf::kMaxFusedLayer)
+    for (int shifted = 1; shifted >= 0; shifted--) {
+      fs.ysh = shifted ? (W - (fy0 + 1) % W) % W : 0;
+      fs.zsh = shifted ? (Z - fz0 % Z) % Z : 0;
+      fs.ty_lo = (fy0 + 1 + fs.ysh + W - 1) / W;  // j0 - 1 >= fy0
+      fs.ty_hi = (fy1 + 1 + fs.ysh) / W;          // j0 + W - 1 <= fy1
+      fs.zc_lo = (fz0 + fs.zsh + Z - 1) / Z;      // k0 >= fz0
+      fs.zc_hi = (fz1 + 1 + fs.zsh) / Z;          // k1 - 1 <= fz1
+      const bool rect = kernel == CHF_KERNEL_FUSED && fs.ty_hi > fs.ty_lo && fs.zc_hi > fs.zc_lo &&
+                        2 * nl <= chf::kMaxFusedLayer && fy1 >= fy0 && fz1 >= fz0;
+      if (rect) break;
       fs.ty_lo = fs.ty_hi = fs.zc_lo = fs.zc_hi = 0;
+    }
+    fs.nty = (G.ny + fs.ysh + fs.waves - 1) / fs.waves;
+    fs.nzc = (G.nz + fs.zsh + fs.zchunk - 1) / fs.zchunk;
+    fs.n_tiles = fs.nty * fs.nzc;
+    fs.n_blocks = (fs.n_tiles + 7) / 8 * 8;
     fs.n_fast = (fs.ty_hi - fs.ty_lo) * (fs.zc_hi - fs.zc_lo);
     fs.fast_blocks = (fs.n_fast + 7) / 8 * 8;
     fs.n_layer = fs.layer_blocks = 0;
@@ -258,25 +266,33 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
       return fail(CHF_EINVAL, "the two-step sweep takes waves_per_block 4, 7 or 8");
     }
     const int W = f2.waves, Z = f2.zchunk;
-    f2.nty = (G.ny + W - 1) / W;
-    f2.nzc = (G.nz + Z - 1) / Z;
     // rectangle: computed rows j0-2 .. j0+W within [fy0, fy1], stage planes k0-2 .. k1 within
-    // [fz0, fz1] (nodes with no wall and no layer term)
+    // [fz0, fz1] (nodes with no wall and no layer term); rectangle tile ty owns rows from
+    // ty*W - ysh and chunk zc planes from zc*Z - zsh, the shifts chosen so that the rectangle
+    // starts at row fy0 + 2 and plane fz0 + 2 (the boundary tiles, which recompute halo rows,
+    // then cover only the walls and layers and less than one tile or chunk beyond them)
     const int fy0 = std::max(1, nl), fy1 = G.ny - 2 - nl;
     const int fz0 = std::max(1, nl), fz1 = G.nz - 2 - nl;
-    f2.ty_lo = (fy0 + 2 + W - 1) / W;
-    f2.ty_hi = fy1 - W >= 0 ? (fy1 - W) / W + 1 : 0;
-    f2.zc_lo = (fz0 + 2 + Z - 1) / Z;
-    f2.zc_hi = fz1 - Z >= 0 ? (fz1 - Z) / Z + 1 : 0;
-    f2.ty_hi = std::min(f2.ty_hi, f2.nty);
-    f2.zc_hi = std::min(f2.zc_hi, f2.nzc);
-    if (f2.ty_hi <= f2.ty_lo || f2.zc_hi <= f2.zc_lo) f2.ty_lo = f2.ty_hi = f2.zc_lo = f2.zc_hi = 0;
+    for (int shifted = 1; shifted >= 0; shifted--) {
+      f2.ysh = shifted ? (W - (fy0 + 2) % W) % W : 0;
+      f2.zsh = shifted ? (Z - (fz0 + 2) % Z) % Z : 0;
+      f2.nty = (G.ny + f2.ysh + W - 1) / W;
+      f2.nzc = (G.nz + f2.zsh + Z - 1) / Z;
+      f2.ty_lo = (fy0 + 2 + f2.ysh + W - 1) / W;                           // j0 - 2 >= fy0
+      f2.ty_hi = fy1 - W + f2.ysh >= 0 ? (fy1 - W + f2.ysh) / W + 1 : 0;  // j0 + W <= fy1
+      f2.zc_lo = (fz0 + 2 + f2.zsh + Z - 1) / Z;                           // k0 - 2 >= fz0
+      f2.zc_hi = fz1 - Z + f2.zsh >= 0 ? (fz1 - Z + f2.zsh) / Z + 1 : 0;  // k1 <= fz1
+      f2.ty_hi = std::min(f2.ty_hi, f2.nty);
+      f2.zc_hi = std::min(f2.zc_hi, f2.nzc);
+      if (f2.ty_hi > f2.ty_lo && f2.zc_hi > f2.zc_lo) break;
+      f2.ty_lo = f2.ty_hi = f2.zc_lo = f2.zc_hi = 0;
+    }
     f2.n_fast = (f2.ty_hi - f2.ty_lo) * (f2.zc_hi - f2.zc_lo);
     f2.fast_blocks = (f2.n_fast + 7) / 8 * 8;
     // boundary tiles of kStep2BoundaryRows rows: the rows below and above the rectangle in its z
     // range, then every row of the other chunks
     const int B = chf::kStep2BoundaryRows;
-    const int ya = f2.ty_lo * W, yb = f2.ty_hi * W;
+    const int ya = f2.ty_lo * W - f2.ysh, yb = f2.ty_hi * W - f2.ysh;
     auto cover = [&](int zc, int lo, int hi) {
       for (int j0 = lo; j0 < hi; j0 += B) {
         p->tiles2.push_back(j0);
@@ -609,6 +625,8 @@ chf_status chf_plan_create(const chf_grid *grid, const chf_medium *medium, const
   D.npml = npml;
   D.np2 = np2;
   D.plane = (long long)pitch * G.ny;
+  D.ysh = p->fs.ysh;
+  D.zsh = p->fs.zsh;
   D.ca = (float)p->ca;
   D.se = (float)p->scale_e;
   D.sh = (float)p->scale_h;

@@ -35,6 +35,10 @@ struct AxisTab {
 // Everything a kernel needs, passed by value.
 struct Dev {
   int nx, ny, nz, pitch, npml, np2;
+  // origin of the one-step tile grid: tile ty holds rows from ty*W - ysh, chunk zc planes from
+  // zc*Z - zsh (clipped to the grid), so that the interior rectangle starts at the first row and
+  // plane clear of walls and layers
+  int ysh, zsh;
   long long plane;           // pitch*ny
   float ca;
   // field arrays, [time level][component]; element type depends on the storage
@@ -101,6 +105,7 @@ struct FusedShape {
   int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_layer, layer_blocks, n_slow, slow_blocks;
   int n_slow_y;  // leading entries of the tile table whose planes lie in [zc_lo, zc_hi) chunks
   int prefetch;  // interior tiles issue each plane's loads one plane ahead
+  int ysh, zsh;  // tile grid origin (rows from ty*waves - ysh, planes from zc*zchunk - zsh)
   int xs;        // waves per row: 2 splits rows of 257-512 nodes (prefetching sweep, VX 4)
 };
 
@@ -112,6 +117,7 @@ struct FusedShape {
 struct Shape2 {
   int on, vx, xs, waves, zchunk, nty, nzc;
   int ty_lo, ty_hi, zc_lo, zc_hi, n_fast, fast_blocks, n_slow, n_slow_y;
+  int ysh, zsh;  // grid origin: rectangle tile ty owns rows from ty*waves - ysh, chunk zc planes from zc*zchunk - zsh
 };
 
 }  // namespace chf

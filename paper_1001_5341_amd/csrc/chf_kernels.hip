@@ -108,14 +108,14 @@ __device__ __forceinline__ void fused_body(const Dev &d, int ty, int zc, int zch
   const int wv = threadIdx.x >> 6;
   const int r = wv / XS, xs = wv - r * XS;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const int j0 = ty * W;
+  const int j0 = ty * W - d.ysh;
   const int j = j0 - 1 + r;
   constexpr bool GY = G >= 1, GZ = G >= 2;
   const bool act = !GY || (j >= 0 && j < ny);  // row exists (always, in the interior rectangle)
   const int jc = G ? min(max(j, 0), ny - 1) : j;
   const bool own = r > 0 && act, top = r == W;
   const bool top_ld = top && (!GY || j + 1 < ny);
-  const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
+  const int k0 = max(zc * zchunk - d.zsh, 0), k1 = min(zc * zchunk - d.zsh + zchunk, nz);
   const int ib = xs * 64 * VX + lane * VX;
   const bool on = ib < nx && act;
   // x-slab psi slots this wave writes back: those whose node lies in its segment
@@ -672,7 +672,7 @@ __device__ __forceinline__ void split_e_body(const Dev &d, int i, int j, int k0,
 
 template <typename T>
 __device__ __forceinline__ void split_h_body(const Dev &d, int i, int j, int k0, int k1, int par) {
-  if (i >= d.nx || j >= d.ny) return;
+  if (i >= d.nx || j < 0 || j >= d.ny) return;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const T *E0 = (const T *)d.e[par][0], *E1 = (const T *)d.e[par][1], *E2 = (const T *)d.e[par][2];
   const T *Hi0 = (const T *)d.h[par][0], *Hi1 = (const T *)d.h[par][1], *Hi2 = (const T *)d.h[par][2];
@@ -730,7 +730,7 @@ __device__ __forceinline__ void split_h_body(const Dev &d, int i, int j, int k0,
 
 template <typename T>
 __device__ __forceinline__ void split_e_body(const Dev &d, int i, int j, int k0, int k1, int par) {
-  if (i >= d.nx || j >= d.ny) return;
+  if (i >= d.nx || j < 0 || j >= d.ny) return;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const T *Ei0 = (const T *)d.e[par][0], *Ei1 = (const T *)d.e[par][1], *Ei2 = (const T *)d.e[par][2];
   const T *H0 = (const T *)d.h[par ^ 1][0], *H1 = (const T *)d.h[par ^ 1][1], *H2 = (const T *)d.h[par ^ 1][2];
@@ -788,8 +788,8 @@ __global__ void __launch_bounds__(1024) k_split(Dev d, FusedShape fs, const int 
   if (tile >= n_tiles) return;
   const int ty = tiles[2 * tile], zc = tiles[2 * tile + 1];
   const int i = (blockIdx.x % nxb) * 64 + (threadIdx.x & 63);
-  const int j = ty * fs.waves + (threadIdx.x >> 6);
-  const int k0 = zc * fs.zchunk, k1 = min(k0 + fs.zchunk, d.nz);
+  const int j = ty * fs.waves - d.ysh + (threadIdx.x >> 6);
+  const int k0 = max(zc * fs.zchunk - d.zsh, 0), k1 = min(zc * fs.zchunk - d.zsh + fs.zchunk, d.nz);
   if constexpr (H) split_h_body<T>(d, i, j, k0, k1, par);
   else split_e_body<T>(d, i, j, k0, k1, par);
 }
@@ -803,8 +803,8 @@ __global__ void __launch_bounds__(1024) k_split_batch(const Dev *devs, const int
   const Dev &d = devs[e[0]];
   const int zchunk = zchunks[e[0]];
   const int i = e[3] * 64 + (threadIdx.x & 63);
-  const int j = e[1] * rows + (threadIdx.x >> 6);
-  const int k0 = e[2] * zchunk, k1 = min(k0 + zchunk, d.nz);
+  const int j = e[1] * rows - d.ysh + (threadIdx.x >> 6);
+  const int k0 = max(e[2] * zchunk - d.zsh, 0), k1 = min(e[2] * zchunk - d.zsh + zchunk, d.nz);
   if constexpr (H) split_h_body<T>(d, i, j, k0, k1, par);
   else split_e_body<T>(d, i, j, k0, k1, par);
 }

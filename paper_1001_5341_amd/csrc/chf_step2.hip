@@ -106,7 +106,7 @@ __device__ __forceinline__ void src_apply(const Dev &d, const SrcLds &S, int st,
 // and its samples work in the units of the level written (chosen for both steps); the wave's
 // largest stored magnitudes raise that level's maxima.
 template <typename T, int VX, int W, int XS, int G, bool DYN = false>
-__device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int zc, int zchunk, int par, int step,
+__device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int k0, int k1, int par, int step,
                                            const double *q) {
   constexpr int NR = W + 3;  // computed rows: j0-2 .. j0+W; row NR (j0+W+1) is only loaded
   constexpr int SEG = 64 * VX, NL = SEG * XS;
@@ -137,7 +137,6 @@ __device__ __forceinline__ void step2_body(const Dev &d, int j0, int jend, int z
   const int jc = GY ? min(max(j, 0), ny - 1) : j;
   const bool doH1 = act && !loader;
   const bool doE1 = r >= 1 && act && !loader, doH2 = r >= 1 && r <= W + 1 && act, own = r >= 2 && r <= W + 1 && act && j < jend;
-  const int k0 = zc * zchunk, k1 = min(k0 + zchunk, nz);
   const int ib = xs * SEG + lane * VX;
   float dyn_r = 1.f, dyn_me = 0.f, dyn_mh = 0.f;
   int dyn_e = 0;  // exponent of the written level
@@ -737,8 +736,9 @@ __global__ void __launch_bounds__(64 * (W + 4) * XS) k_step2(Dev d, Shape2 f2, i
   const int logical = xcd_logical();
   if (logical >= f2.n_fast) return;
   const int fw = f2.ty_hi - f2.ty_lo;
-  const int j0 = (f2.ty_lo + logical % fw) * W;
-  step2_body<T, VX, W, XS, 0, DYN>(d, j0, j0 + W, f2.zc_lo + logical / fw, f2.zchunk, par, step, q);
+  const int j0 = (f2.ty_lo + logical % fw) * W - f2.ysh;
+  const int k0 = (f2.zc_lo + logical / fw) * f2.zchunk - f2.zsh;
+  step2_body<T, VX, W, XS, 0, DYN>(d, j0, j0 + W, k0, k0 + f2.zchunk, par, step, q);
 }
 
 // Boundary tiles of kStep2BoundaryRows rows from the table (first row, end of the rows the tile
@@ -750,7 +750,8 @@ __global__ void __launch_bounds__(64 * (kStep2BoundaryRows + 4) * XS)
   const int logical = xcd_logical();
   if (logical >= n) return;
   const int *t = tiles + 3 * logical;
-  step2_body<T, VX, kStep2BoundaryRows, XS, G, DYN>(d, t[0], t[1], t[2], f2.zchunk, par, step, q);
+  const int k0 = t[2] * f2.zchunk - f2.zsh;
+  step2_body<T, VX, kStep2BoundaryRows, XS, G, DYN>(d, t[0], t[1], max(k0, 0), min(k0 + f2.zchunk, d.nz), par, step, q);
 }
 
 template <typename T>

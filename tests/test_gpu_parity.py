@@ -82,6 +82,12 @@ def test_tile_shape_invariance_bitwise(gpu, shower, waves, zchunk):
     got, info = gpu_run(w, kernel="fused", waves=waves, zchunk=zchunk)
     assert (info["waves_per_block"], info["z_chunk"]) == (waves, zchunk)
     assert np.array_equal(got, base)
+    # the interior rectangle starts at the first row (whose row below is clear) and the first
+    # plane clear of walls and layers, so it holds every whole tile and chunk that fits there
+    nl = w.npml if w.bc == "cpml" else 0
+    fy0, fy1, fz0, fz1 = max(1, nl), w.ny - 2 - nl, max(1, nl), w.nz - 2 - nl
+    ty, tz = (fy1 - fy0) // waves, (fz1 - fz0 + 1) // zchunk
+    assert info["fused_cells"] == (ty * waves * tz * zchunk * w.nx if ty > 0 and tz > 0 else 0)
 
 
 @pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16", "bf16x"])

@@ -91,6 +91,12 @@ def test_two_step_equals_one_step_fp32(gpu, label, w, tiles):
         got = run_fields(w, kernel="fused2", waves=waves, zchunk=zchunk)
         assert got[2]["kernel"] == 4 and got[2]["steps_per_launch"] == 2
         assert (got[2]["waves_per_block"], got[2]["z_chunk"]) == (waves, zchunk)
+        # the rectangle holds every whole tile and chunk whose computed rows (two below, one
+        # above) and staged planes (two below, one above) are clear of walls and layers
+        nl = w.npml if w.bc == "cpml" else 0
+        fy0, fy1, fz0, fz1 = max(1, nl), w.ny - 2 - nl, max(1, nl), w.nz - 2 - nl
+        ty, tz = (fy1 - fy0 - 2) // waves, (fz1 - fz0 - 2) // zchunk
+        assert got[2]["fused_cells"] == (ty * waves * tz * zchunk * w.nx if ty > 0 and tz > 0 else 0)
         assert_same(got, ref, (label, waves, zchunk))
         err = rel_l2(got[0], orc)
         assert np.all(err <= TOL_FP32), err

@@ -686,6 +686,8 @@ void chf_plan_destroy(chf_plan *plan) {
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
   if (plan->aux) (void)hipStreamDestroy(plan->aux);
+  if (plan->ev_join2) (void)hipEventDestroy(plan->ev_join2);
+  if (plan->aux2) (void)hipStreamDestroy(plan->aux2);
   delete plan;
 }
 
@@ -865,6 +867,8 @@ chf_status chf_plan_bind_workspace(chf_plan *p, void *dev_ptr, uint64_t bytes, v
     hipError_t e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->aux2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join2, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "side stream");
   }
   return chf_plan_reset(p, stream);
@@ -1391,6 +1395,8 @@ chf_status chf_batch_bind_workspace(chf_batch *b, void *dev_ptr, uint64_t bytes,
     hipError_t e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join2, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "side stream");
   }
   if (b->graph) {
@@ -1496,6 +1502,8 @@ void chf_batch_destroy(chf_batch *b) {
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->aux) (void)hipStreamDestroy(b->aux);
+  if (b->ev_join2) (void)hipEventDestroy(b->ev_join2);
+  if (b->aux2) (void)hipStreamDestroy(b->aux2);
   delete b;
 }
 

@@ -173,6 +173,9 @@ struct chf_plan {
   // side stream for the boundary H sweep, which runs beside the fused interior sweep
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // a second side stream: the z-boundary sweep beside the y-boundary one
+  hipStream_t aux2 = nullptr;
+  hipEvent_t ev_join2 = nullptr;
   // graph cache
   hipGraphExec_t graph = nullptr;
   const void *graph_w = nullptr, *graph_q = nullptr;
@@ -202,6 +205,9 @@ struct chf_batch {
   hipGraphExec_t graph = nullptr;
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // a second side stream: the z-boundary sweep beside the y-boundary one
+  hipStream_t aux2 = nullptr;
+  hipEvent_t ev_join2 = nullptr;
 };
 
 namespace chf {

@@ -948,8 +948,9 @@ __global__ void k_set_field(Dev d, T *dst, const float *in, float scale, const i
 }
 
 // ------------------------------------------------------------------ launch
+// general sweeps: part bit 0 launches the y-boundary tiles (G = 1), bit 1 the z-boundary ones (G = 2)
 template <typename T, int VX, int W, bool DYN>
-static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s, int part) {
   if (general) {
     if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
       const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
@@ -957,17 +958,17 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
       // SIMD hold their registers; 9- and 12-wave workgroups would need 3 and spill); the plain
       // boundary sweeps of 11-row tiles fit 3 waves per SIMD (the z-wall one with a small spill)
       if (p.fs.prefetch && W <= 7) {
-        if (ny_ > 0)
+        if (ny_ > 0 && (part & 1))
           hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, true, 1, DYN>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles, ny_, par);
-        if (nr > 0)
+        if (nr > 0 && (part & 2))
           hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, true, 1, DYN>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles + 2 * ny_, nr, par);
       } else {
-        if (ny_ > 0)
+        if (ny_ > 0 && (part & 1))
           hipLaunchKernelGGL((k_fused_gen<T, VX, W, 1, false, 1, DYN>), dim3((ny_ + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles, ny_, par);
-        if (nr > 0)
+        if (nr > 0 && (part & 2))
           hipLaunchKernelGGL((k_fused_gen<T, VX, W, 2, false, 1, DYN>), dim3((nr + 7) / 8 * 8), dim3(64 * (W + 1)), 0, s, d,
                              p.fs, d.slow_tiles + 2 * ny_, nr, par);
       }
@@ -984,18 +985,19 @@ static hipError_t fused_launch(const chf_plan &p, const Dev &d, int par, bool ge
 }
 
 template <typename T, int VX, bool DYN>
-static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s,
+                                   int part) {
   switch (p.fs.waves) {
-    case 4: return fused_launch<T, VX, 4, DYN>(p, d, par, general, s);
-    case 7: return fused_launch<T, VX, 7, DYN>(p, d, par, general, s);
+    case 4: return fused_launch<T, VX, 4, DYN>(p, d, par, general, s, part);
+    case 7: return fused_launch<T, VX, 7, DYN>(p, d, par, general, s, part);
     case 8:
-      if constexpr (VX <= 4) return fused_launch<T, VX, 8, DYN>(p, d, par, general, s);
+      if constexpr (VX <= 4) return fused_launch<T, VX, 8, DYN>(p, d, par, general, s, part);
       return hipErrorInvalidValue;
     case 11:
-      if constexpr (VX <= 4) return fused_launch<T, VX, 11, DYN>(p, d, par, general, s);
+      if constexpr (VX <= 4) return fused_launch<T, VX, 11, DYN>(p, d, par, general, s, part);
       return hipErrorInvalidValue;
     case 15:
-      if constexpr (VX <= 4) return fused_launch<T, VX, 15, DYN>(p, d, par, general, s);
+      if constexpr (VX <= 4) return fused_launch<T, VX, 15, DYN>(p, d, par, general, s, part);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -1004,14 +1006,14 @@ static hipError_t fused_dispatch_w(const chf_plan &p, const Dev &d, int par, boo
 // Rows of up to 512 nodes split across two waves (VX 4): the prefetching interior sweep with 4 or 5
 // rows per tile (10 or 12 waves) and the plain general sweep for the boundary tiles.
 template <typename T, int W, bool DYN>
-static hipError_t split_rows_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+static hipError_t split_rows_launch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s, int part) {
   const dim3 block(64 * (W + 1) * 2);
   if (general) {
     const int ny_ = p.fs.n_slow_y, nr = p.fs.n_slow - p.fs.n_slow_y;
-    if (ny_ > 0)
+    if (ny_ > 0 && (part & 1))
       hipLaunchKernelGGL((k_fused_gen<T, 4, W, 1, false, 2, DYN>), dim3((ny_ + 7) / 8 * 8), block, 0, s, d, p.fs,
                          d.slow_tiles, ny_, par);
-    if (nr > 0)
+    if (nr > 0 && (part & 2))
       hipLaunchKernelGGL((k_fused_gen<T, 4, W, 2, false, 2, DYN>), dim3((nr + 7) / 8 * 8), block, 0, s, d, p.fs,
                          d.slow_tiles + 2 * ny_, nr, par);
   } else {
@@ -1022,17 +1024,18 @@ static hipError_t split_rows_launch(const chf_plan &p, const Dev &d, int par, bo
 
 // general = false: the interior rectangle; true: the boundary tiles of the tile table
 template <typename T, bool DYN>
-static hipError_t fused_dispatch_t(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+static hipError_t fused_dispatch_t(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s,
+                                   int part = 3) {
   if (p.fs.xs == 2) {
-    if (p.fs.waves == 4) return split_rows_launch<T, 4, DYN>(p, d, par, general, s);
-    if (p.fs.waves == 5) return split_rows_launch<T, 5, DYN>(p, d, par, general, s);
+    if (p.fs.waves == 4) return split_rows_launch<T, 4, DYN>(p, d, par, general, s, part);
+    if (p.fs.waves == 5) return split_rows_launch<T, 5, DYN>(p, d, par, general, s, part);
     return hipErrorInvalidValue;
   }
   switch (p.fs.vx) {
-    case 1: return fused_dispatch_w<T, 1, DYN>(p, d, par, general, s);
-    case 2: return fused_dispatch_w<T, 2, DYN>(p, d, par, general, s);
-    case 4: return fused_dispatch_w<T, 4, DYN>(p, d, par, general, s);
-    case 8: return fused_dispatch_w<T, 8, DYN>(p, d, par, general, s);
+    case 1: return fused_dispatch_w<T, 1, DYN>(p, d, par, general, s, part);
+    case 2: return fused_dispatch_w<T, 2, DYN>(p, d, par, general, s, part);
+    case 4: return fused_dispatch_w<T, 4, DYN>(p, d, par, general, s, part);
+    case 8: return fused_dispatch_w<T, 8, DYN>(p, d, par, general, s, part);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1040,13 +1043,14 @@ static hipError_t fused_dispatch_t(const chf_plan &p, const Dev &d, int par, boo
 // Dynamically scaled levels exist for FP16 storage only (plan validation), so only the FP16
 // sweeps are built in that form.
 template <typename T>
-static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s) {
+static hipError_t fused_dispatch(const chf_plan &p, const Dev &d, int par, bool general, hipStream_t s,
+                                 int part = 3) {
   if constexpr (std::is_same<T, _Float16>::value) {
-    if (d.dyn) return fused_dispatch_t<T, true>(p, d, par, general, s);
+    if (d.dyn) return fused_dispatch_t<T, true>(p, d, par, general, s, part);
   } else {
     if (d.dyn) return hipErrorInvalidValue;
   }
-  return fused_dispatch_t<T, false>(p, d, par, general, s);
+  return fused_dispatch_t<T, false>(p, d, par, general, s, part);
 }
 
 template <typename T>
@@ -1061,14 +1065,21 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
     // (or, for rows wider than 256 nodes and for 15-row tiles, whose general sweep would not
     // fit its registers, in split H and E sweeps).  Both read only the input
     // level and write disjoint nodes, so the boundary sweep (its H half, when split) runs on
-    // the side stream beside the interior one.
+    // the side stream beside the interior one; the general sweep's z-boundary tiles on a second
+    // side stream beside its y-boundary ones.
     const bool gen = (p.fs.vx <= kMaxGeneralVX && p.fs.waves <= kMaxGeneralW) || p.fs.xs == 2;
     const bool fork = p.fs.n_fast > 0 && p.fs.n_slow > 0 && p.aux;
+    const bool fork2 = fork && gen && p.aux2 && p.fs.n_slow_y > 0 && p.fs.n_slow > p.fs.n_slow_y;
     if (fork) {
       e = hipEventRecord(p.ev_fork, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.ev_fork, 0);
+      if (e == hipSuccess && fork2) e = hipStreamWaitEvent(p.aux2, p.ev_fork, 0);
       if (e == hipSuccess) {
-        if (gen) {
+        if (fork2) {
+          e = fused_dispatch<T>(p, d, par, true, p.aux, 1);
+          if (e == hipSuccess) e = fused_dispatch<T>(p, d, par, true, p.aux2, 2);
+          if (e == hipSuccess) e = hipEventRecord(p.ev_join2, p.aux2);
+        } else if (gen) {
           e = fused_dispatch<T>(p, d, par, true, p.aux);
         } else {
           hipLaunchKernelGGL((k_split<T, true>), sgrid, sblock, 0, p.aux, d, p.fs, d.slow_tiles, p.fs.n_slow, par);
@@ -1087,6 +1098,7 @@ static hipError_t step_t(const chf_plan &p, const Dev &d_in, int par, int step, 
     if (p.fs.n_slow > 0) {
       if (fork) {
         e = hipStreamWaitEvent(s, p.ev_join, 0);
+        if (e == hipSuccess && fork2) e = hipStreamWaitEvent(s, p.ev_join2, 0);
       } else if (gen) {
         e = fused_dispatch<T>(p, d, par, true, s);
       } else {
@@ -1135,23 +1147,23 @@ hipError_t launch_step(const chf_plan &p, const Dev &d, int par, int step, const
 // general = false: the interior tiles of every member; true: their boundary tiles
 template <typename T, int VX, int W>
 static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z, int par, bool general,
-                              hipStream_t s) {
+                              hipStream_t s, int part) {
   if (general) {
     if constexpr (VX <= kMaxGeneralVX && W <= kMaxGeneralW) {
       const int n1 = (int)(b.gen_tab[0].size() / 3), n2 = (int)(b.gen_tab[1].size() / 3);
       const int *t1 = (const int *)(b.ws + b.off_gen[0]), *t2 = (const int *)(b.ws + b.off_gen[1]);
       if (b.prefetch && W <= 7) {  // as for single plans: only 8-wave workgroups hold the registers
-        if (n1 > 0)
+        if (n1 > 0 && (part & 1))
           hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 1, true>), dim3((n1 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
                              s, devs, z, t1, n1, par);
-        if (n2 > 0)
+        if (n2 > 0 && (part & 2))
           hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 2, true>), dim3((n2 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
                              s, devs, z, t2, n2, par);
       } else {
-        if (n1 > 0)
+        if (n1 > 0 && (part & 1))
           hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 1, false>), dim3((n1 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
                              s, devs, z, t1, n1, par);
-        if (n2 > 0)
+        if (n2 > 0 && (part & 2))
           hipLaunchKernelGGL((k_fused_gen_batch<T, VX, W, 2, false>), dim3((n2 + 7) / 8 * 8), dim3(64 * (W + 1)), 0,
                              s, devs, z, t2, n2, par);
       }
@@ -1177,18 +1189,18 @@ static hipError_t batch_fused(const chf_batch &b, const Dev *devs, const int *z,
 
 template <typename T, int VX>
 static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *z, int par, bool general,
-                                hipStream_t s) {
+                                hipStream_t s, int part) {
   switch (b.waves) {
-    case 4: return batch_fused<T, VX, 4>(b, devs, z, par, general, s);
-    case 7: return batch_fused<T, VX, 7>(b, devs, z, par, general, s);
+    case 4: return batch_fused<T, VX, 4>(b, devs, z, par, general, s, part);
+    case 7: return batch_fused<T, VX, 7>(b, devs, z, par, general, s, part);
     case 8:
-      if constexpr (VX <= 4) return batch_fused<T, VX, 8>(b, devs, z, par, general, s);
+      if constexpr (VX <= 4) return batch_fused<T, VX, 8>(b, devs, z, par, general, s, part);
       return hipErrorInvalidValue;
     case 11:
-      if constexpr (VX <= 4) return batch_fused<T, VX, 11>(b, devs, z, par, general, s);
+      if constexpr (VX <= 4) return batch_fused<T, VX, 11>(b, devs, z, par, general, s, part);
       return hipErrorInvalidValue;
     case 15:
-      if constexpr (VX <= 4) return batch_fused<T, VX, 15>(b, devs, z, par, general, s);
+      if constexpr (VX <= 4) return batch_fused<T, VX, 15>(b, devs, z, par, general, s, part);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
@@ -1196,12 +1208,12 @@ static hipError_t batch_fused_w(const chf_batch &b, const Dev *devs, const int *
 
 template <typename T>
 static hipError_t batch_fused_v(const chf_batch &b, const Dev *devs, const int *z, int par, bool general,
-                                hipStream_t s) {
+                                hipStream_t s, int part = 3) {
   switch (b.vx) {
-    case 1: return batch_fused_w<T, 1>(b, devs, z, par, general, s);
-    case 2: return batch_fused_w<T, 2>(b, devs, z, par, general, s);
-    case 4: return batch_fused_w<T, 4>(b, devs, z, par, general, s);
-    default: return batch_fused_w<T, 8>(b, devs, z, par, general, s);
+    case 1: return batch_fused_w<T, 1>(b, devs, z, par, general, s, part);
+    case 2: return batch_fused_w<T, 2>(b, devs, z, par, general, s, part);
+    case 4: return batch_fused_w<T, 4>(b, devs, z, par, general, s, part);
+    default: return batch_fused_w<T, 8>(b, devs, z, par, general, s, part);
   }
 }
 
@@ -1215,14 +1227,21 @@ static hipError_t batch_step_t(const chf_batch &b, int par, int step, hipStream_
   // boundary tiles (general fused sweep, or split H then E) on the side stream beside the
   // interior tiles; the source injection joins them
   const bool fork = ns > 0 && !b.fast_tab.empty() && b.aux;
+  // the z-boundary tiles of the general sweep on a second side stream beside the y-boundary ones
+  const bool fork2 = fork && b.gen && b.aux2 && !b.gen_tab[0].empty() && !b.gen_tab[1].empty();
   hipStream_t sb = fork ? b.aux : s;
   if (fork) {
     e = hipEventRecord(b.ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(b.aux, b.ev_fork, 0);
+    if (e == hipSuccess && fork2) e = hipStreamWaitEvent(b.aux2, b.ev_fork, 0);
     if (e != hipSuccess) return e;
   }
   if (ns > 0) {
-    if (b.gen) {
+    if (fork2) {
+      e = batch_fused_v<T>(b, devs, z, par, true, b.aux, 1);
+      if (e == hipSuccess) e = batch_fused_v<T>(b, devs, z, par, true, b.aux2, 2);
+      if (e == hipSuccess) e = hipEventRecord(b.ev_join2, b.aux2);
+    } else if (b.gen) {
       e = batch_fused_v<T>(b, devs, z, par, true, sb);
     } else {
       hipLaunchKernelGGL((k_split_batch<T, true>), dim3(ns), dim3(64 * b.waves), 0, sb, devs, z, stab, ns,
@@ -1235,6 +1254,7 @@ static hipError_t batch_step_t(const chf_batch &b, int par, int step, hipStream_
   e = batch_fused_v<T>(b, devs, z, par, false, s);
   if (e != hipSuccess) return e;
   if (fork) e = hipStreamWaitEvent(s, b.ev_join, 0);
+  if (e == hipSuccess && fork2) e = hipStreamWaitEvent(s, b.ev_join2, 0);
   if (e != hipSuccess) return e;
   // the split E sweep reads the fresh H of the interior tiles next to the boundary ones
   if (ns > 0 && !b.gen)

@@ -784,16 +784,16 @@ __global__ void __launch_bounds__(64) k_gather_smp(Dev d, int par, double *w, in
 
 template <typename T, int VX, int W, bool DYN>
 static hipError_t step2_launch(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
-                               hipStream_t s) {
+                               hipStream_t s, int part) {
   const Shape2 &f2 = p.fs2;
   if (general) {
     const dim3 block(64 * (kStep2BoundaryRows + 4));
     const int *tiles = (const int *)(p.ws + p.off_tiles2);
     const int n1 = f2.n_slow_y, n2 = f2.n_slow - f2.n_slow_y;
-    if (n1 > 0)
+    if (n1 > 0 && (part & 1))
       hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 1, DYN>), dim3((n1 + 7) / 8 * 8), block, 0, s, d, f2, tiles, n1, par, step,
                          q);
-    if (n2 > 0)
+    if (n2 > 0 && (part & 2))
       hipLaunchKernelGGL((k_step2_gen<T, VX, 1, 2, DYN>), dim3((n2 + 7) / 8 * 8), block, 0, s, d, f2, tiles + 3 * n1, n2,
                          par, step, q);
   } else if (f2.n_fast > 0) {
@@ -804,18 +804,18 @@ static hipError_t step2_launch(const chf_plan &p, const Dev &d, int par, int ste
 
 template <typename T, bool DYN>
 static hipError_t step2_dispatch_t(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
-                                   hipStream_t s) {
+                                   hipStream_t s, int part) {
   const Shape2 &f2 = p.fs2;
   switch (f2.vx * 100 + f2.waves) {
-    case 104: return step2_launch<T, 1, 4, DYN>(p, d, par, step, q, general, s);
-    case 107: return step2_launch<T, 1, 7, DYN>(p, d, par, step, q, general, s);
-    case 108: return step2_launch<T, 1, 8, DYN>(p, d, par, step, q, general, s);
-    case 204: return step2_launch<T, 2, 4, DYN>(p, d, par, step, q, general, s);
-    case 207: return step2_launch<T, 2, 7, DYN>(p, d, par, step, q, general, s);
-    case 208: return step2_launch<T, 2, 8, DYN>(p, d, par, step, q, general, s);
-    case 404: return step2_launch<T, 4, 4, DYN>(p, d, par, step, q, general, s);
-    case 407: return step2_launch<T, 4, 7, DYN>(p, d, par, step, q, general, s);
-    case 408: return step2_launch<T, 4, 8, DYN>(p, d, par, step, q, general, s);
+    case 104: return step2_launch<T, 1, 4, DYN>(p, d, par, step, q, general, s, part);
+    case 107: return step2_launch<T, 1, 7, DYN>(p, d, par, step, q, general, s, part);
+    case 108: return step2_launch<T, 1, 8, DYN>(p, d, par, step, q, general, s, part);
+    case 204: return step2_launch<T, 2, 4, DYN>(p, d, par, step, q, general, s, part);
+    case 207: return step2_launch<T, 2, 7, DYN>(p, d, par, step, q, general, s, part);
+    case 208: return step2_launch<T, 2, 8, DYN>(p, d, par, step, q, general, s, part);
+    case 404: return step2_launch<T, 4, 4, DYN>(p, d, par, step, q, general, s, part);
+    case 407: return step2_launch<T, 4, 7, DYN>(p, d, par, step, q, general, s, part);
+    case 408: return step2_launch<T, 4, 8, DYN>(p, d, par, step, q, general, s, part);
   }
   return hipErrorInvalidValue;
 }
@@ -823,13 +823,13 @@ static hipError_t step2_dispatch_t(const chf_plan &p, const Dev &d, int par, int
 // dynamically scaled levels exist for FP16 storage only
 template <typename T>
 static hipError_t step2_dispatch(const chf_plan &p, const Dev &d, int par, int step, const double *q, bool general,
-                                 hipStream_t s) {
+                                 hipStream_t s, int part = 3) {
   if constexpr (std::is_same<T, _Float16>::value) {
-    if (d.dyn) return step2_dispatch_t<T, true>(p, d, par, step, q, general, s);
+    if (d.dyn) return step2_dispatch_t<T, true>(p, d, par, step, q, general, s, part);
   } else {
     if (d.dyn) return hipErrorInvalidValue;
   }
-  return step2_dispatch_t<T, false>(p, d, par, step, q, general, s);
+  return step2_dispatch_t<T, false>(p, d, par, step, q, general, s, part);
 }
 
 template <typename T>
@@ -839,12 +839,21 @@ static hipError_t step2_t(const chf_plan &p, const Dev &d, int par, int step, co
   const double *qq = q ? q : d.q_bins;
   hipError_t e = hipSuccess;
   // boundary tiles on the side stream beside the interior ones (both read only level par and
-  // write disjoint nodes of level par^1)
+  // write disjoint nodes of level par^1), the z-boundary tiles on a second side stream beside
+  // the y-boundary ones
   const bool fork = f2.n_fast > 0 && f2.n_slow > 0 && p.aux;
+  const bool fork2 = fork && p.aux2 && f2.n_slow_y > 0 && f2.n_slow > f2.n_slow_y;
   if (fork) {
     e = hipEventRecord(p.ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.ev_fork, 0);
-    if (e == hipSuccess) e = step2_dispatch<T>(p, d, par, step, qq, true, p.aux);
+    if (fork2) {
+      if (e == hipSuccess) e = hipStreamWaitEvent(p.aux2, p.ev_fork, 0);
+      if (e == hipSuccess) e = step2_dispatch<T>(p, d, par, step, qq, true, p.aux, 1);
+      if (e == hipSuccess) e = step2_dispatch<T>(p, d, par, step, qq, true, p.aux2, 2);
+      if (e == hipSuccess) e = hipEventRecord(p.ev_join2, p.aux2);
+    } else if (e == hipSuccess) {
+      e = step2_dispatch<T>(p, d, par, step, qq, true, p.aux);
+    }
     if (e == hipSuccess) e = hipEventRecord(p.ev_join, p.aux);
     if (e != hipSuccess) return e;
   }
@@ -856,6 +865,7 @@ static hipError_t step2_t(const chf_plan &p, const Dev &d, int par, int step, co
   }
   if (f2.n_slow > 0) {
     e = fork ? hipStreamWaitEvent(s, p.ev_join, 0) : step2_dispatch<T>(p, d, par, step, qq, true, s);
+    if (e == hipSuccess && fork2) e = hipStreamWaitEvent(s, p.ev_join2, 0);
     if (e != hipSuccess) return e;
   }
   if (d.dyn) {

@@ -81,9 +81,22 @@ def kernel_digest_for(workload: str) -> str:
                                 else ("chf_kernels.hip", "chf_step2.hip", "chf_cell.h", "chf_internal.h"))
 
 
+def canonical_workload(name: str) -> str:
+    """The full name of a workload given by its short name ("precision" ->
+    "precision-512x512x4096"); (r, z) names and full names pass through."""
+    if is_rz(name):
+        return name
+    from paper_1001_5341_amd import workloads as W
+
+    try:
+        return W.workload_by_name(name).name
+    except KeyError:
+        return name
+
+
 def traffic_path(workload: str, storage: str) -> str:
     kern = "rz_step" if is_rz(workload) else "fused_sweep"
-    return os.path.join(ROOT, "profiles", f"traffic_{kern}_{workload}_{storage}.json")
+    return os.path.join(ROOT, "profiles", f"traffic_{kern}_{canonical_workload(workload)}_{storage}.json")
 
 
 def measured_traffic(workload: str, storage: str, tile=None):
@@ -128,7 +141,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
     kdesc = ("axisymmetric two-step launch (k_rz_step2)" if is_rz(workload)
              else "two-step interior sweep (chf::k_step2)" if kname == STEP2_KERNEL
              else "fused interior sweep (chf::k_fused)")
-    rec = {"workload": workload, "storage": storage, "kernel": kdesc,
+    rec = {"workload": canonical_workload(workload), "storage": storage, "kernel": kdesc,
            "kernel_digest": kernel_digest_for(workload), "command": command, "tile": tile,
            "fetch": out["fetch"], "write": out["write"],
            "bytes_per_launch": out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]}

@@ -103,3 +103,15 @@ def test_waveform_error_metrics():
     got2[2] *= 1.01
     e2 = bench.waveform_error(got2, ref)
     assert abs(e2["rel_l2_max"] - 1e-2) < 1e-12 and e2["rel_l2_median"] == 0.0
+
+
+def test_traffic_records_are_found_under_the_short_workload_names():
+    """The bench is run with short workload names ("precision", "single-shower"); the counter
+    records are named for the full workload, so both names find the same committed record."""
+    p = bench.traffic_path("precision", "fp32")
+    assert p.endswith("traffic_fused_sweep_precision-512x512x4096_fp32.json")
+    assert p == bench.traffic_path("precision-512x512x4096", "fp32")
+    assert bench.traffic_path("single-shower", "fp32") == bench.traffic_path("single-shower-256x256x2048", "fp32")
+    assert bench.traffic_path("rz-8192", "fp32").endswith("traffic_rz_step_rz-8192_fp32.json")
+    for wl in ("precision", "single-shower", "rz-8192"):
+        assert os.path.exists(bench.traffic_path(wl, "fp32")), wl

@@ -290,3 +290,36 @@ def test_bf16x_plan_layout():
     finally:
         N.lib().chf_plan_destroy(h)
     assert _rz_status(W.rz_small(), storage="bf16x") == "CHF_EINVAL"  # the (r, z) scheme does not take it
+
+
+def _fused_cells(w, **kw):
+    h = solver.create_plan_handle(w, **kw)
+    try:
+        info = N.PlanInfo()
+        assert N.lib().chf_plan_get_info(h, ct.byref(info)) == 0
+        return info.fused_cells, info.kernel
+    finally:
+        N.lib().chf_plan_destroy(h)
+
+
+@pytest.mark.parametrize("bc,npml", [("cpml", 10), ("cpml", 6), ("pec", 0)])
+def test_interior_rectangle_starts_at_the_first_clear_row_and_plane(bc, npml):
+    """The tile grids are shifted so that the interior rectangle holds every whole tile and
+    chunk that fits in the region clear of walls and layers: for the one-step sweep the tile's
+    rows and the row below it, for the two-step pass the computed rows and staged planes (two
+    below, one above)."""
+    for ny, nz in ((44, 72), (60, 150), (57, 131)):
+        w = W.small_shower(seed=3, nx=64, ny=ny, nz=nz, n_steps=10, n_obs=2, npml=max(npml, 6), bc=bc)
+        nl = w.npml if bc == "cpml" else 0
+        fy0, fy1, fz0, fz1 = max(1, nl), ny - 2 - nl, max(1, nl), nz - 2 - nl
+        for waves, zc in ((4, 7), (7, 8), (8, 12), (11, 5), (5, 9)):
+            if waves == 5:
+                continue  # 5 rows is the split-row tile of 257-512-node rows
+            ty, tz = (fy1 - fy0) // waves, (fz1 - fz0 + 1) // zc
+            cells, kern = _fused_cells(w, kernel="fused", waves=waves, zchunk=zc)
+            assert cells == (ty * waves * tz * zc * w.nx if ty > 0 and tz > 0 else 0), (ny, nz, waves, zc)
+            if waves in (4, 7, 8):
+                ty, tz = (fy1 - fy0 - 2) // waves, (fz1 - fz0 - 2) // zc
+                cells, kern = _fused_cells(w, kernel="fused2", waves=waves, zchunk=zc)
+                assert kern == 4
+                assert cells == (ty * waves * tz * zc * w.nx if ty > 0 and tz > 0 else 0), (ny, nz, waves, zc)

@@ -49,6 +49,8 @@ HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20
 FUSED_KERNEL = "chf::k_fused<"
 STEP2_KERNEL = "chf::k_step2<"
+# the profiler leaves names it cannot demangle (the _Float16 instances) mangled
+MANGLED = {FUSED_KERNEL: "_ZN3chf7k_fusedI", STEP2_KERNEL: "_ZN3chf7k_step2I"}
 RZ_KERNEL = "k_rz_step2<"
 RZ_BYTES_PER_NODE = 24.0  # read E_r, E_z, H_phi once and write them once (FP32)
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -131,7 +133,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, storage: str, c
         if not copies:
             raise SystemExit(f"{path}: no calibration copy dispatch (run with --copy-probe)")
         copy_kib = max(copies)  # the 256 MiB probe is by far the largest copy
-        fused = [v for k, g, v in rows if kname in k]
+        fused = [v for k, g, v in rows if kname in k or (kname in MANGLED and k.startswith(MANGLED[kname]))]
         if not fused:
             raise SystemExit(f"{path}: no {kname} dispatch")
         factor = (COPY_PROBE_BYTES / 1024.0) / copy_kib

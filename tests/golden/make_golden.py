@@ -35,10 +35,10 @@ def main(name: str):
                       "cell_updates_per_s": w.n_cells * w.n_steps / wall}))
 
 
-# members of the 32-shower batch whose waveforms are stored: every member up to 5.1e10
-# cell-updates, which spans every width from 96 to 256 nodes (the other eight, 6.4e10 to 1.0e11
-# each, would take the host oracle about two more hours)
-BATCH_SAMPLE = (24, 20, 19, 26, 15, 6, 12, 5, 28, 31, 25, 29, 3, 23, 27, 7, 2, 30, 13, 16, 17, 22, 14, 18)
+# members of the 32-shower batch whose waveforms are stored: all 32, smallest first (about 3 h
+# of the host oracle on 8 threads; the file is rewritten after each member)
+BATCH_SAMPLE = (24, 20, 19, 26, 15, 6, 12, 5, 28, 31, 25, 29, 3, 23, 27, 7, 2, 30, 13, 16, 17, 22, 14, 18,
+                4, 21, 10, 1, 8, 11, 0, 9)
 
 
 def adjoint_golden():

@@ -4,8 +4,7 @@ oracle):
 
 - single shower 256x256x2048, CPML-10, 4000 steps, 64 observers: every waveform;
 - the 32-shower batch (uneven grids up to 256x256x1024, 2000 steps, 16 observers each), run
-  as one batch: the stored members (every member up to 5.1e10 cell-updates, 24 of the 32,
-  spanning every width from 96 to 256 nodes);
+  as one batch: every member;
 - differentiation 128x128x1024, 3000 steps, 128 profile bins: waveforms and dL/dq, by the
   one-sweep and the checkpointed (every 55 steps) adjoint.
 

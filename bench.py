@@ -596,8 +596,8 @@ BATCH_CANDIDATES = tuple((wv, z, "fused") for wv in (7, 8) for z in (8, 12, 16, 
 
 
 def batch_accuracy(ws, outs):
-    """Waveform error of the members whose FP64 oracle waveforms are stored (the oracle cannot
-    afford the whole batch), max over those members."""
+    """Waveform error of the members whose FP64 oracle waveforms are stored (all 32 of the
+    batch), max over those members."""
     from paper_1001_5341_amd.workloads import workload_digest
 
     gold = os.path.join(ROOT, "tests", "golden", "batch_oracle.npz")

@@ -61,7 +61,7 @@ def test_single_shower_full_size_against_stored_oracle(gpu):
     assert np.all(err <= 1e-5), err
 
 
-def test_batch_full_size_sampled_members_against_stored_oracle(gpu):
+def test_batch_full_size_members_against_stored_oracle(gpu):
     rec = stored("batch_oracle.npz")
     ws = W.batch_showers()
     members = [int(m) for m in rec["members"]]
